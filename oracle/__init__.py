@@ -1,0 +1,213 @@
+"""CPU oracle for the fast-HOG hot path -- test infrastructure only.
+
+A thin ctypes wrapper over ``oracle.c`` (plain C, FP64, brute force; see
+that file's header for what each function follows in the paper). Only the
+test suite, the smoke check and the benchmark's CPU-baseline leg import
+this package. It never imports the product package and the product never
+imports it.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+NO_BIN = 255
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile oracle.c into liboracle.so with gcc (plain -O2, one thread)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-Wall",
+                               "-Wextra", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=True)
+        lib = ctypes.CDLL(_LIB)
+        i32, i64, dbl = ctypes.c_int, ctypes.c_int64, ctypes.c_double
+        p = ctypes.c_void_p
+        lib.orc_bin.argtypes = [i32, i32, i32]
+        lib.orc_bin.restype = i32
+        lib.orc_bin_table.argtypes = [i32, p]
+        lib.orc_bin_table.restype = i32
+        lib.orc_bin_map.argtypes = [p, i32, i32, i32, i64, i32, p]
+        lib.orc_pyramid.argtypes = [i32, i32, dbl, i32, i32, i32, i32, p, p, p]
+        lib.orc_resize_nn.argtypes = [p, i32, i32, i32, i64, dbl, i32, i32, p]
+        lib.orc_integral.argtypes = [p, i32, i32, i32, p]
+        lib.orc_integral_literal.argtypes = [p, i32, i32, i32, p]
+        lib.orc_cell_hist.argtypes = [p, i32, i32, i32, i32, p]
+        lib.orc_feature_dim.argtypes = [i32, i32, i32, i32, i32]
+        lib.orc_window_feature.argtypes = [p, i32, i32, i32, i32, i32, i32, i32, i32, dbl,
+                                           i32, i32, p]
+        lib.orc_window_grid.argtypes = [i32, i32, i32, i32, i32, p, p]
+        lib.orc_score_windows.argtypes = [p, i32, i32, i32, i32, i32, i32, i32, i32, dbl,
+                                          p, p, i32, i32, p, p, p, p, p]
+        for name in ("orc_bin_map", "orc_pyramid", "orc_resize_nn", "orc_integral",
+                     "orc_integral_literal", "orc_cell_hist", "orc_feature_dim",
+                     "orc_window_feature", "orc_window_grid", "orc_score_windows"):
+            getattr(lib, name).restype = i32
+        _lib = lib
+    return _lib
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _check(rc: int, what: str):
+    if rc < 0:
+        raise ValueError(f"oracle {what} rejected its arguments (rc={rc})")
+
+
+# --------------------------------------------------------------------------
+def bin_of(dx: int, dy: int, n_bins: int) -> int:
+    """Orientation bin of one gradient (FP64 atan2; 255 for a zero gradient)."""
+    r = _load().orc_bin(int(dx), int(dy), int(n_bins))
+    _check(r, "bin")
+    return r
+
+
+def bin_table(n_bins: int) -> np.ndarray:
+    """bin_of over every (dx, dy) in [-255, 255]^2, as uint8[dy+255][dx+255]."""
+    out = np.empty((511, 511), dtype=np.uint8)
+    _check(_load().orc_bin_table(int(n_bins), _ptr(out)), "bin_table")
+    return out
+
+
+def bin_map(img: np.ndarray, n_bins: int) -> np.ndarray:
+    """Bin map (uint8, h x w) of an image of shape (h, w) or (h, w, c)."""
+    img = np.ascontiguousarray(img, dtype=np.uint8)
+    if img.ndim == 2:
+        img = img[:, :, None]
+    h, w, c = img.shape
+    out = np.empty((h, w), dtype=np.uint8)
+    _check(_load().orc_bin_map(_ptr(img), w, h, c, w * c, n_bins, _ptr(out)), "bin_map")
+    return out
+
+
+def pyramid(w: int, h: int, scale: float, min_w: int, min_h: int, max_levels: int = 0):
+    """[(w_l, h_l, s_l)] of the nearest-neighbour pyramid."""
+    cap = 4096
+    lw = np.zeros(cap, np.int32)
+    lh = np.zeros(cap, np.int32)
+    ls = np.zeros(cap, np.float64)
+    n = _load().orc_pyramid(w, h, float(scale), min_w, min_h, max_levels, cap,
+                            _ptr(lw), _ptr(lh), _ptr(ls))
+    _check(n, "pyramid")
+    return [(int(lw[i]), int(lh[i]), float(ls[i])) for i in range(n)]
+
+
+def resize_nn(img: np.ndarray, s: float, lw: int, lh: int) -> np.ndarray:
+    img = np.ascontiguousarray(img, dtype=np.uint8)
+    if img.ndim == 2:
+        img = img[:, :, None]
+    h, w, c = img.shape
+    out = np.empty((lh, lw, c), dtype=np.uint8)
+    _check(_load().orc_resize_nn(_ptr(img), w, h, c, w * c, float(s), lw, lh, _ptr(out)),
+           "resize_nn")
+    return out
+
+
+def integral(bins: np.ndarray, n_bins: int) -> np.ndarray:
+    """uint32[n_bins][h+1][w+1]; [n][y+1][x+1] = ii_n(x, y)."""
+    bins = np.ascontiguousarray(bins, dtype=np.uint8)
+    h, w = bins.shape
+    out = np.empty((n_bins, h + 1, w + 1), dtype=np.uint32)
+    _check(_load().orc_integral(_ptr(bins), w, h, n_bins, _ptr(out)), "integral")
+    return out
+
+
+def integral_literal(bins: np.ndarray, n_bins: int) -> np.ndarray:
+    bins = np.ascontiguousarray(bins, dtype=np.uint8)
+    h, w = bins.shape
+    out = np.empty((n_bins, h + 1, w + 1), dtype=np.uint32)
+    _check(_load().orc_integral_literal(_ptr(bins), w, h, n_bins, _ptr(out)),
+           "integral_literal")
+    return out
+
+
+def cell_hist(bins: np.ndarray, n_bins: int, cell: int = 8) -> np.ndarray:
+    """uint32[h//cell][w//cell][n_bins], brute-force counts."""
+    bins = np.ascontiguousarray(bins, dtype=np.uint8)
+    h, w = bins.shape
+    out = np.empty((h // cell, w // cell, n_bins), dtype=np.uint32)
+    _check(_load().orc_cell_hist(_ptr(bins), w, h, n_bins, cell, _ptr(out)), "cell_hist")
+    return out
+
+
+class ScanParams:
+    """Window geometry: cell size in pixels, window size in cells, block size
+    in cells, normalisation (0 raw, 1 L2) and eps."""
+
+    def __init__(self, cell=8, win_cells_x=8, win_cells_y=16, block=2, norm=0, eps=1e-3):
+        self.cell, self.wcx, self.wcy = cell, win_cells_x, win_cells_y
+        self.block, self.norm, self.eps = block, norm, eps
+
+    def dim(self, n_bins: int) -> int:
+        d = _load().orc_feature_dim(n_bins, self.wcx, self.wcy, self.block, self.norm)
+        _check(d, "feature_dim")
+        return d
+
+
+def window_grid(w: int, h: int, p: ScanParams):
+    a = ctypes.c_int(0)
+    b = ctypes.c_int(0)
+    _check(_load().orc_window_grid(w, h, p.cell, p.wcx, p.wcy, ctypes.byref(a),
+                                   ctypes.byref(b)), "window_grid")
+    return a.value, b.value
+
+
+def window_feature(bins: np.ndarray, n_bins: int, p: ScanParams, wx: int, wy: int):
+    bins = np.ascontiguousarray(bins, dtype=np.uint8)
+    h, w = bins.shape
+    out = np.empty(p.dim(n_bins), dtype=np.float64)
+    _check(_load().orc_window_feature(_ptr(bins), w, h, n_bins, p.cell, p.wcx, p.wcy, p.block,
+                                      p.norm, p.eps, wx, wy, _ptr(out)), "window_feature")
+    return out
+
+
+def score_windows(bins: np.ndarray, n_bins: int, p: ScanParams, tmpl: np.ndarray,
+                  bias: np.ndarray, wxs=None, wys=None, want_feats: bool = False):
+    """Scores of the listed windows (all windows when wxs/wys are None).
+
+    Returns (scores[n, k], absterms[n, k], feats[n, dim] or None, wxs, wys).
+    """
+    bins = np.ascontiguousarray(bins, dtype=np.uint8)
+    h, w = bins.shape
+    tmpl = np.ascontiguousarray(tmpl, dtype=np.float32)
+    if tmpl.ndim == 1:
+        tmpl = tmpl[None, :]
+    bias = np.ascontiguousarray(bias, dtype=np.float32).reshape(-1)
+    k = tmpl.shape[0]
+    dim = p.dim(n_bins)
+    if tmpl.shape[1] != dim or bias.shape[0] != k:
+        raise ValueError("template shape does not match the feature length")
+    if wxs is None:
+        nwx, nwy = window_grid(w, h, p)
+        gy, gx = np.meshgrid(np.arange(nwy), np.arange(nwx), indexing="ij")
+        wxs, wys = gx.reshape(-1), gy.reshape(-1)
+    wxs = np.ascontiguousarray(wxs, dtype=np.int32)
+    wys = np.ascontiguousarray(wys, dtype=np.int32)
+    n = wxs.shape[0]
+    scores = np.empty((n, k), np.float64)
+    absterms = np.empty((n, k), np.float64)
+    feats = np.empty((n, dim), np.float64) if want_feats else None
+    _check(_load().orc_score_windows(_ptr(bins), w, h, n_bins, p.cell, p.wcx, p.wcy, p.block,
+                                     p.norm, p.eps, _ptr(tmpl), _ptr(bias), k, n, _ptr(wxs),
+                                     _ptr(wys), _ptr(scores),
+                                     _ptr(feats) if feats is not None else None,
+                                     _ptr(absterms)), "score_windows")
+    return scores, absterms, feats, wxs, wys
