@@ -1,0 +1,217 @@
+/*
+ * hog.h -- C ABI of the MI355X fast-HOG library (libhog.so).
+ *
+ * The library implements the method of "A Fast HOG Descriptor Using Lookup
+ * Table and Integral Image" (Huang & Huang, arXiv:1703.06256) as
+ * hand-written HIP kernels for gfx950:
+ *
+ *   hog_lut_build     Sec. 2: a 511 x 511 table from every integer (dx, dy)
+ *                     to its orientation bin, built once at start-up.
+ *   hog_bin_map       Eq. 1 + Sec. 2: central differences per pixel, the
+ *                     table lookup, unit magnitude (the oriented gradients
+ *                     map of Sec. 3.1).
+ *   hog_integral      Eq. 4 + Eq. 5: one integral image per bin.
+ *   hog_scan_windows  Eq. 6 + Sec. 3.3 + Sec. 4: per-cell histograms as
+ *                     four-corner sums of the integral images, cached once
+ *                     per image, concatenated per detection window and
+ *                     scored by linear templates (inner products).
+ *
+ * Conventions shared by every call:
+ *   - Device buffers are owned by the caller and passed as plain device
+ *     pointers; they must stay valid until the stream's work has finished.
+ *     Objects created by the library (hog_lut, hog_plan) own their device
+ *     tables and are freed with the matching *_free / *_destroy call.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Calls enqueue work and return; none of them synchronises.
+ *   - Argument errors are found before anything is enqueued: the call
+ *     returns HOG_E_INVALID and enqueues nothing. Launch failures return
+ *     HOG_E_DEVICE. hog_last_error() gives a message for the calling
+ *     thread's last failing call. No C++ exception crosses this boundary.
+ *   - Calls on different plans or buffers are re-entrant; concurrent calls
+ *     that write the same buffers race.
+ *   - Bins are uint8 with 255 meaning "no bin" (image border, zero
+ *     gradient); 1 <= n_bins <= 64.
+ */
+#ifndef HOG_H_
+#define HOG_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    HOG_OK = 0,
+    HOG_E_INVALID = 1,   /* bad argument; nothing was enqueued */
+    HOG_E_NOMEM = 2,     /* a host or device allocation failed */
+    HOG_E_DEVICE = 3,    /* a HIP call or kernel launch failed */
+    HOG_E_BUSY = 4,      /* reserved for the request queue */
+    HOG_E_NOT_READY = 5  /* reserved for the request queue */
+} hog_status;
+
+#define HOG_NO_BIN 255
+#define HOG_MAX_BINS 64
+#define HOG_LUT_SIDE 511 /* dx, dy in [-255, 255] */
+
+enum { HOG_NORM_RAW = 0, HOG_NORM_L2 = 1 };
+
+/* Message for the calling thread's last failing call ("" if none). */
+const char *hog_last_error(void);
+
+/* ------------------------------------------------------------------------ */
+/* Lookup table (Sec. 2; Fig. 2 shows 8 bins).                              */
+/* ------------------------------------------------------------------------ */
+typedef struct hog_lut hog_lut;
+
+/* Fill table[(dy+255)*511 + (dx+255)] with the bin of (dx, dy) for every
+ * dx, dy in [-255, 255]: the angle of (dx, dy) in [0, 2 pi), measured from
+ * +x towards +y (y = row index, growing downwards), falls in the half-open
+ * sector [k 2pi/n, (k+1) 2pi/n) and the entry is k; (0, 0) gives 255. The
+ * angle is evaluated in FP64 on the host; gradients along the axes and
+ * diagonals, the only integer directions that can sit exactly on a sector
+ * edge, are binned with exact integer arithmetic. Host-only: table is a
+ * caller-owned host buffer of 511*511 bytes. No device call is made. */
+hog_status hog_lut_fill_host(int n_bins, uint8_t *table);
+
+/* Build the table for n_bins once and upload it to the current device.
+ * *out is library-owned (host copy + device copy); free with hog_lut_free.
+ * Synchronous. */
+hog_status hog_lut_build(int n_bins, hog_lut **out);
+void hog_lut_free(hog_lut *lut);
+int hog_lut_bins(const hog_lut *lut);
+/* Host copy of the table (511*511 bytes, layout as hog_lut_fill_host),
+ * valid until hog_lut_free. */
+const uint8_t *hog_lut_host(const hog_lut *lut);
+
+/* ------------------------------------------------------------------------ */
+/* Plan: level geometry and buffer layout for one image shape.              */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int32_t cell;        /* cell side in pixels (Sec. 3.1 "sub areas"); 1..32 */
+    int32_t win_cells_x; /* window width in cells; 8 for a 64-pixel window */
+    int32_t win_cells_y; /* window height in cells; 16 for 128 pixels; <= 64 */
+    int32_t block;       /* L2 blocks: block x block cells, stepping one cell;
+                            must be 2 with HOG_NORM_L2 */
+    int32_t norm;        /* HOG_NORM_RAW or HOG_NORM_L2 */
+    float eps;           /* L2: v / sqrt(|v|^2 + eps^2) */
+} hog_scan_params;
+
+typedef struct {
+    int32_t width, height; /* source image, pixels; each <= 32767 */
+    int32_t channels;      /* 1 (grey) or 3 (interleaved RGB) */
+    int32_t n_bins;        /* 1..64 */
+    int32_t max_levels;    /* 1: the image only; 0: pyramid down to the window
+                              size; k > 1: at most k levels */
+    double scale;          /* pyramid step (> 1) when max_levels != 1 */
+    int32_t n_templates;   /* K >= 1 linear templates */
+    hog_scan_params scan;
+} hog_plan_desc;
+
+typedef struct hog_plan hog_plan;
+
+/* One pyramid level. All offsets are from the base pointers passed to the
+ * calls below. Level 0 is the source image; level l has scale s_l = s_{l-1}
+ * * scale (s_0 = 1, FP64) and size floor(W / s_l) x floor(H / s_l); pixel
+ * (x, y) of level l is source pixel (min(W-1, floor(x s_l)),
+ * min(H-1, floor(y s_l))) (nearest neighbour). Levels are kept while both
+ * sides are at least the window size. */
+typedef struct {
+    int32_t width, height;
+    double scale;
+    int64_t bins_offset;     /* bytes; bin (x, y) at bins[bins_offset + y*bins_pitch + x] */
+    int64_t bins_pitch;      /* bytes */
+    int64_t ii_offset;       /* elements; see hog_integral for the layout */
+    int64_t ii_pitch;        /* elements between rows, multiple of 64 */
+    int64_t ii_plane_stride; /* elements between bins' planes, multiple of 64 */
+    int32_t cells_x, cells_y;    /* whole cells: floor(width / cell), ... */
+    int32_t windows_x, windows_y;/* window grid; 0 x 0 if the level is smaller than a window */
+    int64_t score_offset;    /* elements; scores[score_offset + (wy*windows_x + wx)*K + k] */
+    int64_t cell_offset;     /* elements; cell_hist[cell_offset + (cy*cells_x + cx)*n_bins + n] */
+    int64_t block_offset;    /* elements; block_feat[block_offset +
+                                ((by*(cells_x-1) + bx)*4 + (v*2 + u))*n_bins + n] (L2 only) */
+} hog_level_info;
+
+typedef struct {
+    int32_t n_levels;
+    int64_t bins_bytes;       /* size of the bins buffer */
+    int64_t ii_elems;         /* uint32 elements of the integral-image buffer */
+    int64_t score_elems;      /* float elements of the score buffer */
+    int64_t cell_elems;       /* uint32 elements of the optional cell_hist buffer */
+    int64_t block_elems;      /* float elements of the optional block_feat buffer */
+    int64_t workspace_bytes;  /* scratch needed by hog_integral and hog_scan_windows */
+    int32_t feature_dim;      /* window feature length D */
+    int64_t total_pixels;     /* sum of level areas */
+    int64_t total_windows;    /* sum of window counts */
+} hog_plan_sizes;
+
+/* Validate desc, plan the levels, tiles and buffer layout, and upload the
+ * plan's tables to the current device (library-owned; synchronous). */
+hog_status hog_plan_create(const hog_plan_desc *desc, hog_plan **out);
+void hog_plan_destroy(hog_plan *plan);
+hog_status hog_plan_get_sizes(const hog_plan *plan, hog_plan_sizes *out);
+hog_status hog_plan_get_level(const hog_plan *plan, int level, hog_level_info *out);
+
+/* ------------------------------------------------------------------------ */
+/* The hot path.                                                            */
+/* ------------------------------------------------------------------------ */
+
+/* Eq. 1 + Sec. 2. img: device, uint8, row-major, channels interleaved,
+ * img_pitch bytes per row (>= width*channels). For every level, writes the
+ * bin map into bins (device, plan layout): for interior pixels, per channel
+ * dx = P[x+1][y] - P[x-1][y], dy = P[x][y+1] - P[x][y-1] (on the level's
+ * nearest-neighbour image); the channel with the largest dx^2 + dy^2 wins
+ * (ties to the lowest index); the bin is lut[(dy+255)*511 + dx+255]. Border
+ * pixels and zero gradients get 255. lut must have the plan's n_bins. */
+hog_status hog_bin_map(const hog_plan *plan, const hog_lut *lut, const uint8_t *img,
+                       int64_t img_pitch, uint8_t *bins, void *stream);
+
+/* Eq. 4 + Eq. 5. bins: device, plan layout (as written by hog_bin_map).
+ * Writes, for every level and bin n, the integral image
+ *   ii[ii_offset + n*ii_plane_stride + (y+1)*ii_pitch + (x+1)]
+ *       = #{ (x', y') : x' <= x, y' <= y, bin(x', y') = n }
+ * with a zero guard row 0 and guard column 0, i.e. columns 0..width and
+ * rows 0..height of each plane (uint32, exact). Padding elements between
+ * width+1 and ii_pitch are not written. workspace: device, at least
+ * workspace_bytes, contents on entry ignored. */
+hog_status hog_integral(const hog_plan *plan, const uint8_t *bins, uint32_t *ii,
+                        void *workspace, void *stream);
+
+/* Eq. 6, Sec. 3.3, Sec. 4. ii: device, as written by hog_integral.
+ * For every level: the histogram of cell (cx, cy), the cell x cell square
+ * at (cx*cell, cy*cell), is ii(4) + ii(1) - ii(2) - ii(3) on each bin's
+ * plane, computed once per cell and cached. Window (wx, wy) covers cells
+ * [wx, wx+win_cells_x) x [wy, wy+win_cells_y). Its feature f is, for
+ * HOG_NORM_RAW, the cell histograms in row-major cell order,
+ * f[(cy*win_cells_x + cx)*n_bins + n]; for HOG_NORM_L2, the 2x2-cell blocks
+ * stepping one cell, each normalised as v / sqrt(|v|^2 + eps^2) in FP32,
+ * f[((by*(win_cells_x-1) + bx)*4 + (v*2 + u))*n_bins + n]. Scores:
+ *   scores[score_offset + (wy*windows_x + wx)*K + k] = bias[k] + sum_d tmpl[k*D + d] f[d]
+ * in FP32 (blocked sums: each block's, or each cell's, partial dot product
+ * is rounded once and the partials are added in FP64).
+ * tmpl: device, float[K][D]; bias: device, float[K].
+ * cell_hist (nullable): device, uint32, receives every cell histogram.
+ * block_feat (nullable, L2 only): device, float, receives every normalised
+ * block. workspace: as for hog_integral. */
+hog_status hog_scan_windows(const hog_plan *plan, const uint32_t *ii, const float *tmpl,
+                            const float *bias, float *scores, uint32_t *cell_hist,
+                            float *block_feat, void *workspace, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Kernel timing. When enabled, every kernel launch of the calls above is   */
+/* bracketed by a pair of HIP events recorded on the launch stream; totals  */
+/* accumulate per kernel name until hog_timing_reset. Not thread-safe.      */
+/* Names: "bin_map", "integral_reduce", "integral_scan", "integral_emit",   */
+/* "cells", "score", "block_features".                                       */
+/* ------------------------------------------------------------------------ */
+hog_status hog_timing_enable(int on);
+hog_status hog_timing_reset(void);
+/* Waits for the recorded events, then reports launches and total ms. */
+hog_status hog_timing_get(const char *kernel, int64_t *launches, double *total_ms);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HOG_H_ */

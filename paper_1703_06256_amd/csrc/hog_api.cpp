@@ -1,0 +1,592 @@
+// Host half of libhog: argument checking, the lookup table (Sec. 2), level
+// planning and buffer layout, launches, errors and kernel timing. Every
+// public entry point is declared in include/hog.h.
+#include "hog.h"
+#include "hog_internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <vector>
+
+using hogk::Level;
+using hogk::PlanDev;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+hog_status fail(hog_status st, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return st;
+}
+
+hog_status device_fail(hipError_t e, const char *what)
+{
+    return fail(HOG_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
+
+// ---------------------------------------------------------------------------
+// Kernel timing: HIP event pairs around each launch, on the launch stream.
+// ---------------------------------------------------------------------------
+struct PendingTiming {
+    std::string name;
+    hipEvent_t start, stop;
+};
+bool g_timing_on = false;
+std::vector<PendingTiming> g_pending;
+std::vector<hipEvent_t> g_event_pool;
+std::map<std::string, std::pair<int64_t, double>> g_timing_totals;
+
+hipError_t take_event(hipEvent_t *ev)
+{
+    if (!g_event_pool.empty()) {
+        *ev = g_event_pool.back();
+        g_event_pool.pop_back();
+        return hipSuccess;
+    }
+    return hipEventCreate(ev);
+}
+
+template <class F>
+hipError_t timed_launch(const char *name, hipStream_t stream, F &&launch)
+{
+    if (!g_timing_on) return launch();
+    hipEvent_t a = nullptr, b = nullptr;
+    hipError_t e = take_event(&a);
+    if (e == hipSuccess) e = take_event(&b);
+    if (e != hipSuccess) return e;
+    if ((e = hipEventRecord(a, stream)) != hipSuccess) return e;
+    const hipError_t le = launch();
+    if ((e = hipEventRecord(b, stream)) != hipSuccess) return e;
+    g_pending.push_back({name, a, b});
+    return le;
+}
+
+hipError_t drain_timing()
+{
+    hipError_t first_err = hipSuccess;
+    for (auto &p : g_pending) {
+        float ms = 0.f;
+        hipError_t e = hipEventSynchronize(p.stop);
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, p.start, p.stop);
+        if (e != hipSuccess && first_err == hipSuccess) first_err = e;
+        auto &tot = g_timing_totals[p.name];
+        tot.first += 1;
+        tot.second += ms;
+        g_event_pool.push_back(p.start);
+        g_event_pool.push_back(p.stop);
+    }
+    g_pending.clear();
+    return first_err;
+}
+
+// ---------------------------------------------------------------------------
+// Sec. 2: the bin of one integer gradient. Angle in [0, 2 pi) from +x towards
+// +y, n half-open sectors of 2 pi / n. Integer gradients lie exactly on a
+// multiple of pi/4 only along the axes and diagonals (Niven's theorem rules
+// out any other rational slope at a rational multiple of pi); those are the
+// only places a sector edge can be hit exactly, and there the sector is
+// floor(m n / 8) for the direction m pi/4, computed in integers. Elsewhere
+// the FP64 angle is far (> 1e-9 of a sector) from every edge.
+// ---------------------------------------------------------------------------
+uint8_t lut_entry(int dx, int dy, int n)
+{
+    if (dx == 0 && dy == 0) return HOG_NO_BIN;
+    if (dx == 0 || dy == 0 || dx == dy || dx == -dy) {
+        int m;
+        if (dy == 0) m = dx > 0 ? 0 : 4;
+        else if (dx == 0) m = dy > 0 ? 2 : 6;
+        else if (dx > 0) m = dy > 0 ? 1 : 7;
+        else m = dy > 0 ? 3 : 5;
+        return (uint8_t)((m * n) / 8);
+    }
+    const double two_pi = 6.283185307179586476925286766559;
+    double a = std::atan2((double)dy, (double)dx);
+    if (a < 0.0) a += two_pi;
+    int k = (int)std::floor(a * (double)n / two_pi);
+    if (k >= n) k = n - 1;
+    return (uint8_t)k;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+struct hog_lut {
+    int n_bins;
+    std::vector<uint8_t> host;
+    uint8_t *dev;
+};
+
+struct hog_plan {
+    hog_plan_desc desc;
+    std::vector<Level> levels;
+    std::vector<hog_level_info> info;
+    hog_plan_sizes sizes;
+    PlanDev dev;
+    void *dev_mem;
+};
+
+extern "C" {
+
+const char *hog_last_error(void) { return g_last_error.c_str(); }
+
+hog_status hog_lut_fill_host(int n_bins, uint8_t *table)
+{
+    if (n_bins < 1 || n_bins > HOG_MAX_BINS)
+        return fail(HOG_E_INVALID, "n_bins must be in [1, %d], got %d", HOG_MAX_BINS, n_bins);
+    if (!table) return fail(HOG_E_INVALID, "table is NULL");
+    for (int dy = -255; dy <= 255; ++dy)
+        for (int dx = -255; dx <= 255; ++dx)
+            table[(dy + 255) * HOG_LUT_SIDE + (dx + 255)] = lut_entry(dx, dy, n_bins);
+    return HOG_OK;
+}
+
+hog_status hog_lut_build(int n_bins, hog_lut **out)
+{
+    if (!out) return fail(HOG_E_INVALID, "out is NULL");
+    *out = nullptr;
+    hog_lut *lut = new (std::nothrow) hog_lut;
+    if (!lut) return fail(HOG_E_NOMEM, "host allocation failed");
+    lut->n_bins = n_bins;
+    lut->dev = nullptr;
+    try {
+        lut->host.resize((size_t)HOG_LUT_SIDE * HOG_LUT_SIDE);
+    } catch (...) {
+        delete lut;
+        return fail(HOG_E_NOMEM, "host allocation failed");
+    }
+    hog_status st = hog_lut_fill_host(n_bins, lut->host.data());
+    if (st != HOG_OK) {
+        delete lut;
+        return st;
+    }
+    hipError_t e = hipMalloc((void **)&lut->dev, lut->host.size());
+    if (e != hipSuccess) {
+        delete lut;
+        return device_fail(e, "hipMalloc(lut)");
+    }
+    e = hipMemcpy(lut->dev, lut->host.data(), lut->host.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(lut->dev);
+        delete lut;
+        return device_fail(e, "hipMemcpy(lut)");
+    }
+    *out = lut;
+    return HOG_OK;
+}
+
+void hog_lut_free(hog_lut *lut)
+{
+    if (!lut) return;
+    if (lut->dev) (void)hipFree(lut->dev);
+    delete lut;
+}
+
+int hog_lut_bins(const hog_lut *lut) { return lut ? lut->n_bins : 0; }
+
+const uint8_t *hog_lut_host(const hog_lut *lut) { return lut ? lut->host.data() : nullptr; }
+
+// ---------------------------------------------------------------------------
+// Planning.
+// ---------------------------------------------------------------------------
+static hog_status check_desc(const hog_plan_desc *d)
+{
+    if (!d) return fail(HOG_E_INVALID, "desc is NULL");
+    if (d->width < 1 || d->height < 1 || d->width > 32767 || d->height > 32767)
+        return fail(HOG_E_INVALID, "image size %dx%d outside [1, 32767]", d->width, d->height);
+    if (d->channels != 1 && d->channels != 3)
+        return fail(HOG_E_INVALID, "channels must be 1 or 3, got %d", d->channels);
+    if (d->n_bins < 1 || d->n_bins > HOG_MAX_BINS)
+        return fail(HOG_E_INVALID, "n_bins must be in [1, %d], got %d", HOG_MAX_BINS, d->n_bins);
+    if (d->max_levels < 0 || d->max_levels > 256)
+        return fail(HOG_E_INVALID, "max_levels must be in [0, 256], got %d", d->max_levels);
+    if (d->max_levels != 1 && !(d->scale > 1.0 && d->scale < 1e6))
+        return fail(HOG_E_INVALID, "a pyramid needs scale > 1, got %g", d->scale);
+    if (d->n_templates < 1 || d->n_templates > 4096)
+        return fail(HOG_E_INVALID, "n_templates must be in [1, 4096], got %d", d->n_templates);
+    const hog_scan_params &s = d->scan;
+    if (s.cell < 1 || s.cell > 32) return fail(HOG_E_INVALID, "cell must be in [1, 32], got %d", s.cell);
+    if (s.win_cells_x < 1 || s.win_cells_x > 64 || s.win_cells_y < 1 || s.win_cells_y > 64)
+        return fail(HOG_E_INVALID, "window must be 1..64 cells per side");
+    if (s.norm != HOG_NORM_RAW && s.norm != HOG_NORM_L2)
+        return fail(HOG_E_INVALID, "norm must be HOG_NORM_RAW or HOG_NORM_L2");
+    if (s.norm == HOG_NORM_L2) {
+        if (s.block != 2) return fail(HOG_E_INVALID, "L2 blocks must be 2x2 cells");
+        if (s.win_cells_x < 2 || s.win_cells_y < 2)
+            return fail(HOG_E_INVALID, "an L2 window needs at least 2x2 cells");
+        if (!(s.eps >= 0.f) || !std::isfinite(s.eps)) return fail(HOG_E_INVALID, "eps must be finite and >= 0");
+    }
+    return HOG_OK;
+}
+
+extern "C" hog_status hog_plan_create(const hog_plan_desc *desc, hog_plan **out)
+{
+    if (!out) return fail(HOG_E_INVALID, "out is NULL");
+    *out = nullptr;
+    hog_status st = check_desc(desc);
+    if (st != HOG_OK) return st;
+    const hog_plan_desc d = *desc;
+    const hog_scan_params &sp = d.scan;
+    const int nb = d.n_bins, K = d.n_templates;
+    const int win_w = sp.cell * sp.win_cells_x, win_h = sp.cell * sp.win_cells_y;
+    const int dim = sp.norm == HOG_NORM_RAW
+                        ? sp.win_cells_x * sp.win_cells_y * nb
+                        : (sp.win_cells_x - 1) * (sp.win_cells_y - 1) * 4 * nb;
+
+    // Scorer tile: windows per workgroup (<= 256 threads) and LDS staging.
+    const int nbp = (int)round_up(nb, 4);
+    int best_tw = 0, best_th = 0;
+    int64_t best_lds = 0;
+    double best_cost = 1e30;
+    for (int tw = 1; tw <= 64; tw *= 2)
+        for (int th = 1; tw * th <= 256; th *= 2) {
+            const int64_t CW = tw + sp.win_cells_x - 1, CH = th + sp.win_cells_y - 1;
+            const int64_t lds = CH * CW * nbp * 4 + (CH - 1) * (CW - 1) * 4;
+            if (lds > 65536) continue;
+            const double cost = (double)(CH * CW) / (tw * th) + (tw * th < 64 ? 4.0 : 0.0);
+            if (cost < best_cost - 1e-9 || (std::fabs(cost - best_cost) <= 1e-9 && tw * th > best_tw * best_th)) {
+                best_cost = cost;
+                best_tw = tw;
+                best_th = th;
+                best_lds = lds;
+            }
+        }
+    if (best_tw == 0)
+        return fail(HOG_E_INVALID, "window of %dx%d cells with %d bins does not fit the scorer's LDS",
+                    sp.win_cells_x, sp.win_cells_y, nb);
+
+    hog_plan *p = new (std::nothrow) hog_plan;
+    if (!p) return fail(HOG_E_NOMEM, "host allocation failed");
+    p->desc = d;
+    p->dev_mem = nullptr;
+    std::vector<int32_t> mapx, mapy;
+
+    // Levels (nearest-neighbour pyramid): s_0 = 1, s_l = s_{l-1} * scale.
+    double s = 1.0;
+    int64_t bins_off = 0, ii_off = 0, score_off = 0, cell_off = 0, block_off = 0, ws_off = 0;
+    int64_t tot_px = 0, tot_win = 0;
+    const int n_chunks = (nb + hogk::kMaxBinChunk - 1) / hogk::kMaxBinChunk;
+    const int chunk = (nb + n_chunks - 1) / n_chunks;
+    for (int l = 0;; ++l) {
+        if (d.max_levels > 0 && l >= d.max_levels) break;
+        if (l >= 256) break;
+        const int lw = (int)std::floor((double)d.width / s);
+        const int lh = (int)std::floor((double)d.height / s);
+        if (l > 0 && (lw < win_w || lh < win_h || lw < 1 || lh < 1)) break;
+        Level v;
+        std::memset(&v, 0, sizeof v);
+        hog_level_info info;
+        std::memset(&info, 0, sizeof info);
+        v.w = lw;
+        v.h = lh;
+        v.cells_x = lw / sp.cell;
+        v.cells_y = lh / sp.cell;
+        v.win_x = v.cells_x - sp.win_cells_x + 1;
+        v.win_y = v.cells_y - sp.win_cells_y + 1;
+        if (v.win_x <= 0 || v.win_y <= 0) v.win_x = v.win_y = 0;
+        v.tiles_x = (int)((lw + 1 + hogk::kIntTileCols - 1) / hogk::kIntTileCols);
+        v.tiles_y = (int)((lh + 1 + hogk::kIntTileRows - 1) / hogk::kIntTileRows);
+        v.bm_gx = (lw + hogk::kBinCols - 1) / hogk::kBinCols;
+        v.bm_gy = (lh + hogk::kBinRows - 1) / hogk::kBinRows;
+        v.st_x = v.win_x ? (v.win_x + best_tw - 1) / best_tw : 0;
+        v.st_y = v.win_y ? (v.win_y + best_th - 1) / best_th : 0;
+        v.mapx_off = (int64_t)mapx.size();
+        v.mapy_off = (int64_t)mapy.size();
+        for (int x = 0; x < lw; ++x) {
+            int64_t sx = (int64_t)std::floor((double)x * s);
+            mapx.push_back((int32_t)std::min<int64_t>(sx, d.width - 1));
+        }
+        for (int y = 0; y < lh; ++y) {
+            int64_t sy = (int64_t)std::floor((double)y * s);
+            mapy.push_back((int32_t)std::min<int64_t>(sy, d.height - 1));
+        }
+        v.bins_pitch = round_up(lw, 64);
+        v.bins_off = bins_off;
+        bins_off = round_up(bins_off + v.bins_pitch * lh, 256);
+        v.ii_pitch = round_up(lw + 1, 64);
+        v.ii_plane = round_up(v.ii_pitch * (lh + 1), 64);
+        v.ii_off = ii_off;
+        ii_off += v.ii_plane * nb;
+        v.score_off = score_off;
+        score_off += (int64_t)v.win_x * v.win_y * K;
+        v.cell_off = cell_off;
+        cell_off += (int64_t)v.cells_x * v.cells_y * nb;
+        v.block_off = block_off;
+        if (sp.norm == HOG_NORM_L2 && v.cells_x >= 2 && v.cells_y >= 2)
+            block_off += (int64_t)(v.cells_x - 1) * (v.cells_y - 1) * 4 * nb;
+        // workspace
+        v.ws_rowtot = ws_off;
+        ws_off = round_up(ws_off + (int64_t)v.tiles_x * (lh + 1) * nb, 256);
+        v.ws_coltot = ws_off;
+        ws_off = round_up(ws_off + (int64_t)v.tiles_y * nb * (lw + 1), 256);
+        v.ws_e = ws_off;
+        ws_off = round_up(ws_off + (int64_t)v.tiles_x * (lh + 1) * nb * 4, 256);
+        v.ws_t = ws_off;
+        ws_off = round_up(ws_off + (int64_t)v.tiles_y * nb * (lw + 1) * 4, 256);
+        v.ws_cache = ws_off;
+        ws_off = round_up(ws_off + (int64_t)nb * v.cells_y * v.cells_x * 2, 256);
+
+        info.width = lw;
+        info.height = lh;
+        info.scale = s;
+        info.bins_offset = v.bins_off;
+        info.bins_pitch = v.bins_pitch;
+        info.ii_offset = v.ii_off;
+        info.ii_pitch = v.ii_pitch;
+        info.ii_plane_stride = v.ii_plane;
+        info.cells_x = v.cells_x;
+        info.cells_y = v.cells_y;
+        info.windows_x = v.win_x;
+        info.windows_y = v.win_y;
+        info.score_offset = v.score_off;
+        info.cell_offset = v.cell_off;
+        info.block_offset = v.block_off;
+        p->levels.push_back(v);
+        p->info.push_back(info);
+        tot_px += (int64_t)lw * lh;
+        tot_win += (int64_t)v.win_x * v.win_y;
+        s = s * d.scale;
+        if (d.max_levels == 1) break;
+    }
+    const int L = (int)p->levels.size();
+
+    // Per-kernel prefix tables.
+    std::vector<int32_t> first((size_t)hogk::KB_COUNT * (L + 1), 0);
+    int64_t totals[hogk::KB_COUNT] = {0};
+    for (int l = 0; l < L; ++l) {
+        const Level &v = p->levels[l];
+        int64_t items[hogk::KB_COUNT];
+        items[hogk::KB_BINMAP] = (int64_t)v.bm_gx * v.bm_gy;
+        items[hogk::KB_ITILE] = (int64_t)v.tiles_x * v.tiles_y;
+        items[hogk::KB_TSCAN] = (int64_t)v.tiles_y * nb;
+        items[hogk::KB_ESCAN] = (int64_t)(v.h + 1) * nb;
+        items[hogk::KB_CELL] = (int64_t)v.cells_x * v.cells_y;
+        items[hogk::KB_STILE] = (int64_t)v.st_x * v.st_y;
+        items[hogk::KB_BLOCK] = (sp.norm == HOG_NORM_L2 && v.cells_x >= 2 && v.cells_y >= 2)
+                                    ? (int64_t)(v.cells_x - 1) * (v.cells_y - 1)
+                                    : 0;
+        for (int k = 0; k < hogk::KB_COUNT; ++k) {
+            first[(size_t)k * (L + 1) + l] = (int32_t)totals[k];
+            totals[k] += items[k];
+        }
+    }
+    for (int k = 0; k < hogk::KB_COUNT; ++k) {
+        if (totals[k] >= ((int64_t)1 << 30)) {
+            delete p;
+            return fail(HOG_E_INVALID, "image too large for one plan (kernel %d has %lld items)", k,
+                        (long long)totals[k]);
+        }
+        first[(size_t)k * (L + 1) + L] = (int32_t)totals[k];
+    }
+
+    // Device tables: levels | first | mapx | mapy.
+    const size_t lv_bytes = sizeof(Level) * L;
+    const size_t first_bytes = sizeof(int32_t) * first.size();
+    const size_t mx_bytes = sizeof(int32_t) * mapx.size();
+    const size_t my_bytes = sizeof(int32_t) * mapy.size();
+    const size_t o_first = round_up(lv_bytes, 256);
+    const size_t o_mx = o_first + round_up(first_bytes, 256);
+    const size_t o_my = o_mx + round_up(mx_bytes, 256);
+    const size_t total_bytes = o_my + round_up(my_bytes, 256) + 256;
+    std::vector<uint8_t> blob(total_bytes, 0);
+    std::memcpy(blob.data(), p->levels.data(), lv_bytes);
+    std::memcpy(blob.data() + o_first, first.data(), first_bytes);
+    std::memcpy(blob.data() + o_mx, mapx.data(), mx_bytes);
+    std::memcpy(blob.data() + o_my, mapy.data(), my_bytes);
+    hipError_t e = hipMalloc(&p->dev_mem, total_bytes);
+    if (e != hipSuccess) {
+        delete p;
+        return device_fail(e, "hipMalloc(plan tables)");
+    }
+    e = hipMemcpy(p->dev_mem, blob.data(), total_bytes, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(p->dev_mem);
+        delete p;
+        return device_fail(e, "hipMemcpy(plan tables)");
+    }
+    uint8_t *base = (uint8_t *)p->dev_mem;
+    PlanDev &pd = p->dev;
+    std::memset(&pd, 0, sizeof pd);
+    pd.levels = (const Level *)base;
+    pd.first = (const int32_t *)(base + o_first);
+    pd.mapx = (const int32_t *)(base + o_mx);
+    pd.mapy = (const int32_t *)(base + o_my);
+    pd.n_levels = L;
+    pd.n_bins = nb;
+    pd.channels = d.channels;
+    pd.src_w = d.width;
+    pd.src_h = d.height;
+    pd.n_templates = K;
+    pd.cell = sp.cell;
+    pd.win_cells_x = sp.win_cells_x;
+    pd.win_cells_y = sp.win_cells_y;
+    pd.block = sp.block;
+    pd.norm = sp.norm;
+    pd.eps = sp.eps;
+    pd.feat_dim = dim;
+    pd.st_tw = best_tw;
+    pd.st_th = best_th;
+    pd.st_lds_bytes = (int32_t)best_lds;
+    pd.cell_stride = nbp;
+    pd.bin_chunk = chunk;
+    pd.n_chunks = n_chunks;
+    for (int k = 0; k < hogk::KB_COUNT; ++k) pd.total[k] = totals[k];
+
+    hog_plan_sizes &z = p->sizes;
+    std::memset(&z, 0, sizeof z);
+    z.n_levels = L;
+    z.bins_bytes = bins_off;
+    z.ii_elems = ii_off;
+    z.score_elems = score_off;
+    z.cell_elems = cell_off;
+    z.block_elems = block_off;
+    z.workspace_bytes = ws_off;
+    z.feature_dim = dim;
+    z.total_pixels = tot_px;
+    z.total_windows = tot_win;
+    *out = p;
+    return HOG_OK;
+}
+
+extern "C" void hog_plan_destroy(hog_plan *plan)
+{
+    if (!plan) return;
+    if (plan->dev_mem) (void)hipFree(plan->dev_mem);
+    delete plan;
+}
+
+extern "C" hog_status hog_plan_get_sizes(const hog_plan *plan, hog_plan_sizes *out)
+{
+    if (!plan || !out) return fail(HOG_E_INVALID, "plan or out is NULL");
+    *out = plan->sizes;
+    return HOG_OK;
+}
+
+extern "C" hog_status hog_plan_get_level(const hog_plan *plan, int level, hog_level_info *out)
+{
+    if (!plan || !out) return fail(HOG_E_INVALID, "plan or out is NULL");
+    if (level < 0 || level >= (int)plan->info.size())
+        return fail(HOG_E_INVALID, "level %d outside [0, %d)", level, (int)plan->info.size());
+    *out = plan->info[level];
+    return HOG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// The hot path.
+// ---------------------------------------------------------------------------
+extern "C" hog_status hog_bin_map(const hog_plan *plan, const hog_lut *lut, const uint8_t *img,
+                                  int64_t img_pitch, uint8_t *bins, void *stream)
+{
+    if (!plan || !lut || !img || !bins) return fail(HOG_E_INVALID, "NULL argument");
+    if (lut->n_bins != plan->desc.n_bins)
+        return fail(HOG_E_INVALID, "lut has %d bins, plan has %d", lut->n_bins, plan->desc.n_bins);
+    if (img_pitch < (int64_t)plan->desc.width * plan->desc.channels)
+        return fail(HOG_E_INVALID, "img_pitch %lld < width*channels", (long long)img_pitch);
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = timed_launch("bin_map", s, [&] {
+        return hogk::launch_bin_map(plan->dev, lut->dev, img, img_pitch, bins, s);
+    });
+    if (e != hipSuccess) return device_fail(e, "bin_map launch");
+    return HOG_OK;
+}
+
+extern "C" hog_status hog_integral(const hog_plan *plan, const uint8_t *bins, uint32_t *ii,
+                                   void *workspace, void *stream)
+{
+    if (!plan || !bins || !ii || !workspace) return fail(HOG_E_INVALID, "NULL argument");
+    hipStream_t s = (hipStream_t)stream;
+    uint8_t *ws = (uint8_t *)workspace;
+    hipError_t e = timed_launch("integral_reduce", s, [&] {
+        return hogk::launch_int_reduce(plan->dev, bins, ws, s);
+    });
+    if (e != hipSuccess) return device_fail(e, "integral_reduce launch");
+    e = timed_launch("integral_scan", s, [&] {
+        hipError_t e1 = hogk::launch_int_scan_rows(plan->dev, ws, s);
+        if (e1 != hipSuccess) return e1;
+        return hogk::launch_int_scan_cols(plan->dev, ws, s);
+    });
+    if (e != hipSuccess) return device_fail(e, "integral_scan launch");
+    e = timed_launch("integral_emit", s, [&] {
+        return hogk::launch_int_emit(plan->dev, bins, ws, ii, s);
+    });
+    if (e != hipSuccess) return device_fail(e, "integral_emit launch");
+    return HOG_OK;
+}
+
+extern "C" hog_status hog_scan_windows(const hog_plan *plan, const uint32_t *ii, const float *tmpl,
+                                       const float *bias, float *scores, uint32_t *cell_hist,
+                                       float *block_feat, void *workspace, void *stream)
+{
+    if (!plan || !ii || !workspace) return fail(HOG_E_INVALID, "NULL argument");
+    const bool need_scores = plan->sizes.score_elems > 0;
+    if (need_scores && (!tmpl || !bias || !scores))
+        return fail(HOG_E_INVALID, "tmpl, bias and scores are required when the plan has windows");
+    if (block_feat && plan->desc.scan.norm != HOG_NORM_L2)
+        return fail(HOG_E_INVALID, "block_feat is only defined for HOG_NORM_L2");
+    hipStream_t s = (hipStream_t)stream;
+    uint8_t *ws = (uint8_t *)workspace;
+    hipError_t e = timed_launch("cells", s, [&] {
+        return hogk::launch_cells(plan->dev, ii, ws, cell_hist, s);
+    });
+    if (e != hipSuccess) return device_fail(e, "cells launch");
+    if (block_feat) {
+        e = timed_launch("block_features", s, [&] {
+            return hogk::launch_block_features(plan->dev, ws, block_feat, s);
+        });
+        if (e != hipSuccess) return device_fail(e, "block_features launch");
+    }
+    if (need_scores) {
+        e = timed_launch("score", s, [&] {
+            return hogk::launch_score(plan->dev, ws, tmpl, bias, scores, s);
+        });
+        if (e != hipSuccess) return device_fail(e, "score launch");
+    }
+    return HOG_OK;
+}
+
+// ---------------------------------------------------------------------------
+extern "C" hog_status hog_timing_enable(int on)
+{
+    g_timing_on = on != 0;
+    return HOG_OK;
+}
+
+extern "C" hog_status hog_timing_reset(void)
+{
+    hipError_t e = drain_timing();
+    g_timing_totals.clear();
+    if (e != hipSuccess) return device_fail(e, "timing events");
+    return HOG_OK;
+}
+
+extern "C" hog_status hog_timing_get(const char *kernel, int64_t *launches, double *total_ms)
+{
+    if (!kernel || !launches || !total_ms) return fail(HOG_E_INVALID, "NULL argument");
+    hipError_t e = drain_timing();
+    if (e != hipSuccess) return device_fail(e, "timing events");
+    auto it = g_timing_totals.find(kernel);
+    if (it == g_timing_totals.end()) {
+        *launches = 0;
+        *total_ms = 0.0;
+    } else {
+        *launches = it->second.first;
+        *total_ms = it->second.second;
+    }
+    return HOG_OK;
+}
+
+}  // extern "C"

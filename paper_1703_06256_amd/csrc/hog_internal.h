@@ -1,0 +1,95 @@
+// Internal interface between the host half of libhog (hog_api.cpp) and the
+// gfx950 kernels (hog_kernels.hip). Not installed; not part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hogk {
+
+constexpr int kNoBin = 255;
+
+// Bin map: a wave owns 64 consecutive level columns (62 outputs plus one
+// halo column each side, so left/right neighbours come from adjacent lanes)
+// and walks kBinRows rows, rolling the up/centre/down samples in registers.
+constexpr int kBinCols = 62;
+constexpr int kBinRows = 16;
+
+// Integral images: a tile is 64 padded columns (one per lane) by
+// kIntTileRows padded rows, one wave per tile and per chunk of bins.
+constexpr int kIntTileCols = 64;
+constexpr int kIntTileRows = 64;
+constexpr int kMaxBinChunk = 9;
+
+// Kernel indices into the per-kernel prefix tables.
+enum {
+    KB_BINMAP = 0,  // waves
+    KB_ITILE,       // integral tiles
+    KB_TSCAN,       // workgroups of the column-carry scan: tiles_y * n_bins
+    KB_ESCAN,       // threads of the row-carry scan: (h + 1) * n_bins
+    KB_CELL,        // threads of the cell kernel: cells
+    KB_STILE,       // workgroups of the scorer: window tiles
+    KB_BLOCK,       // threads of the block-feature kernel: blocks
+    KB_COUNT
+};
+
+// One pyramid level as the kernels see it. Offsets are in elements of the
+// buffer they index (bytes for uint8 buffers).
+struct Level {
+    int32_t w, h;
+    int32_t cells_x, cells_y;
+    int32_t win_x, win_y;
+    int32_t tiles_x, tiles_y;  // integral tiles over the padded (w+1) x (h+1) grid
+    int32_t bm_gx, bm_gy;      // bin-map waves
+    int32_t st_x, st_y;        // scorer tiles
+    int64_t mapx_off, mapy_off;
+    int64_t bins_off, bins_pitch;
+    int64_t ii_off, ii_pitch, ii_plane;
+    int64_t score_off, cell_off, block_off;
+    // workspace (bytes from the workspace base)
+    int64_t ws_rowtot;  // uint8  [tiles_x][h+1][nb]   per-tile row counts
+    int64_t ws_coltot;  // uint8  [tiles_y][nb][w+1]   per-tile column counts
+    int64_t ws_e;       // uint32 [tiles_x][h+1][nb]   row carry from the tiles on the left
+    int64_t ws_t;       // uint32 [tiles_y][nb][w+1]   plane row just above each tile row
+    int64_t ws_cache;   // uint16 [nb][cells_y][cells_x] cell histogram cache
+};
+
+struct PlanDev {
+    const Level *levels;   // device [n_levels]
+    const int32_t *first;  // device [KB_COUNT][n_levels + 1]
+    const int32_t *mapx;   // device
+    const int32_t *mapy;   // device
+    int32_t n_levels;
+    int32_t n_bins;
+    int32_t channels;
+    int32_t src_w, src_h;
+    int32_t n_templates;
+    int32_t cell, win_cells_x, win_cells_y, block, norm;
+    float eps;
+    int32_t feat_dim;
+    int32_t st_tw, st_th;      // scorer tile (windows)
+    int32_t st_lds_bytes;      // scorer dynamic LDS
+    int32_t cell_stride;       // floats per staged cell in the scorer's LDS
+    int32_t bin_chunk;         // bins per integral wave
+    int32_t n_chunks;
+    int64_t total[KB_COUNT];   // totals (= first[k][n_levels])
+};
+
+// Launchers (hog_kernels.hip). Each enqueues one kernel on `stream` and
+// returns the launch status.
+hipError_t launch_bin_map(const PlanDev &p, const uint8_t *lut, const uint8_t *img,
+                          int64_t img_pitch, uint8_t *bins, hipStream_t stream);
+hipError_t launch_int_reduce(const PlanDev &p, const uint8_t *bins, uint8_t *ws,
+                             hipStream_t stream);
+hipError_t launch_int_scan_rows(const PlanDev &p, uint8_t *ws, hipStream_t stream);
+hipError_t launch_int_scan_cols(const PlanDev &p, uint8_t *ws, hipStream_t stream);
+hipError_t launch_int_emit(const PlanDev &p, const uint8_t *bins, const uint8_t *ws,
+                           uint32_t *ii, hipStream_t stream);
+hipError_t launch_cells(const PlanDev &p, const uint32_t *ii, uint8_t *ws, uint32_t *cell_hist,
+                        hipStream_t stream);
+hipError_t launch_score(const PlanDev &p, const uint8_t *ws, const float *tmpl, const float *bias,
+                        float *scores, hipStream_t stream);
+hipError_t launch_block_features(const PlanDev &p, const uint8_t *ws, float *block_feat,
+                                 hipStream_t stream);
+
+}  // namespace hogk

@@ -1,0 +1,326 @@
+"""Python binding of libhog (include/hog.h): argument marshalling only.
+
+Every function here forwards to the C ABI function of the same name; all
+arithmetic happens in the library's HIP kernels. PyTorch supplies device
+memory (tensors, passed by data_ptr) and streams (the current stream unless
+one is given). If libhog.so has not been built, the first call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libhog.so")
+
+HOG_OK, HOG_E_INVALID, HOG_E_NOMEM, HOG_E_DEVICE, HOG_E_BUSY, HOG_E_NOT_READY = range(6)
+HOG_NO_BIN = 255
+HOG_NORM_RAW, HOG_NORM_L2 = 0, 1
+LUT_SIDE = 511
+
+# Every symbol include/hog.h declares.
+EXPORTS = (
+    "hog_last_error", "hog_lut_fill_host", "hog_lut_build", "hog_lut_free", "hog_lut_bins",
+    "hog_lut_host", "hog_plan_create", "hog_plan_destroy", "hog_plan_get_sizes",
+    "hog_plan_get_level", "hog_bin_map", "hog_integral", "hog_scan_windows",
+    "hog_timing_enable", "hog_timing_reset", "hog_timing_get",
+)
+
+
+class HogError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"libhog status {status}: {msg}")
+        self.status = status
+
+
+class ScanParams(ctypes.Structure):
+    _fields_ = [("cell", ctypes.c_int32), ("win_cells_x", ctypes.c_int32),
+                ("win_cells_y", ctypes.c_int32), ("block", ctypes.c_int32),
+                ("norm", ctypes.c_int32), ("eps", ctypes.c_float)]
+
+
+class PlanDesc(ctypes.Structure):
+    _fields_ = [("width", ctypes.c_int32), ("height", ctypes.c_int32),
+                ("channels", ctypes.c_int32), ("n_bins", ctypes.c_int32),
+                ("max_levels", ctypes.c_int32), ("scale", ctypes.c_double),
+                ("n_templates", ctypes.c_int32), ("scan", ScanParams)]
+
+
+class LevelInfo(ctypes.Structure):
+    _fields_ = [("width", ctypes.c_int32), ("height", ctypes.c_int32),
+                ("scale", ctypes.c_double), ("bins_offset", ctypes.c_int64),
+                ("bins_pitch", ctypes.c_int64), ("ii_offset", ctypes.c_int64),
+                ("ii_pitch", ctypes.c_int64), ("ii_plane_stride", ctypes.c_int64),
+                ("cells_x", ctypes.c_int32), ("cells_y", ctypes.c_int32),
+                ("windows_x", ctypes.c_int32), ("windows_y", ctypes.c_int32),
+                ("score_offset", ctypes.c_int64), ("cell_offset", ctypes.c_int64),
+                ("block_offset", ctypes.c_int64)]
+
+
+class PlanSizes(ctypes.Structure):
+    _fields_ = [("n_levels", ctypes.c_int32), ("bins_bytes", ctypes.c_int64),
+                ("ii_elems", ctypes.c_int64), ("score_elems", ctypes.c_int64),
+                ("cell_elems", ctypes.c_int64), ("block_elems", ctypes.c_int64),
+                ("workspace_bytes", ctypes.c_int64), ("feature_dim", ctypes.c_int32),
+                ("total_pixels", ctypes.c_int64), ("total_windows", ctypes.c_int64)]
+
+
+_lib = None
+
+
+def load_library():
+    """Load libhog.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                           "`python -m paper_1703_06256_amd.build` (there is no fallback path)")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64
+    sig = {
+        "hog_last_error": ([], ctypes.c_char_p),
+        "hog_lut_fill_host": ([i32, vp], i32),
+        "hog_lut_build": ([i32, ctypes.POINTER(vp)], i32),
+        "hog_lut_free": ([vp], None),
+        "hog_lut_bins": ([vp], i32),
+        "hog_lut_host": ([vp], vp),
+        "hog_plan_create": ([ctypes.POINTER(PlanDesc), ctypes.POINTER(vp)], i32),
+        "hog_plan_destroy": ([vp], None),
+        "hog_plan_get_sizes": ([vp, ctypes.POINTER(PlanSizes)], i32),
+        "hog_plan_get_level": ([vp, i32, ctypes.POINTER(LevelInfo)], i32),
+        "hog_bin_map": ([vp, vp, vp, i64, vp, vp], i32),
+        "hog_integral": ([vp, vp, vp, vp, vp], i32),
+        "hog_scan_windows": ([vp, vp, vp, vp, vp, vp, vp, vp, vp], i32),
+        "hog_timing_enable": ([i32], i32),
+        "hog_timing_reset": ([], i32),
+        "hog_timing_get": ([ctypes.c_char_p, ctypes.POINTER(i64),
+                            ctypes.POINTER(ctypes.c_double)], i32),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = lib
+    return lib
+
+
+def _check(status: int):
+    if status != HOG_OK:
+        raise HogError(status, load_library().hog_last_error().decode())
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _dptr(t, dtype, min_elems: int, name: str):
+    """Device pointer of a contiguous CUDA tensor of the given dtype and size."""
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must have dtype {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.numel() < min_elems:
+        raise ValueError(f"{name} has {t.numel()} elements, needs {min_elems}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+# ----------------------------------------------------------------------------
+def hog_lut_fill_host(n_bins: int) -> np.ndarray:
+    """Host-only table: uint8[dy+255][dx+255]."""
+    out = np.empty((LUT_SIDE, LUT_SIDE), np.uint8)
+    _check(load_library().hog_lut_fill_host(int(n_bins), out.ctypes.data_as(ctypes.c_void_p)))
+    return out
+
+
+class Lut:
+    """Library-owned lookup table (host + device copies)."""
+
+    def __init__(self, handle, n_bins):
+        self.handle = handle
+        self.n_bins = n_bins
+
+    def host_table(self) -> np.ndarray:
+        p = load_library().hog_lut_host(self.handle)
+        buf = (ctypes.c_uint8 * (LUT_SIDE * LUT_SIDE)).from_address(p)
+        return np.frombuffer(buf, dtype=np.uint8).reshape(LUT_SIDE, LUT_SIDE).copy()
+
+    def free(self):
+        if self.handle:
+            load_library().hog_lut_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def hog_lut_build(n_bins: int) -> Lut:
+    h = ctypes.c_void_p()
+    _check(load_library().hog_lut_build(int(n_bins), ctypes.byref(h)))
+    return Lut(h, int(n_bins))
+
+
+def make_desc(width, height, channels=1, n_bins=8, max_levels=1, scale=1.0, n_templates=1,
+              cell=8, win_cells_x=8, win_cells_y=16, block=2, norm=HOG_NORM_RAW,
+              eps=1e-3) -> PlanDesc:
+    return PlanDesc(width, height, channels, n_bins, max_levels, scale, n_templates,
+                    ScanParams(cell, win_cells_x, win_cells_y, block, norm, eps))
+
+
+class Plan:
+    """Level geometry and buffer layout for one image shape."""
+
+    def __init__(self, desc: PlanDesc):
+        self.desc = desc
+        h = ctypes.c_void_p()
+        _check(load_library().hog_plan_create(ctypes.byref(desc), ctypes.byref(h)))
+        self.handle = h
+        sz = PlanSizes()
+        _check(load_library().hog_plan_get_sizes(h, ctypes.byref(sz)))
+        self.sizes = sz
+        self.levels = []
+        for l in range(sz.n_levels):
+            li = LevelInfo()
+            _check(load_library().hog_plan_get_level(h, l, ctypes.byref(li)))
+            self.levels.append(li)
+
+    def destroy(self):
+        if self.handle:
+            load_library().hog_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def hog_bin_map(plan: Plan, lut: Lut, img, bins, stream=None, img_pitch=None):
+    import torch
+    d = plan.desc
+    pitch = d.width * d.channels if img_pitch is None else int(img_pitch)
+    need = (d.height - 1) * pitch + d.width * d.channels
+    _check(load_library().hog_bin_map(
+        plan.handle, lut.handle, _dptr(img, torch.uint8, need, "img"), pitch,
+        _dptr(bins, torch.uint8, plan.sizes.bins_bytes, "bins"), _stream(stream)))
+
+
+def hog_integral(plan: Plan, bins, ii, workspace, stream=None):
+    import torch
+    _check(load_library().hog_integral(
+        plan.handle, _dptr(bins, torch.uint8, plan.sizes.bins_bytes, "bins"),
+        _dptr(ii, torch.int32, plan.sizes.ii_elems, "ii"),
+        _dptr(workspace, torch.uint8, plan.sizes.workspace_bytes, "workspace"),
+        _stream(stream)))
+
+
+def hog_scan_windows(plan: Plan, ii, tmpl, bias, scores, workspace, cell_hist=None,
+                     block_feat=None, stream=None):
+    import torch
+    k = plan.desc.n_templates
+    _check(load_library().hog_scan_windows(
+        plan.handle, _dptr(ii, torch.int32, plan.sizes.ii_elems, "ii"),
+        _dptr(tmpl, torch.float32, k * plan.sizes.feature_dim, "tmpl"),
+        _dptr(bias, torch.float32, k, "bias"),
+        _dptr(scores, torch.float32, plan.sizes.score_elems, "scores"),
+        _dptr(cell_hist, torch.int32, plan.sizes.cell_elems, "cell_hist"),
+        _dptr(block_feat, torch.float32, plan.sizes.block_elems, "block_feat"),
+        _dptr(workspace, torch.uint8, plan.sizes.workspace_bytes, "workspace"),
+        _stream(stream)))
+
+
+def hog_timing_enable(on: bool):
+    _check(load_library().hog_timing_enable(1 if on else 0))
+
+
+def hog_timing_reset():
+    _check(load_library().hog_timing_reset())
+
+
+def hog_timing_get(kernel: str):
+    n = ctypes.c_int64()
+    ms = ctypes.c_double()
+    _check(load_library().hog_timing_get(kernel.encode(), ctypes.byref(n), ctypes.byref(ms)))
+    return n.value, ms.value
+
+
+class Buffers:
+    """Device buffers (torch tensors) sized for a plan. uint32 data is held in
+    int32 tensors (same bits); use .view or & 0xffffffff to read counts."""
+
+    def __init__(self, plan: Plan, device="cuda", cell_hist=False, block_feat=False):
+        import torch
+        s = plan.sizes
+        self.bins = torch.empty(max(s.bins_bytes, 1), dtype=torch.uint8, device=device)
+        self.ii = torch.empty(max(s.ii_elems, 1), dtype=torch.int32, device=device)
+        self.scores = torch.empty(max(s.score_elems, 1), dtype=torch.float32, device=device)
+        self.workspace = torch.empty(max(s.workspace_bytes, 1), dtype=torch.uint8, device=device)
+        self.cell_hist = (torch.empty(max(s.cell_elems, 1), dtype=torch.int32, device=device)
+                          if cell_hist else None)
+        self.block_feat = (torch.empty(max(s.block_elems, 1), dtype=torch.float32, device=device)
+                           if block_feat else None)
+
+
+def run_path(plan: Plan, lut: Lut, img, tmpl, bias, buf: Buffers, stream=None):
+    """The whole hot path: hog_bin_map, hog_integral, hog_scan_windows."""
+    hog_bin_map(plan, lut, img, buf.bins, stream)
+    hog_integral(plan, buf.bins, buf.ii, buf.workspace, stream)
+    hog_scan_windows(plan, buf.ii, tmpl, bias, buf.scores, buf.workspace, buf.cell_hist,
+                     buf.block_feat, stream)
+
+
+# ----------------------------------------------------------------------------
+# Views of one level inside the plan-layout buffers (host numpy arrays).
+def level_bins(plan: Plan, bins_host: np.ndarray, l: int) -> np.ndarray:
+    li = plan.levels[l]
+    a = bins_host[li.bins_offset: li.bins_offset + li.bins_pitch * li.height]
+    return a.reshape(li.height, li.bins_pitch)[:, :li.width]
+
+
+def level_planes(plan: Plan, ii_host: np.ndarray, l: int) -> np.ndarray:
+    """uint32[n_bins][h+1][w+1] of level l."""
+    li = plan.levels[l]
+    nb = plan.desc.n_bins
+    a = ii_host.view(np.uint32)[li.ii_offset: li.ii_offset + li.ii_plane_stride * nb]
+    a = a.reshape(nb, li.ii_plane_stride)[:, :li.ii_pitch * (li.height + 1)]
+    return a.reshape(nb, li.height + 1, li.ii_pitch)[:, :, :li.width + 1]
+
+
+def level_scores(plan: Plan, scores_host: np.ndarray, l: int) -> np.ndarray:
+    """float32[windows_y][windows_x][K] of level l."""
+    li = plan.levels[l]
+    k = plan.desc.n_templates
+    n = li.windows_x * li.windows_y * k
+    return scores_host[li.score_offset: li.score_offset + n].reshape(li.windows_y, li.windows_x, k)
+
+
+def level_cells(plan: Plan, cell_host: np.ndarray, l: int) -> np.ndarray:
+    li = plan.levels[l]
+    nb = plan.desc.n_bins
+    n = li.cells_x * li.cells_y * nb
+    return cell_host.view(np.uint32)[li.cell_offset: li.cell_offset + n].reshape(
+        li.cells_y, li.cells_x, nb)
+
+
+def level_blocks(plan: Plan, block_host: np.ndarray, l: int) -> np.ndarray:
+    """float32[cells_y-1][cells_x-1][4][n_bins] of level l (L2 plans)."""
+    li = plan.levels[l]
+    nb = plan.desc.n_bins
+    bw, bh = li.cells_x - 1, li.cells_y - 1
+    if bw < 1 or bh < 1:
+        return np.zeros((0, 0, 4, nb), np.float32)
+    n = bw * bh * 4 * nb
+    return block_host[li.block_offset: li.block_offset + n].reshape(bh, bw, 4, nb)

@@ -1,0 +1,84 @@
+"""Host-side checks of libhog: it loads, exports every symbol the header
+declares, builds the lookup table on the host exactly as the oracle bins,
+and rejects bad arguments before touching a device."""
+import ctypes
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1703_06256_amd import hog
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "hog.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(hog_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    declared = _declared()
+    assert set(declared) == set(hog.EXPORTS)
+    out = subprocess.run(["nm", "-D", "--defined-only", hog.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = {line.split()[-1] for line in out.splitlines() if line.strip()}
+    missing = [s for s in declared if s not in exported]
+    assert not missing, missing
+    lib = hog.load_library()
+    for s in declared:
+        assert getattr(lib, s) is not None
+
+
+@pytest.mark.parametrize("nb", list(range(1, 65)))
+def test_host_lut_equals_oracle_bins(nb):
+    assert np.array_equal(hog.hog_lut_fill_host(nb), oracle.bin_table(nb))
+
+
+def test_lut_fill_rejects_bad_bins():
+    for nb in (0, -1, 65):
+        with pytest.raises(hog.HogError) as e:
+            hog.hog_lut_fill_host(nb)
+        assert e.value.status == hog.HOG_E_INVALID
+
+
+BAD_DESCS = [
+    dict(width=0), dict(height=-3), dict(width=40000), dict(channels=2), dict(n_bins=0),
+    dict(n_bins=65), dict(max_levels=-1), dict(max_levels=0, scale=1.0),
+    dict(max_levels=3, scale=0.9), dict(n_templates=0), dict(cell=0), dict(cell=33),
+    dict(win_cells_x=0), dict(win_cells_y=65), dict(norm=2),
+    dict(norm=hog.HOG_NORM_L2, block=3), dict(norm=hog.HOG_NORM_L2, win_cells_x=1),
+    dict(norm=hog.HOG_NORM_L2, eps=float("nan")),
+]
+
+
+@pytest.mark.parametrize("bad", BAD_DESCS)
+def test_plan_create_rejects_bad_descriptions(bad):
+    args = dict(width=320, height=240, channels=1, n_bins=8)
+    args.update(bad)
+    desc = hog.make_desc(**args)
+    lib = hog.load_library()
+    h = ctypes.c_void_p()
+    st = lib.hog_plan_create(ctypes.byref(desc), ctypes.byref(h))
+    assert st == hog.HOG_E_INVALID
+    assert not h.value
+    assert lib.hog_last_error().decode()
+
+
+def test_calls_reject_null_arguments():
+    lib = hog.load_library()
+    assert lib.hog_bin_map(None, None, None, 0, None, None) == hog.HOG_E_INVALID
+    assert lib.hog_integral(None, None, None, None, None) == hog.HOG_E_INVALID
+    assert lib.hog_scan_windows(None, None, None, None, None, None, None, None,
+                                None) == hog.HOG_E_INVALID
+    assert lib.hog_plan_create(None, None) == hog.HOG_E_INVALID
+    assert lib.hog_lut_build(1, None) == hog.HOG_E_INVALID
+    assert lib.hog_plan_get_sizes(None, None) == hog.HOG_E_INVALID
+    assert "NULL" in lib.hog_last_error().decode()
+    lib.hog_plan_destroy(None)
+    lib.hog_lut_free(None)

@@ -1,0 +1,171 @@
+"""Parity of the HIP path (through the C ABI) against the CPU oracle.
+
+Bins, integral images and cell histograms must match bit for bit; block
+features and scores within the FP32 tolerance stated in hog_cases.
+Every input is seeded and synthetic (paper_1703_06256_amd.inputs).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1703_06256_amd import hog
+from paper_1703_06256_amd import inputs
+
+from hog_cases import (check_features, check_scores, oracle_level_bins, oracle_params,
+                       run_gpu, templates_for)
+
+pytestmark = pytest.mark.gpu
+
+
+def _check_level(plan, out, img, l, check_all_scores=True, sample=None, seed=0, tmpl=None,
+                 bias=None):
+    """Compare level l: bins, planes, cells exactly; scores (and blocks) within tol."""
+    d = plan.desc
+    nb = d.n_bins
+    li = plan.levels[l]
+    want_bins = oracle_level_bins(img, plan, l)
+    got_bins = hog.level_bins(plan, out["bins"], l)
+    assert np.array_equal(got_bins, want_bins), f"bins differ at level {l}"
+    planes = hog.level_planes(plan, out["ii"], l)
+    want_planes = oracle.integral(want_bins, nb)
+    assert np.array_equal(planes, want_planes), f"planes differ at level {l}"
+    binned = np.count_nonzero(want_bins != oracle.NO_BIN)
+    assert int(planes[:, li.height, li.width].astype(np.int64).sum()) == binned
+    if out["cells"] is not None and li.cells_x > 0 and li.cells_y > 0:
+        want_cells = oracle.cell_hist(want_bins, nb, d.scan.cell)
+        assert np.array_equal(hog.level_cells(plan, out["cells"], l), want_cells), \
+            f"cells differ at level {l}"
+    if li.windows_x == 0:
+        return
+    p = oracle_params(d)
+    if check_all_scores:
+        wxs = wys = None
+    else:
+        rng = np.random.default_rng(seed + l)
+        n = min(sample, li.windows_x * li.windows_y)
+        idx = rng.choice(li.windows_x * li.windows_y, size=n, replace=False)
+        wys, wxs = idx // li.windows_x, idx % li.windows_x
+    s_ref, absterm, feats, wxs, wys = oracle.score_windows(
+        want_bins, nb, p, tmpl, bias, wxs, wys, want_feats=d.scan.norm == hog.HOG_NORM_L2)
+    got = hog.level_scores(plan, out["scores"], l)[wys, wxs, :]
+    check_scores(got, s_ref, absterm)
+    if d.scan.norm == hog.HOG_NORM_L2 and out["blocks"] is not None:
+        blocks = hog.level_blocks(plan, out["blocks"], l)  # [by][bx][4][nb]
+        nbx, nby = d.scan.win_cells_x - 1, d.scan.win_cells_y - 1
+        for i in range(min(len(wxs), 64)):
+            g = blocks[wys[i]:wys[i] + nby, wxs[i]:wxs[i] + nbx].reshape(-1)
+            check_features(g, feats[i])
+
+
+GRAY_SIZES = [(1, 1), (2, 2), (3, 3), (7, 5), (63, 130), (64, 128), (65, 129), (127, 131),
+              (129, 140), (130, 257), (321, 241), (320, 240)]
+
+
+@pytest.mark.parametrize("w,h", GRAY_SIZES)
+def test_gray_raw_single_level(w, h):
+    """Plain path, grey, N_b = 8, raw 8x16x8 cell features (320x240 is the
+    small standard workload)."""
+    desc = hog.make_desc(w, h, channels=1, n_bins=8, norm=hog.HOG_NORM_RAW)
+    img = inputs.synth_image(w, h, 1, inputs.SEED_IMAGE_BASE + 0 + w * 7 + h)
+    tmpl, bias = templates_for(desc, inputs.SEED_TEMPLATE_BASE + 0)
+    plan, out = run_gpu(desc, img, tmpl, bias)
+    assert plan.sizes.n_levels == 1
+    _check_level(plan, out, img[:, :, 0], 0, tmpl=tmpl, bias=bias)
+
+
+def test_gray_raw_several_templates_and_bias():
+    desc = hog.make_desc(200, 150, channels=1, n_bins=8, n_templates=3)
+    img = inputs.synth_image(200, 150, 1, 77)
+    tmpl, _ = templates_for(desc, 78)
+    bias = np.array([0.5, -2.0, 3.25], np.float32)
+    plan, out = run_gpu(desc, img, tmpl, bias)
+    _check_level(plan, out, img[:, :, 0], 0, tmpl=tmpl, bias=bias)
+
+
+@pytest.mark.parametrize("w,h", [(65, 129), (130, 200), (203, 333), (800, 600)])
+def test_rgb_l2_single_level(w, h):
+    """RGB, channel with the largest gradient, N_b = 8, 2x2-cell blocks with L2
+    normalisation, 3360-dim feature (800x600 is the standard colour workload)."""
+    desc = hog.make_desc(w, h, channels=3, n_bins=8, norm=hog.HOG_NORM_L2)
+    img = inputs.synth_image(w, h, 3, inputs.SEED_IMAGE_BASE + 1 + (0 if (w, h) == (800, 600) else w))
+    tmpl, bias = templates_for(desc, inputs.SEED_TEMPLATE_BASE + 1)
+    plan, out = run_gpu(desc, img, tmpl, bias)
+    _check_level(plan, out, img, 0, tmpl=tmpl, bias=bias)
+
+
+@pytest.mark.parametrize("nb", [9, 18])
+def test_rgb_pyramid_small(nb):
+    """Nearest-neighbour pyramid at scale 1.05 down to the window size, every
+    level compared in full."""
+    desc = hog.make_desc(230, 300, channels=3, n_bins=nb, max_levels=0, scale=1.05,
+                         norm=hog.HOG_NORM_L2)
+    img = inputs.synth_image(230, 300, 3, 4242 + nb)
+    tmpl, bias = templates_for(desc, 99 + nb)
+    plan, out = run_gpu(desc, img, tmpl, bias)
+    assert plan.sizes.n_levels > 5
+    for l in range(plan.sizes.n_levels):
+        _check_level(plan, out, img, l, tmpl=tmpl, bias=bias)
+
+
+def test_full_1920x1080_pyramid_n18():
+    """The standard pyramid workload at full size (1920x1080 RGB, N_b = 18,
+    44 levels at 1.05, 7560-dim L2 features): bins, planes and cells of every
+    level bit-exact; scores on a random sample of windows of every level."""
+    desc = hog.make_desc(1920, 1080, channels=3, n_bins=18, max_levels=0, scale=1.05,
+                         norm=hog.HOG_NORM_L2)
+    img = inputs.synth_image(1920, 1080, 3, inputs.SEED_IMAGE_BASE + 2)
+    tmpl, bias = templates_for(desc, inputs.SEED_TEMPLATE_BASE + 2)
+    plan, out = run_gpu(desc, img, tmpl, bias)
+    assert plan.sizes.n_levels == 44
+    assert plan.sizes.total_pixels == 21970720
+    assert plan.sizes.feature_dim == 7560
+    for l in range(plan.sizes.n_levels):
+        _check_level(plan, out, img, l, check_all_scores=False, sample=40, seed=5, tmpl=tmpl,
+                     bias=bias)
+
+
+@pytest.mark.parametrize("nb,w,h", [(1, 70, 65), (2, 64, 64), (5, 129, 66), (8, 191, 127),
+                                    (10, 65, 200), (17, 300, 129), (18, 257, 300),
+                                    (33, 100, 90), (64, 130, 131)])
+def test_integral_on_random_bin_maps(nb, w, h):
+    """hog_integral alone, fed random bin maps (every bin value present, 10%
+    empty), against the Eq. 5 recurrence."""
+    import torch
+    desc = hog.make_desc(w, h, channels=1, n_bins=nb)
+    plan = hog.Plan(desc)
+    li = plan.levels[0]
+    bm = inputs.synth_bin_map(w, h, nb, 1000 + nb)
+    host = np.zeros(plan.sizes.bins_bytes, np.uint8)
+    host[li.bins_offset: li.bins_offset + li.bins_pitch * h].reshape(h, li.bins_pitch)[:, :w] = bm
+    buf = hog.Buffers(plan)
+    buf.bins.copy_(torch.from_numpy(host))
+    hog.hog_integral(plan, buf.bins, buf.ii, buf.workspace)
+    torch.cuda.synchronize()
+    planes = hog.level_planes(plan, buf.ii.cpu().numpy(), 0)
+    assert np.array_equal(planes, oracle.integral(bm, nb))
+
+
+def test_repeat_is_bitwise_identical():
+    desc = hog.make_desc(640, 480, channels=3, n_bins=18, max_levels=0, scale=1.1,
+                         norm=hog.HOG_NORM_L2)
+    img = inputs.synth_image(640, 480, 3, 31337)
+    tmpl, bias = templates_for(desc, 31338)
+    _, outs = run_gpu(desc, img, tmpl, bias, repeat=2)
+    for key in ("bins", "ii", "scores", "cells", "blocks"):
+        assert np.array_equal(outs[0][key], outs[1][key]), key
+
+
+def test_lut_device_copy_matches_oracle():
+    for nb in (8, 18, 20):
+        lut = hog.hog_lut_build(nb)
+        assert np.array_equal(lut.host_table(), oracle.bin_table(nb))
+        lut.free()
+
+
+def test_image_smaller_than_window_has_no_windows():
+    desc = hog.make_desc(60, 100, channels=3, n_bins=8, norm=hog.HOG_NORM_L2)
+    img = inputs.synth_image(60, 100, 3, 5)
+    tmpl, bias = templates_for(desc, 6)
+    plan, out = run_gpu(desc, img, tmpl, bias)
+    assert plan.sizes.total_windows == 0 and plan.sizes.score_elems == 0
+    _check_level(plan, out, img, 0, tmpl=tmpl, bias=bias)
