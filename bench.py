@@ -1,0 +1,204 @@
+"""Benchmark of the fast-HOG hot path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+
+A step is one pass of the whole path over one synthetic image:
+hog_bin_map (every pyramid level), hog_integral (one integral image per bin
+per level) and hog_scan_windows (cells, blocks, window scores), through the
+C ABI, with the image, templates and all buffers resident in HBM.
+
+Prints one JSON line: processed Mpixel/s (pixels summed over pyramid
+levels), per-step latency percentiles, per-kernel times, the roofline of the
+dominant kernel (the integral-image writer) measured live with HIP events,
+and the CPU oracle timed on this host over one full step.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "Mpixel/s end-to-end (bins+integrals+window scores) vs HBM roofline; p99 latency"
+
+WORKLOADS = {
+    # 1920x1080 RGB, N_b = 18, nearest-neighbour pyramid at 1.05 down to the
+    # 64x128 window (44 levels), 2x2-cell L2 blocks (7560-dim), one template.
+    "pyramid_1920x1080": dict(width=1920, height=1080, channels=3, n_bins=18, max_levels=0,
+                              scale=1.05, norm=1, seed=1002, tseed=9002),
+    # 800x600 RGB, N_b = 8, single level, L2 blocks (3360-dim), one template.
+    "rgb_800x600": dict(width=800, height=600, channels=3, n_bins=8, max_levels=1, scale=1.0,
+                        norm=1, seed=1001, tseed=9001),
+    # 320x240 grey, N_b = 8, single level, raw 8x16x8 cell features.
+    "gray_320x240": dict(width=320, height=240, channels=1, n_bins=8, max_levels=1, scale=1.0,
+                         norm=0, seed=1000, tseed=9000),
+}
+KERNELS = ("bin_map", "integral_reduce", "integral_scan", "integral_emit", "cells", "score")
+
+
+def cpu_baseline(wl, desc, tmpl, bias):
+    """The oracle (single thread) over one full step of the same workload."""
+    import oracle
+    from paper_1703_06256_amd import inputs
+    img = inputs.synth_image(wl["width"], wl["height"], wl["channels"], wl["seed"])
+    p = oracle.ScanParams(norm=wl["norm"])
+    nb = wl["n_bins"]
+    levels = oracle.pyramid(wl["width"], wl["height"], wl["scale"], 64, 128,
+                            wl["max_levels"]) if wl["max_levels"] != 1 else \
+        [(wl["width"], wl["height"], 1.0)]
+    t0 = time.perf_counter()
+    px = 0
+    for l, (w, h, s) in enumerate(levels):
+        lvl = img if l == 0 else oracle.resize_nn(img, s, w, h)
+        bins = oracle.bin_map(lvl, nb)
+        oracle.integral(bins, nb)
+        nwx, nwy = oracle.window_grid(w, h, p)
+        if nwx:
+            oracle.score_windows(bins, nb, p, tmpl, bias)
+        px += w * h
+    dt = time.perf_counter() - t0
+    return dict(value=px / dt / 1e6, unit="Mpixel/s", cores=1, kind="oracle",
+                sample=f"one full step ({len(levels)} levels, {px} processed pixels: FP64 bins, "
+                       f"Eq.5 integrals, brute-force window scores) in {dt:.2f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="pyramid_1920x1080", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(each image's path is independent, so images shard across GPUs without any "
+              "exchange; no multi-GPU run is part of this benchmark).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_1703_06256_amd import hog, inputs
+
+    torch.cuda.set_device(0)
+    wl = WORKLOADS[args.workload]
+    desc = hog.make_desc(wl["width"], wl["height"], channels=wl["channels"], n_bins=wl["n_bins"],
+                         max_levels=wl["max_levels"], scale=wl["scale"], norm=wl["norm"])
+    plan = hog.Plan(desc)
+    sz = plan.sizes
+    lut = hog.hog_lut_build(wl["n_bins"])
+    img = inputs.synth_image(wl["width"], wl["height"], wl["channels"], wl["seed"])
+    tmpl, bias = inputs.synth_templates(1, sz.feature_dim, wl["tseed"])
+    img_t = torch.from_numpy(img.reshape(-1)).cuda()
+    tmpl_t = torch.from_numpy(tmpl.reshape(-1)).cuda()
+    bias_t = torch.from_numpy(bias).cuda()
+    buf = hog.Buffers(plan)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        hog.run_path(plan, lut, img_t, tmpl_t, bias_t, buf, stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    # Timed region: exactly K steps.
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        step()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall_ms = (time.perf_counter() - t0) * 1e3
+    ms_per_step = ev0.elapsed_time(ev1) / args.steps
+    value = sz.total_pixels / (ms_per_step * 1e3)
+
+    # Per-step latency (each step alone between two events).
+    lat = []
+    n_lat = min(args.steps, 200)
+    for _ in range(n_lat):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        step()
+        b.record(stream)
+        b.synchronize()
+        lat.append(a.elapsed_time(b))
+    lat = np.array(lat)
+
+    # Per-kernel times: HIP event pairs recorded by the library around each
+    # launch, on the launch stream.
+    hog.hog_timing_enable(True)
+    hog.hog_timing_reset()
+    n_k = min(args.steps, 50)
+    for _ in range(n_k):
+        step()
+    torch.cuda.synchronize()
+    kern_us = {}
+    for k in KERNELS:
+        n, tot = hog.hog_timing_get(k)
+        if n:
+            kern_us[k] = round(tot / n * 1e3, 2)
+    hog.hog_timing_enable(False)
+
+    # Roofline of the dominant kernel: the integral-image writer moves, per
+    # processed pixel, 4*N_b bytes of planes (write) and 1 byte of bins (read).
+    emit_bytes = sz.total_pixels * (4 * wl["n_bins"] + 1)
+    emit_us = kern_us.get("integral_emit", float("nan"))
+    achieved = emit_bytes / (emit_us * 1e-6) / 1e9
+    roofline = dict(bound="hbm", kernel="integral_emit", achieved=round(achieved, 1),
+                    peak=HBM_PEAK_GBS, unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4),
+                    traffic=None,
+                    algorithmic_bytes_per_launch=emit_bytes)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(wl, desc, tmpl, bias)
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "Mpixel/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {
+            "workload": args.workload,
+            "image": f"{wl['width']}x{wl['height']}x{wl['channels']} uint8",
+            "n_bins": wl["n_bins"],
+            "levels": sz.n_levels,
+            "pyramid_scale": wl["scale"],
+            "processed_pixels": sz.total_pixels,
+            "windows": sz.total_windows,
+            "feature_dim": sz.feature_dim,
+            "norm": "l2" if wl["norm"] else "raw",
+            "templates": 1,
+        },
+        "base_mpixel_per_s": round(wl["width"] * wl["height"] / (ms_per_step * 1e3), 2),
+        "p50_ms": round(float(np.percentile(lat, 50)), 4),
+        "p99_ms": round(float(np.percentile(lat, 99)), 4),
+        "wall_ms_timed": round(wall_ms, 2),
+        "kernel_us": kern_us,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

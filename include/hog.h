@@ -172,28 +172,34 @@ hog_status hog_bin_map(const hog_plan *plan, const hog_lut *lut, const uint8_t *
  *   ii[ii_offset + n*ii_plane_stride + (y+1)*ii_pitch + (x+1)]
  *       = #{ (x', y') : x' <= x, y' <= y, bin(x', y') = n }
  * with a zero guard row 0 and guard column 0, i.e. columns 0..width and
- * rows 0..height of each plane (uint32, exact). Padding elements between
- * width+1 and ii_pitch are not written. workspace: device, at least
+ * rows 0..height of each plane (uint32, exact). Elements of a row beyond
+ * column width hold unspecified values. As a by-product it caches every
+ * cell histogram (Eq. 6, the four-corner sums of the planes it writes) in
+ * the workspace for hog_scan_windows. workspace: device, at least
  * workspace_bytes, contents on entry ignored. */
 hog_status hog_integral(const hog_plan *plan, const uint8_t *bins, uint32_t *ii,
                         void *workspace, void *stream);
 
-/* Eq. 6, Sec. 3.3, Sec. 4. ii: device, as written by hog_integral.
- * For every level: the histogram of cell (cx, cy), the cell x cell square
- * at (cx*cell, cy*cell), is ii(4) + ii(1) - ii(2) - ii(3) on each bin's
- * plane, computed once per cell and cached. Window (wx, wy) covers cells
- * [wx, wx+win_cells_x) x [wy, wy+win_cells_y). Its feature f is, for
- * HOG_NORM_RAW, the cell histograms in row-major cell order,
- * f[(cy*win_cells_x + cx)*n_bins + n]; for HOG_NORM_L2, the 2x2-cell blocks
- * stepping one cell, each normalised as v / sqrt(|v|^2 + eps^2) in FP32,
- * f[((by*(win_cells_x-1) + bx)*4 + (v*2 + u))*n_bins + n]. Scores:
+/* Eq. 6, Sec. 3.3, Sec. 4. For every level: the histogram of cell (cx, cy),
+ * the cell x cell square at (cx*cell, cy*cell), is ii(4) + ii(1) - ii(2) -
+ * ii(3) on each bin's plane, computed once per cell and cached. If ii is
+ * non-NULL (device, layout as written by hog_integral) the cells are
+ * computed from it; if ii is NULL the histograms cached by the last
+ * hog_integral call on this plan and workspace are used (Sec. 3.3: areas
+ * visited more than once are cached before evaluation).
+ * Window (wx, wy) covers cells [wx, wx+win_cells_x) x [wy, wy+win_cells_y).
+ * Its feature f is, for HOG_NORM_RAW, the cell histograms in row-major cell
+ * order, f[(cy*win_cells_x + cx)*n_bins + n]; for HOG_NORM_L2, the 2x2-cell
+ * blocks stepping one cell, each normalised as v / sqrt(|v|^2 + eps^2) in
+ * FP32, f[((by*(win_cells_x-1) + bx)*4 + (v*2 + u))*n_bins + n]. Scores:
  *   scores[score_offset + (wy*windows_x + wx)*K + k] = bias[k] + sum_d tmpl[k*D + d] f[d]
- * in FP32 (blocked sums: each block's, or each cell's, partial dot product
- * is rounded once and the partials are added in FP64).
- * tmpl: device, float[K][D]; bias: device, float[K].
+ * in FP32 arithmetic: the partial dot product over each block (L2) or each
+ * cell (raw) is accumulated in FP32, scaled by the block's 1/norm, and the
+ * partials are summed in FP64 before the final rounding to FP32.
+ * tmpl: device, float[K][D]; bias: device, float[K]; scores: device, float.
  * cell_hist (nullable): device, uint32, receives every cell histogram.
  * block_feat (nullable, L2 only): device, float, receives every normalised
- * block. workspace: as for hog_integral. */
+ * block. workspace: the one passed to hog_integral. */
 hog_status hog_scan_windows(const hog_plan *plan, const uint32_t *ii, const float *tmpl,
                             const float *bias, float *scores, uint32_t *cell_hist,
                             float *block_feat, void *workspace, void *stream);

@@ -128,7 +128,8 @@ uint8_t lut_entry(int dx, int dy, int n)
 struct hog_lut {
     int n_bins;
     std::vector<uint8_t> host;
-    uint8_t *dev;
+    uint8_t *dev;       // full table, 511 * 511 bytes
+    uint8_t *dev_half;  // dy >= 0 half with mirror flags, as the kernels stage it in LDS
 };
 
 struct hog_plan {
@@ -163,6 +164,7 @@ hog_status hog_lut_build(int n_bins, hog_lut **out)
     if (!lut) return fail(HOG_E_NOMEM, "host allocation failed");
     lut->n_bins = n_bins;
     lut->dev = nullptr;
+    lut->dev_half = nullptr;
     try {
         lut->host.resize((size_t)HOG_LUT_SIDE * HOG_LUT_SIDE);
     } catch (...) {
@@ -174,14 +176,42 @@ hog_status hog_lut_build(int n_bins, hog_lut **out)
         delete lut;
         return st;
     }
+    // Half table: entry (dx, dy >= 0) = bin(dx, dy) | f << 6, where
+    // bin(dx, -dy) = n - 1 - bin(dx, dy) + f. Mirroring dy maps the angle t to
+    // 2 pi - t, so off the sector edges the bin becomes n - 1 - bin and on an
+    // edge n - bin; f is read off the full table and checked.
+    std::vector<uint8_t> half((size_t)hogk::kLutHalfBytes, 0);
+    for (int dy = 0; dy <= 255; ++dy)
+        for (int dx = -255; dx <= 255; ++dx) {
+            const uint8_t up = lut->host[(dy + 255) * HOG_LUT_SIDE + (dx + 255)];
+            const uint8_t dn = lut->host[(-dy + 255) * HOG_LUT_SIDE + (dx + 255)];
+            uint8_t e = up;
+            if (up != HOG_NO_BIN && dy > 0) {
+                const int f = (int)dn - (n_bins - 1 - (int)up);
+                if (f != 0 && f != 1) {
+                    delete lut;
+                    return fail(HOG_E_INVALID, "lookup table is not mirror-symmetric at (%d,%d)", dx, dy);
+                }
+                e = (uint8_t)(up | (f << 6));
+            }
+            half[(size_t)dy * HOG_LUT_SIDE + (dx + 255)] = e;
+        }
     hipError_t e = hipMalloc((void **)&lut->dev, lut->host.size());
     if (e != hipSuccess) {
         delete lut;
         return device_fail(e, "hipMalloc(lut)");
     }
-    e = hipMemcpy(lut->dev, lut->host.data(), lut->host.size(), hipMemcpyHostToDevice);
+    e = hipMalloc((void **)&lut->dev_half, half.size());
     if (e != hipSuccess) {
         (void)hipFree(lut->dev);
+        delete lut;
+        return device_fail(e, "hipMalloc(lut half)");
+    }
+    e = hipMemcpy(lut->dev, lut->host.data(), lut->host.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(lut->dev_half, half.data(), half.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(lut->dev);
+        (void)hipFree(lut->dev_half);
         delete lut;
         return device_fail(e, "hipMemcpy(lut)");
     }
@@ -193,6 +223,7 @@ void hog_lut_free(hog_lut *lut)
 {
     if (!lut) return;
     if (lut->dev) (void)hipFree(lut->dev);
+    if (lut->dev_half) (void)hipFree(lut->dev_half);
     delete lut;
 }
 
@@ -281,6 +312,7 @@ extern "C" hog_status hog_plan_create(const hog_plan_desc *desc, hog_plan **out)
     int64_t tot_px = 0, tot_win = 0;
     const int n_chunks = (nb + hogk::kMaxBinChunk - 1) / hogk::kMaxBinChunk;
     const int chunk = (nb + n_chunks - 1) / n_chunks;
+    int chunk_final = chunk;
     for (int l = 0;; ++l) {
         if (d.max_levels > 0 && l >= d.max_levels) break;
         if (l >= 256) break;
@@ -295,11 +327,13 @@ extern "C" hog_status hog_plan_create(const hog_plan_desc *desc, hog_plan **out)
         v.h = lh;
         v.cells_x = lw / sp.cell;
         v.cells_y = lh / sp.cell;
+        v.cbx = (v.cells_x + 7) / 8;
+        v.cby = (v.cells_y + 7) / 8;
         v.win_x = v.cells_x - sp.win_cells_x + 1;
         v.win_y = v.cells_y - sp.win_cells_y + 1;
         if (v.win_x <= 0 || v.win_y <= 0) v.win_x = v.win_y = 0;
-        v.tiles_x = (int)((lw + 1 + hogk::kIntTileCols - 1) / hogk::kIntTileCols);
-        v.tiles_y = (int)((lh + 1 + hogk::kIntTileRows - 1) / hogk::kIntTileRows);
+        v.tiles_x = (lw + hogk::kTile - 1) / hogk::kTile;
+        v.tiles_y = (lh + hogk::kTile - 1) / hogk::kTile;
         v.bm_gx = (lw + hogk::kBinCols - 1) / hogk::kBinCols;
         v.bm_gy = (lh + hogk::kBinRows - 1) / hogk::kBinRows;
         v.st_x = v.win_x ? (v.win_x + best_tw - 1) / best_tw : 0;
@@ -317,10 +351,13 @@ extern "C" hog_status hog_plan_create(const hog_plan_desc *desc, hog_plan **out)
         v.bins_pitch = round_up(lw, 64);
         v.bins_off = bins_off;
         bins_off = round_up(bins_off + v.bins_pitch * lh, 256);
-        v.ii_pitch = round_up(lw + 1, 64);
-        v.ii_plane = round_up(v.ii_pitch * (lh + 1), 64);
-        v.ii_off = ii_off;
-        ii_off += v.ii_plane * nb;
+        // Planes: padded column 1 (pixel x = 0) starts a 256-byte line, so
+        // each tile's 64 columns are one aligned line pair; a row has room
+        // for every tile's full 64 columns plus the guard column.
+        v.ii_pitch = (int64_t)hogk::kTile * (v.tiles_x + 1);
+        v.ii_plane = v.ii_pitch * (lh + 1);
+        v.ii_off = round_up(ii_off, 64) + 63;
+        ii_off = v.ii_off + v.ii_plane * nb;
         v.score_off = score_off;
         score_off += (int64_t)v.win_x * v.win_y * K;
         v.cell_off = cell_off;
@@ -338,7 +375,7 @@ extern "C" hog_status hog_plan_create(const hog_plan_desc *desc, hog_plan **out)
         v.ws_t = ws_off;
         ws_off = round_up(ws_off + (int64_t)v.tiles_y * nb * (lw + 1) * 4, 256);
         v.ws_cache = ws_off;
-        ws_off = round_up(ws_off + (int64_t)nb * v.cells_y * v.cells_x * 2, 256);
+        ws_off = round_up(ws_off + (int64_t)nb * v.cby * v.cbx * 64 * 2, 256);
 
         info.width = lw;
         info.height = lh;
@@ -363,6 +400,23 @@ extern "C" hog_status hog_plan_create(const hog_plan_desc *desc, hog_plan **out)
         if (d.max_levels == 1) break;
     }
     const int L = (int)p->levels.size();
+    // The integral kernels address a chunk of planes (and a level's bins)
+    // through one buffer descriptor with 31-bit byte offsets.
+    {
+        int64_t max_plane = 0, max_bins = 0;
+        for (const Level &v : p->levels) {
+            max_plane = std::max(max_plane, v.ii_plane);
+            max_bins = std::max(max_bins, v.bins_pitch * v.h);
+        }
+        const int64_t lim = ((int64_t)1 << 31) - 1;
+        int c = chunk;
+        while (c > 1 && (int64_t)c * max_plane * 4 > lim) --c;
+        if ((int64_t)c * max_plane * 4 > lim || max_bins > lim) {
+            delete p;
+            return fail(HOG_E_INVALID, "image too large: one integral image exceeds 2 GiB");
+        }
+        chunk_final = c;
+    }
 
     // Per-kernel prefix tables.
     std::vector<int32_t> first((size_t)hogk::KB_COUNT * (L + 1), 0);
@@ -442,9 +496,17 @@ extern "C" hog_status hog_plan_create(const hog_plan_desc *desc, hog_plan **out)
     pd.st_th = best_th;
     pd.st_lds_bytes = (int32_t)best_lds;
     pd.cell_stride = nbp;
-    pd.bin_chunk = chunk;
-    pd.n_chunks = n_chunks;
+    pd.bin_chunk = chunk_final;  // bins per wave; a last, smaller chunk takes the rest
+    pd.n_chunks = (nb + chunk_final - 1) / chunk_final;
     for (int k = 0; k < hogk::KB_COUNT; ++k) pd.total[k] = totals[k];
+    {
+        int dev = 0, ncu = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            ncu < 1)
+            ncu = 256;
+        pd.n_cu = ncu;
+    }
 
     hog_plan_sizes &z = p->sizes;
     std::memset(&z, 0, sizeof z);
@@ -498,7 +560,7 @@ extern "C" hog_status hog_bin_map(const hog_plan *plan, const hog_lut *lut, cons
         return fail(HOG_E_INVALID, "img_pitch %lld < width*channels", (long long)img_pitch);
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = timed_launch("bin_map", s, [&] {
-        return hogk::launch_bin_map(plan->dev, lut->dev, img, img_pitch, bins, s);
+        return hogk::launch_bin_map(plan->dev, lut->dev_half, img, img_pitch, bins, s);
     });
     if (e != hipSuccess) return device_fail(e, "bin_map launch");
     return HOG_OK;
@@ -531,7 +593,7 @@ extern "C" hog_status hog_scan_windows(const hog_plan *plan, const uint32_t *ii,
                                        const float *bias, float *scores, uint32_t *cell_hist,
                                        float *block_feat, void *workspace, void *stream)
 {
-    if (!plan || !ii || !workspace) return fail(HOG_E_INVALID, "NULL argument");
+    if (!plan || !workspace) return fail(HOG_E_INVALID, "NULL argument");
     const bool need_scores = plan->sizes.score_elems > 0;
     if (need_scores && (!tmpl || !bias || !scores))
         return fail(HOG_E_INVALID, "tmpl, bias and scores are required when the plan has windows");
@@ -539,10 +601,18 @@ extern "C" hog_status hog_scan_windows(const hog_plan *plan, const uint32_t *ii,
         return fail(HOG_E_INVALID, "block_feat is only defined for HOG_NORM_L2");
     hipStream_t s = (hipStream_t)stream;
     uint8_t *ws = (uint8_t *)workspace;
-    hipError_t e = timed_launch("cells", s, [&] {
-        return hogk::launch_cells(plan->dev, ii, ws, cell_hist, s);
-    });
-    if (e != hipSuccess) return device_fail(e, "cells launch");
+    hipError_t e = hipSuccess;
+    if (ii) {
+        // Cell histograms from the given planes (four-corner sums).
+        e = timed_launch("cells", s, [&] { return hogk::launch_cells(plan->dev, ii, ws, cell_hist, s); });
+        if (e != hipSuccess) return device_fail(e, "cells launch");
+    } else if (plan->desc.scan.cell != 8) {
+        return fail(HOG_E_INVALID, "hog_integral caches cells only for 8-pixel cells; pass ii");
+    } else if (cell_hist) {
+        // Cell histograms cached by hog_integral in this workspace.
+        e = timed_launch("cells", s, [&] { return hogk::launch_cache_export(plan->dev, ws, cell_hist, s); });
+        if (e != hipSuccess) return device_fail(e, "cache export launch");
+    }
     if (block_feat) {
         e = timed_launch("block_features", s, [&] {
             return hogk::launch_block_features(plan->dev, ws, block_feat, s);

@@ -14,11 +14,13 @@ constexpr int kNoBin = 255;
 // and walks kBinRows rows, rolling the up/centre/down samples in registers.
 constexpr int kBinCols = 62;
 constexpr int kBinRows = 16;
+// dy >= 0 half of the 511 x 511 lookup table, as staged in LDS.
+constexpr int kLutHalfBytes = 256 * 511;
 
-// Integral images: a tile is 64 padded columns (one per lane) by
-// kIntTileRows padded rows, one wave per tile and per chunk of bins.
-constexpr int kIntTileCols = 64;
-constexpr int kIntTileRows = 64;
+// Integral images: a tile is kTile x kTile pixels, one wave per tile and per
+// chunk of at most kMaxBinChunk bins; bins are read kRowBatch rows at a time.
+constexpr int kTile = 64;
+constexpr int kRowBatch = 16;
 constexpr int kMaxBinChunk = 9;
 
 // Kernel indices into the per-kernel prefix tables.
@@ -39,19 +41,20 @@ struct Level {
     int32_t w, h;
     int32_t cells_x, cells_y;
     int32_t win_x, win_y;
-    int32_t tiles_x, tiles_y;  // integral tiles over the padded (w+1) x (h+1) grid
+    int32_t tiles_x, tiles_y;  // integral tiles: ceil(w / kTile) x ceil(h / kTile)
     int32_t bm_gx, bm_gy;      // bin-map waves
     int32_t st_x, st_y;        // scorer tiles
+    int32_t cbx, cby;          // 8 x 8-cell blocks of the cell cache: ceil(cells / 8)
     int64_t mapx_off, mapy_off;
     int64_t bins_off, bins_pitch;
     int64_t ii_off, ii_pitch, ii_plane;
     int64_t score_off, cell_off, block_off;
     // workspace (bytes from the workspace base)
-    int64_t ws_rowtot;  // uint8  [tiles_x][h+1][nb]   per-tile row counts
-    int64_t ws_coltot;  // uint8  [tiles_y][nb][w+1]   per-tile column counts
-    int64_t ws_e;       // uint32 [tiles_x][h+1][nb]   row carry from the tiles on the left
-    int64_t ws_t;       // uint32 [tiles_y][nb][w+1]   plane row just above each tile row
-    int64_t ws_cache;   // uint16 [nb][cells_y][cells_x] cell histogram cache
+    int64_t ws_rowtot;  // uint8  [tiles_x][nb][h+1]   per-tile row counts (padded rows)
+    int64_t ws_coltot;  // uint8  [tiles_y][nb][w+1]   per-tile column counts (padded cols)
+    int64_t ws_e;       // uint32 [tiles_x][nb][h+1]   row carry from the tiles on the left
+    int64_t ws_t;       // uint32 [tiles_y][nb][w+1]   plane row 64 ty of every tile row
+    int64_t ws_cache;   // uint16 [nb][cby][cbx][8][8] cell histogram cache
 };
 
 struct PlanDev {
@@ -72,21 +75,24 @@ struct PlanDev {
     int32_t cell_stride;       // floats per staged cell in the scorer's LDS
     int32_t bin_chunk;         // bins per integral wave
     int32_t n_chunks;
+    int32_t n_cu;              // compute units of the device (persistent grids)
     int64_t total[KB_COUNT];   // totals (= first[k][n_levels])
 };
 
 // Launchers (hog_kernels.hip). Each enqueues one kernel on `stream` and
 // returns the launch status.
-hipError_t launch_bin_map(const PlanDev &p, const uint8_t *lut, const uint8_t *img,
+hipError_t launch_bin_map(const PlanDev &p, const uint8_t *lut_half, const uint8_t *img,
                           int64_t img_pitch, uint8_t *bins, hipStream_t stream);
 hipError_t launch_int_reduce(const PlanDev &p, const uint8_t *bins, uint8_t *ws,
                              hipStream_t stream);
 hipError_t launch_int_scan_rows(const PlanDev &p, uint8_t *ws, hipStream_t stream);
 hipError_t launch_int_scan_cols(const PlanDev &p, uint8_t *ws, hipStream_t stream);
-hipError_t launch_int_emit(const PlanDev &p, const uint8_t *bins, const uint8_t *ws,
-                           uint32_t *ii, hipStream_t stream);
+hipError_t launch_int_emit(const PlanDev &p, const uint8_t *bins, uint8_t *ws, uint32_t *ii,
+                           hipStream_t stream);
 hipError_t launch_cells(const PlanDev &p, const uint32_t *ii, uint8_t *ws, uint32_t *cell_hist,
                         hipStream_t stream);
+hipError_t launch_cache_export(const PlanDev &p, const uint8_t *ws, uint32_t *cell_hist,
+                               hipStream_t stream);
 hipError_t launch_score(const PlanDev &p, const uint8_t *ws, const float *tmpl, const float *bias,
                         float *scores, hipStream_t stream);
 hipError_t launch_block_features(const PlanDev &p, const uint8_t *ws, float *block_feat,

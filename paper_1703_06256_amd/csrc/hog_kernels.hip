@@ -15,6 +15,8 @@
 //   k_block_features  (optional output) normalised block vectors
 #include "hog_internal.h"
 
+#include <algorithm>
+
 namespace hogk {
 namespace {
 
@@ -34,6 +36,35 @@ __device__ __forceinline__ int find_level(const int32_t *__restrict__ first, int
     return lo;
 }
 
+// base + byte_off, where base is wave-uniform and byte_off a 32-bit per-lane
+// byte offset: lets loads and stores use the scalar-base addressing form.
+template <class T>
+__device__ __forceinline__ T *at_byte(T *base, uint32_t byte_off)
+{
+    return reinterpret_cast<T *>(reinterpret_cast<char *>(base) + byte_off);
+}
+template <class T>
+__device__ __forceinline__ const T *at_byte(const T *base, uint32_t byte_off)
+{
+    return reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + byte_off);
+}
+
+// Raw buffer resource over [base, base + bytes): gfx9 descriptor word 3.
+// Accesses outside the range read 0 and drop writes.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_rsrc(const void *base, uint32_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes,
+                                             0x00020000);
+}
+
+// Cell histogram cache (uint16): 8 x 8-cell blocks, block (bx, by) of bin n
+// at ((n * cby + by) * cbx + bx) * 64, cell (cx, cy) at (cy % 8) * 8 + cx % 8
+// within its block. With 8-pixel cells a block is one integral tile.
+__device__ __forceinline__ int64_t cache_index(const Level &v, int n, int cy, int cx)
+{
+    return (((int64_t)n * v.cby + (cy >> 3)) * v.cbx + (cx >> 3)) * 64 + ((cy & 7) << 3) + (cx & 7);
+}
+
 __device__ __forceinline__ float inv_block_norm(float ss, float eps)
 {
     // v / sqrt(|v|^2 + eps^2): the sum of squares of integer counts is exact
@@ -41,58 +72,103 @@ __device__ __forceinline__ float inv_block_norm(float ss, float eps)
     return 1.0f / sqrtf(ss + eps * eps);
 }
 
+// Lane i receives lane i-1's value (wave_shr:1) / lane i+1's (wave_shl:1);
+// the lanes at the wave's ends keep their own value.
+__device__ __forceinline__ uint32_t from_left_lane(uint32_t v)
+{
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x138, 0xF, 0xF, false);
+}
+__device__ __forceinline__ uint32_t from_right_lane(uint32_t v)
+{
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x130, 0xF, 0xF, false);
+}
+
 // ---------------------------------------------------------------------------
-// Eq. 1 + Sec. 2: bin map. A wave owns level columns x0-1 .. x0+62 (lane L
-// is column x0-1+L) and kBinRows rows. Each lane reads one sample per row
-// (the nearest-neighbour source pixel of its column); left and right come
-// from the adjacent lanes, up and down from the previous and next row kept
-// in registers. Lanes 1..62 write bins.
+// Eq. 1 + Sec. 2: bin map. The lookup table lives in LDS as its dy >= 0 half
+// (kLutHalfBytes): entry (dx, |dy|) holds bin(dx, |dy|) in bits 0..5 and, in
+// bit 6, f with bin(dx, -|dy|) = n - 1 - bin(dx, |dy|) + f (f = 1 exactly
+// when the mirrored direction lies on a sector edge); 255 marks (0, 0).
+// A persistent workgroup of 16 waves per CU loads the half table once, then
+// each wave walks bin-map items: level columns x0-1 .. x0+62 (lane L is
+// column x0-1+L) by kBinRows rows. Each lane reads one sample per row, the
+// nearest-neighbour source pixel of its column (all channels in one dword);
+// left and right neighbours come from the adjacent lanes, up and down from
+// the rows above and below. All samples are loaded first, then every lookup
+// is made, then lanes 1..62 store their bins.
 // ---------------------------------------------------------------------------
 template <int C>
-__global__ __launch_bounds__(256) void k_bin_map(const Level *__restrict__ lv,
-                                                 const int32_t *__restrict__ first, int n_levels,
-                                                 const int32_t *__restrict__ mapx,
-                                                 const int32_t *__restrict__ mapy,
-                                                 const uint8_t *__restrict__ img, int64_t pitch,
-                                                 const uint8_t *__restrict__ lut,
-                                                 uint8_t *__restrict__ bins)
+__global__ __launch_bounds__(1024) void k_bin_map(const Level *__restrict__ lv,
+                                                  const int32_t *__restrict__ first, int n_levels,
+                                                  const int32_t *__restrict__ mapx,
+                                                  const int32_t *__restrict__ mapy,
+                                                  const uint8_t *__restrict__ img, int64_t pitch,
+                                                  int src_w, int nb,
+                                                  const uint8_t *__restrict__ lut_half,
+                                                  uint8_t *__restrict__ bins)
 {
-    const int wave = (int)blockIdx.x * 4 + wave_id_in_block();
+    __shared__ __attribute__((aligned(16))) uint8_t lut[kLutHalfBytes];
+    {
+        typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+        const u32x4 *src = reinterpret_cast<const u32x4 *>(lut_half);
+        u32x4 *dst = reinterpret_cast<u32x4 *>(lut);
+        for (int i = threadIdx.x; i < kLutHalfBytes / 16; i += blockDim.x) dst[i] = src[i];
+    }
+    __syncthreads();
+
     const int lane = threadIdx.x & 63;
-    if (wave >= first[n_levels]) return;
-    const int l = find_level(first, n_levels, wave);
-    const Level &v = lv[l];
-    const int W = v.w, H = v.h;
-    const int t = wave - first[l];
-    const int gx = t % v.bm_gx, gy = t / v.bm_gx;
-    const int x = gx * kBinCols - 1 + lane;
-    const bool col_ok = x >= 0 && x < W;
-    const int32_t *my = mapy + v.mapy_off;
-    const uint8_t *colp = img + (int64_t)(col_ok ? mapx[v.mapx_off + x] : 0) * C;
-
-    auto sample = [&](int r) -> uint32_t {
-        if (!col_ok || r < 0 || r >= H) return 0u;
-        const uint8_t *p = colp + (int64_t)my[r] * pitch;
-        if constexpr (C == 1) {
-            return p[0];
-        } else {
-            return (uint32_t)p[0] | ((uint32_t)p[1] << 8) | ((uint32_t)p[2] << 16);
+    const int n_items = first[n_levels];
+    const int waves_per_block = (int)(blockDim.x >> 6);
+    for (int item = (int)blockIdx.x * waves_per_block + wave_id_in_block(); item < n_items;
+         item += (int)gridDim.x * waves_per_block) {
+        const int l = find_level(first, n_levels, item);
+        const Level &v = lv[l];
+        const int W = v.w, H = v.h;
+        const int t = item - first[l];
+        const int gx = t % v.bm_gx, gy = t / v.bm_gx;
+        const int x = gx * kBinCols - 1 + lane;
+        const bool col_ok = x >= 0 && x < W;
+        const int32_t *my = mapy + v.mapy_off;
+        const int sx = col_ok ? mapx[v.mapx_off + x] : 0;
+        // Byte offset of the sample in a source row; for RGB a 4-byte read that
+        // stays inside the row (it starts one byte early at the last column).
+        int64_t coff = sx;
+        uint32_t shift = 0;
+        bool can_load = col_ok;
+        if constexpr (C == 3) {
+            const bool last = sx >= src_w - 1;
+            coff = last ? 3 * (int64_t)sx - 1 : 3 * (int64_t)sx;
+            shift = last ? 8u : 0u;
+            can_load = col_ok && src_w >= 2;  // a 1-pixel-wide image has no interior
         }
-    };
+        const uint8_t *colp = img + coff;
+        const int y0 = gy * kBinRows;
 
-    const int y0 = gy * kBinRows;
-    const int y1 = min(y0 + kBinRows, H);
-    uint32_t up = sample(y0 - 1);
-    uint32_t cur = sample(y0);
-    uint8_t *out = bins + v.bins_off + x;
-    const bool writer = lane >= 1 && lane <= kBinCols && col_ok;
-    const bool col_interior = x >= 1 && x <= W - 2;
-    for (int y = y0; y < y1; ++y) {
-        const uint32_t down = sample(y + 1);
-        const uint32_t left = __shfl_up(cur, 1u);
-        const uint32_t right = __shfl_down(cur, 1u);
-        uint8_t b = (uint8_t)kNoBin;
-        if (col_interior && y >= 1 && y <= H - 2) {
+        uint32_t smp[kBinRows + 2];
+#pragma unroll
+        for (int i = 0; i < kBinRows + 2; ++i) {
+            const int r = y0 - 1 + i;
+            uint32_t val = 0;
+            if (r >= 0 && r < H) {
+                const uint8_t *p = colp + (int64_t)my[r] * pitch;
+                if (can_load) {
+                    if constexpr (C == 1) {
+                        val = *p;
+                    } else {
+                        uint32_t w4;
+                        __builtin_memcpy(&w4, p, 4);
+                        val = (w4 >> shift) & 0xFFFFFFu;
+                    }
+                }
+            }
+            smp[i] = val;
+        }
+        const bool col_interior = x >= 1 && x <= W - 2;
+        uint8_t b[kBinRows];
+#pragma unroll
+        for (int i = 0; i < kBinRows; ++i) {
+            const int y = y0 + i;
+            const uint32_t up = smp[i], cur = smp[i + 1], down = smp[i + 2];
+            const uint32_t left = from_left_lane(cur), right = from_right_lane(cur);
             int best = 0, bdx = 0, bdy = 0;
 #pragma unroll
             for (int c = 0; c < C; ++c) {
@@ -101,72 +177,119 @@ __global__ __launch_bounds__(256) void k_bin_map(const Level *__restrict__ lv,
                 const int m = dx * dx + dy * dy;
                 if (m > best) { best = m; bdx = dx; bdy = dy; }  // ties keep the lower channel
             }
-            if (best > 0) b = lut[(bdy + 255) * 511 + (bdx + 255)];
+            const bool ok = col_interior && y >= 1 && y <= H - 2 && best > 0;
+            const int ady = bdy < 0 ? -bdy : bdy;
+            const uint32_t e = lut[ok ? ady * 511 + (bdx + 255) : 0];
+            const uint32_t half_bin = e & 63u;
+            const uint32_t bin = bdy < 0 ? (uint32_t)(nb - 1) - half_bin + (e >> 6) : half_bin;
+            b[i] = ok ? (uint8_t)bin : (uint8_t)kNoBin;
         }
-        if (writer) out[(int64_t)y * v.bins_pitch] = b;
-        up = cur;
-        cur = down;
+        const bool writer = lane >= 1 && lane <= kBinCols && col_ok;
+        uint8_t *out = bins + v.bins_off + x;
+#pragma unroll
+        for (int i = 0; i < kBinRows; ++i)
+            if (writer && y0 + i < H) out[(int64_t)(y0 + i) * v.bins_pitch] = b[i];
     }
 }
 
+// Stage the kTile x kTile bins of tile (tx, ty) into this wave's LDS slice
+// (row-major, kTile bytes per row): 4 x 16-byte loads per lane. Rows past
+// the level's height read as 0 (outside the buffer range); columns past its
+// width are masked by the caller.
+__device__ __forceinline__ void stage_bin_tile(uint8_t *tb, __amdgpu_buffer_rsrc_t bsrc, int bpitch,
+                                               int tx, int y0, int lane)
+{
+    typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        const int k = lane + 64 * m;
+        const int row = k >> 2, seg = k & 3;
+        const u32x4 d = __builtin_amdgcn_raw_buffer_load_b128(bsrc, tx * kTile + 16 * seg,
+                                                              (y0 + row) * bpitch, 0);
+        *reinterpret_cast<u32x4 *>(tb + row * kTile + 16 * seg) = d;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+}
+
 // ---------------------------------------------------------------------------
-// Eq. 5, pass 1. Tile (tx, ty): padded columns [64 tx, 64 tx + 64), padded
-// rows [TH ty, TH ty + TH); padded (r, c) holds pixel (c-1, r-1), and row 0
-// / column 0 hold nothing. For the wave's chunk of bins, count per tile row
-// (a ballot per bin) and per column (registers).
+// Integral images (Eq. 4 + Eq. 5) over pixel tiles of kTile x kTile: tile
+// (tx, ty) holds pixels [64 tx, 64 tx + 64) x [64 ty, 64 ty + 64), one wave
+// per tile and per chunk of bins, lane L on pixel column 64 tx + L. In the
+// planes, pixel (x, y) is padded element (y + 1, x + 1); padded row 0 and
+// column 0 are the zero guards.
+//
+// Pass 1 (k_int_reduce): per tile, the count of each bin in each tile row
+// (a ballot per bin) and in each tile column (registers).
 // ---------------------------------------------------------------------------
 template <int NBC>
 __global__ __launch_bounds__(256) void k_int_reduce(const Level *__restrict__ lv,
                                                     const int32_t *__restrict__ first, int n_levels,
-                                                    int nb, const uint8_t *__restrict__ bins,
+                                                    int nb, int b_first, int n_chunk,
+                                                    const uint8_t *__restrict__ bins,
                                                     uint8_t *__restrict__ ws)
 {
-    const int tile = (int)blockIdx.x * 4 + wave_id_in_block();
+    // Consecutive waves take the chunks of one tile.
+    const int gw = (int)blockIdx.x * 4 + wave_id_in_block();
     const int lane = threadIdx.x & 63;
+    const int tile = gw / n_chunk;
     if (tile >= first[n_levels]) return;
     const int l = find_level(first, n_levels, tile);
     const Level &v = lv[l];
     const int t = tile - first[l];
     const int tx = t % v.tiles_x, ty = t / v.tiles_x;
-    const int b0 = (int)blockIdx.y * NBC;
-    const int nbh = min(NBC, nb - b0);
-    const int c = tx * kIntTileCols + lane;
-    const int x = c - 1;
-    const bool cin = x >= 0 && x < v.w;
-    const int r0 = ty * kIntTileRows, r1 = min(r0 + kIntTileRows, v.h + 1);
-    const uint8_t *bcol = bins + v.bins_off + x;
-    uint8_t *rowtot = ws + v.ws_rowtot + (int64_t)tx * (v.h + 1) * nb + b0;
+    const int b0 = b_first + (gw - tile * n_chunk) * NBC;
+    const int x = tx * kTile + lane;
+    const bool xin = x < v.w;
+    const int y0 = ty * kTile, y1 = min(y0 + kTile, v.h);
+    __shared__ uint8_t tiles[4][kTile * kTile];
+    uint8_t *tb = tiles[wave_id_in_block()];
+    stage_bin_tile(tb, buffer_rsrc(bins + v.bins_off, (uint32_t)(v.bins_pitch * v.h)),
+                   (int)v.bins_pitch, tx, y0, lane);
 
-    uint32_t colcnt[NBC];
+    uint32_t colcnt[NBC], rowcnt[NBC];
 #pragma unroll
-    for (int j = 0; j < NBC; ++j) colcnt[j] = 0;
+    for (int j = 0; j < NBC; ++j) colcnt[j] = rowcnt[j] = 0;
 
-    for (int r = r0; r < r1; ++r) {
-        const int y = r - 1;
-        const int bin = (cin && y >= 0) ? (int)bcol[(int64_t)y * v.bins_pitch] : kNoBin;
+    auto count_row = [&](int bin, int rr) {
         const int rel = bin - b0;
-        uint32_t mine = 0;
 #pragma unroll
         for (int j = 0; j < NBC; ++j) {
-            if (j < nbh) {
-                const bool hit = rel == j;
-                colcnt[j] += hit ? 1u : 0u;
-                const uint32_t cnt = (uint32_t)__popcll(__ballot(hit));
-                mine = (lane == j) ? cnt : mine;
-            }
+            const bool hit = rel == j;
+            colcnt[j] += hit ? 1u : 0u;
+            const uint32_t cnt = (uint32_t)__popcll(__ballot(hit));
+            rowcnt[j] = (lane == rr) ? cnt : rowcnt[j];
         }
-        if (lane < nbh) rowtot[(int64_t)r * nb + lane] = (uint8_t)mine;
-    }
-    if (c <= v.w) {
-        uint8_t *coltot = ws + v.ws_coltot + ((int64_t)ty * nb + b0) * (v.w + 1) + c;
+    };
+    const int nrows = y1 - y0;
+    int rr = 0;
+    for (; rr + kRowBatch <= nrows; rr += kRowBatch) {
+        int bb[kRowBatch];
 #pragma unroll
-        for (int j = 0; j < NBC; ++j)
-            if (j < nbh) coltot[(int64_t)j * (v.w + 1)] = (uint8_t)colcnt[j];
+        for (int i = 0; i < kRowBatch; ++i) bb[i] = tb[(rr + i) * kTile + lane];
+#pragma unroll
+        for (int i = 0; i < kRowBatch; ++i) count_row(xin ? bb[i] : kNoBin, rr + i);
+    }
+    for (; rr < nrows; ++rr) {
+        const int raw = tb[rr * kTile + lane];
+        count_row(xin ? raw : kNoBin, rr);
+    }
+
+    // rowtot [tx][n][h+1] (padded rows), lane = row of the tile.
+    if (y0 + lane < y1) {
+        uint8_t *rowtot = ws + v.ws_rowtot + ((int64_t)tx * nb + b0) * (v.h + 1) + (y0 + 1 + lane);
+#pragma unroll
+        for (int j = 0; j < NBC; ++j) rowtot[(int64_t)j * (v.h + 1)] = (uint8_t)rowcnt[j];
+    }
+    // coltot [ty][n][w+1] (padded columns).
+    if (xin) {
+        uint8_t *coltot = ws + v.ws_coltot + ((int64_t)ty * nb + b0) * (v.w + 1) + x + 1;
+#pragma unroll
+        for (int j = 0; j < NBC; ++j) coltot[(int64_t)j * (v.w + 1)] = (uint8_t)colcnt[j];
     }
 }
 
-// Eq. 5, pass 2a: for every padded row r and bin n, the number of n-pixels
-// of row r in the tiles left of tile column tx (exclusive scan over tx).
+// Pass 2a: E[tx][n][r] = number of n-pixels of padded row r in the tiles left
+// of tile column tx (exclusive scan over tx); row 0 is zero.
 __global__ __launch_bounds__(256) void k_int_scan_rows(const Level *__restrict__ lv,
                                                        const int32_t *__restrict__ first,
                                                        int n_levels, int nb,
@@ -176,20 +299,33 @@ __global__ __launch_bounds__(256) void k_int_scan_rows(const Level *__restrict__
     if (g >= first[n_levels]) return;
     const int l = find_level(first, n_levels, g);
     const Level &v = lv[l];
-    const int rel = g - first[l];  // r * nb + n
-    const int64_t stride = (int64_t)(v.h + 1) * nb;
+    const int rel = g - first[l];  // n * (h + 1) + r
+    const int H1 = v.h + 1;
+    const int64_t stride = (int64_t)nb * H1;
     const uint8_t *rt = ws + v.ws_rowtot + rel;
     uint32_t *e = reinterpret_cast<uint32_t *>(ws + v.ws_e) + rel;
+    const bool row0 = (rel % H1) == 0;
     uint32_t acc = 0;
-    for (int tx = 0; tx < v.tiles_x; ++tx) {
+    int tx = 0;
+    for (; tx + 8 <= v.tiles_x; tx += 8) {
+        uint32_t c[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) c[i] = row0 ? 0u : rt[(tx + i) * stride];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            e[(tx + i) * stride] = acc;
+            acc += c[i];
+        }
+    }
+    for (; tx < v.tiles_x; ++tx) {
+        const uint32_t c = row0 ? 0u : rt[tx * stride];
         e[tx * stride] = acc;
-        acc += rt[tx * stride];
+        acc += c;
     }
 }
 
-// Eq. 5, pass 2b: for tile row ty and bin n, the plane row just above the
-// tile row, T(c) = ii at padded row TH ty - 1, padded column c: the inclusive
-// prefix over c of the column counts of all tile rows above.
+// Pass 2b: T[ty][n][c] = plane value at padded row 64 ty, padded column c:
+// the inclusive prefix over c of the column counts of every tile row above.
 __global__ __launch_bounds__(256) void k_int_scan_cols(const Level *__restrict__ lv,
                                                        const int32_t *__restrict__ first,
                                                        int n_levels, int nb,
@@ -211,8 +347,15 @@ __global__ __launch_bounds__(256) void k_int_scan_cols(const Level *__restrict__
     for (int base = 0; base < W1; base += 256) {
         const int c = base + (int)threadIdx.x;
         uint32_t a = 0;
-        if (c < W1)
-            for (int k = 0; k < ty; ++k) a += ct[k * ct_stride + c];
+        if (c >= 1 && c < W1) {
+            int k = 0;
+            for (; k + 4 <= ty; k += 4) {
+                const uint32_t a0 = ct[(k + 0) * ct_stride + c], a1 = ct[(k + 1) * ct_stride + c];
+                const uint32_t a2 = ct[(k + 2) * ct_stride + c], a3 = ct[(k + 3) * ct_stride + c];
+                a += (a0 + a1) + (a2 + a3);
+            }
+            for (; k < ty; ++k) a += ct[k * ct_stride + c];
+        }
         uint32_t s = a;
 #pragma unroll
         for (int d = 1; d < 64; d <<= 1) {
@@ -231,63 +374,158 @@ __global__ __launch_bounds__(256) void k_int_scan_cols(const Level *__restrict__
 }
 
 // ---------------------------------------------------------------------------
-// Eq. 4 + Eq. 5, pass 3. Each lane owns one padded column of the tile and
-// keeps, per bin of the wave's chunk, the running plane value of its column
-// in a register, seeded with the plane row above the tile. Per row: the
-// one-hot image of Eq. 4 is a ballot per bin, its inclusive prefix along the
-// row is a masked popcount (mbcnt), the row carry of the tiles on the left
-// is added, and the running value is stored: ii(r, c) = ii(r-1, c) + R(r, c).
+// Pass 3 (k_int_emit), Eq. 4 + Eq. 5 + Eq. 6. Each lane keeps, per bin of the
+// wave's chunk, the running plane value of its column, seeded with the plane
+// row 64 ty (T). Per pixel row: the one-hot image of Eq. 4 is a ballot per
+// bin; its inclusive prefix along the tile row is a masked popcount (mbcnt);
+// with the row carry E of the tiles on the left it gives the row prefix R,
+// and ii(r, c) = ii(r-1, c) + R(r, c) is stored.
+//
+// Every 8th padded row is a row of cell corners: the lanes on every 8th
+// padded column hold P(r, c); P(r, c-8) comes from the lane 8 to the left
+// (or, for the tile's first cell, the plane column 64 tx, kept as a scalar:
+// its value at row 64 ty plus the row carries E), P(r-8, .) from the
+// previous corner row. Their four-corner sum (Eq. 6) is the cell's
+// histogram entry, cached here once per cell (uint16 [n][cy][cx]).
+//
+// Stores are full 64-lane rows; lanes right of the image repeat column w
+// (same values), inside the row pitch.
 // ---------------------------------------------------------------------------
-template <int NBC>
+template <int NBC, bool CELLS>
 __global__ __launch_bounds__(256) void k_int_emit(const Level *__restrict__ lv,
                                                   const int32_t *__restrict__ first, int n_levels,
-                                                  int nb, const uint8_t *__restrict__ bins,
-                                                  const uint8_t *__restrict__ ws,
+                                                  int nb, int b_first, int n_chunk,
+                                                  const uint8_t *__restrict__ bins,
+                                                  uint8_t *__restrict__ ws,
                                                   uint32_t *__restrict__ ii)
 {
-    const int tile = (int)blockIdx.x * 4 + wave_id_in_block();
+    // Consecutive waves take the chunks of one tile.
+    const int gw = (int)blockIdx.x * 4 + wave_id_in_block();
     const int lane = threadIdx.x & 63;
+    const int tile = gw / n_chunk;
     if (tile >= first[n_levels]) return;
     const int l = find_level(first, n_levels, tile);
     const Level &v = lv[l];
     const int t = tile - first[l];
     const int tx = t % v.tiles_x, ty = t / v.tiles_x;
-    const int b0 = (int)blockIdx.y * NBC;
-    const int nbh = min(NBC, nb - b0);
-    const int c = tx * kIntTileCols + lane;
-    const int x = c - 1;
-    const bool cin = x >= 0 && x < v.w;
-    const int W1 = v.w + 1;
-    const bool cst = c < W1;
-    const int r0 = ty * kIntTileRows, r1 = min(r0 + kIntTileRows, v.h + 1);
+    const int b0 = b_first + (gw - tile * n_chunk) * NBC;
+    const int W = v.w, H = v.h;
+    const int W1 = W + 1, H1 = H + 1;
+    const int x = tx * kTile + lane;
+    const bool xin = x < W;
+    const int y0 = ty * kTile, y1 = min(y0 + kTile, H);
+    const uint32_t col4 = (uint32_t)(x + 1) * 4u;  // byte offset of this lane's padded column
+    // The last tile of a tile row also writes the row's last line of 64
+    // columns: padding whose final element is the next row's guard column
+    // (a plane row is kTile * (tiles_x + 1) elements). Every plane line is
+    // thus written whole, never as a partial line.
+    const bool last_tx = tx == v.tiles_x - 1;
 
-    const uint32_t *T = reinterpret_cast<const uint32_t *>(ws + v.ws_t) +
-                        ((int64_t)ty * nb + b0) * W1 + c;
-    uint32_t run[NBC];
+    const uint32_t *T = reinterpret_cast<const uint32_t *>(ws + v.ws_t) + ((int64_t)ty * nb + b0) * W1;
+    const uint32_t *Eb = reinterpret_cast<const uint32_t *>(ws + v.ws_e) + ((int64_t)tx * nb + b0) * H1;
+    const uint32_t tcol = (uint32_t)min(x + 1, W);
+    const int er = y0 + 1 + lane;  // padded row whose carry this lane holds
+    uint32_t run[NBC], top[NBC], ecar[NBC], lrun[NBC], ltop[NBC], cellacc[NBC];
 #pragma unroll
-    for (int j = 0; j < NBC; ++j) run[j] = (j < nbh && cst) ? T[(int64_t)j * W1] : 0u;
+    for (int j = 0; j < NBC; ++j) {
+        run[j] = T[(int64_t)j * W1 + tcol];
+        top[j] = run[j];
+        lrun[j] = T[(int64_t)j * W1 + tx * kTile];
+        ltop[j] = lrun[j];
+        ecar[j] = (er <= H) ? Eb[(int64_t)j * H1 + er] : 0u;
+        cellacc[j] = 0u;
+    }
+    // All global loads of the tile happen here, before the first plane store:
+    // on gfx9 one counter tracks loads and stores, so a load waited for later
+    // would also wait for every store issued before it.
+    __shared__ uint8_t tiles[4][kTile * kTile];
+    uint8_t *tb = tiles[wave_id_in_block()];
+    stage_bin_tile(tb, buffer_rsrc(bins + v.bins_off, (uint32_t)(v.bins_pitch * v.h)),
+                   (int)v.bins_pitch, tx, y0, lane);
 
-    const uint32_t *E = reinterpret_cast<const uint32_t *>(ws + v.ws_e) +
-                        (int64_t)tx * (v.h + 1) * nb + b0;
-    uint32_t *out = ii + v.ii_off + (int64_t)b0 * v.ii_plane + c;
-    const uint8_t *bcol = bins + v.bins_off + x;
-
-    for (int r = r0; r < r1; ++r) {
-        const int y = r - 1;
-        const int bin = (cin && y >= 0) ? (int)bcol[(int64_t)y * v.bins_pitch] : kNoBin;
-        const int rel = bin - b0;
-        const uint32_t *Er = E + (int64_t)r * nb;
-        uint32_t *orow = out + (int64_t)r * v.ii_pitch;
+    // The chunk's NBC planes as one buffer; the plan keeps NBC * plane * 4 < 2^31.
+    const int plane4 = (int)(v.ii_plane * 4), pitch4 = (int)(v.ii_pitch * 4);
+    const __amdgpu_buffer_rsrc_t isrc =
+        buffer_rsrc(ii + v.ii_off + (int64_t)b0 * v.ii_plane, (uint32_t)(NBC * plane4));
+    auto store_row = [&](int j, int r, uint32_t val) {
+        __builtin_amdgcn_raw_buffer_store_b32(val, isrc, (int)col4, j * plane4 + r * pitch4, 0);
+        if (last_tx)
+            __builtin_amdgcn_raw_buffer_store_b32(lane == 63 ? 0u : val, isrc, (int)col4 + 4 * kTile,
+                                                  j * plane4 + r * pitch4, 0);
+    };
+    if (ty == 0) {  // zero guard row (and the plane's first guard element)
 #pragma unroll
         for (int j = 0; j < NBC; ++j) {
-            if (j < nbh) {
-                const bool hit = rel == j;
-                const uint64_t m = __ballot(hit);
-                const uint32_t pre = __builtin_amdgcn_mbcnt_hi(
-                    (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-                run[j] += Er[j] + pre + (hit ? 1u : 0u);
-                if (cst) orow[(int64_t)j * v.ii_plane] = run[j];
+            store_row(j, 0, 0u);
+            if (tx == 0 && lane == 0)
+                __builtin_amdgcn_raw_buffer_store_b32(0u, isrc, 0, j * plane4, 0);
+        }
+    }
+
+    auto do_row = [&](int bin, int y) {
+        const int rel = bin - b0;
+        const int r = y + 1;
+        const int rr = y - y0;
+#pragma unroll
+        for (int j = 0; j < NBC; ++j) {
+            const bool hit = rel == j;
+            const uint64_t m = __ballot(hit);
+            const uint32_t e = (uint32_t)__builtin_amdgcn_readlane((int)ecar[j], rr);
+            run[j] += e + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                    __builtin_amdgcn_mbcnt_lo((uint32_t)m, hit ? 1u : 0u));
+            lrun[j] += e;
+            store_row(j, r, run[j]);
+        }
+    };
+    // Padded row r = y + 1 is a row of cell corners when r % 8 == 0. Lane
+    // 8k + 7 computes the cell (k, q) of the tile (q = its cell row); the value
+    // moves to lane 8q + k, so after the tile's 8 corner rows each lane holds
+    // one cell of the tile's 8 x 8 block.
+    auto do_corners = [&](int y) {
+        if constexpr (CELLS) {
+            const int q = ((y + 1) >> 3) - 1 - 8 * ty;
+            const int src = 8 * (lane & 7) + 7;
+#pragma unroll
+            for (int j = 0; j < NBC; ++j) {
+                const uint32_t rl = __shfl_up(run[j], 8u);
+                const uint32_t tl = __shfl_up(top[j], 8u);
+                const uint32_t left = (lane == 7) ? lrun[j] : rl;
+                const uint32_t ltl = (lane == 7) ? ltop[j] : tl;
+                const uint32_t h = run[j] - left - top[j] + ltl;
+                const uint32_t moved = __shfl(h, src);
+                cellacc[j] = ((lane >> 3) == q) ? moved : cellacc[j];
+                top[j] = run[j];
+                ltop[j] = lrun[j];
             }
+        }
+    };
+    auto load_bin = [&](int y) -> int {
+        const int raw = tb[(y - y0) * kTile + lane];
+        return xin ? raw : kNoBin;
+    };
+
+    int yb = y0;
+    for (; yb + kRowBatch <= y1; yb += kRowBatch) {  // yb is a multiple of 16
+        int bb[kRowBatch];
+#pragma unroll
+        for (int i = 0; i < kRowBatch; ++i) bb[i] = load_bin(yb + i);
+#pragma unroll
+        for (int i = 0; i < kRowBatch; ++i) {
+            do_row(bb[i], yb + i);
+            if ((i & 7) == 7) do_corners(yb + i);
+        }
+    }
+    for (; yb < y1; ++yb) {
+        do_row(load_bin(yb), yb);
+        if (((yb + 1) & 7) == 0) do_corners(yb);
+    }
+    if constexpr (CELLS) {
+        // One whole 128-byte line per bin: the tile's 8 x 8 cells.
+        if (tx < v.cbx && ty < v.cby) {
+            uint16_t *cache = reinterpret_cast<uint16_t *>(ws + v.ws_cache);
+#pragma unroll
+            for (int j = 0; j < NBC; ++j)
+                cache[(((int64_t)(b0 + j) * v.cby + ty) * v.cbx + tx) * 64 + lane] = (uint16_t)cellacc[j];
         }
     }
 }
@@ -314,15 +552,32 @@ __global__ __launch_bounds__(256) void k_cells(const Level *__restrict__ lv,
     const int64_t r0 = (int64_t)cy * cell * v.ii_pitch;
     const int64_t r1 = r0 + (int64_t)cell * v.ii_pitch;
     const int64_t c0 = (int64_t)cx * cell, c1 = c0 + cell;
-    const int64_t cstride = (int64_t)v.cells_x * v.cells_y;
-    uint16_t *cache = reinterpret_cast<uint16_t *>(ws + v.ws_cache) + rel;
+    uint16_t *cache = reinterpret_cast<uint16_t *>(ws + v.ws_cache);
     uint32_t *ch = cell_hist ? cell_hist + v.cell_off + (int64_t)rel * nb : nullptr;
     for (int n = 0; n < nb; ++n) {
         const uint32_t *p = P + (int64_t)n * v.ii_plane;
         const uint32_t h = p[r1 + c1] + p[r0 + c0] - p[r0 + c1] - p[r1 + c0];
-        cache[n * cstride] = (uint16_t)h;
+        cache[cache_index(v, n, cy, cx)] = (uint16_t)h;
         if (ch) ch[n] = h;
     }
+}
+
+// Cell histograms cached by k_int_emit, exported as uint32 [cy][cx][n].
+__global__ __launch_bounds__(256) void k_cache_export(const Level *__restrict__ lv,
+                                                      const int32_t *__restrict__ first,
+                                                      int n_levels, int nb,
+                                                      const uint8_t *__restrict__ ws,
+                                                      uint32_t *__restrict__ cell_hist)
+{
+    const int g = (int)(blockIdx.x * 256 + threadIdx.x);
+    if (g >= first[n_levels]) return;
+    const int l = find_level(first, n_levels, g);
+    const Level &v = lv[l];
+    const int rel = g - first[l];
+    const int cy = rel / v.cells_x, cx = rel % v.cells_x;
+    const uint16_t *cache = reinterpret_cast<const uint16_t *>(ws + v.ws_cache);
+    uint32_t *ch = cell_hist + v.cell_off + (int64_t)rel * nb;
+    for (int n = 0; n < nb; ++n) ch[n] = cache[cache_index(v, n, cy, cx)];
 }
 
 struct ScoreArgs {
@@ -383,7 +638,6 @@ __global__ __launch_bounds__(256) void k_score(const Level *__restrict__ lv,
 
     // Stage the tile's cells (zero outside the level's cell grid).
     const uint16_t *cache = reinterpret_cast<const uint16_t *>(ws + v.ws_cache);
-    const int64_t cstride = (int64_t)v.cells_x * v.cells_y;
     const int total = CH * CW * nb;
     for (int i = threadIdx.x; i < total; i += blockDim.x) {
         const int j = i % CW;
@@ -392,7 +646,7 @@ __global__ __launch_bounds__(256) void k_score(const Level *__restrict__ lv,
         const int cy = wy0 + r, cx = wx0 + j;
         float val = 0.f;
         if (cy < v.cells_y && cx < v.cells_x)
-            val = (float)cache[n * cstride + (int64_t)cy * v.cells_x + cx];
+            val = (float)cache[cache_index(v, n, cy, cx)];
         hc[(r * CW + j) * nbp + n] = val;
     }
     __syncthreads();
@@ -499,12 +753,11 @@ __global__ __launch_bounds__(256) void k_block_features(const Level *__restrict_
     const int bw = v.cells_x - 1;
     const int by = rel / bw, bx = rel % bw;
     const uint16_t *cache = reinterpret_cast<const uint16_t *>(ws + v.ws_cache);
-    const int64_t cstride = (int64_t)v.cells_x * v.cells_y;
     float ss = 0.f;
     for (int vv = 0; vv < 2; ++vv)
         for (int uu = 0; uu < 2; ++uu)
             for (int n = 0; n < nb; ++n) {
-                const float h = (float)cache[n * cstride + (int64_t)(by + vv) * v.cells_x + bx + uu];
+                const float h = (float)cache[cache_index(v, n, by + vv, bx + uu)];
                 ss = fmaf(h, h, ss);
             }
     const float iv = inv_block_norm(ss, eps);
@@ -512,7 +765,7 @@ __global__ __launch_bounds__(256) void k_block_features(const Level *__restrict_
     for (int vv = 0; vv < 2; ++vv)
         for (int uu = 0; uu < 2; ++uu)
             for (int n = 0; n < nb; ++n) {
-                const float h = (float)cache[n * cstride + (int64_t)(by + vv) * v.cells_x + bx + uu];
+                const float h = (float)cache[cache_index(v, n, by + vv, bx + uu)];
                 o[(vv * 2 + uu) * nb + n] = h * iv;
             }
 }
@@ -529,44 +782,55 @@ inline const int32_t *first_of(const PlanDev &p, int k)
 
 }  // namespace
 
-hipError_t launch_bin_map(const PlanDev &p, const uint8_t *lut, const uint8_t *img,
+hipError_t launch_bin_map(const PlanDev &p, const uint8_t *lut_half, const uint8_t *img,
                           int64_t img_pitch, uint8_t *bins, hipStream_t stream)
 {
-    const int64_t waves = p.total[KB_BINMAP];
-    if (waves == 0) return hipSuccess;
-    const dim3 grid(blocks_for(waves, 4));
+    const int64_t items = p.total[KB_BINMAP];
+    if (items == 0) return hipSuccess;
+    const int64_t per_block = 16;  // waves of a 1024-thread workgroup
+    const unsigned grid = (unsigned)std::min<int64_t>((items + per_block - 1) / per_block, p.n_cu);
     if (p.channels == 1)
-        hipLaunchKernelGGL(k_bin_map<1>, grid, dim3(256), 0, stream, p.levels,
+        hipLaunchKernelGGL(k_bin_map<1>, dim3(grid), dim3(1024), 0, stream, p.levels,
                            first_of(p, KB_BINMAP), p.n_levels, p.mapx, p.mapy, img, img_pitch,
-                           lut, bins);
+                           p.src_w, p.n_bins, lut_half, bins);
     else
-        hipLaunchKernelGGL(k_bin_map<3>, grid, dim3(256), 0, stream, p.levels,
+        hipLaunchKernelGGL(k_bin_map<3>, dim3(grid), dim3(1024), 0, stream, p.levels,
                            first_of(p, KB_BINMAP), p.n_levels, p.mapx, p.mapy, img, img_pitch,
-                           lut, bins);
+                           p.src_w, p.n_bins, lut_half, bins);
     return hipGetLastError();
 }
 
-#define HOG_CHUNK_DISPATCH(KERNEL, GRID, STREAM, ...)                                           \
-    switch (p.bin_chunk) {                                                                      \
-    case 1: hipLaunchKernelGGL(KERNEL<1>, GRID, dim3(256), 0, STREAM, __VA_ARGS__); break;      \
-    case 2: hipLaunchKernelGGL(KERNEL<2>, GRID, dim3(256), 0, STREAM, __VA_ARGS__); break;      \
-    case 3: hipLaunchKernelGGL(KERNEL<3>, GRID, dim3(256), 0, STREAM, __VA_ARGS__); break;      \
-    case 4: hipLaunchKernelGGL(KERNEL<4>, GRID, dim3(256), 0, STREAM, __VA_ARGS__); break;      \
-    case 5: hipLaunchKernelGGL(KERNEL<5>, GRID, dim3(256), 0, STREAM, __VA_ARGS__); break;      \
-    case 6: hipLaunchKernelGGL(KERNEL<6>, GRID, dim3(256), 0, STREAM, __VA_ARGS__); break;      \
-    case 7: hipLaunchKernelGGL(KERNEL<7>, GRID, dim3(256), 0, STREAM, __VA_ARGS__); break;      \
-    case 8: hipLaunchKernelGGL(KERNEL<8>, GRID, dim3(256), 0, STREAM, __VA_ARGS__); break;      \
-    case 9: hipLaunchKernelGGL(KERNEL<9>, GRID, dim3(256), 0, STREAM, __VA_ARGS__); break;      \
-    default: return hipErrorInvalidValue;                                                        \
+// One launch per chunk size: the full chunks of p.bin_chunk bins, then, if
+// n_bins is not a multiple of it, one chunk with the remaining bins.
+#define HOG_CHUNK_CASE(KERNEL, NBC, ...) \
+    case NBC: hipLaunchKernelGGL(KERNEL<NBC>, __VA_ARGS__); break;
+#define HOG_CHUNK_DISPATCH(KERNEL, CHUNK, ...)          \
+    switch (CHUNK) {                                    \
+        HOG_CHUNK_CASE(KERNEL, 1, __VA_ARGS__)          \
+        HOG_CHUNK_CASE(KERNEL, 2, __VA_ARGS__)          \
+        HOG_CHUNK_CASE(KERNEL, 3, __VA_ARGS__)          \
+        HOG_CHUNK_CASE(KERNEL, 4, __VA_ARGS__)          \
+        HOG_CHUNK_CASE(KERNEL, 5, __VA_ARGS__)          \
+        HOG_CHUNK_CASE(KERNEL, 6, __VA_ARGS__)          \
+        HOG_CHUNK_CASE(KERNEL, 7, __VA_ARGS__)          \
+        HOG_CHUNK_CASE(KERNEL, 8, __VA_ARGS__)          \
+        HOG_CHUNK_CASE(KERNEL, 9, __VA_ARGS__)          \
+    default: return hipErrorInvalidValue;               \
     }
 
 hipError_t launch_int_reduce(const PlanDev &p, const uint8_t *bins, uint8_t *ws, hipStream_t stream)
 {
     const int64_t tiles = p.total[KB_ITILE];
     if (tiles == 0) return hipSuccess;
-    const dim3 grid(blocks_for(tiles, 4), (unsigned)p.n_chunks);
-    HOG_CHUNK_DISPATCH(k_int_reduce, grid, stream, p.levels, first_of(p, KB_ITILE), p.n_levels,
-                       p.n_bins, bins, ws);
+    const int full = p.n_bins / p.bin_chunk, rem = p.n_bins % p.bin_chunk;
+    const dim3 grid(blocks_for(tiles * full, 4));
+    HOG_CHUNK_DISPATCH(k_int_reduce, p.bin_chunk, grid, dim3(256), 0, stream, p.levels,
+                       first_of(p, KB_ITILE), p.n_levels, p.n_bins, 0, full, bins, ws);
+    if (rem) {
+        const dim3 g1(blocks_for(tiles, 4));
+        HOG_CHUNK_DISPATCH(k_int_reduce, rem, g1, dim3(256), 0, stream, p.levels,
+                           first_of(p, KB_ITILE), p.n_levels, p.n_bins, full * p.bin_chunk, 1, bins, ws);
+    }
     return hipGetLastError();
 }
 
@@ -588,14 +852,40 @@ hipError_t launch_int_scan_cols(const PlanDev &p, uint8_t *ws, hipStream_t strea
     return hipGetLastError();
 }
 
-hipError_t launch_int_emit(const PlanDev &p, const uint8_t *bins, const uint8_t *ws, uint32_t *ii,
+// k_int_emit for chunks of NBC bins, with or without the fused cell cache.
+#define HOG_EMIT_CASE(NBC)                                                                          \
+    case NBC:                                                                                     \
+        if (cells)                                                                                \
+            hipLaunchKernelGGL((k_int_emit<NBC, true>), grid, dim3(256), 0, stream, p.levels,     \
+                               first_of(p, KB_ITILE), p.n_levels, p.n_bins, b_first, n_chunk, bins, \
+                               ws, ii);                                                           \
+        else                                                                                      \
+            hipLaunchKernelGGL((k_int_emit<NBC, false>), grid, dim3(256), 0, stream, p.levels,    \
+                               first_of(p, KB_ITILE), p.n_levels, p.n_bins, b_first, n_chunk, bins, \
+                               ws, ii);                                                           \
+        break;
+
+static hipError_t emit_chunks(const PlanDev &p, int nbc, int b_first, int n_chunk, const uint8_t *bins,
+                              uint8_t *ws, uint32_t *ii, hipStream_t stream)
+{
+    const bool cells = p.cell == 8;
+    const dim3 grid(blocks_for(p.total[KB_ITILE] * n_chunk, 4));
+    switch (nbc) {
+        HOG_EMIT_CASE(1) HOG_EMIT_CASE(2) HOG_EMIT_CASE(3) HOG_EMIT_CASE(4) HOG_EMIT_CASE(5)
+        HOG_EMIT_CASE(6) HOG_EMIT_CASE(7) HOG_EMIT_CASE(8) HOG_EMIT_CASE(9)
+    default: return hipErrorInvalidValue;
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_int_emit(const PlanDev &p, const uint8_t *bins, uint8_t *ws, uint32_t *ii,
                            hipStream_t stream)
 {
-    const int64_t tiles = p.total[KB_ITILE];
-    if (tiles == 0) return hipSuccess;
-    const dim3 grid(blocks_for(tiles, 4), (unsigned)p.n_chunks);
-    HOG_CHUNK_DISPATCH(k_int_emit, grid, stream, p.levels, first_of(p, KB_ITILE), p.n_levels,
-                       p.n_bins, bins, ws, ii);
+    if (p.total[KB_ITILE] == 0) return hipSuccess;
+    const int full = p.n_bins / p.bin_chunk, rem = p.n_bins % p.bin_chunk;
+    hipError_t e = emit_chunks(p, p.bin_chunk, 0, full, bins, ws, ii, stream);
+    if (e == hipSuccess && rem) e = emit_chunks(p, rem, full * p.bin_chunk, 1, bins, ws, ii, stream);
+    if (e != hipSuccess) return e;
     return hipGetLastError();
 }
 
@@ -606,6 +896,16 @@ hipError_t launch_cells(const PlanDev &p, const uint32_t *ii, uint8_t *ws, uint3
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_cells, dim3(blocks_for(n, 256)), dim3(256), 0, stream, p.levels,
                        first_of(p, KB_CELL), p.n_levels, p.n_bins, p.cell, ii, ws, cell_hist);
+    return hipGetLastError();
+}
+
+hipError_t launch_cache_export(const PlanDev &p, const uint8_t *ws, uint32_t *cell_hist,
+                               hipStream_t stream)
+{
+    const int64_t n = p.total[KB_CELL];
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_cache_export, dim3(blocks_for(n, 256)), dim3(256), 0, stream, p.levels,
+                       first_of(p, KB_CELL), p.n_levels, p.n_bins, ws, cell_hist);
     return hipGetLastError();
 }
 

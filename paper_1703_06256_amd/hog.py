@@ -232,7 +232,7 @@ def hog_scan_windows(plan: Plan, ii, tmpl, bias, scores, workspace, cell_hist=No
     import torch
     k = plan.desc.n_templates
     _check(load_library().hog_scan_windows(
-        plan.handle, _dptr(ii, torch.int32, plan.sizes.ii_elems, "ii"),
+        plan.handle, _dptr(ii, torch.int32, plan.sizes.ii_elems, "ii") if ii is not None else None,
         _dptr(tmpl, torch.float32, k * plan.sizes.feature_dim, "tmpl"),
         _dptr(bias, torch.float32, k, "bias"),
         _dptr(scores, torch.float32, plan.sizes.score_elems, "scores"),
@@ -274,12 +274,17 @@ class Buffers:
                            if block_feat else None)
 
 
-def run_path(plan: Plan, lut: Lut, img, tmpl, bias, buf: Buffers, stream=None):
-    """The whole hot path: hog_bin_map, hog_integral, hog_scan_windows."""
+def run_path(plan: Plan, lut: Lut, img, tmpl, bias, buf: Buffers, stream=None,
+             cells_from_planes: bool = False):
+    """The whole hot path: hog_bin_map, hog_integral, hog_scan_windows. By
+    default the scorer uses the cell histograms hog_integral cached (8-pixel
+    cells); with cells_from_planes, or other cell sizes, it recomputes them
+    from the integral images."""
     hog_bin_map(plan, lut, img, buf.bins, stream)
     hog_integral(plan, buf.bins, buf.ii, buf.workspace, stream)
-    hog_scan_windows(plan, buf.ii, tmpl, bias, buf.scores, buf.workspace, buf.cell_hist,
-                     buf.block_feat, stream)
+    from_planes = cells_from_planes or plan.desc.scan.cell != 8
+    hog_scan_windows(plan, buf.ii if from_planes else None, tmpl, bias, buf.scores,
+                     buf.workspace, buf.cell_hist, buf.block_feat, stream)
 
 
 # ----------------------------------------------------------------------------

@@ -15,7 +15,7 @@ SCORE_RTOL = 1e-5
 
 
 def run_gpu(desc: hog.PlanDesc, img: np.ndarray, tmpl: np.ndarray, bias: np.ndarray,
-            cell_hist=True, block_feat=None, repeat=1):
+            cell_hist=True, block_feat=None, repeat=1, cells_from_planes=False):
     """Run the three calls on cuda:0; return host copies of every output."""
     import torch
     plan = hog.Plan(desc)
@@ -28,7 +28,7 @@ def run_gpu(desc: hog.PlanDesc, img: np.ndarray, tmpl: np.ndarray, bias: np.ndar
     bias_t = torch.from_numpy(np.ascontiguousarray(bias, np.float32).reshape(-1)).to("cuda")
     outs = []
     for _ in range(repeat):
-        hog.run_path(plan, lut, img_t, tmpl_t, bias_t, buf)
+        hog.run_path(plan, lut, img_t, tmpl_t, bias_t, buf, cells_from_planes=cells_from_planes)
         torch.cuda.synchronize()
         outs.append(dict(
             bins=buf.bins.cpu().numpy(),

@@ -82,3 +82,20 @@ def test_calls_reject_null_arguments():
     assert "NULL" in lib.hog_last_error().decode()
     lib.hog_plan_destroy(None)
     lib.hog_lut_free(None)
+
+
+@pytest.mark.parametrize("nb", list(range(1, 65)))
+def test_lut_mirror_rule_behind_the_half_table(nb):
+    """The kernels keep only the dy >= 0 half of the table plus one flag:
+    bin(dx, -dy) = nb - 1 - bin(dx, dy) + f with f in {0, 1}, f = 1 exactly on
+    sector edges (where the mirrored angle 2 pi - t is a multiple of 2 pi/nb)."""
+    t = hog.hog_lut_fill_host(nb).astype(np.int64)
+    up = t[255 + 1:, :]          # dy = 1..255
+    dn = t[255 - 1::-1, :]       # dy = -1..-255
+    f = dn - (nb - 1 - up)
+    assert set(np.unique(f)) <= {0, 1}
+    dxs = np.arange(-255, 256)[None, :]
+    dys = np.arange(1, 256)[:, None]
+    # an edge of the mirrored direction can only be an axis or a diagonal
+    edge = (dxs == 0) | (np.abs(dxs) == dys)
+    assert not f[~edge].any()

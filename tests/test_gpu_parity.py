@@ -93,15 +93,16 @@ def test_rgb_l2_single_level(w, h):
     _check_level(plan, out, img, 0, tmpl=tmpl, bias=bias)
 
 
-@pytest.mark.parametrize("nb", [9, 18])
-def test_rgb_pyramid_small(nb):
+@pytest.mark.parametrize("nb,from_planes", [(9, False), (18, False), (18, True), (5, True)])
+def test_rgb_pyramid_small(nb, from_planes):
     """Nearest-neighbour pyramid at scale 1.05 down to the window size, every
-    level compared in full."""
+    level compared in full; cells taken from hog_integral's cache or
+    recomputed from the planes by hog_scan_windows."""
     desc = hog.make_desc(230, 300, channels=3, n_bins=nb, max_levels=0, scale=1.05,
                          norm=hog.HOG_NORM_L2)
     img = inputs.synth_image(230, 300, 3, 4242 + nb)
     tmpl, bias = templates_for(desc, 99 + nb)
-    plan, out = run_gpu(desc, img, tmpl, bias)
+    plan, out = run_gpu(desc, img, tmpl, bias, cells_from_planes=from_planes)
     assert plan.sizes.n_levels > 5
     for l in range(plan.sizes.n_levels):
         _check_level(plan, out, img, l, tmpl=tmpl, bias=bias)
@@ -168,4 +169,16 @@ def test_image_smaller_than_window_has_no_windows():
     tmpl, bias = templates_for(desc, 6)
     plan, out = run_gpu(desc, img, tmpl, bias)
     assert plan.sizes.total_windows == 0 and plan.sizes.score_elems == 0
+    _check_level(plan, out, img, 0, tmpl=tmpl, bias=bias)
+
+
+@pytest.mark.parametrize("cell,norm", [(4, hog.HOG_NORM_RAW), (6, hog.HOG_NORM_L2), (16, hog.HOG_NORM_L2)])
+def test_other_cell_sizes_from_planes(cell, norm):
+    """Cells other than 8 pixels: hog_scan_windows computes them from the
+    integral images (four-corner sums) instead of the fused cache."""
+    desc = hog.make_desc(200, 260, channels=3, n_bins=9, cell=cell, win_cells_x=6, win_cells_y=8,
+                         norm=norm)
+    img = inputs.synth_image(200, 260, 3, 600 + cell)
+    tmpl, bias = templates_for(desc, 601 + cell)
+    plan, out = run_gpu(desc, img, tmpl, bias)
     _check_level(plan, out, img, 0, tmpl=tmpl, bias=bias)
