@@ -122,7 +122,8 @@ typedef struct {
     double scale;
     int64_t bins_offset;     /* bytes; bin (x, y) at bins[bins_offset + y*bins_pitch + x] */
     int64_t bins_pitch;      /* bytes */
-    int64_t ii_offset;       /* elements; see hog_integral for the layout */
+    int64_t ii_offset;       /* elements; ii(x, y) of bin n at ii[ii_offset +
+                                n*ii_plane_stride + y*ii_pitch + x] (hog_integral) */
     int64_t ii_pitch;        /* elements between rows, multiple of 64 */
     int64_t ii_plane_stride; /* elements between bins' planes, multiple of 64 */
     int32_t cells_x, cells_y;    /* whole cells: floor(width / cell), ... */
@@ -169,13 +170,14 @@ hog_status hog_bin_map(const hog_plan *plan, const hog_lut *lut, const uint8_t *
 
 /* Eq. 4 + Eq. 5. bins: device, plan layout (as written by hog_bin_map).
  * Writes, for every level and bin n, the integral image
- *   ii[ii_offset + n*ii_plane_stride + (y+1)*ii_pitch + (x+1)]
+ *   ii[ii_offset + n*ii_plane_stride + y*ii_pitch + x]
  *       = #{ (x', y') : x' <= x, y' <= y, bin(x', y') = n }
- * with a zero guard row 0 and guard column 0, i.e. columns 0..width and
- * rows 0..height of each plane (uint32, exact). Elements of a row beyond
- * column width hold unspecified values. As a by-product it caches every
- * cell histogram (Eq. 6, the four-corner sums of the planes it writes) in
- * the workspace for hog_scan_windows. workspace: device, at least
+ * for 0 <= x < width, 0 <= y < height (uint32, exact). Values at x < 0 or
+ * y < 0 are zero by definition and not stored: a rectangle touching row or
+ * column 0 takes them as 0 in the four-corner sum. Elements of a row beyond
+ * column width - 1 hold unspecified values. As a by-product it caches every
+ * 8 x 8-pixel cell histogram (Eq. 6, the four-corner sums of the planes it
+ * writes) in the workspace for hog_scan_windows. workspace: device, at least
  * workspace_bytes, contents on entry ignored. */
 hog_status hog_integral(const hog_plan *plan, const uint8_t *bins, uint32_t *ii,
                         void *workspace, void *stream);
@@ -186,7 +188,8 @@ hog_status hog_integral(const hog_plan *plan, const uint8_t *bins, uint32_t *ii,
  * non-NULL (device, layout as written by hog_integral) the cells are
  * computed from it; if ii is NULL the histograms cached by the last
  * hog_integral call on this plan and workspace are used (Sec. 3.3: areas
- * visited more than once are cached before evaluation).
+ * visited more than once are cached before evaluation); that needs 8-pixel
+ * cells, otherwise ii is required.
  * Window (wx, wy) covers cells [wx, wx+win_cells_x) x [wy, wy+win_cells_y).
  * Its feature f is, for HOG_NORM_RAW, the cell histograms in row-major cell
  * order, f[(cy*win_cells_x + cx)*n_bins + n]; for HOG_NORM_L2, the 2x2-cell

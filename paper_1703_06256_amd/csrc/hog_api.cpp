@@ -351,12 +351,12 @@ extern "C" hog_status hog_plan_create(const hog_plan_desc *desc, hog_plan **out)
         v.bins_pitch = round_up(lw, 64);
         v.bins_off = bins_off;
         bins_off = round_up(bins_off + v.bins_pitch * lh, 256);
-        // Planes: padded column 1 (pixel x = 0) starts a 256-byte line, so
-        // each tile's 64 columns are one aligned line pair; a row has room
-        // for every tile's full 64 columns plus the guard column.
-        v.ii_pitch = (int64_t)hogk::kTile * (v.tiles_x + 1);
-        v.ii_plane = v.ii_pitch * (lh + 1);
-        v.ii_off = round_up(ii_off, 64) + 63;
+        // Planes: ii(x, y) at [y * pitch + x]; every row starts a 256-byte
+        // line and holds every tile's full 64 columns, so each store is whole
+        // lines.
+        v.ii_pitch = (int64_t)hogk::kTile * v.tiles_x;
+        v.ii_plane = v.ii_pitch * lh;
+        v.ii_off = round_up(ii_off, 64);
         ii_off = v.ii_off + v.ii_plane * nb;
         v.score_off = score_off;
         score_off += (int64_t)v.win_x * v.win_y * K;

@@ -388,8 +388,7 @@ __global__ __launch_bounds__(256) void k_int_scan_cols(const Level *__restrict__
 // previous corner row. Their four-corner sum (Eq. 6) is the cell's
 // histogram entry, cached here once per cell (uint16 [n][cy][cx]).
 //
-// Stores are full 64-lane rows; lanes right of the image repeat column w
-// (same values), inside the row pitch.
+// The planes hold ii(x, y) at [y * pitch + x] (Eq. 5, one value per pixel).
 // ---------------------------------------------------------------------------
 template <int NBC, bool CELLS>
 __global__ __launch_bounds__(256) void k_int_emit(const Level *__restrict__ lv,
@@ -414,12 +413,7 @@ __global__ __launch_bounds__(256) void k_int_emit(const Level *__restrict__ lv,
     const int x = tx * kTile + lane;
     const bool xin = x < W;
     const int y0 = ty * kTile, y1 = min(y0 + kTile, H);
-    const uint32_t col4 = (uint32_t)(x + 1) * 4u;  // byte offset of this lane's padded column
-    // The last tile of a tile row also writes the row's last line of 64
-    // columns: padding whose final element is the next row's guard column
-    // (a plane row is kTile * (tiles_x + 1) elements). Every plane line is
-    // thus written whole, never as a partial line.
-    const bool last_tx = tx == v.tiles_x - 1;
+    const uint32_t col4 = (uint32_t)x * 4u;  // byte offset of this lane's column in a plane row
 
     const uint32_t *T = reinterpret_cast<const uint32_t *>(ws + v.ws_t) + ((int64_t)ty * nb + b0) * W1;
     const uint32_t *Eb = reinterpret_cast<const uint32_t *>(ws + v.ws_e) + ((int64_t)tx * nb + b0) * H1;
@@ -447,20 +441,11 @@ __global__ __launch_bounds__(256) void k_int_emit(const Level *__restrict__ lv,
     const int plane4 = (int)(v.ii_plane * 4), pitch4 = (int)(v.ii_pitch * 4);
     const __amdgpu_buffer_rsrc_t isrc =
         buffer_rsrc(ii + v.ii_off + (int64_t)b0 * v.ii_plane, (uint32_t)(NBC * plane4));
-    auto store_row = [&](int j, int r, uint32_t val) {
-        __builtin_amdgcn_raw_buffer_store_b32(val, isrc, (int)col4, j * plane4 + r * pitch4, 0);
-        if (last_tx)
-            __builtin_amdgcn_raw_buffer_store_b32(lane == 63 ? 0u : val, isrc, (int)col4 + 4 * kTile,
-                                                  j * plane4 + r * pitch4, 0);
+    // Whole 256-byte rows: lanes right of the image (x >= w) repeat column
+    // w - 1 inside the row pitch.
+    auto store_row = [&](int j, int y, uint32_t val) {
+        __builtin_amdgcn_raw_buffer_store_b32(val, isrc, (int)col4, j * plane4 + y * pitch4, 0);
     };
-    if (ty == 0) {  // zero guard row (and the plane's first guard element)
-#pragma unroll
-        for (int j = 0; j < NBC; ++j) {
-            store_row(j, 0, 0u);
-            if (tx == 0 && lane == 0)
-                __builtin_amdgcn_raw_buffer_store_b32(0u, isrc, 0, j * plane4, 0);
-        }
-    }
 
     auto do_row = [&](int bin, int y) {
         const int rel = bin - b0;
@@ -474,7 +459,7 @@ __global__ __launch_bounds__(256) void k_int_emit(const Level *__restrict__ lv,
             run[j] += e + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
                                                     __builtin_amdgcn_mbcnt_lo((uint32_t)m, hit ? 1u : 0u));
             lrun[j] += e;
-            store_row(j, r, run[j]);
+            store_row(j, y, run[j]);
         }
     };
     // Padded row r = y + 1 is a row of cell corners when r % 8 == 0. Lane
@@ -549,14 +534,20 @@ __global__ __launch_bounds__(256) void k_cells(const Level *__restrict__ lv,
     const int rel = g - first[l];
     const int cy = rel / v.cells_x, cx = rel % v.cells_x;
     const uint32_t *P = ii + v.ii_off;
-    const int64_t r0 = (int64_t)cy * cell * v.ii_pitch;
-    const int64_t r1 = r0 + (int64_t)cell * v.ii_pitch;
-    const int64_t c0 = (int64_t)cx * cell, c1 = c0 + cell;
+    // Corners: ii at the cell's last row/column and at the row/column just
+    // before it; ii(-1, .) = ii(., -1) = 0.
+    const int64_t y1 = (int64_t)(cy + 1) * cell - 1, x1 = (int64_t)(cx + 1) * cell - 1;
+    const int64_t y0 = y1 - cell, x0 = x1 - cell;
+    const int64_t r1 = y1 * v.ii_pitch, r0 = y0 * v.ii_pitch;
     uint16_t *cache = reinterpret_cast<uint16_t *>(ws + v.ws_cache);
     uint32_t *ch = cell_hist ? cell_hist + v.cell_off + (int64_t)rel * nb : nullptr;
     for (int n = 0; n < nb; ++n) {
         const uint32_t *p = P + (int64_t)n * v.ii_plane;
-        const uint32_t h = p[r1 + c1] + p[r0 + c0] - p[r0 + c1] - p[r1 + c0];
+        const uint32_t a = p[r1 + x1];
+        const uint32_t b = y0 >= 0 ? p[r0 + x1] : 0u;
+        const uint32_t c = x0 >= 0 ? p[r1 + x0] : 0u;
+        const uint32_t d = (y0 >= 0 && x0 >= 0) ? p[r0 + x0] : 0u;
+        const uint32_t h = a - b - c + d;
         cache[cache_index(v, n, cy, cx)] = (uint16_t)h;
         if (ch) ch[n] = h;
     }

@@ -296,12 +296,12 @@ def level_bins(plan: Plan, bins_host: np.ndarray, l: int) -> np.ndarray:
 
 
 def level_planes(plan: Plan, ii_host: np.ndarray, l: int) -> np.ndarray:
-    """uint32[n_bins][h+1][w+1] of level l."""
+    """uint32[n_bins][h][w] of level l: [n][y][x] = ii_n(x, y)."""
     li = plan.levels[l]
     nb = plan.desc.n_bins
     a = ii_host.view(np.uint32)[li.ii_offset: li.ii_offset + li.ii_plane_stride * nb]
-    a = a.reshape(nb, li.ii_plane_stride)[:, :li.ii_pitch * (li.height + 1)]
-    return a.reshape(nb, li.height + 1, li.ii_pitch)[:, :, :li.width + 1]
+    a = a.reshape(nb, li.ii_plane_stride)[:, :li.ii_pitch * li.height]
+    return a.reshape(nb, li.height, li.ii_pitch)[:, :, :li.width]
 
 
 def level_scores(plan: Plan, scores_host: np.ndarray, l: int) -> np.ndarray:
