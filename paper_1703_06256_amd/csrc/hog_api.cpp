@@ -278,27 +278,57 @@ extern "C" hog_status hog_plan_create(const hog_plan_desc *desc, hog_plan **out)
                         ? sp.win_cells_x * sp.win_cells_y * nb
                         : (sp.win_cells_x - 1) * (sp.win_cells_y - 1) * 4 * nb;
 
-    // Scorer tile: windows per workgroup (<= 256 threads) and LDS staging.
+    // Scorer. L2 blocks go to the matrix-core scorer: a workgroup covers
+    // 32 - (nbx - 1) window columns and th window rows, th chosen so that a
+    // thread owns at most 8 (window, template) accumulators. Otherwise the
+    // vector scorer: tw x th windows per workgroup (<= 256 threads) with the
+    // cells they use staged in LDS.
     const int nbp = (int)round_up(nb, 4);
-    int best_tw = 0, best_th = 0;
+    int best_tw = 0, best_th = 0, mfma_ks = 0;
     int64_t best_lds = 0;
-    double best_cost = 1e30;
-    for (int tw = 1; tw <= 64; tw *= 2)
-        for (int th = 1; tw * th <= 256; th *= 2) {
-            const int64_t CW = tw + sp.win_cells_x - 1, CH = th + sp.win_cells_y - 1;
-            const int64_t lds = CH * CW * nbp * 4 + (CH - 1) * (CW - 1) * 4;
-            if (lds > 65536) continue;
-            const double cost = (double)(CH * CW) / (tw * th) + (tw * th < 64 ? 4.0 : 0.0);
-            if (cost < best_cost - 1e-9 || (std::fabs(cost - best_cost) <= 1e-9 && tw * th > best_tw * best_th)) {
-                best_cost = cost;
-                best_tw = tw;
-                best_th = th;
-                best_lds = lds;
+    if (sp.norm == HOG_NORM_L2 && sp.win_cells_x - 1 <= 16) {
+        const int nbp_set[] = {4, 8, 12, 16, 20, 32};
+        for (int q : nbp_set)
+            if (q >= nb) { mfma_ks = q; break; }
+        const int tw = 32 - (sp.win_cells_x - 2);
+#ifndef HOG_SCORE_TH
+#define HOG_SCORE_TH 16
+#endif
+        int th = HOG_SCORE_TH;
+        while (th > 1 && (int64_t)tw * th * d.n_templates > 2 * 256) th /= 2;
+        if ((int64_t)tw * th * d.n_templates > 2 * 256) mfma_ks = 0;  // too many templates
+        // the blocked cell cache is indexed with 32-bit offsets
+        if ((int64_t)nb * ((d.height / sp.cell + 7) / 8) * ((d.width / sp.cell + 7) / 8) * 64 >= ((int64_t)1 << 31))
+            mfma_ks = 0;
+        // LDS: the workgroup's cell rows, block norms and U of one block row.
+        const int64_t np = (int64_t)(sp.win_cells_x - 1) * (sp.win_cells_y - 1);
+        const int64_t ntiles = (np * d.n_templates + 31) / 32;
+        const int64_t lds = (int64_t)(th + sp.win_cells_y - 1) * 33 * mfma_ks * 2 +
+                            (int64_t)(th + sp.win_cells_y - 2) * 32 * 4 +
+                            std::max<int64_t>(32 * (ntiles * 32 + 1), (int64_t)(th + sp.win_cells_y - 1) * 33) * 4;
+        if (lds > 64 * 1024) mfma_ks = 0;
+        best_tw = tw;
+        best_th = th;
+    }
+    if (mfma_ks == 0) {
+        double best_cost = 1e30;
+        for (int tw = 1; tw <= 64; tw *= 2)
+            for (int th = 1; tw * th <= 256; th *= 2) {
+                const int64_t CW = tw + sp.win_cells_x - 1, CH = th + sp.win_cells_y - 1;
+                const int64_t lds = CH * CW * nbp * 4 + (CH - 1) * (CW - 1) * 4;
+                if (lds > 65536) continue;
+                const double cost = (double)(CH * CW) / (tw * th) + (tw * th < 64 ? 4.0 : 0.0);
+                if (cost < best_cost - 1e-9 || (std::fabs(cost - best_cost) <= 1e-9 && tw * th > best_tw * best_th)) {
+                    best_cost = cost;
+                    best_tw = tw;
+                    best_th = th;
+                    best_lds = lds;
+                }
             }
-        }
-    if (best_tw == 0)
-        return fail(HOG_E_INVALID, "window of %dx%d cells with %d bins does not fit the scorer's LDS",
-                    sp.win_cells_x, sp.win_cells_y, nb);
+        if (best_tw == 0)
+            return fail(HOG_E_INVALID, "window of %dx%d cells with %d bins does not fit the scorer's LDS",
+                        sp.win_cells_x, sp.win_cells_y, nb);
+    }
 
     hog_plan *p = new (std::nothrow) hog_plan;
     if (!p) return fail(HOG_E_NOMEM, "host allocation failed");
@@ -495,6 +525,7 @@ extern "C" hog_status hog_plan_create(const hog_plan_desc *desc, hog_plan **out)
     pd.st_tw = best_tw;
     pd.st_th = best_th;
     pd.st_lds_bytes = (int32_t)best_lds;
+    pd.mfma_ks = mfma_ks;
     pd.cell_stride = nbp;
     pd.bin_chunk = chunk_final;  // bins per wave; a last, smaller chunk takes the rest
     pd.n_chunks = (nb + chunk_final - 1) / chunk_final;

@@ -71,6 +71,7 @@ struct PlanDev {
     float eps;
     int32_t feat_dim;
     int32_t st_tw, st_th;      // scorer tile (windows)
+    int32_t mfma_ks;           // > 0: matrix-core scorer, bins padded to this multiple of 4
     int32_t st_lds_bytes;      // scorer dynamic LDS
     int32_t cell_stride;       // floats per staged cell in the scorer's LDS
     int32_t bin_chunk;         // bins per integral wave

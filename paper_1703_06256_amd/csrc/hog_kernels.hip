@@ -15,6 +15,8 @@
 //   k_block_features  (optional output) normalised block vectors
 #include "hog_internal.h"
 
+#define HOG_MAX_BINS_K 64
+
 #include <algorithm>
 
 namespace hogk {
@@ -221,70 +223,79 @@ __device__ __forceinline__ void stage_bin_tile(uint8_t *tb, __amdgpu_buffer_rsrc
 // Pass 1 (k_int_reduce): per tile, the count of each bin in each tile row
 // (a ballot per bin) and in each tile column (registers).
 // ---------------------------------------------------------------------------
-template <int NBC>
-__global__ __launch_bounds__(256) void k_int_reduce(const Level *__restrict__ lv,
-                                                    const int32_t *__restrict__ first, int n_levels,
-                                                    int nb, int b_first, int n_chunk,
-                                                    const uint8_t *__restrict__ bins,
-                                                    uint8_t *__restrict__ ws)
+__global__ __launch_bounds__(64) void k_int_reduce(const Level *__restrict__ lv,
+                                                   const int32_t *__restrict__ first, int n_levels,
+                                                   int nb, const uint8_t *__restrict__ bins,
+                                                   uint8_t *__restrict__ ws)
 {
-    // Consecutive waves take the chunks of one tile.
-    const int gw = (int)blockIdx.x * 4 + wave_id_in_block();
-    const int lane = threadIdx.x & 63;
-    const int tile = gw / n_chunk;
+    // One wave per tile, every bin at once. LDS: the tile's bins (row stride
+    // kRedStride bytes, 17 dwords, so lane-per-row reads hit distinct banks),
+    // then per-lane histograms colh[n][lane] and rowh[n][lane]: each lane
+    // only ever adds to its own slots.
+    constexpr int kRedStride = 68;
+    extern __shared__ __attribute__((aligned(16))) uint32_t red_smem[];
+    const int tile = (int)blockIdx.x;
+    const int lane = (int)threadIdx.x;
     if (tile >= first[n_levels]) return;
     const int l = find_level(first, n_levels, tile);
     const Level &v = lv[l];
     const int t = tile - first[l];
     const int tx = t % v.tiles_x, ty = t / v.tiles_x;
-    const int b0 = b_first + (gw - tile * n_chunk) * NBC;
+    uint8_t *tb = reinterpret_cast<uint8_t *>(red_smem);
+    uint32_t *colh = red_smem + kTile * kRedStride / 4;
+    uint32_t *rowh = colh + nb * 64;
+    for (int n = 0; n < nb; ++n) {
+        colh[n * 64 + lane] = 0u;
+        rowh[n * 64 + lane] = 0u;
+    }
+    {
+        typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+        const __amdgpu_buffer_rsrc_t bsrc = buffer_rsrc(bins + v.bins_off, (uint32_t)(v.bins_pitch * v.h));
+        const int bpitch = (int)v.bins_pitch;
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            const int k = lane + 64 * m;
+            const int row = k >> 2, seg = k & 3;
+            const u32x4 d = __builtin_amdgcn_raw_buffer_load_b128(bsrc, tx * kTile + 16 * seg,
+                                                                  (ty * kTile + row) * bpitch, 0);
+            uint32_t *dst = reinterpret_cast<uint32_t *>(tb + row * kRedStride + 16 * seg);
+            dst[0] = d[0];
+            dst[1] = d[1];
+            dst[2] = d[2];
+            dst[3] = d[3];
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    const int y0 = ty * kTile, nrows = min(kTile, v.h - y0);
     const int x = tx * kTile + lane;
     const bool xin = x < v.w;
-    const int y0 = ty * kTile, y1 = min(y0 + kTile, v.h);
-    __shared__ uint8_t tiles[4][kTile * kTile];
-    uint8_t *tb = tiles[wave_id_in_block()];
-    stage_bin_tile(tb, buffer_rsrc(bins + v.bins_off, (uint32_t)(v.bins_pitch * v.h)),
-                   (int)v.bins_pitch, tx, y0, lane);
-
-    uint32_t colcnt[NBC], rowcnt[NBC];
-#pragma unroll
-    for (int j = 0; j < NBC; ++j) colcnt[j] = rowcnt[j] = 0;
-
-    auto count_row = [&](int bin, int rr) {
-        const int rel = bin - b0;
-#pragma unroll
-        for (int j = 0; j < NBC; ++j) {
-            const bool hit = rel == j;
-            colcnt[j] += hit ? 1u : 0u;
-            const uint32_t cnt = (uint32_t)__popcll(__ballot(hit));
-            rowcnt[j] = (lane == rr) ? cnt : rowcnt[j];
-        }
-    };
-    const int nrows = y1 - y0;
-    int rr = 0;
-    for (; rr + kRowBatch <= nrows; rr += kRowBatch) {
-        int bb[kRowBatch];
-#pragma unroll
-        for (int i = 0; i < kRowBatch; ++i) bb[i] = tb[(rr + i) * kTile + lane];
-#pragma unroll
-        for (int i = 0; i < kRowBatch; ++i) count_row(xin ? bb[i] : kNoBin, rr + i);
-    }
-    for (; rr < nrows; ++rr) {
-        const int raw = tb[rr * kTile + lane];
-        count_row(xin ? raw : kNoBin, rr);
-    }
-
-    // rowtot [tx][n][h+1] (padded rows), lane = row of the tile.
-    if (y0 + lane < y1) {
-        uint8_t *rowtot = ws + v.ws_rowtot + ((int64_t)tx * nb + b0) * (v.h + 1) + (y0 + 1 + lane);
-#pragma unroll
-        for (int j = 0; j < NBC; ++j) rowtot[(int64_t)j * (v.h + 1)] = (uint8_t)rowcnt[j];
-    }
-    // coltot [ty][n][w+1] (padded columns).
+    const int ncols = min(kTile, v.w - tx * kTile);
+    // Column counts: lane = column.
     if (xin) {
-        uint8_t *coltot = ws + v.ws_coltot + ((int64_t)ty * nb + b0) * (v.w + 1) + x + 1;
+        for (int r = 0; r < nrows; ++r) {
+            const int b = tb[r * kRedStride + lane];
+            if (b < nb) atomicAdd(&colh[b * 64 + lane], 1u);
+        }
+    }
+    // Row counts: lane = row.
+    if (lane < nrows) {
+        const uint32_t *rp = reinterpret_cast<const uint32_t *>(tb + lane * kRedStride);
+        for (int k = 0; k < kTile / 4; ++k) {
+            const uint32_t d = rp[k];
 #pragma unroll
-        for (int j = 0; j < NBC; ++j) coltot[(int64_t)j * (v.w + 1)] = (uint8_t)colcnt[j];
+            for (int e = 0; e < 4; ++e) {
+                const int b = (int)((d >> (8 * e)) & 255u);
+                if (4 * k + e < ncols && b < nb) atomicAdd(&rowh[b * 64 + lane], 1u);
+            }
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    // rowtot [tx][n][h+1] (padded rows), lane = row; coltot [ty][n][w+1] (padded cols).
+    uint8_t *rowtot = ws + v.ws_rowtot + (int64_t)tx * nb * (v.h + 1) + y0 + 1 + lane;
+    uint8_t *coltot = ws + v.ws_coltot + (int64_t)ty * nb * (v.w + 1) + x + 1;
+    for (int n = 0; n < nb; ++n) {
+        if (lane < nrows) rowtot[(int64_t)n * (v.h + 1)] = (uint8_t)rowh[n * 64 + lane];
+        if (xin) coltot[(int64_t)n * (v.w + 1)] = (uint8_t)colh[n * 64 + lane];
     }
 }
 
@@ -729,6 +740,222 @@ __global__ __launch_bounds__(256) void k_score(const Level *__restrict__ lv,
     }
 }
 
+// ---------------------------------------------------------------------------
+// Sec. 3.1 / Fig. 4 + Sec. 4 on the matrix cores (L2 blocks of 2 x 2 cells).
+//
+// The score of window (wy, wx) is bias + sum over its block positions
+// p = (by, bx) of inv(B) * U(B, p), B = (wy + by, wx + bx), where inv(B) is
+// the block's 1/sqrt(|v|^2 + eps^2) and U(B, p) = T[p] . v(B) is the dot
+// product of the block's 4*nb integer counts with the template's weights at
+// position p. Per block row, U over 32 blocks x every position is one GEMM
+// (blocks x features) . (features x positions) on v_mfma_f32_32x32x8f16.
+// The counts are exact in fp16; each weight is split into fp16 hi + lo
+// parts after scaling its column by a power of two (max |T| of the column
+// into [2^14, 2^15)), so hi + lo carries ~22 bits; hi and lo go to separate
+// FP32 accumulators (72 products each for nb = 18).
+//
+// Cells are staged in LDS with their bins padded to NBP (a multiple of 4),
+// so a block's feature k' = c * NBP + n (cell c of the block, bin n; zero
+// for n >= nb) and an A fragment (4 consecutive k') is one 8-byte read of
+// one cell. A workgroup covers kMfmaM - (nbx - 1) window columns and th
+// window rows and walks the block rows. Per block row: one barrier, the
+// GEMM (one 32-position N-tile per wave), U * scale * inv into LDS, a
+// second barrier, and each thread adds, for each window it owns, the nbx
+// terms of this block row (an FP32 sum) into an FP64 accumulator; then
+// threads 0..32 store the next cell row (fetched one row ahead), and from
+// the cells' squared norms the block norms of the next block row.
+// ---------------------------------------------------------------------------
+constexpr int kMfmaM = 32;
+constexpr int kMfmaOwn = 2;  // window x template items per thread
+
+struct MfmaArgs {
+    int nb, nbx, nby, np, k, ntiles, th, tw, dim, ustride;
+    float eps;
+};
+
+typedef _Float16 half4_t __attribute__((ext_vector_type(4)));
+typedef float float16_t __attribute__((ext_vector_type(16)));
+
+template <int NBP>
+__global__ __launch_bounds__(256) void k_score_mfma(const Level *__restrict__ lv,
+                                                    const int32_t *__restrict__ first, int n_levels,
+                                                    MfmaArgs a, const uint8_t *__restrict__ ws,
+                                                    const float *__restrict__ tmpl,
+                                                    const float *__restrict__ bias,
+                                                    float *__restrict__ scores)
+{
+    constexpr int KS = NBP / 2;  // 4 * NBP features, 8 per MFMA step
+    constexpr int kRowHalves = (kMfmaM + 1) * NBP;
+    // Dynamic LDS: cell rows [n_rows][33][NBP] (fp16), block norms
+    // [n_rows - 1][32] (float), U of one block row [32][ustride] (float).
+    extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
+
+    const int wg = (int)blockIdx.x;
+    if (wg >= first[n_levels]) return;
+    const int l = find_level(first, n_levels, wg);
+    const Level &v = lv[l];
+    const int rel = wg - first[l];
+    const int sx = rel % v.st_x, sy = rel / v.st_x;
+    const int wx0 = sx * a.tw, wy0 = sy * a.th;
+    const int BH = v.cells_y - 1;
+    const int Y0 = wy0, Y1 = min(wy0 + a.th + a.nby - 1, BH);  // block rows [Y0, Y1)
+    const int n_rows = Y1 - Y0 + 1;                            // cell rows [Y0, Y1]
+    const int tid = (int)threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int nb = a.nb;
+    _Float16 *crow = reinterpret_cast<_Float16 *>(smem);
+    float *invb = reinterpret_cast<float *>(smem + (size_t)(a.th + a.nby) * kRowHalves * 2);
+    float *ulds = invb + (a.th + a.nby - 1) * kMfmaM;
+
+    // Stage the cell rows: 16-byte loads of 8 consecutive cells of one bin
+    // from the blocked cache, spread to the cells' padded bin slots.
+    {
+        typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
+        const uint16_t *cache = reinterpret_cast<const uint16_t *>(ws + v.ws_cache);
+        const int seg0 = wx0 >> 3;
+        const int n_seg = ((wx0 + kMfmaM) >> 3) - seg0 + 1;
+        const int n_loads = n_rows * NBP * n_seg;
+        for (int q = tid; q < n_loads; q += 256) {
+            const int sg = q % n_seg, rest = q / n_seg;
+            const int n = rest % NBP, r = rest / NBP;
+            const int cy = Y0 + r, bx8 = seg0 + sg;
+            u16x8 vals = {0, 0, 0, 0, 0, 0, 0, 0};
+            if (n < nb && cy < v.cells_y && bx8 < v.cbx)
+                vals = *reinterpret_cast<const u16x8 *>(
+                    cache + (((int64_t)n * v.cby + (cy >> 3)) * v.cbx + bx8) * 64 + (cy & 7) * 8);
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int cx = 8 * bx8 + e, i = cx - wx0;
+                if (i >= 0 && i <= kMfmaM)
+                    crow[(size_t)r * kRowHalves + i * NBP + n] = (cx < v.cells_x) ? (_Float16)(float)vals[e]
+                                                                               : (_Float16)0.f;
+            }
+        }
+    }
+    __syncthreads();
+    // Block norms from the cells' squared norms (sums of squared integer
+    // counts, exact in FP32): first per cell, then four cells per block.
+    float *cellsq = ulds;  // scratch until the first block row (the launch sizes it)
+    for (int q = tid; q < n_rows * (kMfmaM + 1); q += 256) {
+        const _Float16 *cp = crow + (size_t)(q / (kMfmaM + 1)) * kRowHalves + (q % (kMfmaM + 1)) * NBP;
+        float ss = 0.f;
+#pragma unroll
+        for (int n = 0; n < NBP; ++n) ss = fmaf((float)cp[n], (float)cp[n], ss);
+        cellsq[q] = ss;
+    }
+    __syncthreads();
+    for (int q = tid; q < (n_rows - 1) * kMfmaM; q += 256) {
+        const int i = q % kMfmaM, r = q / kMfmaM;
+        const float *c0 = cellsq + r * (kMfmaM + 1) + i;
+        const float ss = (c0[0] + c0[1]) + (c0[kMfmaM + 1] + c0[kMfmaM + 2]);
+        invb[q] = inv_block_norm(ss, a.eps);
+    }
+
+    // B fragments of N-tile t: column gn = 32 t + lane % 32 is (template k,
+    // position p), gn = k * np + p; rows k' = 8 s + 4 (lane / 32) + i.
+    half4_t bh[KS], bl[KS];
+    float cscale = 1.f;
+    auto load_b = [&](int t) {
+        const int gn = 32 * t + (lane & 31);
+        const int kk = gn / a.np, p = gn - kk * a.np;
+        const bool colok = gn < a.np * a.k;
+        const float *tp = tmpl + (int64_t)kk * a.dim + (int64_t)p * 4 * nb;
+        float vals[KS][4];
+        float mx = 0.f;
+#pragma unroll
+        for (int s2 = 0; s2 < KS; ++s2)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int kp = 8 * s2 + 4 * (lane >> 5) + i;
+                const int c = kp / NBP, n = kp % NBP;
+                const float val = (colok && n < nb) ? tp[c * nb + n] : 0.f;
+                vals[s2][i] = val;
+                mx = fmaxf(mx, fabsf(val));
+            }
+        mx = fmaxf(mx, __shfl_xor(mx, 32));
+        int ex = 0;
+        if (mx > 0.f) (void)frexpf(mx, &ex);  // mx = f 2^ex, f in [0.5, 1)
+        const int e = mx > 0.f ? 15 - ex : 0;
+        cscale = ldexpf(1.f, -e);
+#pragma unroll
+        for (int s2 = 0; s2 < KS; ++s2)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const float sv = ldexpf(vals[s2][i], e);
+                const _Float16 hi = (_Float16)sv;
+                bh[s2][i] = hi;
+                bl[s2][i] = (_Float16)(sv - (float)hi);
+            }
+    };
+    const bool resident = a.ntiles <= 4;
+    if (resident && wave < a.ntiles) load_b(wave);
+
+    // A fragment of step s: cell c = k' / NBP of block (lane % 32), bins
+    // n0..n0+3, k' = 8 s + 4 (lane / 32).
+    const int a_lane = (lane & 31) * NBP, a_half = 4 * (lane >> 5);
+
+    // Windows owned by this thread: item = (window, template), window-major.
+    double acc[kMfmaOwn];
+    int item_base[kMfmaOwn], item_wy[kMfmaOwn];
+    const int n_items = a.tw * a.th * a.k;
+#pragma unroll
+    for (int m = 0; m < kMfmaOwn; ++m) {
+        acc[m] = 0.0;
+        const int item = tid + 256 * m;
+        const int kk = item % a.k, w = item / a.k;
+        const int wxl = w % a.tw, wyl = w / a.tw;
+        item_base[m] = wxl * a.ustride + kk * a.np;
+        item_wy[m] = item < n_items ? wy0 + wyl : -(1 << 30);
+    }
+
+    for (int Y = Y0; Y < Y1; ++Y) {
+        __syncthreads();  // norms ready; U of the previous row consumed
+        const _Float16 *c0 = crow + (size_t)(Y - Y0) * kRowHalves;
+        const float *iv = invb + (Y - Y0) * kMfmaM;
+        for (int t = wave; t < a.ntiles; t += 4) {
+            if (!resident) load_b(t);
+            float16_t ah = {}, al = {};
+#pragma unroll
+            for (int s2 = 0; s2 < KS; ++s2) {
+                const int kp = 8 * s2 + a_half;
+                const int c = kp / NBP, n0 = kp - c * NBP;
+                const half4_t av = *reinterpret_cast<const half4_t *>(
+                    c0 + (c >> 1) * kRowHalves + a_lane + (c & 1) * NBP + n0);
+                ah = __builtin_amdgcn_mfma_f32_32x32x8f16(av, bh[s2], ah, 0, 0, 0);
+                al = __builtin_amdgcn_mfma_f32_32x32x8f16(av, bl[s2], al, 0, 0, 0);
+            }
+            const int gn = 32 * t + (lane & 31);
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int i = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                ulds[i * a.ustride + gn] = (ah[r] + al[r]) * cscale * iv[i];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < kMfmaOwn; ++m) {
+            const int by = Y - item_wy[m];
+            if (by >= 0 && by < a.nby) {
+                const float *u = ulds + item_base[m] + by * a.nbx;
+                float sum = 0.f;
+                for (int bx = 0; bx < a.nbx; ++bx) sum += u[bx * (a.ustride + 1)];
+                acc[m] += (double)sum;
+            }
+        }
+    }
+#pragma unroll
+    for (int m = 0; m < kMfmaOwn; ++m) {
+        const int item = tid + 256 * m;
+        if (item < n_items) {
+            const int kk = item % a.k, w = item / a.k;
+            const int wx = wx0 + w % a.tw, wy = wy0 + w / a.tw;
+            if (wx < v.win_x && wy < v.win_y)
+                scores[v.score_off + ((int64_t)wy * v.win_x + wx) * a.k + kk] =
+                    (float)((double)bias[kk] + acc[m]);
+        }
+    }
+}
+
 // Optional output: every normalised 2x2 block, f = h / sqrt(|v|^2 + eps^2).
 __global__ __launch_bounds__(256) void k_block_features(const Level *__restrict__ lv,
                                                         const int32_t *__restrict__ first,
@@ -813,15 +1040,9 @@ hipError_t launch_int_reduce(const PlanDev &p, const uint8_t *bins, uint8_t *ws,
 {
     const int64_t tiles = p.total[KB_ITILE];
     if (tiles == 0) return hipSuccess;
-    const int full = p.n_bins / p.bin_chunk, rem = p.n_bins % p.bin_chunk;
-    const dim3 grid(blocks_for(tiles * full, 4));
-    HOG_CHUNK_DISPATCH(k_int_reduce, p.bin_chunk, grid, dim3(256), 0, stream, p.levels,
-                       first_of(p, KB_ITILE), p.n_levels, p.n_bins, 0, full, bins, ws);
-    if (rem) {
-        const dim3 g1(blocks_for(tiles, 4));
-        HOG_CHUNK_DISPATCH(k_int_reduce, rem, g1, dim3(256), 0, stream, p.levels,
-                           first_of(p, KB_ITILE), p.n_levels, p.n_bins, full * p.bin_chunk, 1, bins, ws);
-    }
+    const size_t lds = (size_t)kTile * 68 + (size_t)p.n_bins * 64 * 4 * 2;
+    hipLaunchKernelGGL(k_int_reduce, dim3((unsigned)tiles), dim3(64), lds, stream, p.levels,
+                       first_of(p, KB_ITILE), p.n_levels, p.n_bins, bins, ws);
     return hipGetLastError();
 }
 
@@ -905,6 +1126,35 @@ hipError_t launch_score(const PlanDev &p, const uint8_t *ws, const float *tmpl, 
 {
     const int64_t n = p.total[KB_STILE];
     if (n == 0) return hipSuccess;
+    const dim3 grid((unsigned)n), block(256);
+    const int32_t *f = first_of(p, KB_STILE);
+    if (p.mfma_ks > 0) {
+        MfmaArgs m;
+        m.nb = p.n_bins;
+        m.nbx = p.win_cells_x - 1;
+        m.nby = p.win_cells_y - 1;
+        m.np = m.nbx * m.nby;
+        m.k = p.n_templates;
+        m.ntiles = (m.np * m.k + 31) / 32;
+        m.th = p.st_th;
+        m.tw = p.st_tw;
+        m.dim = p.feat_dim;
+        m.ustride = m.ntiles * 32 + 1;
+        m.eps = p.eps;
+        const size_t u_floats = std::max<size_t>((size_t)kMfmaM * m.ustride, (size_t)(m.th + m.nby) * (kMfmaM + 1));
+        const size_t lds = (size_t)(m.th + m.nby) * (kMfmaM + 1) * p.mfma_ks * 2 +
+                           (size_t)(m.th + m.nby - 1) * kMfmaM * 4 + u_floats * 4;
+        switch (p.mfma_ks) {
+        case 4: hipLaunchKernelGGL(k_score_mfma<4>, grid, block, lds, stream, p.levels, f, p.n_levels, m, ws, tmpl, bias, scores); break;
+        case 8: hipLaunchKernelGGL(k_score_mfma<8>, grid, block, lds, stream, p.levels, f, p.n_levels, m, ws, tmpl, bias, scores); break;
+        case 12: hipLaunchKernelGGL(k_score_mfma<12>, grid, block, lds, stream, p.levels, f, p.n_levels, m, ws, tmpl, bias, scores); break;
+        case 16: hipLaunchKernelGGL(k_score_mfma<16>, grid, block, lds, stream, p.levels, f, p.n_levels, m, ws, tmpl, bias, scores); break;
+        case 20: hipLaunchKernelGGL(k_score_mfma<20>, grid, block, lds, stream, p.levels, f, p.n_levels, m, ws, tmpl, bias, scores); break;
+        case 32: hipLaunchKernelGGL(k_score_mfma<32>, grid, block, lds, stream, p.levels, f, p.n_levels, m, ws, tmpl, bias, scores); break;
+        default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
     ScoreArgs a;
     a.nb = p.n_bins;
     a.wcx = p.win_cells_x;
@@ -916,9 +1166,7 @@ hipError_t launch_score(const PlanDev &p, const uint8_t *ws, const float *tmpl, 
     a.th = p.st_th;
     a.nbp = p.cell_stride;
     a.eps = p.eps;
-    const dim3 grid((unsigned)n), block(256);
     const size_t lds = (size_t)p.st_lds_bytes;
-    const int32_t *f = first_of(p, KB_STILE);
     const bool w8 = p.win_cells_x == 8 && p.norm == 1;
     if (w8 && p.n_bins == 8)
         hipLaunchKernelGGL((k_score<8, 8>), grid, block, lds, stream, p.levels, f, p.n_levels, a,

@@ -182,3 +182,27 @@ def test_other_cell_sizes_from_planes(cell, norm):
     tmpl, bias = templates_for(desc, 601 + cell)
     plan, out = run_gpu(desc, img, tmpl, bias)
     _check_level(plan, out, img, 0, tmpl=tmpl, bias=bias)
+
+
+@pytest.mark.parametrize("k", [2, 3])
+def test_l2_several_templates(k):
+    """Several templates on the matrix-core scorer (template weights reloaded
+    per block row when they do not stay in registers), with a bias."""
+    desc = hog.make_desc(300, 280, channels=3, n_bins=18, n_templates=k, norm=hog.HOG_NORM_L2)
+    img = inputs.synth_image(300, 280, 3, 700 + k)
+    tmpl, _ = templates_for(desc, 701 + k)
+    bias = np.linspace(-1.0, 2.0, k).astype(np.float32)
+    plan, out = run_gpu(desc, img, tmpl, bias)
+    _check_level(plan, out, img, 0, tmpl=tmpl, bias=bias)
+
+
+def test_l2_scores_with_extreme_template_scales():
+    """Templates whose values span many orders of magnitude (per-column power
+    of two scaling before the fp16 split) still meet the tolerance."""
+    desc = hog.make_desc(260, 300, channels=3, n_bins=9, norm=hog.HOG_NORM_L2)
+    img = inputs.synth_image(260, 300, 3, 808)
+    tmpl, bias = templates_for(desc, 809)
+    rng = np.random.default_rng(5)
+    tmpl = (tmpl * np.float32(10.0) ** rng.integers(-20, 20, tmpl.shape)).astype(np.float32)
+    plan, out = run_gpu(desc, img, tmpl, bias)
+    _check_level(plan, out, img, 0, tmpl=tmpl, bias=bias)
