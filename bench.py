@@ -15,8 +15,10 @@ and the CPU oracle timed on this host over one full step.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -40,6 +42,29 @@ WORKLOADS = {
                          norm=0, seed=1000, tseed=9000),
 }
 KERNELS = ("bin_map", "integral_reduce", "integral_scan", "integral_emit", "cells", "score")
+
+
+def kernel_sources_sha256():
+    h = hashlib.sha256()
+    for f in ("hog_kernels.hip", "hog_internal.h"):
+        with open(os.path.join(ROOT, "paper_1703_06256_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload):
+    """HBM bytes per integral_emit launch from the committed FETCH_SIZE /
+    WRITE_SIZE summary of this workload (copy-calibrated), or None when there
+    is none or the kernel sources have changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"hbm_traffic_{workload}.txt")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    h = re.search(r"kernel sources sha256 \(hog_kernels.hip \+ hog_internal.h\): ([0-9a-f]{64})", text)
+    t = re.search(r"integral_emit traffic per launch: (\d+) bytes", text)
+    if not h or not t or h.group(1) != kernel_sources_sha256():
+        return None
+    return int(t.group(1))
 
 
 def cpu_baseline(wl, desc, tmpl, bias):
@@ -159,7 +184,7 @@ def main():
     achieved = emit_bytes / (emit_us * 1e-6) / 1e9
     roofline = dict(bound="hbm", kernel="integral_emit", achieved=round(achieved, 1),
                     peak=HBM_PEAK_GBS, unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4),
-                    traffic=None,
+                    traffic=measured_traffic(args.workload),
                     algorithmic_bytes_per_launch=emit_bytes)
 
     if args.copy_calibration:

@@ -1018,24 +1018,6 @@ hipError_t launch_bin_map(const PlanDev &p, const uint8_t *lut_half, const uint8
     return hipGetLastError();
 }
 
-// One launch per chunk size: the full chunks of p.bin_chunk bins, then, if
-// n_bins is not a multiple of it, one chunk with the remaining bins.
-#define HOG_CHUNK_CASE(KERNEL, NBC, ...) \
-    case NBC: hipLaunchKernelGGL(KERNEL<NBC>, __VA_ARGS__); break;
-#define HOG_CHUNK_DISPATCH(KERNEL, CHUNK, ...)          \
-    switch (CHUNK) {                                    \
-        HOG_CHUNK_CASE(KERNEL, 1, __VA_ARGS__)          \
-        HOG_CHUNK_CASE(KERNEL, 2, __VA_ARGS__)          \
-        HOG_CHUNK_CASE(KERNEL, 3, __VA_ARGS__)          \
-        HOG_CHUNK_CASE(KERNEL, 4, __VA_ARGS__)          \
-        HOG_CHUNK_CASE(KERNEL, 5, __VA_ARGS__)          \
-        HOG_CHUNK_CASE(KERNEL, 6, __VA_ARGS__)          \
-        HOG_CHUNK_CASE(KERNEL, 7, __VA_ARGS__)          \
-        HOG_CHUNK_CASE(KERNEL, 8, __VA_ARGS__)          \
-        HOG_CHUNK_CASE(KERNEL, 9, __VA_ARGS__)          \
-    default: return hipErrorInvalidValue;               \
-    }
-
 hipError_t launch_int_reduce(const PlanDev &p, const uint8_t *bins, uint8_t *ws, hipStream_t stream)
 {
     const int64_t tiles = p.total[KB_ITILE];
