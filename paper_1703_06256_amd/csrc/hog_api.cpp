@@ -278,37 +278,21 @@ extern "C" hog_status hog_plan_create(const hog_plan_desc *desc, hog_plan **out)
                         ? sp.win_cells_x * sp.win_cells_y * nb
                         : (sp.win_cells_x - 1) * (sp.win_cells_y - 1) * 4 * nb;
 
-    // Scorer. L2 blocks go to the matrix-core scorer: a workgroup covers
-    // 32 - (nbx - 1) window columns and th window rows, th chosen so that a
-    // thread owns at most 8 (window, template) accumulators. Otherwise the
-    // vector scorer: tw x th windows per workgroup (<= 256 threads) with the
-    // cells they use staged in LDS.
+    // Scorer. L2 blocks of 2 x 2 cells in windows 8 cells wide and at most 17 high, with
+    // at most 20 bins go to the matrix-core scorer: one wave per strip of 16
+    // window columns and kStripTH window rows (and per template). Otherwise
+    // the vector scorer: tw x th windows per workgroup (<= 256 threads) with
+    // the cells they use staged in LDS.
     const int nbp = (int)round_up(nb, 4);
     int best_tw = 0, best_th = 0, mfma_ks = 0;
     int64_t best_lds = 0;
-    if (sp.norm == HOG_NORM_L2 && sp.win_cells_x - 1 <= 16) {
-        const int nbp_set[] = {4, 8, 12, 16, 20, 32};
-        for (int q : nbp_set)
-            if (q >= nb) { mfma_ks = q; break; }
-        const int tw = 32 - (sp.win_cells_x - 2);
-#ifndef HOG_SCORE_TH
-#define HOG_SCORE_TH 16
-#endif
-        int th = HOG_SCORE_TH;
-        while (th > 1 && (int64_t)tw * th * d.n_templates > 2 * 256) th /= 2;
-        if ((int64_t)tw * th * d.n_templates > 2 * 256) mfma_ks = 0;  // too many templates
-        // the blocked cell cache is indexed with 32-bit offsets
-        if ((int64_t)nb * ((d.height / sp.cell + 7) / 8) * ((d.width / sp.cell + 7) / 8) * 64 >= ((int64_t)1 << 31))
-            mfma_ks = 0;
-        // LDS: the workgroup's cell rows, block norms and U of one block row.
-        const int64_t np = (int64_t)(sp.win_cells_x - 1) * (sp.win_cells_y - 1);
-        const int64_t ntiles = (np * d.n_templates + 31) / 32;
-        const int64_t lds = (int64_t)(th + sp.win_cells_y - 1) * 33 * mfma_ks * 2 +
-                            (int64_t)(th + sp.win_cells_y - 2) * 32 * 4 +
-                            std::max<int64_t>(32 * (ntiles * 32 + 1), (int64_t)(th + sp.win_cells_y - 1) * 33) * 4;
-        if (lds > 64 * 1024) mfma_ks = 0;
-        best_tw = tw;
-        best_th = th;
+    if (sp.norm == HOG_NORM_L2 && sp.win_cells_x - 1 == hogk::kStripMaxBX &&
+        sp.win_cells_y - 1 <= 16 && nb <= 20) {
+        mfma_ks = nb <= 8 ? 8 : nb <= 16 ? 16 : 20;  // bin slots per cell
+        best_tw = hogk::kStripW;
+        best_th = hogk::kStripTH;
+        const int64_t rowh = (int64_t)(hogk::kStripW + 8) * mfma_ks;  // halves per staged cell row
+        best_lds = 4 * round_up(4 * rowh * 2 + 64 * 4 + (int64_t)hogk::kStripW * best_th * 4, 16);
     }
     if (mfma_ks == 0) {
         double best_cost = 1e30;
@@ -430,6 +414,14 @@ extern "C" hog_status hog_plan_create(const hog_plan_desc *desc, hog_plan **out)
         if (d.max_levels == 1) break;
     }
     const int L = (int)p->levels.size();
+    // Prepared template fragments of the matrix-core scorer (rewritten by
+    // every hog_scan_windows call).
+    int64_t tprep_off = 0, tprep_stride = 0;
+    if (mfma_ks > 0) {
+        tprep_stride = round_up(hogk::strip_prep_bytes(mfma_ks), 256);
+        tprep_off = round_up(ws_off, 256);
+        ws_off = tprep_off + tprep_stride * K;
+    }
     // The integral kernels address a chunk of planes (and a level's bins)
     // through one buffer descriptor with 31-bit byte offsets.
     {
@@ -459,7 +451,7 @@ extern "C" hog_status hog_plan_create(const hog_plan_desc *desc, hog_plan **out)
         items[hogk::KB_TSCAN] = (int64_t)v.tiles_y * nb;
         items[hogk::KB_ESCAN] = (int64_t)(v.h + 1) * nb;
         items[hogk::KB_CELL] = (int64_t)v.cells_x * v.cells_y;
-        items[hogk::KB_STILE] = (int64_t)v.st_x * v.st_y;
+        items[hogk::KB_STILE] = (int64_t)v.st_x * v.st_y * (mfma_ks ? K : 1);
         items[hogk::KB_BLOCK] = (sp.norm == HOG_NORM_L2 && v.cells_x >= 2 && v.cells_y >= 2)
                                     ? (int64_t)(v.cells_x - 1) * (v.cells_y - 1)
                                     : 0;
@@ -537,6 +529,8 @@ extern "C" hog_status hog_plan_create(const hog_plan_desc *desc, hog_plan **out)
             ncu < 1)
             ncu = 256;
         pd.n_cu = ncu;
+        pd.tprep_off = tprep_off;
+        pd.tprep_stride = tprep_stride;
     }
 
     hog_plan_sizes &z = p->sizes;

@@ -23,6 +23,21 @@ constexpr int kTile = 64;
 constexpr int kRowBatch = 16;
 constexpr int kMaxBinChunk = 9;
 
+// Matrix-core window scorer: one wave per strip of kStripW window columns and
+// kStripTH window rows; windows kStripMaxBX + 1 cells wide.
+constexpr int kStripW = 16;
+constexpr int kStripTH = 16;
+constexpr int kStripMaxBX = 7;
+
+// Workspace bytes of one template's prepared weights for nbp bin slots per
+// cell: fragments [bx][step][hi|lo][lane] of 16 bytes (one step per 32 or, at
+// the end, 16 features of the 4 nbp), then column scales [bx][lane] (float).
+constexpr int64_t strip_prep_bytes(int nbp)
+{
+    return (int64_t)kStripMaxBX * ((4 * nbp) / 32 + ((4 * nbp) % 32) / 16) * 2 * 64 * 16 +
+           (int64_t)kStripMaxBX * 64 * 4;
+}
+
 // Kernel indices into the per-kernel prefix tables.
 enum {
     KB_BINMAP = 0,  // waves
@@ -71,12 +86,14 @@ struct PlanDev {
     float eps;
     int32_t feat_dim;
     int32_t st_tw, st_th;      // scorer tile (windows)
-    int32_t mfma_ks;           // > 0: matrix-core scorer, bins padded to this multiple of 4
+    int32_t mfma_ks;           // > 0: matrix-core scorer, bin slots per cell (8, 16 or 20)
     int32_t st_lds_bytes;      // scorer dynamic LDS
     int32_t cell_stride;       // floats per staged cell in the scorer's LDS
     int32_t bin_chunk;         // bins per integral wave
     int32_t n_chunks;
     int32_t n_cu;              // compute units of the device (persistent grids)
+    int64_t tprep_off;         // workspace bytes: prepared template fragments (matrix-core scorer)
+    int64_t tprep_stride;      // bytes per template
     int64_t total[KB_COUNT];   // totals (= first[k][n_levels])
 };
 

@@ -743,216 +743,337 @@ __global__ __launch_bounds__(256) void k_score(const Level *__restrict__ lv,
 // ---------------------------------------------------------------------------
 // Sec. 3.1 / Fig. 4 + Sec. 4 on the matrix cores (L2 blocks of 2 x 2 cells).
 //
-// The score of window (wy, wx) is bias + sum over its block positions
-// p = (by, bx) of inv(B) * U(B, p), B = (wy + by, wx + bx), where inv(B) is
-// the block's 1/sqrt(|v|^2 + eps^2) and U(B, p) = T[p] . v(B) is the dot
-// product of the block's 4*nb integer counts with the template's weights at
-// position p. Per block row, U over 32 blocks x every position is one GEMM
-// (blocks x features) . (features x positions) on v_mfma_f32_32x32x8f16.
-// The counts are exact in fp16; each weight is split into fp16 hi + lo
-// parts after scaling its column by a power of two (max |T| of the column
-// into [2^14, 2^15)), so hi + lo carries ~22 bits; hi and lo go to separate
-// FP32 accumulators (72 products each for nb = 18).
+// score(wx, wy) = bias + sum over block positions (by, bx) of
+//     inv(B) * (T[by][bx] . v(B)),   B = (wy + by, wx + bx),
+// with v(B) the block's 4 nb integer counts and inv(B) = 1/sqrt(|v|^2 + eps^2).
 //
-// Cells are staged in LDS with their bins padded to NBP (a multiple of 4),
-// so a block's feature k' = c * NBP + n (cell c of the block, bin n; zero
-// for n >= nb) and an A fragment (4 consecutive k') is one 8-byte read of
-// one cell. A workgroup covers kMfmaM - (nbx - 1) window columns and th
-// window rows and walks the block rows. Per block row: one barrier, the
-// GEMM (one 32-position N-tile per wave), U * scale * inv into LDS, a
-// second barrier, and each thread adds, for each window it owns, the nbx
-// terms of this block row (an FP32 sum) into an FP64 accumulator; then
-// threads 0..32 store the next cell row (fetched one row ahead), and from
-// the cells' squared norms the block norms of the next block row.
+// One wave scores a strip of kStripW window columns (wx0 ..) over a range of
+// window rows, walking the block rows Y. For block row Y and each bx, matrix
+// instructions (16 x 16 outputs, fp16 inputs, FP32 accumulation) give
+//     D_bx[m][n] = v(Y, wx0 + m + bx) . T[n][bx]      (m window column, n = by),
+// the A rows being the row's blocks shifted by bx and B column n the weights
+// at block position (n, bx). Then
+//     acc32[m][n] = sum_bx inv(Y, wx0 + m + bx) * D_bx[m][n]       (FP32)
+// is block row Y's share of window (wx0 + m, Y - n), added to that window's
+// FP64 running sum, which lives in column n = Y - wy: after each block row
+// every sum moves one column right (DPP row_shr:1), so a window enters at
+// column 0 on its first block row and leaves column nby - 1 complete.
+//
+// The counts are exact in fp16. k_score_prep scales each weight column
+// (n, bx) by a power of two (its max |T| into [2^14, 2^15)) and splits it into
+// fp16 hi + lo (~22 bits of each weight); both products are added into the
+// block's FP32 accumulator. A block's 4 NBP features are its cells (u, w) in the
+// order w, u with NBP bin slots each (padding zero); the feature axis is
+// covered by 16x16x32 steps, plus one 16x16x16 step when 4 NBP = 80.
+// Cells sit in LDS as fp16 [cell][NBP] in a ring of four cell rows; each row
+// is fetched from the blocked cache two block rows before it is needed.
+// Waves are independent: no workgroup barrier.
 // ---------------------------------------------------------------------------
-constexpr int kMfmaM = 32;
-constexpr int kMfmaOwn = 2;  // window x template items per thread
+constexpr int kStripCells = kStripW + 8;    // cell columns staged per row
 
-struct MfmaArgs {
-    int nb, nbx, nby, np, k, ntiles, th, tw, dim, ustride;
+struct StripArgs {
+    int nb, nby, k, th, dim, lds_wave;
+    int64_t tprep_off, tprep_stride;
     float eps;
 };
 
+typedef _Float16 half8_t __attribute__((ext_vector_type(8)));
 typedef _Float16 half4_t __attribute__((ext_vector_type(4)));
-typedef float float16_t __attribute__((ext_vector_type(16)));
+typedef float float4_t __attribute__((ext_vector_type(4)));
+typedef uint16_t u16x8_t __attribute__((ext_vector_type(8)));
 
 template <int NBP>
-__global__ __launch_bounds__(256) void k_score_mfma(const Level *__restrict__ lv,
-                                                    const int32_t *__restrict__ first, int n_levels,
-                                                    MfmaArgs a, const uint8_t *__restrict__ ws,
-                                                    const float *__restrict__ tmpl,
-                                                    const float *__restrict__ bias,
-                                                    float *__restrict__ scores)
+struct StripShape {
+    static constexpr int K32 = (4 * NBP) / 32;         // 16x16x32 steps per block
+    static constexpr int K16 = ((4 * NBP) % 32) / 16;  // 16x16x16 steps (0 or 1)
+    static constexpr int S = K32 + K16;                // prepared fragments per (bx, hi|lo)
+    static_assert(4 * NBP == 32 * K32 + 16 * K16, "bin padding must fill the steps");
+};
+
+// Lane i of each 16-lane row takes lane i-1's value; lane 0 of a row takes 0.
+__device__ __forceinline__ double shift_row_right(double x)
 {
-    constexpr int KS = NBP / 2;  // 4 * NBP features, 8 per MFMA step
-    constexpr int kRowHalves = (kMfmaM + 1) * NBP;
-    // Dynamic LDS: cell rows [n_rows][33][NBP] (fp16), block norms
-    // [n_rows - 1][32] (float), U of one block row [32][ustride] (float).
+    const uint64_t u = __builtin_bit_cast(uint64_t, x);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, 0x111, 0xF, 0xF, true);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), 0x111, 0xF, 0xF, true);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// Feature k of a block (cell order w, u; NBP slots per cell) -> template
+// element of block position (n, bx), or -1 for a padding slot / n >= nby.
+__device__ __forceinline__ int strip_weight_index(int k, int nbp, int nb, int nby, int n, int bx)
+{
+    const int w = k / (2 * nbp), rem = k % (2 * nbp);
+    const int u = rem / nbp, bin = rem % nbp;
+    if (n >= nby || bin >= nb) return -1;
+    return ((n * kStripMaxBX + bx) * 4 + w * 2 + u) * nb + bin;
+}
+
+// One wave per (template, bx): the B fragments of every step, hi and lo, and
+// the column scales, in the layout the strip kernel loads.
+template <int NBP>
+__global__ __launch_bounds__(256) void k_score_prep(StripArgs a, const float *__restrict__ tmpl,
+                                                    uint8_t *__restrict__ ws)
+{
+    using Sh = StripShape<NBP>;
+    const int lane = threadIdx.x & 63;
+    const int g = (int)blockIdx.x * 4 + wave_id_in_block();
+    if (g >= a.k * kStripMaxBX) return;
+    const int kk = g / kStripMaxBX, bx = g % kStripMaxBX;
+    const int n = lane & 15, q = lane >> 4;
+    const float *tk = tmpl + (int64_t)kk * a.dim;
+    float vals[Sh::S][8];
+    float mx = 0.f;
+#pragma unroll
+    for (int j = 0; j < Sh::S; ++j)
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            float val = 0.f;
+            if (j < Sh::K32 || i < 4) {
+                const int k = j < Sh::K32 ? 32 * j + 8 * q + i : 32 * Sh::K32 + 4 * q + i;
+                const int idx = strip_weight_index(k, NBP, a.nb, a.nby, n, bx);
+                if (idx >= 0) val = tk[idx];
+            }
+            vals[j][i] = val;
+            mx = fmaxf(mx, fabsf(val));
+        }
+    mx = fmaxf(mx, __shfl_xor(mx, 16));
+    mx = fmaxf(mx, __shfl_xor(mx, 32));
+    int ex = 0;
+    if (mx > 0.f) (void)frexpf(mx, &ex);  // mx = f 2^ex, f in [0.5, 1)
+    const int e = mx > 0.f ? 15 - ex : 0;
+    uint8_t *tp = ws + a.tprep_off + (int64_t)kk * a.tprep_stride;
+#pragma unroll
+    for (int j = 0; j < Sh::S; ++j) {
+        half8_t h, lo;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const float sv = ldexpf(vals[j][i], e);
+            h[i] = (_Float16)sv;
+            lo[i] = (_Float16)(sv - (float)h[i]);
+        }
+        *reinterpret_cast<half8_t *>(tp + (((int64_t)(bx * Sh::S + j) * 2 + 0) * 64 + lane) * 16) = h;
+        *reinterpret_cast<half8_t *>(tp + (((int64_t)(bx * Sh::S + j) * 2 + 1) * 64 + lane) * 16) = lo;
+    }
+    reinterpret_cast<float *>(tp + (int64_t)kStripMaxBX * Sh::S * 2 * 64 * 16)[bx * 64 + lane] = ldexpf(1.f, -e);
+}
+
+template <int NBP>
+__global__ __launch_bounds__(256, 2) void k_score_strip(const Level *__restrict__ lv,
+                                                     const int32_t *__restrict__ first, int n_levels,
+                                                     StripArgs a, const uint8_t *__restrict__ ws,
+                                                     const float *__restrict__ bias,
+                                                     float *__restrict__ scores)
+{
+    using Sh = StripShape<NBP>;
+    constexpr int ROWH = kStripCells * NBP;         // halves per staged cell row
+    constexpr int NSEG = kStripCells / 8;           // 8-cell segments of the blocked cache
     extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
 
-    const int wg = (int)blockIdx.x;
-    if (wg >= first[n_levels]) return;
-    const int l = find_level(first, n_levels, wg);
+    const int lane = threadIdx.x & 63, wave = wave_id_in_block();
+    const int g = (int)blockIdx.x * 4 + wave;
+    if (g >= first[n_levels]) return;
+    const int l = find_level(first, n_levels, g);
     const Level &v = lv[l];
-    const int rel = wg - first[l];
-    const int sx = rel % v.st_x, sy = rel / v.st_x;
-    const int wx0 = sx * a.tw, wy0 = sy * a.th;
-    const int BH = v.cells_y - 1;
-    const int Y0 = wy0, Y1 = min(wy0 + a.th + a.nby - 1, BH);  // block rows [Y0, Y1)
-    const int n_rows = Y1 - Y0 + 1;                            // cell rows [Y0, Y1]
-    const int tid = (int)threadIdx.x;
-    const int lane = tid & 63, wave = tid >> 6;
+    int rel = g - first[l];
+    const int sx = rel % v.st_x;
+    rel /= v.st_x;
+    const int sy = rel % v.st_y, kk = rel / v.st_y;
+    const int wx0 = sx * kStripW, wy_lo = sy * a.th;
+    const int wy_hi = min(wy_lo + a.th, v.win_y);
+    const int y_last = wy_hi - 1 + a.nby - 1;  // last block row
     const int nb = a.nb;
-    _Float16 *crow = reinterpret_cast<_Float16 *>(smem);
-    float *invb = reinterpret_cast<float *>(smem + (size_t)(a.th + a.nby) * kRowHalves * 2);
-    float *ulds = invb + (a.th + a.nby - 1) * kMfmaM;
 
-    // Stage the cell rows: 16-byte loads of 8 consecutive cells of one bin
-    // from the blocked cache, spread to the cells' padded bin slots.
+    uint8_t *wl = smem + (size_t)wave * a.lds_wave;
+    _Float16 *ring = reinterpret_cast<_Float16 *>(wl);
+    float *invb = reinterpret_cast<float *>(wl + 4 * ROWH * 2);  // [2][32]: rows Y, Y + 1
+    float *outb = invb + 64;
     {
-        typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
-        const uint16_t *cache = reinterpret_cast<const uint16_t *>(ws + v.ws_cache);
-        const int seg0 = wx0 >> 3;
-        const int n_seg = ((wx0 + kMfmaM) >> 3) - seg0 + 1;
-        const int n_loads = n_rows * NBP * n_seg;
-        for (int q = tid; q < n_loads; q += 256) {
-            const int sg = q % n_seg, rest = q / n_seg;
-            const int n = rest % NBP, r = rest / NBP;
-            const int cy = Y0 + r, bx8 = seg0 + sg;
-            u16x8 vals = {0, 0, 0, 0, 0, 0, 0, 0};
-            if (n < nb && cy < v.cells_y && bx8 < v.cbx)
-                vals = *reinterpret_cast<const u16x8 *>(
-                    cache + (((int64_t)n * v.cby + (cy >> 3)) * v.cbx + bx8) * 64 + (cy & 7) * 8);
+        typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+        u32x4 *rz = reinterpret_cast<u32x4 *>(ring);
+        for (int i = lane; i < 4 * ROWH / 8; i += 64) rz[i] = u32x4{0u, 0u, 0u, 0u};
+    }
+
+    // One 16-byte load per lane and row: lane t < nb * NSEG loads bin t / NSEG,
+    // cells 8 (t % NSEG) .. + 7 of the strip (the plan keeps nb * NSEG <= 64).
+    const uint16_t *cache = reinterpret_cast<const uint16_t *>(ws + v.ws_cache);
+    const int f_bin = lane / NSEG, f_seg = lane - f_bin * NSEG;
+    const bool f_on = lane < nb * NSEG && (wx0 >> 3) + f_seg < v.cbx;
+    const uint16_t *f_base = cache + ((int64_t)f_bin * v.cby * v.cbx + (wx0 >> 3) + f_seg) * 64;
+    const int64_t f_rowblk = (int64_t)v.cbx * 64;  // elements between 8-cell-row blocks
+    auto fetch = [&](int cy) -> u16x8_t {
+        u16x8_t val = {0, 0, 0, 0, 0, 0, 0, 0};
+        if (f_on && cy < v.cells_y)
+            val = *reinterpret_cast<const u16x8_t *>(f_base + (cy >> 3) * f_rowblk + (cy & 7) * 8);
+        return val;
+    };
+    auto store_row = [&](int slot, const u16x8_t &val) {
+        _Float16 *rp = ring + slot * ROWH + f_bin;
+        if (lane < nb * NSEG) {
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
-                const int cx = 8 * bx8 + e, i = cx - wx0;
-                if (i >= 0 && i <= kMfmaM)
-                    crow[(size_t)r * kRowHalves + i * NBP + n] = (cx < v.cells_x) ? (_Float16)(float)vals[e]
-                                                                               : (_Float16)0.f;
+                const int c = 8 * f_seg + e;
+                rp[c * NBP] = (wx0 + c < v.cells_x) ? (_Float16)(float)val[e] : (_Float16)0.f;
             }
         }
-    }
-    __syncthreads();
-    // Block norms from the cells' squared norms (sums of squared integer
-    // counts, exact in FP32): first per cell, then four cells per block.
-    float *cellsq = ulds;  // scratch until the first block row (the launch sizes it)
-    for (int q = tid; q < n_rows * (kMfmaM + 1); q += 256) {
-        const _Float16 *cp = crow + (size_t)(q / (kMfmaM + 1)) * kRowHalves + (q % (kMfmaM + 1)) * NBP;
-        float ss = 0.f;
-#pragma unroll
-        for (int n = 0; n < NBP; ++n) ss = fmaf((float)cp[n], (float)cp[n], ss);
-        cellsq[q] = ss;
-    }
-    __syncthreads();
-    for (int q = tid; q < (n_rows - 1) * kMfmaM; q += 256) {
-        const int i = q % kMfmaM, r = q / kMfmaM;
-        const float *c0 = cellsq + r * (kMfmaM + 1) + i;
-        const float ss = (c0[0] + c0[1]) + (c0[kMfmaM + 1] + c0[kMfmaM + 2]);
-        invb[q] = inv_block_norm(ss, a.eps);
-    }
-
-    // B fragments of N-tile t: column gn = 32 t + lane % 32 is (template k,
-    // position p), gn = k * np + p; rows k' = 8 s + 4 (lane / 32) + i.
-    half4_t bh[KS], bl[KS];
-    float cscale = 1.f;
-    auto load_b = [&](int t) {
-        const int gn = 32 * t + (lane & 31);
-        const int kk = gn / a.np, p = gn - kk * a.np;
-        const bool colok = gn < a.np * a.k;
-        const float *tp = tmpl + (int64_t)kk * a.dim + (int64_t)p * 4 * nb;
-        float vals[KS][4];
-        float mx = 0.f;
-#pragma unroll
-        for (int s2 = 0; s2 < KS; ++s2)
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int kp = 8 * s2 + 4 * (lane >> 5) + i;
-                const int c = kp / NBP, n = kp % NBP;
-                const float val = (colok && n < nb) ? tp[c * nb + n] : 0.f;
-                vals[s2][i] = val;
-                mx = fmaxf(mx, fabsf(val));
-            }
-        mx = fmaxf(mx, __shfl_xor(mx, 32));
-        int ex = 0;
-        if (mx > 0.f) (void)frexpf(mx, &ex);  // mx = f 2^ex, f in [0.5, 1)
-        const int e = mx > 0.f ? 15 - ex : 0;
-        cscale = ldexpf(1.f, -e);
-#pragma unroll
-        for (int s2 = 0; s2 < KS; ++s2)
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const float sv = ldexpf(vals[s2][i], e);
-                const _Float16 hi = (_Float16)sv;
-                bh[s2][i] = hi;
-                bl[s2][i] = (_Float16)(sv - (float)hi);
-            }
     };
-    const bool resident = a.ntiles <= 4;
-    if (resident && wave < a.ntiles) load_b(wave);
-
-    // A fragment of step s: cell c = k' / NBP of block (lane % 32), bins
-    // n0..n0+3, k' = 8 s + 4 (lane / 32).
-    const int a_lane = (lane & 31) * NBP, a_half = 4 * (lane >> 5);
-
-    // Windows owned by this thread: item = (window, template), window-major.
-    double acc[kMfmaOwn];
-    int item_base[kMfmaOwn], item_wy[kMfmaOwn];
-    const int n_items = a.tw * a.th * a.k;
+    // Sum of squared counts of staged cell `lane` (exact in FP32).
+    auto row_sq = [&](int slot) -> float {
+        float s = 0.f;
+        if (lane < kStripCells) {
+            const _Float16 *cp = ring + slot * ROWH + lane * NBP;
 #pragma unroll
-    for (int m = 0; m < kMfmaOwn; ++m) {
-        acc[m] = 0.0;
-        const int item = tid + 256 * m;
-        const int kk = item % a.k, w = item / a.k;
-        const int wxl = w % a.tw, wyl = w / a.tw;
-        item_base[m] = wxl * a.ustride + kk * a.np;
-        item_wy[m] = item < n_items ? wy0 + wyl : -(1 << 30);
+            for (int j = 0; j < NBP / 4; ++j) {
+                const half4_t h = *reinterpret_cast<const half4_t *>(cp + 4 * j);
+#pragma unroll
+                for (int e = 0; e < 4; ++e) s = fmaf((float)h[e], (float)h[e], s);
+            }
+        }
+        return s;
+    };
+
+    // The first four cell rows are in flight while the weights are loaded.
+    u16x8_t pre0 = fetch(wy_lo), pre1 = fetch(wy_lo + 1);
+    u16x8_t pre2 = fetch(wy_lo + 2), pre3 = fetch(wy_lo + 3);
+
+    // Prepared B fragments (k_score_prep) and column scales.
+    const uint8_t *tp = ws + a.tprep_off + (int64_t)kk * a.tprep_stride;
+    half8_t bh[kStripMaxBX][Sh::K32], bl[kStripMaxBX][Sh::K32];
+    half4_t bh16[kStripMaxBX], bl16[kStripMaxBX];
+    float cs[kStripMaxBX];
+#pragma unroll
+    for (int bx = 0; bx < kStripMaxBX; ++bx) {
+#pragma unroll
+        for (int j = 0; j < Sh::K32; ++j) {
+            bh[bx][j] = *reinterpret_cast<const half8_t *>(tp + (((int64_t)(bx * Sh::S + j) * 2 + 0) * 64 + lane) * 16);
+            bl[bx][j] = *reinterpret_cast<const half8_t *>(tp + (((int64_t)(bx * Sh::S + j) * 2 + 1) * 64 + lane) * 16);
+        }
+        if constexpr (Sh::K16 > 0) {
+            bh16[bx] = *reinterpret_cast<const half4_t *>(tp + (((int64_t)(bx * Sh::S + Sh::K32) * 2 + 0) * 64 + lane) * 16);
+            bl16[bx] = *reinterpret_cast<const half4_t *>(tp + (((int64_t)(bx * Sh::S + Sh::K32) * 2 + 1) * 64 + lane) * 16);
+        }
+        cs[bx] = reinterpret_cast<const float *>(tp + (int64_t)kStripMaxBX * Sh::S * 2 * 64 * 16)[bx * 64 + lane];
+    }
+    // Keep the fragments in registers for the whole strip: without this the
+    // compiler may reload them from memory inside the row loop.
+#pragma unroll
+    for (int bx = 0; bx < kStripMaxBX; ++bx) {
+#pragma unroll
+        for (int j = 0; j < Sh::K32; ++j) asm volatile("" : "+v"(bh[bx][j]), "+v"(bl[bx][j]));
+        if constexpr (Sh::K16 > 0) asm volatile("" : "+v"(bh16[bx]), "+v"(bl16[bx]));
+        asm volatile("" : "+v"(cs[bx]));
     }
 
-    for (int Y = Y0; Y < Y1; ++Y) {
-        __syncthreads();  // norms ready; U of the previous row consumed
-        const _Float16 *c0 = crow + (size_t)(Y - Y0) * kRowHalves;
-        const float *iv = invb + (Y - Y0) * kMfmaM;
-        for (int t = wave; t < a.ntiles; t += 4) {
-            if (!resident) load_b(t);
-            float16_t ah = {}, al = {};
+    // A fragments: window column m = lane % 16; lane group q = lane / 16 takes
+    // features k0 .. k0 + 7 (16x16x32) or k0 .. k0 + 3 (16x16x16) of each block:
+    // cell row Y + k0 / 2NBP, offset k0 % 2NBP into the block's two cells.
+    const int m = lane & 15, q = lane >> 4;
+    int a_row[Sh::S], a_off[Sh::S];
 #pragma unroll
-            for (int s2 = 0; s2 < KS; ++s2) {
-                const int kp = 8 * s2 + a_half;
-                const int c = kp / NBP, n0 = kp - c * NBP;
-                const half4_t av = *reinterpret_cast<const half4_t *>(
-                    c0 + (c >> 1) * kRowHalves + a_lane + (c & 1) * NBP + n0);
-                ah = __builtin_amdgcn_mfma_f32_32x32x8f16(av, bh[s2], ah, 0, 0, 0);
-                al = __builtin_amdgcn_mfma_f32_32x32x8f16(av, bl[s2], al, 0, 0, 0);
-            }
-            const int gn = 32 * t + (lane & 31);
-#pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int i = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-                ulds[i * a.ustride + gn] = (ah[r] + al[r]) * cscale * iv[i];
-            }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int m = 0; m < kMfmaOwn; ++m) {
-            const int by = Y - item_wy[m];
-            if (by >= 0 && by < a.nby) {
-                const float *u = ulds + item_base[m] + by * a.nbx;
-                float sum = 0.f;
-                for (int bx = 0; bx < a.nbx; ++bx) sum += u[bx * (a.ustride + 1)];
-                acc[m] += (double)sum;
-            }
-        }
+    for (int j = 0; j < Sh::S; ++j) {
+        const int k0 = j < Sh::K32 ? 32 * j + 8 * q : 32 * Sh::K32 + 4 * q;
+        a_row[j] = k0 / (2 * NBP);
+        a_off[j] = m * NBP + k0 % (2 * NBP);
     }
-#pragma unroll
-    for (int m = 0; m < kMfmaOwn; ++m) {
-        const int item = tid + 256 * m;
-        if (item < n_items) {
-            const int kk = item % a.k, w = item / a.k;
-            const int wx = wx0 + w % a.tw, wy = wy0 + w / a.tw;
-            if (wx < v.win_x && wy < v.win_y)
-                scores[v.score_off + ((int64_t)wy * v.win_x + wx) * a.k + kk] =
-                    (float)((double)bias[kk] + acc[m]);
+    auto load_a8 = [&](const _Float16 *p) -> half8_t {
+        if constexpr ((NBP % 8) == 0) {
+            return *reinterpret_cast<const half8_t *>(p);
+        } else {  // 8-byte aligned
+            const half4_t x = *reinterpret_cast<const half4_t *>(p), y = *reinterpret_cast<const half4_t *>(p + 4);
+            return __builtin_shufflevector(x, y, 0, 1, 2, 3, 4, 5, 6, 7);
         }
+    };
+
+    // Norms of block row Y's blocks: block j = cells j, j + 1 of cell rows
+    // Y, Y + 1 (sq0, sq1: each lane's cell), into invb[Y & 1].
+    auto block_norms = [&](int Y, float sq0, float sq1) {
+        const float t = sq0 + sq1;
+        const float t1 = __builtin_bit_cast(float, from_right_lane(__builtin_bit_cast(uint32_t, t)));
+        if (lane < kStripCells) invb[(Y & 1) * 32 + lane] = inv_block_norm(t + t1, a.eps);
+    };
+    store_row(wy_lo & 3, pre0);
+    store_row((wy_lo + 1) & 3, pre1);
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront", "local");
+    float sq1 = row_sq((wy_lo + 1) & 3);
+    block_norms(wy_lo, row_sq(wy_lo & 3), sq1);
+    const double bk = (double)bias[kk];
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+
+    // Cell rows Y and Y + 1 are in the ring; rows Y + 2 and Y + 3 are in
+    // flight in pre2 and pre3 (fetched two block rows ahead).
+    for (int Y = wy_lo; Y <= y_last; ++Y) {
+        const bool more = Y + 2 <= y_last + 1;
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront", "local");
+        // iv[t] = inv of block 4 q + t of this row (t = r + bx <= 9).
+        float iv[10];
+        {
+            const float *ib = invb + (Y & 1) * 32 + 4 * q;
+            const float4_t f0 = *reinterpret_cast<const float4_t *>(ib);
+            const float4_t f1 = *reinterpret_cast<const float4_t *>(ib + 4);
+            const float2 f2 = *reinterpret_cast<const float2 *>(ib + 8);
+            iv[0] = f0[0]; iv[1] = f0[1]; iv[2] = f0[2]; iv[3] = f0[3];
+            iv[4] = f1[0]; iv[5] = f1[1]; iv[6] = f1[2]; iv[7] = f1[3];
+            iv[8] = f2.x; iv[9] = f2.y;
+        }
+        // One FP32 accumulator per bx; the hi and lo products of a step are
+        // issued bx-interleaved so consecutive instructions are independent.
+        float4_t d[kStripMaxBX];
+#pragma unroll
+        for (int bx = 0; bx < kStripMaxBX; ++bx) d[bx] = float4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int j = 0; j < Sh::K32; ++j) {
+            const _Float16 *ap = ring + ((Y + a_row[j]) & 3) * ROWH + a_off[j];
+            half8_t av[kStripMaxBX];
+#pragma unroll
+            for (int bx = 0; bx < kStripMaxBX; ++bx) av[bx] = load_a8(ap + bx * NBP);
+#pragma unroll
+            for (int bx = 0; bx < kStripMaxBX; ++bx)
+                d[bx] = __builtin_amdgcn_mfma_f32_16x16x32_f16(av[bx], bh[bx][j], d[bx], 0, 0, 0);
+#pragma unroll
+            for (int bx = 0; bx < kStripMaxBX; ++bx)
+                d[bx] = __builtin_amdgcn_mfma_f32_16x16x32_f16(av[bx], bl[bx][j], d[bx], 0, 0, 0);
+        }
+        if constexpr (Sh::K16 > 0) {
+            const _Float16 *ap = ring + ((Y + a_row[Sh::K32]) & 3) * ROWH + a_off[Sh::K32];
+            half4_t av[kStripMaxBX];
+#pragma unroll
+            for (int bx = 0; bx < kStripMaxBX; ++bx) av[bx] = *reinterpret_cast<const half4_t *>(ap + bx * NBP);
+#pragma unroll
+            for (int bx = 0; bx < kStripMaxBX; ++bx)
+                d[bx] = __builtin_amdgcn_mfma_f32_16x16x16f16(av[bx], bh16[bx], d[bx], 0, 0, 0);
+#pragma unroll
+            for (int bx = 0; bx < kStripMaxBX; ++bx)
+                d[bx] = __builtin_amdgcn_mfma_f32_16x16x16f16(av[bx], bl16[bx], d[bx], 0, 0, 0);
+        }
+        float acc32[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int bx = 0; bx < kStripMaxBX; ++bx)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc32[r] = fmaf(d[bx][r], iv[r + bx] * cs[bx], acc32[r]);
+        const int wy_done = Y - (a.nby - 1);
+        const bool done = m == a.nby - 1 && wy_done >= wy_lo && wy_done < wy_hi;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            acc[r] += (double)acc32[r];
+            if (done) outb[(wy_done - wy_lo) * kStripW + 4 * q + r] = (float)(bk + acc[r]);
+            acc[r] = shift_row_right(acc[r]);
+        }
+        if (more) {
+            store_row((Y + 2) & 3, pre2);
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront", "local");
+            // Next block row's norms, one row ahead of their use.
+            const float sq2 = row_sq((Y + 2) & 3);
+            block_norms(Y + 1, sq1, sq2);
+            sq1 = sq2;
+        }
+        pre2 = pre3;
+        if (Y + 4 <= y_last + 1) pre3 = fetch(Y + 4);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront", "local");
+    const int n_out = (wy_hi - wy_lo) * kStripW;
+    for (int i = lane; i < n_out; i += 64) {
+        const int wx = wx0 + i % kStripW, wy = wy_lo + i / kStripW;
+        if (wx < v.win_x) scores[v.score_off + ((int64_t)wy * v.win_x + wx) * a.k + kk] = outb[i];
     }
 }
 
@@ -1111,28 +1232,33 @@ hipError_t launch_score(const PlanDev &p, const uint8_t *ws, const float *tmpl, 
     const dim3 grid((unsigned)n), block(256);
     const int32_t *f = first_of(p, KB_STILE);
     if (p.mfma_ks > 0) {
-        MfmaArgs m;
+        StripArgs m;
         m.nb = p.n_bins;
-        m.nbx = p.win_cells_x - 1;
         m.nby = p.win_cells_y - 1;
-        m.np = m.nbx * m.nby;
         m.k = p.n_templates;
-        m.ntiles = (m.np * m.k + 31) / 32;
         m.th = p.st_th;
-        m.tw = p.st_tw;
         m.dim = p.feat_dim;
-        m.ustride = m.ntiles * 32 + 1;
+        m.lds_wave = p.st_lds_bytes / 4;
+        m.tprep_off = p.tprep_off;
+        m.tprep_stride = p.tprep_stride;
         m.eps = p.eps;
-        const size_t u_floats = std::max<size_t>((size_t)kMfmaM * m.ustride, (size_t)(m.th + m.nby) * (kMfmaM + 1));
-        const size_t lds = (size_t)(m.th + m.nby) * (kMfmaM + 1) * p.mfma_ks * 2 +
-                           (size_t)(m.th + m.nby - 1) * kMfmaM * 4 + u_floats * 4;
+        const dim3 pgrid(blocks_for((int64_t)m.k * kStripMaxBX, 4)), sgrid(blocks_for(n, 4));
+        // The prepared weights are rewritten in the workspace by every call.
+        uint8_t *wsw = const_cast<uint8_t *>(ws);
+        const size_t lds = (size_t)p.st_lds_bytes;
         switch (p.mfma_ks) {
-        case 4: hipLaunchKernelGGL(k_score_mfma<4>, grid, block, lds, stream, p.levels, f, p.n_levels, m, ws, tmpl, bias, scores); break;
-        case 8: hipLaunchKernelGGL(k_score_mfma<8>, grid, block, lds, stream, p.levels, f, p.n_levels, m, ws, tmpl, bias, scores); break;
-        case 12: hipLaunchKernelGGL(k_score_mfma<12>, grid, block, lds, stream, p.levels, f, p.n_levels, m, ws, tmpl, bias, scores); break;
-        case 16: hipLaunchKernelGGL(k_score_mfma<16>, grid, block, lds, stream, p.levels, f, p.n_levels, m, ws, tmpl, bias, scores); break;
-        case 20: hipLaunchKernelGGL(k_score_mfma<20>, grid, block, lds, stream, p.levels, f, p.n_levels, m, ws, tmpl, bias, scores); break;
-        case 32: hipLaunchKernelGGL(k_score_mfma<32>, grid, block, lds, stream, p.levels, f, p.n_levels, m, ws, tmpl, bias, scores); break;
+        case 8:
+            hipLaunchKernelGGL(k_score_prep<8>, pgrid, block, 0, stream, m, tmpl, wsw);
+            hipLaunchKernelGGL(k_score_strip<8>, sgrid, block, lds, stream, p.levels, f, p.n_levels, m, ws, bias, scores);
+            break;
+        case 16:
+            hipLaunchKernelGGL(k_score_prep<16>, pgrid, block, 0, stream, m, tmpl, wsw);
+            hipLaunchKernelGGL(k_score_strip<16>, sgrid, block, lds, stream, p.levels, f, p.n_levels, m, ws, bias, scores);
+            break;
+        case 20:
+            hipLaunchKernelGGL(k_score_prep<20>, pgrid, block, 0, stream, m, tmpl, wsw);
+            hipLaunchKernelGGL(k_score_strip<20>, sgrid, block, lds, stream, p.levels, f, p.n_levels, m, ws, bias, scores);
+            break;
         default: return hipErrorInvalidValue;
         }
         return hipGetLastError();
