@@ -31,11 +31,10 @@ constexpr int kStripMaxBX = 7;
 
 // Workspace bytes of one template's prepared weights for nbp bin slots per
 // cell: fragments [bx][step][hi|lo][lane] of 16 bytes (one step per 32 or, at
-// the end, 16 features of the 4 nbp), then column scales [bx][lane] (float).
+// the end, 16 features of the 4 nbp), then the column scales [lane] (float).
 constexpr int64_t strip_prep_bytes(int nbp)
 {
-    return (int64_t)kStripMaxBX * ((4 * nbp) / 32 + ((4 * nbp) % 32) / 16) * 2 * 64 * 16 +
-           (int64_t)kStripMaxBX * 64 * 4;
+    return (int64_t)kStripMaxBX * ((4 * nbp) / 32 + ((4 * nbp) % 32) / 16) * 2 * 64 * 16 + 64 * 4;
 }
 
 // Kernel indices into the per-kernel prefix tables.

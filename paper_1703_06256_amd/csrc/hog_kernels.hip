@@ -759,15 +759,17 @@ __global__ __launch_bounds__(256) void k_score(const Level *__restrict__ lv,
 // every sum moves one column right (DPP row_shr:1), so a window enters at
 // column 0 on its first block row and leaves column nby - 1 complete.
 //
-// The counts are exact in fp16. k_score_prep scales each weight column
-// (n, bx) by a power of two (its max |T| into [2^14, 2^15)) and splits it into
-// fp16 hi + lo (~22 bits of each weight); both products are added into the
-// block's FP32 accumulator. A block's 4 NBP features are its cells (u, w) in the
+// The counts are exact in fp16. k_score_prep scales each weight column n
+// by a power of two (its max |T| over all bx into [2^14, 2^15)) and splits it
+// into fp16 hi + lo (~22 bits of each weight); both products are added into
+// the block's FP32 accumulator. A block's 4 NBP features are its cells (u, w) in the
 // order w, u with NBP bin slots each (padding zero); the feature axis is
 // covered by 16x16x32 steps, plus one 16x16x16 step when 4 NBP = 80.
 // Cells sit in LDS as fp16 [cell][NBP] in a ring of four cell rows; each row
 // is fetched from the blocked cache two block rows before it is needed.
-// Waves are independent: no workgroup barrier.
+// Waves are independent: no workgroup barrier. A wave's LDS operations are
+// performed in issue order, so its own writes are visible to its later reads
+// once the compiler keeps them in order (lds_order).
 // ---------------------------------------------------------------------------
 constexpr int kStripCells = kStripW + 8;    // cell columns staged per row
 
@@ -790,6 +792,13 @@ struct StripShape {
     static_assert(4 * NBP == 32 * K32 + 16 * K16, "bin padding must fill the steps");
 };
 
+// Compiler-only ordering point for wave-private LDS traffic.
+__device__ __forceinline__ void lds_order()
+{
+    __builtin_amdgcn_wave_barrier();
+    asm volatile("" ::: "memory");
+}
+
 // Lane i of each 16-lane row takes lane i-1's value; lane 0 of a row takes 0.
 __device__ __forceinline__ double shift_row_right(double x)
 {
@@ -809,17 +818,17 @@ __device__ __forceinline__ int strip_weight_index(int k, int nbp, int nb, int nb
     return ((n * kStripMaxBX + bx) * 4 + w * 2 + u) * nb + bin;
 }
 
-// One wave per (template, bx): the B fragments of every step, hi and lo, and
-// the column scales, in the layout the strip kernel loads.
+// One workgroup per template, wave bx (kStripMaxBX waves): the B fragments of
+// every step for that bx, hi and lo, in the layout the strip kernel loads.
+// Column n (block row offset) gets one power-of-two scale for all its bx.
 template <int NBP>
-__global__ __launch_bounds__(256) void k_score_prep(StripArgs a, const float *__restrict__ tmpl,
-                                                    uint8_t *__restrict__ ws)
+__global__ __launch_bounds__(64 * kStripMaxBX) void k_score_prep(StripArgs a, const float *__restrict__ tmpl,
+                                                                 uint8_t *__restrict__ ws)
 {
     using Sh = StripShape<NBP>;
-    const int lane = threadIdx.x & 63;
-    const int g = (int)blockIdx.x * 4 + wave_id_in_block();
-    if (g >= a.k * kStripMaxBX) return;
-    const int kk = g / kStripMaxBX, bx = g % kStripMaxBX;
+    __shared__ float colmax[kStripMaxBX][64];
+    const int lane = threadIdx.x & 63, bx = wave_id_in_block();
+    const int kk = (int)blockIdx.x;
     const int n = lane & 15, q = lane >> 4;
     const float *tk = tmpl + (int64_t)kk * a.dim;
     float vals[Sh::S][8];
@@ -837,8 +846,13 @@ __global__ __launch_bounds__(256) void k_score_prep(StripArgs a, const float *__
             vals[j][i] = val;
             mx = fmaxf(mx, fabsf(val));
         }
-    mx = fmaxf(mx, __shfl_xor(mx, 16));
-    mx = fmaxf(mx, __shfl_xor(mx, 32));
+    colmax[bx][lane] = mx;
+    __syncthreads();
+    mx = 0.f;
+#pragma unroll
+    for (int b = 0; b < kStripMaxBX; ++b)
+#pragma unroll
+        for (int g = 0; g < 4; ++g) mx = fmaxf(mx, colmax[b][16 * g + n]);
     int ex = 0;
     if (mx > 0.f) (void)frexpf(mx, &ex);  // mx = f 2^ex, f in [0.5, 1)
     const int e = mx > 0.f ? 15 - ex : 0;
@@ -855,7 +869,7 @@ __global__ __launch_bounds__(256) void k_score_prep(StripArgs a, const float *__
         *reinterpret_cast<half8_t *>(tp + (((int64_t)(bx * Sh::S + j) * 2 + 0) * 64 + lane) * 16) = h;
         *reinterpret_cast<half8_t *>(tp + (((int64_t)(bx * Sh::S + j) * 2 + 1) * 64 + lane) * 16) = lo;
     }
-    reinterpret_cast<float *>(tp + (int64_t)kStripMaxBX * Sh::S * 2 * 64 * 16)[bx * 64 + lane] = ldexpf(1.f, -e);
+    if (bx == 0) reinterpret_cast<float *>(tp + (int64_t)kStripMaxBX * Sh::S * 2 * 64 * 16)[lane] = ldexpf(1.f, -e);
 }
 
 template <int NBP>
@@ -907,14 +921,13 @@ __global__ __launch_bounds__(256, 2) void k_score_strip(const Level *__restrict_
             val = *reinterpret_cast<const u16x8_t *>(f_base + (cy >> 3) * f_rowblk + (cy & 7) * 8);
         return val;
     };
+    // Cells right of the level's last whole cell hold finite partial counts
+    // (or 0 past the cache); they only reach windows that are not stored.
     auto store_row = [&](int slot, const u16x8_t &val) {
-        _Float16 *rp = ring + slot * ROWH + f_bin;
+        _Float16 *rp = ring + slot * ROWH + f_bin + 8 * f_seg * NBP;
         if (lane < nb * NSEG) {
 #pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                const int c = 8 * f_seg + e;
-                rp[c * NBP] = (wx0 + c < v.cells_x) ? (_Float16)(float)val[e] : (_Float16)0.f;
-            }
+            for (int e = 0; e < 8; ++e) rp[e * NBP] = (_Float16)val[e];
         }
     };
     // Sum of squared counts of staged cell `lane` (exact in FP32).
@@ -922,11 +935,13 @@ __global__ __launch_bounds__(256, 2) void k_score_strip(const Level *__restrict_
         float s = 0.f;
         if (lane < kStripCells) {
             const _Float16 *cp = ring + slot * ROWH + lane * NBP;
+            typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
 #pragma unroll
             for (int j = 0; j < NBP / 4; ++j) {
                 const half4_t h = *reinterpret_cast<const half4_t *>(cp + 4 * j);
-#pragma unroll
-                for (int e = 0; e < 4; ++e) s = fmaf((float)h[e], (float)h[e], s);
+                const half2_t h0 = {h[0], h[1]}, h1 = {h[2], h[3]};
+                s = __builtin_amdgcn_fdot2(h0, h0, s, false);
+                s = __builtin_amdgcn_fdot2(h1, h1, s, false);
             }
         }
         return s;
@@ -940,7 +955,6 @@ __global__ __launch_bounds__(256, 2) void k_score_strip(const Level *__restrict_
     const uint8_t *tp = ws + a.tprep_off + (int64_t)kk * a.tprep_stride;
     half8_t bh[kStripMaxBX][Sh::K32], bl[kStripMaxBX][Sh::K32];
     half4_t bh16[kStripMaxBX], bl16[kStripMaxBX];
-    float cs[kStripMaxBX];
 #pragma unroll
     for (int bx = 0; bx < kStripMaxBX; ++bx) {
 #pragma unroll
@@ -952,8 +966,8 @@ __global__ __launch_bounds__(256, 2) void k_score_strip(const Level *__restrict_
             bh16[bx] = *reinterpret_cast<const half4_t *>(tp + (((int64_t)(bx * Sh::S + Sh::K32) * 2 + 0) * 64 + lane) * 16);
             bl16[bx] = *reinterpret_cast<const half4_t *>(tp + (((int64_t)(bx * Sh::S + Sh::K32) * 2 + 1) * 64 + lane) * 16);
         }
-        cs[bx] = reinterpret_cast<const float *>(tp + (int64_t)kStripMaxBX * Sh::S * 2 * 64 * 16)[bx * 64 + lane];
     }
+    float cs = reinterpret_cast<const float *>(tp + (int64_t)kStripMaxBX * Sh::S * 2 * 64 * 16)[lane];
     // Keep the fragments in registers for the whole strip: without this the
     // compiler may reload them from memory inside the row loop.
 #pragma unroll
@@ -961,7 +975,6 @@ __global__ __launch_bounds__(256, 2) void k_score_strip(const Level *__restrict_
 #pragma unroll
         for (int j = 0; j < Sh::K32; ++j) asm volatile("" : "+v"(bh[bx][j]), "+v"(bl[bx][j]));
         if constexpr (Sh::K16 > 0) asm volatile("" : "+v"(bh16[bx]), "+v"(bl16[bx]));
-        asm volatile("" : "+v"(cs[bx]));
     }
 
     // A fragments: window column m = lane % 16; lane group q = lane / 16 takes
@@ -993,7 +1006,7 @@ __global__ __launch_bounds__(256, 2) void k_score_strip(const Level *__restrict_
     };
     store_row(wy_lo & 3, pre0);
     store_row((wy_lo + 1) & 3, pre1);
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront", "local");
+    lds_order();
     float sq1 = row_sq((wy_lo + 1) & 3);
     block_norms(wy_lo, row_sq(wy_lo & 3), sq1);
     const double bk = (double)bias[kk];
@@ -1003,7 +1016,7 @@ __global__ __launch_bounds__(256, 2) void k_score_strip(const Level *__restrict_
     // flight in pre2 and pre3 (fetched two block rows ahead).
     for (int Y = wy_lo; Y <= y_last; ++Y) {
         const bool more = Y + 2 <= y_last + 1;
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront", "local");
+        lds_order();
         // iv[t] = inv of block 4 q + t of this row (t = r + bx <= 9).
         float iv[10];
         {
@@ -1049,18 +1062,18 @@ __global__ __launch_bounds__(256, 2) void k_score_strip(const Level *__restrict_
 #pragma unroll
         for (int bx = 0; bx < kStripMaxBX; ++bx)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) acc32[r] = fmaf(d[bx][r], iv[r + bx] * cs[bx], acc32[r]);
+            for (int r = 0; r < 4; ++r) acc32[r] = fmaf(d[bx][r], iv[r + bx], acc32[r]);
         const int wy_done = Y - (a.nby - 1);
         const bool done = m == a.nby - 1 && wy_done >= wy_lo && wy_done < wy_hi;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            acc[r] += (double)acc32[r];
+            acc[r] += (double)(acc32[r] * cs);
             if (done) outb[(wy_done - wy_lo) * kStripW + 4 * q + r] = (float)(bk + acc[r]);
             acc[r] = shift_row_right(acc[r]);
         }
         if (more) {
             store_row((Y + 2) & 3, pre2);
-            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront", "local");
+            lds_order();
             // Next block row's norms, one row ahead of their use.
             const float sq2 = row_sq((Y + 2) & 3);
             block_norms(Y + 1, sq1, sq2);
@@ -1069,7 +1082,7 @@ __global__ __launch_bounds__(256, 2) void k_score_strip(const Level *__restrict_
         pre2 = pre3;
         if (Y + 4 <= y_last + 1) pre3 = fetch(Y + 4);
     }
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront", "local");
+    lds_order();
     const int n_out = (wy_hi - wy_lo) * kStripW;
     for (int i = lane; i < n_out; i += 64) {
         const int wx = wx0 + i % kStripW, wy = wy_lo + i / kStripW;
@@ -1242,21 +1255,21 @@ hipError_t launch_score(const PlanDev &p, const uint8_t *ws, const float *tmpl, 
         m.tprep_off = p.tprep_off;
         m.tprep_stride = p.tprep_stride;
         m.eps = p.eps;
-        const dim3 pgrid(blocks_for((int64_t)m.k * kStripMaxBX, 4)), sgrid(blocks_for(n, 4));
+        const dim3 pgrid((unsigned)m.k), pblock(64 * kStripMaxBX), sgrid(blocks_for(n, 4));
         // The prepared weights are rewritten in the workspace by every call.
         uint8_t *wsw = const_cast<uint8_t *>(ws);
         const size_t lds = (size_t)p.st_lds_bytes;
         switch (p.mfma_ks) {
         case 8:
-            hipLaunchKernelGGL(k_score_prep<8>, pgrid, block, 0, stream, m, tmpl, wsw);
+            hipLaunchKernelGGL(k_score_prep<8>, pgrid, pblock, 0, stream, m, tmpl, wsw);
             hipLaunchKernelGGL(k_score_strip<8>, sgrid, block, lds, stream, p.levels, f, p.n_levels, m, ws, bias, scores);
             break;
         case 16:
-            hipLaunchKernelGGL(k_score_prep<16>, pgrid, block, 0, stream, m, tmpl, wsw);
+            hipLaunchKernelGGL(k_score_prep<16>, pgrid, pblock, 0, stream, m, tmpl, wsw);
             hipLaunchKernelGGL(k_score_strip<16>, sgrid, block, lds, stream, p.levels, f, p.n_levels, m, ws, bias, scores);
             break;
         case 20:
-            hipLaunchKernelGGL(k_score_prep<20>, pgrid, block, 0, stream, m, tmpl, wsw);
+            hipLaunchKernelGGL(k_score_prep<20>, pgrid, pblock, 0, stream, m, tmpl, wsw);
             hipLaunchKernelGGL(k_score_strip<20>, sgrid, block, lds, stream, p.levels, f, p.n_levels, m, ws, bias, scores);
             break;
         default: return hipErrorInvalidValue;
