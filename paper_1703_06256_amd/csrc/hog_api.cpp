@@ -379,15 +379,24 @@ extern "C" hog_status hog_plan_create(const hog_plan_desc *desc, hog_plan **out)
         v.block_off = block_off;
         if (sp.norm == HOG_NORM_L2 && v.cells_x >= 2 && v.cells_y >= 2)
             block_off += (int64_t)(v.cells_x - 1) * (v.cells_y - 1) * 4 * nb;
-        // workspace
-        v.ws_rowtot = ws_off;
-        ws_off = round_up(ws_off + (int64_t)v.tiles_x * (lh + 1) * nb, 256);
-        v.ws_coltot = ws_off;
-        ws_off = round_up(ws_off + (int64_t)v.tiles_y * nb * (lw + 1), 256);
-        v.ws_e = ws_off;
-        ws_off = round_up(ws_off + (int64_t)v.tiles_x * (lh + 1) * nb * 4, 256);
-        v.ws_t = ws_off;
-        ws_off = round_up(ws_off + (int64_t)v.tiles_y * nb * (lw + 1) * 4, 256);
+        // workspace: integral carries (hp, wp = rows, columns rounded up to
+        // whole tiles), then the cell cache
+        {
+            const int64_t hp = (int64_t)hogk::kTile * v.tiles_y, wp = (int64_t)hogk::kTile * v.tiles_x;
+            const int64_t tiles = (int64_t)v.tiles_x * v.tiles_y;
+            v.ws_rowtot = ws_off;
+            ws_off = round_up(ws_off + (int64_t)v.tiles_x * nb * hp, 256);
+            v.ws_coltot = ws_off;
+            ws_off = round_up(ws_off + (int64_t)v.tiles_y * nb * wp, 256);
+            v.ws_tiletot = ws_off;
+            ws_off = round_up(ws_off + tiles * nb * 4, 256);
+            v.ws_e = ws_off;
+            ws_off = round_up(ws_off + (int64_t)v.tiles_x * nb * hp * 2, 256);
+            v.ws_cs = ws_off;
+            ws_off = round_up(ws_off + (int64_t)v.tiles_y * nb * wp * 2, 256);
+            v.ws_p = ws_off;
+            ws_off = round_up(ws_off + tiles * nb * 4, 256);
+        }
         v.ws_cache = ws_off;
         ws_off = round_up(ws_off + (int64_t)nb * v.cby * v.cbx * 64 * 2, 256);
 
@@ -448,8 +457,9 @@ extern "C" hog_status hog_plan_create(const hog_plan_desc *desc, hog_plan **out)
         int64_t items[hogk::KB_COUNT];
         items[hogk::KB_BINMAP] = (int64_t)v.bm_gx * v.bm_gy;
         items[hogk::KB_ITILE] = (int64_t)v.tiles_x * v.tiles_y;
-        items[hogk::KB_TSCAN] = (int64_t)v.tiles_y * nb;
-        items[hogk::KB_ESCAN] = (int64_t)(v.h + 1) * nb;
+        items[hogk::KB_CSCAN] = (int64_t)hogk::kTile * v.tiles_x * nb;
+        items[hogk::KB_ESCAN] = (int64_t)v.h * nb;
+        items[hogk::KB_PSCAN] = nb;
         items[hogk::KB_CELL] = (int64_t)v.cells_x * v.cells_y;
         items[hogk::KB_STILE] = (int64_t)v.st_x * v.st_y * (mfma_ks ? K : 1);
         items[hogk::KB_BLOCK] = (sp.norm == HOG_NORM_L2 && v.cells_x >= 2 && v.cells_y >= 2)
@@ -602,9 +612,7 @@ extern "C" hog_status hog_integral(const hog_plan *plan, const uint8_t *bins, ui
     });
     if (e != hipSuccess) return device_fail(e, "integral_reduce launch");
     e = timed_launch("integral_scan", s, [&] {
-        hipError_t e1 = hogk::launch_int_scan_rows(plan->dev, ws, s);
-        if (e1 != hipSuccess) return e1;
-        return hogk::launch_int_scan_cols(plan->dev, ws, s);
+        return hogk::launch_int_scan(plan->dev, ws, s);
     });
     if (e != hipSuccess) return device_fail(e, "integral_scan launch");
     e = timed_launch("integral_emit", s, [&] {

@@ -41,8 +41,9 @@ constexpr int64_t strip_prep_bytes(int nbp)
 enum {
     KB_BINMAP = 0,  // waves
     KB_ITILE,       // integral tiles
-    KB_TSCAN,       // workgroups of the column-carry scan: tiles_y * n_bins
-    KB_ESCAN,       // threads of the row-carry scan: (h + 1) * n_bins
+    KB_CSCAN,       // threads of the column-prefix scan: 64 tiles_x * n_bins
+    KB_ESCAN,       // threads of the row-carry scan: h * n_bins
+    KB_PSCAN,       // waves of the tile-total prefix: n_bins
     KB_CELL,        // threads of the cell kernel: cells
     KB_STILE,       // workgroups of the scorer: window tiles
     KB_BLOCK,       // threads of the block-feature kernel: blocks
@@ -63,11 +64,13 @@ struct Level {
     int64_t bins_off, bins_pitch;
     int64_t ii_off, ii_pitch, ii_plane;
     int64_t score_off, cell_off, block_off;
-    // workspace (bytes from the workspace base)
-    int64_t ws_rowtot;  // uint8  [tiles_x][nb][h+1]   per-tile row counts (padded rows)
-    int64_t ws_coltot;  // uint8  [tiles_y][nb][w+1]   per-tile column counts (padded cols)
-    int64_t ws_e;       // uint32 [tiles_x][nb][h+1]   row carry from the tiles on the left
-    int64_t ws_t;       // uint32 [tiles_y][nb][w+1]   plane row 64 ty of every tile row
+    // workspace (bytes from the workspace base); hp = 64 tiles_y, wp = 64 tiles_x
+    int64_t ws_rowtot;  // uint8  [tiles_x][nb][hp]   count of bin n in row y of tile column tx
+    int64_t ws_coltot;  // uint8  [tiles_y][nb][wp]   count of bin n in column x of tile row ty
+    int64_t ws_tiletot; // uint32 [tiles_y][tiles_x][nb]  count of bin n in each tile
+    int64_t ws_e;       // uint16 [tiles_x][nb][hp]   row y's count left of tile column tx
+    int64_t ws_cs;      // uint16 [tiles_y][nb][wp]   column x's count above tile row ty
+    int64_t ws_p;       // uint32 [tiles_y][tiles_x][nb]  count above and left of the tile
     int64_t ws_cache;   // uint16 [nb][cby][cbx][8][8] cell histogram cache
 };
 
@@ -102,8 +105,7 @@ hipError_t launch_bin_map(const PlanDev &p, const uint8_t *lut_half, const uint8
                           int64_t img_pitch, uint8_t *bins, hipStream_t stream);
 hipError_t launch_int_reduce(const PlanDev &p, const uint8_t *bins, uint8_t *ws,
                              hipStream_t stream);
-hipError_t launch_int_scan_rows(const PlanDev &p, uint8_t *ws, hipStream_t stream);
-hipError_t launch_int_scan_cols(const PlanDev &p, uint8_t *ws, hipStream_t stream);
+hipError_t launch_int_scan(const PlanDev &p, uint8_t *ws, hipStream_t stream);
 hipError_t launch_int_emit(const PlanDev &p, const uint8_t *bins, uint8_t *ws, uint32_t *ii,
                            hipStream_t stream);
 hipError_t launch_cells(const PlanDev &p, const uint32_t *ii, uint8_t *ws, uint32_t *cell_hist,

@@ -6,9 +6,9 @@
 // its level by a binary search over that table.
 //
 //   k_bin_map         Eq. 1 + Sec. 2    gradients, channel choice, table lookup
-//   k_int_reduce      Eq. 5 (pass 1)    per-tile row and column bin counts
-//   k_int_scan_rows   Eq. 5 (pass 2)    row carries from the tiles on the left
-//   k_int_scan_cols   Eq. 5 (pass 2)    plane row just above every tile row
+//   k_int_reduce      Eq. 5 (pass 1)    per-tile row, column and total bin counts
+//   k_int_scan        Eq. 5 (pass 2)    carries: row counts left of each tile, column
+//                                       counts above it, counts above-left of it
 //   k_int_emit        Eq. 4 + Eq. 5     one-hot in registers, write the planes
 //   k_cells           Eq. 6, Sec. 3.3   four-corner cell histograms, cached
 //   k_score           Sec. 3.1, Sec. 4  window features and inner products
@@ -215,13 +215,11 @@ __device__ __forceinline__ void stage_bin_tile(uint8_t *tb, __amdgpu_buffer_rsrc
 
 // ---------------------------------------------------------------------------
 // Integral images (Eq. 4 + Eq. 5) over pixel tiles of kTile x kTile: tile
-// (tx, ty) holds pixels [64 tx, 64 tx + 64) x [64 ty, 64 ty + 64), one wave
-// per tile and per chunk of bins, lane L on pixel column 64 tx + L. In the
-// planes, pixel (x, y) is padded element (y + 1, x + 1); padded row 0 and
-// column 0 are the zero guards.
+// (tx, ty) holds pixels [64 tx, 64 tx + 64) x [64 ty, 64 ty + 64), lane L on
+// pixel column 64 tx + L.
 //
-// Pass 1 (k_int_reduce): per tile, the count of each bin in each tile row
-// (a ballot per bin) and in each tile column (registers).
+// Pass 1 (k_int_reduce): per tile, the count of each bin in each of its rows,
+// in each of its columns, and in the whole tile.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(64) void k_int_reduce(const Level *__restrict__ lv,
                                                    const int32_t *__restrict__ first, int n_levels,
@@ -290,104 +288,161 @@ __global__ __launch_bounds__(64) void k_int_reduce(const Level *__restrict__ lv,
         }
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    // rowtot [tx][n][h+1] (padded rows), lane = row; coltot [ty][n][w+1] (padded cols).
-    uint8_t *rowtot = ws + v.ws_rowtot + (int64_t)tx * nb * (v.h + 1) + y0 + 1 + lane;
-    uint8_t *coltot = ws + v.ws_coltot + (int64_t)ty * nb * (v.w + 1) + x + 1;
+    // rowtot [tx][n][hp], lane = row; coltot [ty][n][wp], lane = column (0
+    // right of the level); tiletot [ty][tx][n].
+    const int hp = kTile * v.tiles_y, wp = kTile * v.tiles_x;
+    uint8_t *rowtot = ws + v.ws_rowtot + (int64_t)tx * nb * hp + y0 + lane;
+    uint8_t *coltot = ws + v.ws_coltot + (int64_t)ty * nb * wp + x;
+    uint32_t *tiletot = reinterpret_cast<uint32_t *>(ws + v.ws_tiletot) + ((int64_t)ty * v.tiles_x + tx) * nb;
     for (int n = 0; n < nb; ++n) {
-        if (lane < nrows) rowtot[(int64_t)n * (v.h + 1)] = (uint8_t)rowh[n * 64 + lane];
-        if (xin) coltot[(int64_t)n * (v.w + 1)] = (uint8_t)colh[n * 64 + lane];
+        if (lane < nrows) rowtot[(int64_t)n * hp] = (uint8_t)rowh[n * 64 + lane];
+        coltot[(int64_t)n * wp] = (uint8_t)colh[n * 64 + lane];
     }
-}
-
-// Pass 2a: E[tx][n][r] = number of n-pixels of padded row r in the tiles left
-// of tile column tx (exclusive scan over tx); row 0 is zero.
-__global__ __launch_bounds__(256) void k_int_scan_rows(const Level *__restrict__ lv,
-                                                       const int32_t *__restrict__ first,
-                                                       int n_levels, int nb,
-                                                       uint8_t *__restrict__ ws)
-{
-    const int g = (int)(blockIdx.x * 256 + threadIdx.x);
-    if (g >= first[n_levels]) return;
-    const int l = find_level(first, n_levels, g);
-    const Level &v = lv[l];
-    const int rel = g - first[l];  // n * (h + 1) + r
-    const int H1 = v.h + 1;
-    const int64_t stride = (int64_t)nb * H1;
-    const uint8_t *rt = ws + v.ws_rowtot + rel;
-    uint32_t *e = reinterpret_cast<uint32_t *>(ws + v.ws_e) + rel;
-    const bool row0 = (rel % H1) == 0;
-    uint32_t acc = 0;
-    int tx = 0;
-    for (; tx + 8 <= v.tiles_x; tx += 8) {
-        uint32_t c[8];
+    // Lane n < nb sums bin n's 64 column counts.
+    if (lane < nb) {
+        typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+        const u32x4 *cp = reinterpret_cast<const u32x4 *>(colh + lane * 64);
+        uint32_t t = 0;
 #pragma unroll
-        for (int i = 0; i < 8; ++i) c[i] = row0 ? 0u : rt[(tx + i) * stride];
-#pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            e[(tx + i) * stride] = acc;
-            acc += c[i];
+        for (int k = 0; k < 16; ++k) {
+            const u32x4 q4 = cp[k];
+            t += (q4[0] + q4[1]) + (q4[2] + q4[3]);
         }
-    }
-    for (; tx < v.tiles_x; ++tx) {
-        const uint32_t c = row0 ? 0u : rt[tx * stride];
-        e[tx * stride] = acc;
-        acc += c;
+        tiletot[lane] = t;
     }
 }
 
-// Pass 2b: T[ty][n][c] = plane value at padded row 64 ty, padded column c:
-// the inclusive prefix over c of the column counts of every tile row above.
-__global__ __launch_bounds__(256) void k_int_scan_cols(const Level *__restrict__ lv,
-                                                       const int32_t *__restrict__ first,
-                                                       int n_levels, int nb,
-                                                       uint8_t *__restrict__ ws)
+// Pass 2 (k_int_scan), one launch with three kinds of work (block ranges):
+//   rows:  E[tx][n][y]  = sum over t < tx of rowtot[t][n][y]   (thread per (n, y))
+//   cols:  CS[ty][n][x] = sum over k < ty of coltot[k][n][x]   (thread per (n, x))
+//   tiles: P[ty][tx][n] = sum over k < ty, t < tx of tiletot[k][t][n]
+//          (wave per n; lanes over tx, a wave scan per tile row)
+// From these the plane value just above a tile row is P + a prefix over the
+// tile's columns of CS, and the row carry of a pixel row is E (k_int_emit).
+struct ScanRanges {
+    int rows_blocks, cols_blocks;  // blocks of the first two kinds; the rest are tiles
+};
+
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v, int lane)
 {
-    const int wg = (int)blockIdx.x;
-    if (wg >= first[n_levels]) return;
-    const int l = find_level(first, n_levels, wg);
-    const Level &v = lv[l];
-    const int rel = wg - first[l];
-    const int ty = rel / nb, n = rel % nb;
-    const int W1 = v.w + 1;
-    const uint8_t *ct = ws + v.ws_coltot + (int64_t)n * W1;
-    const int64_t ct_stride = (int64_t)nb * W1;
-    uint32_t *T = reinterpret_cast<uint32_t *>(ws + v.ws_t) + ((int64_t)ty * nb + n) * W1;
-    __shared__ uint32_t wsum[4];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    uint32_t carry = 0;
-    for (int base = 0; base < W1; base += 256) {
-        const int c = base + (int)threadIdx.x;
-        uint32_t a = 0;
-        if (c >= 1 && c < W1) {
-            int k = 0;
-            for (; k + 4 <= ty; k += 4) {
-                const uint32_t a0 = ct[(k + 0) * ct_stride + c], a1 = ct[(k + 1) * ct_stride + c];
-                const uint32_t a2 = ct[(k + 2) * ct_stride + c], a3 = ct[(k + 3) * ct_stride + c];
-                a += (a0 + a1) + (a2 + a3);
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t o = __shfl_up(v, (unsigned)d);
+        if (lane >= d) v += o;
+    }
+    return v;
+}
+
+__global__ __launch_bounds__(256) void k_int_scan(const Level *__restrict__ lv,
+                                                  const int32_t *__restrict__ first_e,
+                                                  const int32_t *__restrict__ first_c,
+                                                  const int32_t *__restrict__ first_p, int n_levels,
+                                                  int nb, ScanRanges r, uint8_t *__restrict__ ws)
+{
+    const int blk = (int)blockIdx.x;
+    if (blk < r.rows_blocks) {
+        const int g = blk * 256 + (int)threadIdx.x;
+        if (g >= first_e[n_levels]) return;
+        const int l = find_level(first_e, n_levels, g);
+        const Level &v = lv[l];
+        const int rel = g - first_e[l];
+        const int n = rel / v.h, y = rel - n * v.h;
+        const int64_t hp = (int64_t)kTile * v.tiles_y, stride = (int64_t)nb * hp;
+        const uint8_t *rt = ws + v.ws_rowtot + n * hp + y;
+        uint16_t *e = reinterpret_cast<uint16_t *>(ws + v.ws_e) + n * hp + y;
+        uint32_t acc = 0;
+        int tx = 0;
+        for (; tx + 8 <= v.tiles_x; tx += 8) {
+            uint32_t c[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) c[i] = rt[(tx + i) * stride];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                e[(tx + i) * stride] = (uint16_t)acc;
+                acc += c[i];
             }
-            for (; k < ty; ++k) a += ct[k * ct_stride + c];
         }
-        uint32_t s = a;
+        for (; tx < v.tiles_x; ++tx) {
+            const uint32_t c = rt[tx * stride];
+            e[tx * stride] = (uint16_t)acc;
+            acc += c;
+        }
+        return;
+    }
+    if (blk < r.rows_blocks + r.cols_blocks) {
+        const int g = (blk - r.rows_blocks) * 256 + (int)threadIdx.x;
+        if (g >= first_c[n_levels]) return;
+        const int l = find_level(first_c, n_levels, g);
+        const Level &v = lv[l];
+        const int rel = g - first_c[l];
+        const int64_t wp = (int64_t)kTile * v.tiles_x, stride = (int64_t)nb * wp;
+        const int n = rel / (int)wp, x = rel - n * (int)wp;
+        const uint8_t *ct = ws + v.ws_coltot + n * wp + x;
+        uint16_t *cs = reinterpret_cast<uint16_t *>(ws + v.ws_cs) + n * wp + x;
+        uint32_t acc = 0;
+        int ty = 0;
+        for (; ty + 8 <= v.tiles_y; ty += 8) {
+            uint32_t c[8];
 #pragma unroll
-        for (int d = 1; d < 64; d <<= 1) {
-            const uint32_t o = __shfl_up(s, (unsigned)d);
-            if (lane >= d) s += o;
+            for (int i = 0; i < 8; ++i) c[i] = ct[(ty + i) * stride];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                cs[(ty + i) * stride] = (uint16_t)acc;
+                acc += c[i];
+            }
         }
-        if (lane == 63) wsum[wv] = s;
-        __syncthreads();
-        uint32_t off = carry;
-        for (int k = 0; k < wv; ++k) off += wsum[k];
-        const uint32_t tot = wsum[0] + wsum[1] + wsum[2] + wsum[3];
-        if (c < W1) T[c] = off + s;
-        carry += tot;
-        __syncthreads();
+        for (; ty < v.tiles_y; ++ty) {
+            const uint32_t c = ct[ty * stride];
+            cs[ty * stride] = (uint16_t)acc;
+            acc += c;
+        }
+        return;
+    }
+    // Tiles: one wave per (level, n); lanes over tile columns in chunks of 64.
+    const int lane = threadIdx.x & 63;
+    const int g = (blk - r.rows_blocks - r.cols_blocks) * 4 + wave_id_in_block();
+    if (g >= first_p[n_levels]) return;
+    const int l = find_level(first_p, n_levels, g);
+    const Level &v = lv[l];
+    const int n = g - first_p[l];
+    const uint32_t *tt = reinterpret_cast<const uint32_t *>(ws + v.ws_tiletot) + n;
+    uint32_t *P = reinterpret_cast<uint32_t *>(ws + v.ws_p) + n;
+    constexpr int kMaxChunks = 512 / 64;  // tiles_x <= 512 (width <= 32767)
+    constexpr int kRows = 8;              // tile rows whose totals are loaded together
+    uint32_t above[kMaxChunks];           // P of the current tile row, lane's columns
+#pragma unroll
+    for (int c = 0; c < kMaxChunks; ++c) above[c] = 0u;
+    for (int ty0 = 0; ty0 < v.tiles_y; ty0 += kRows) {
+        uint32_t carry[kRows];  // per row: its tiles left of the current chunk
+#pragma unroll
+        for (int i = 0; i < kRows; ++i) carry[i] = 0u;
+#pragma unroll
+        for (int c = 0; c < kMaxChunks; ++c) {
+            if (64 * c < v.tiles_x) {  // wave-uniform
+                const int tx = 64 * c + lane;
+                const bool on = tx < v.tiles_x;
+                uint32_t t[kRows];
+#pragma unroll
+                for (int i = 0; i < kRows; ++i)
+                    t[i] = (on && ty0 + i < v.tiles_y) ? tt[((int64_t)(ty0 + i) * v.tiles_x + tx) * nb] : 0u;
+#pragma unroll
+                for (int i = 0; i < kRows; ++i) {
+                    if (ty0 + i < v.tiles_y) {  // wave-uniform
+                        if (on) P[((int64_t)(ty0 + i) * v.tiles_x + tx) * nb] = above[c];
+                        const uint32_t incl = wave_incl_scan(t[i], lane);
+                        above[c] += carry[i] + incl - t[i];  // plus this row's tiles left of tx
+                        carry[i] += (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
+                    }
+                }
+            }
+        }
     }
 }
 
 // ---------------------------------------------------------------------------
 // Pass 3 (k_int_emit), Eq. 4 + Eq. 5 + Eq. 6. Each lane keeps, per bin of the
 // wave's chunk, the running plane value of its column, seeded with the plane
-// row 64 ty (T). Per pixel row: the one-hot image of Eq. 4 is a ballot per
+// value just above the tile. Per pixel row: the one-hot image of Eq. 4 is a ballot per
 // bin; its inclusive prefix along the tile row is a masked popcount (mbcnt);
 // with the row carry E of the tiles on the left it gives the row prefix R,
 // and ii(r, c) = ii(r-1, c) + R(r, c) is stored.
@@ -420,24 +475,30 @@ __global__ __launch_bounds__(256) void k_int_emit(const Level *__restrict__ lv,
     const int tx = t % v.tiles_x, ty = t / v.tiles_x;
     const int b0 = b_first + (gw - tile * n_chunk) * NBC;
     const int W = v.w, H = v.h;
-    const int W1 = W + 1, H1 = H + 1;
     const int x = tx * kTile + lane;
     const bool xin = x < W;
     const int y0 = ty * kTile, y1 = min(y0 + kTile, H);
     const uint32_t col4 = (uint32_t)x * 4u;  // byte offset of this lane's column in a plane row
 
-    const uint32_t *T = reinterpret_cast<const uint32_t *>(ws + v.ws_t) + ((int64_t)ty * nb + b0) * W1;
-    const uint32_t *Eb = reinterpret_cast<const uint32_t *>(ws + v.ws_e) + ((int64_t)tx * nb + b0) * H1;
-    const uint32_t tcol = (uint32_t)min(x + 1, W);
-    const int er = y0 + 1 + lane;  // padded row whose carry this lane holds
+    // Carries (k_int_scan): the plane value at (x, 64 ty - 1) is P (pixels
+    // above and left of the tile) plus the tile's columns' counts above it up
+    // to x (a wave scan of CS); row y's count left of the tile is E (lane
+    // y - y0 holds it). Right of the level CS is 0, so those lanes repeat the
+    // value at column w - 1.
+    const int64_t hp = (int64_t)kTile * v.tiles_y, wp = (int64_t)kTile * v.tiles_x;
+    const uint16_t *Eb = reinterpret_cast<const uint16_t *>(ws + v.ws_e) + ((int64_t)tx * nb + b0) * hp;
+    const uint16_t *CSb = reinterpret_cast<const uint16_t *>(ws + v.ws_cs) + ((int64_t)ty * nb + b0) * wp;
+    const uint32_t *Pb = reinterpret_cast<const uint32_t *>(ws + v.ws_p) + ((int64_t)ty * v.tiles_x + tx) * nb + b0;
+    const int er = y0 + lane;  // row whose carry this lane holds
     uint32_t run[NBC], top[NBC], ecar[NBC], lrun[NBC], ltop[NBC], cellacc[NBC];
 #pragma unroll
     for (int j = 0; j < NBC; ++j) {
-        run[j] = T[(int64_t)j * W1 + tcol];
+        const uint32_t pj = Pb[j];
+        run[j] = pj + wave_incl_scan((uint32_t)CSb[(int64_t)j * wp + x], lane);
         top[j] = run[j];
-        lrun[j] = T[(int64_t)j * W1 + tx * kTile];
-        ltop[j] = lrun[j];
-        ecar[j] = (er <= H) ? Eb[(int64_t)j * H1 + er] : 0u;
+        lrun[j] = pj;
+        ltop[j] = pj;
+        ecar[j] = (er < H) ? (uint32_t)Eb[(int64_t)j * hp + er] : 0u;
         cellacc[j] = 0u;
     }
     // All global loads of the tile happen here, before the first plane store:
@@ -1162,21 +1223,16 @@ hipError_t launch_int_reduce(const PlanDev &p, const uint8_t *bins, uint8_t *ws,
     return hipGetLastError();
 }
 
-hipError_t launch_int_scan_rows(const PlanDev &p, uint8_t *ws, hipStream_t stream)
+hipError_t launch_int_scan(const PlanDev &p, uint8_t *ws, hipStream_t stream)
 {
-    const int64_t n = p.total[KB_ESCAN];
+    ScanRanges r;
+    r.rows_blocks = (int)blocks_for(p.total[KB_ESCAN], 256);
+    r.cols_blocks = (int)blocks_for(p.total[KB_CSCAN], 256);
+    const int tile_blocks = (int)blocks_for(p.total[KB_PSCAN], 4);
+    const int n = r.rows_blocks + r.cols_blocks + tile_blocks;
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_int_scan_rows, dim3(blocks_for(n, 256)), dim3(256), 0, stream, p.levels,
-                       first_of(p, KB_ESCAN), p.n_levels, p.n_bins, ws);
-    return hipGetLastError();
-}
-
-hipError_t launch_int_scan_cols(const PlanDev &p, uint8_t *ws, hipStream_t stream)
-{
-    const int64_t n = p.total[KB_TSCAN];
-    if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_int_scan_cols, dim3((unsigned)n), dim3(256), 0, stream, p.levels,
-                       first_of(p, KB_TSCAN), p.n_levels, p.n_bins, ws);
+    hipLaunchKernelGGL(k_int_scan, dim3((unsigned)n), dim3(256), 0, stream, p.levels, first_of(p, KB_ESCAN),
+                       first_of(p, KB_CSCAN), first_of(p, KB_PSCAN), p.n_levels, p.n_bins, r, ws);
     return hipGetLastError();
 }
 
