@@ -124,8 +124,8 @@ typedef struct {
     int64_t bins_pitch;      /* bytes */
     int64_t ii_offset;       /* elements; ii(x, y) of bin n at ii[ii_offset +
                                 n*ii_plane_stride + y*ii_pitch + x] (hog_integral) */
-    int64_t ii_pitch;        /* elements between rows, multiple of 64 */
-    int64_t ii_plane_stride; /* elements between bins' planes, multiple of 64 */
+    int64_t ii_pitch;        /* elements between rows, multiple of 32 */
+    int64_t ii_plane_stride; /* elements between bins' planes, multiple of 32 */
     int32_t cells_x, cells_y;    /* whole cells: floor(width / cell), ... */
     int32_t windows_x, windows_y;/* window grid; 0 x 0 if the level is smaller than a window */
     int64_t score_offset;    /* elements; scores[score_offset + (wy*windows_x + wx)*K + k] */

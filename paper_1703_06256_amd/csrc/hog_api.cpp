@@ -365,10 +365,9 @@ extern "C" hog_status hog_plan_create(const hog_plan_desc *desc, hog_plan **out)
         v.bins_pitch = round_up(lw, 64);
         v.bins_off = bins_off;
         bins_off = round_up(bins_off + v.bins_pitch * lh, 256);
-        // Planes: ii(x, y) at [y * pitch + x]; every row starts a 256-byte
-        // line and holds every tile's full 64 columns, so each store is whole
-        // lines.
-        v.ii_pitch = (int64_t)hogk::kTile * v.tiles_x;
+        // Planes: ii(x, y) at [y * pitch + x]; rows are whole 128-byte lines
+        // (pitch a multiple of 32), so every row store is whole lines.
+        v.ii_pitch = round_up(lw, 32);
         v.ii_plane = v.ii_pitch * lh;
         v.ii_off = round_up(ii_off, 64);
         ii_off = v.ii_off + v.ii_plane * nb;

@@ -478,7 +478,11 @@ __global__ __launch_bounds__(256) void k_int_emit(const Level *__restrict__ lv,
     const int x = tx * kTile + lane;
     const bool xin = x < W;
     const int y0 = ty * kTile, y1 = min(y0 + kTile, H);
-    const uint32_t col4 = (uint32_t)x * 4u;  // byte offset of this lane's column in a plane row
+    // Byte offset of this lane's column in a plane row. Lanes right of the
+    // row pitch store at its last element: right of the level every lane
+    // holds the value of column w - 1, so those duplicate stores write the
+    // same value and every row store covers whole lines.
+    const uint32_t col4 = (uint32_t)min(x, (int)v.ii_pitch - 1) * 4u;
 
     // Carries (k_int_scan): the plane value at (x, 64 ty - 1) is P (pixels
     // above and left of the tile) plus the tile's columns' counts above it up
@@ -513,8 +517,6 @@ __global__ __launch_bounds__(256) void k_int_emit(const Level *__restrict__ lv,
     const int plane4 = (int)(v.ii_plane * 4), pitch4 = (int)(v.ii_pitch * 4);
     const __amdgpu_buffer_rsrc_t isrc =
         buffer_rsrc(ii + v.ii_off + (int64_t)b0 * v.ii_plane, (uint32_t)(NBC * plane4));
-    // Whole 256-byte rows: lanes right of the image (x >= w) repeat column
-    // w - 1 inside the row pitch.
     auto store_row = [&](int j, int y, uint32_t val) {
         __builtin_amdgcn_raw_buffer_store_b32(val, isrc, (int)col4, j * plane4 + y * pitch4, 0);
     };
