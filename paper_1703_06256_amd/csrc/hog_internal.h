@@ -21,7 +21,7 @@ constexpr int kLutHalfBytes = 256 * 511;
 // chunk of at most kMaxBinChunk bins; bins are read kRowBatch rows at a time.
 constexpr int kTile = 64;
 constexpr int kRowBatch = 16;
-constexpr int kMaxBinChunk = 9;
+constexpr int kMaxBinChunk = 6;
 
 // Matrix-core window scorer: one wave per strip of kStripW window columns and
 // kStripTH window rows; windows kStripMaxBX + 1 cells wide.

@@ -459,7 +459,7 @@ __global__ __launch_bounds__(256) void k_int_scan(const Level *__restrict__ lv,
 template <int NBC, bool CELLS>
 __global__ __launch_bounds__(256) void k_int_emit(const Level *__restrict__ lv,
                                                   const int32_t *__restrict__ first, int n_levels,
-                                                  int nb, int b_first, int n_chunk,
+                                                  int nb, int n_chunk,
                                                   const uint8_t *__restrict__ bins,
                                                   uint8_t *__restrict__ ws,
                                                   uint32_t *__restrict__ ii)
@@ -473,7 +473,9 @@ __global__ __launch_bounds__(256) void k_int_emit(const Level *__restrict__ lv,
     const Level &v = lv[l];
     const int t = tile - first[l];
     const int tx = t % v.tiles_x, ty = t / v.tiles_x;
-    const int b0 = b_first + (gw - tile * n_chunk) * NBC;
+    // This wave's bins: b0 .. b0 + nbc - 1 (the last chunk may be short).
+    const int b0 = (gw - tile * n_chunk) * NBC;
+    const int nbc = min(NBC, nb - b0);
     const int W = v.w, H = v.h;
     const int x = tx * kTile + lane;
     const bool xin = x < W;
@@ -497,12 +499,12 @@ __global__ __launch_bounds__(256) void k_int_emit(const Level *__restrict__ lv,
     uint32_t run[NBC], top[NBC], ecar[NBC], lrun[NBC], ltop[NBC], cellacc[NBC];
 #pragma unroll
     for (int j = 0; j < NBC; ++j) {
-        const uint32_t pj = Pb[j];
-        run[j] = pj + wave_incl_scan((uint32_t)CSb[(int64_t)j * wp + x], lane);
+        const uint32_t pj = j < nbc ? Pb[j] : 0u;
+        run[j] = pj + wave_incl_scan(j < nbc ? (uint32_t)CSb[(int64_t)j * wp + x] : 0u, lane);
         top[j] = run[j];
         lrun[j] = pj;
         ltop[j] = pj;
-        ecar[j] = (er < H) ? (uint32_t)Eb[(int64_t)j * hp + er] : 0u;
+        ecar[j] = (j < nbc && er < H) ? (uint32_t)Eb[(int64_t)j * hp + er] : 0u;
         cellacc[j] = 0u;
     }
     // All global loads of the tile happen here, before the first plane store:
@@ -513,10 +515,10 @@ __global__ __launch_bounds__(256) void k_int_emit(const Level *__restrict__ lv,
     stage_bin_tile(tb, buffer_rsrc(bins + v.bins_off, (uint32_t)(v.bins_pitch * v.h)),
                    (int)v.bins_pitch, tx, y0, lane);
 
-    // The chunk's NBC planes as one buffer; the plan keeps NBC * plane * 4 < 2^31.
+    // The chunk's nbc planes as one buffer; the plan keeps NBC * plane * 4 < 2^31.
     const int plane4 = (int)(v.ii_plane * 4), pitch4 = (int)(v.ii_pitch * 4);
     const __amdgpu_buffer_rsrc_t isrc =
-        buffer_rsrc(ii + v.ii_off + (int64_t)b0 * v.ii_plane, (uint32_t)(NBC * plane4));
+        buffer_rsrc(ii + v.ii_off + (int64_t)b0 * v.ii_plane, (uint32_t)(nbc * plane4));
     auto store_row = [&](int j, int y, uint32_t val) {
         __builtin_amdgcn_raw_buffer_store_b32(val, isrc, (int)col4, j * plane4 + y * pitch4, 0);
     };
@@ -527,6 +529,7 @@ __global__ __launch_bounds__(256) void k_int_emit(const Level *__restrict__ lv,
         const int rr = y - y0;
 #pragma unroll
         for (int j = 0; j < NBC; ++j) {
+            if (j >= nbc) break;  // wave-uniform
             const bool hit = rel == j;
             const uint64_t m = __ballot(hit);
             const uint32_t e = (uint32_t)__builtin_amdgcn_readlane((int)ecar[j], rr);
@@ -546,6 +549,7 @@ __global__ __launch_bounds__(256) void k_int_emit(const Level *__restrict__ lv,
             const int src = 8 * (lane & 7) + 7;
 #pragma unroll
             for (int j = 0; j < NBC; ++j) {
+                if (j >= nbc) break;  // wave-uniform
                 const uint32_t rl = __shfl_up(run[j], 8u);
                 const uint32_t tl = __shfl_up(top[j], 8u);
                 const uint32_t left = (lane == 7) ? lrun[j] : rl;
@@ -584,7 +588,7 @@ __global__ __launch_bounds__(256) void k_int_emit(const Level *__restrict__ lv,
             uint16_t *cache = reinterpret_cast<uint16_t *>(ws + v.ws_cache);
 #pragma unroll
             for (int j = 0; j < NBC; ++j)
-                cache[(((int64_t)(b0 + j) * v.cby + ty) * v.cbx + tx) * 64 + lane] = (uint16_t)cellacc[j];
+                if (j < nbc) cache[(((int64_t)(b0 + j) * v.cby + ty) * v.cbx + tx) * 64 + lane] = (uint16_t)cellacc[j];
         }
     }
 }
@@ -1238,40 +1242,32 @@ hipError_t launch_int_scan(const PlanDev &p, uint8_t *ws, hipStream_t stream)
     return hipGetLastError();
 }
 
-// k_int_emit for chunks of NBC bins, with or without the fused cell cache.
-#define HOG_EMIT_CASE(NBC)                                                                          \
+// k_int_emit for chunks of NBC bins (the last one possibly shorter), with or
+// without the fused cell cache.
+#define HOG_EMIT_CASE(NBC)                                                                        \
     case NBC:                                                                                     \
         if (cells)                                                                                \
             hipLaunchKernelGGL((k_int_emit<NBC, true>), grid, dim3(256), 0, stream, p.levels,     \
-                               first_of(p, KB_ITILE), p.n_levels, p.n_bins, b_first, n_chunk, bins, \
-                               ws, ii);                                                           \
+                               first_of(p, KB_ITILE), p.n_levels, p.n_bins, p.n_chunks, bins, ws, \
+                               ii);                                                               \
         else                                                                                      \
             hipLaunchKernelGGL((k_int_emit<NBC, false>), grid, dim3(256), 0, stream, p.levels,    \
-                               first_of(p, KB_ITILE), p.n_levels, p.n_bins, b_first, n_chunk, bins, \
-                               ws, ii);                                                           \
+                               first_of(p, KB_ITILE), p.n_levels, p.n_bins, p.n_chunks, bins, ws, \
+                               ii);                                                               \
         break;
-
-static hipError_t emit_chunks(const PlanDev &p, int nbc, int b_first, int n_chunk, const uint8_t *bins,
-                              uint8_t *ws, uint32_t *ii, hipStream_t stream)
-{
-    const bool cells = p.cell == 8;
-    const dim3 grid(blocks_for(p.total[KB_ITILE] * n_chunk, 4));
-    switch (nbc) {
-        HOG_EMIT_CASE(1) HOG_EMIT_CASE(2) HOG_EMIT_CASE(3) HOG_EMIT_CASE(4) HOG_EMIT_CASE(5)
-        HOG_EMIT_CASE(6) HOG_EMIT_CASE(7) HOG_EMIT_CASE(8) HOG_EMIT_CASE(9)
-    default: return hipErrorInvalidValue;
-    }
-    return hipSuccess;
-}
 
 hipError_t launch_int_emit(const PlanDev &p, const uint8_t *bins, uint8_t *ws, uint32_t *ii,
                            hipStream_t stream)
 {
     if (p.total[KB_ITILE] == 0) return hipSuccess;
-    const int full = p.n_bins / p.bin_chunk, rem = p.n_bins % p.bin_chunk;
-    hipError_t e = emit_chunks(p, p.bin_chunk, 0, full, bins, ws, ii, stream);
-    if (e == hipSuccess && rem) e = emit_chunks(p, rem, full * p.bin_chunk, 1, bins, ws, ii, stream);
-    if (e != hipSuccess) return e;
+    const bool cells = p.cell == 8;
+    const dim3 grid(blocks_for(p.total[KB_ITILE] * p.n_chunks, 4));
+    static_assert(kMaxBinChunk == 6, "one case per chunk size");
+    switch (p.bin_chunk) {
+        HOG_EMIT_CASE(1) HOG_EMIT_CASE(2) HOG_EMIT_CASE(3) HOG_EMIT_CASE(4) HOG_EMIT_CASE(5)
+        HOG_EMIT_CASE(6)
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
