@@ -147,9 +147,32 @@ typedef struct {
     int64_t total_windows;    /* sum of window counts */
 } hog_plan_sizes;
 
+/* One image of a plan: its levels, and where hog_bin_map reads it. */
+typedef struct {
+    int32_t first_level, n_levels; /* the image's levels among the plan's */
+    int32_t width, height;
+    int64_t img_offset;   /* bytes from the input pointer to the image's first pixel */
+    int64_t img_pitch;    /* bytes per row; 0: the img_pitch passed to hog_bin_map */
+    int64_t total_pixels; /* sum of the image's level areas */
+    int64_t total_windows;
+} hog_image_info;
+
 /* Validate desc, plan the levels, tiles and buffer layout, and upload the
  * plan's tables to the current device (library-owned; synchronous). */
 hog_status hog_plan_create(const hog_plan_desc *desc, hog_plan **out);
+
+/* A batch: n_images images of any sizes (descs[i]: image i's size and
+ * pyramid), planned together so that each call below is one launch per kernel
+ * for every level of every image -- the scan of Sec. 4 over many images at
+ * once. channels, n_bins, n_templates and scan must be equal across the
+ * descriptions (HOG_E_INVALID otherwise). The input of hog_bin_map is one
+ * device buffer holding the images packed in order, image i at img_offset
+ * with rows of width*channels bytes (hog_plan_get_image); pass img_pitch = 0.
+ * Levels are numbered image by image; each image's results equal those of a
+ * single-image plan of the same description. 1 <= n_images <= 65536. */
+hog_status hog_plan_create_batch(const hog_plan_desc *descs, int n_images, hog_plan **out);
+int hog_plan_images(const hog_plan *plan);
+hog_status hog_plan_get_image(const hog_plan *plan, int image, hog_image_info *out);
 void hog_plan_destroy(hog_plan *plan);
 hog_status hog_plan_get_sizes(const hog_plan *plan, hog_plan_sizes *out);
 hog_status hog_plan_get_level(const hog_plan *plan, int level, hog_level_info *out);
@@ -159,7 +182,8 @@ hog_status hog_plan_get_level(const hog_plan *plan, int level, hog_level_info *o
 /* ------------------------------------------------------------------------ */
 
 /* Eq. 1 + Sec. 2. img: device, uint8, row-major, channels interleaved,
- * img_pitch bytes per row (>= width*channels). For every level, writes the
+ * img_pitch bytes per row (>= width*channels; 0 for a batch plan, whose
+ * images are packed as hog_plan_get_image says). For every level, writes the
  * bin map into bins (device, plan layout): for interior pixels, per channel
  * dx = P[x+1][y] - P[x-1][y], dy = P[x][y+1] - P[x][y-1] (on the level's
  * nearest-neighbour image); the channel with the largest dx^2 + dy^2 wins

@@ -133,7 +133,9 @@ struct hog_lut {
 };
 
 struct hog_plan {
-    hog_plan_desc desc;
+    hog_plan_desc desc;  // image 0's (shared fields are equal across images)
+    bool batch;          // images packed in one buffer; hog_bin_map takes img_pitch 0
+    std::vector<hog_image_info> images;
     std::vector<Level> levels;
     std::vector<hog_level_info> info;
     hog_plan_sizes sizes;
@@ -264,15 +266,30 @@ static hog_status check_desc(const hog_plan_desc *d)
     return HOG_OK;
 }
 
-extern "C" hog_status hog_plan_create(const hog_plan_desc *desc, hog_plan **out)
+static bool same_scan(const hog_scan_params &a, const hog_scan_params &b)
+{
+    return a.cell == b.cell && a.win_cells_x == b.win_cells_x && a.win_cells_y == b.win_cells_y &&
+           a.block == b.block && a.norm == b.norm && (a.eps == b.eps || a.norm == HOG_NORM_RAW);
+}
+
+// Builds a plan over n_img images (batch: packed input, per-level pitch).
+static hog_status create_plan(const hog_plan_desc *descs, int n_img, bool batch, hog_plan **out)
 {
     if (!out) return fail(HOG_E_INVALID, "out is NULL");
     *out = nullptr;
-    hog_status st = check_desc(desc);
-    if (st != HOG_OK) return st;
-    const hog_plan_desc d = *desc;
-    const hog_scan_params &sp = d.scan;
-    const int nb = d.n_bins, K = d.n_templates;
+    if (!descs) return fail(HOG_E_INVALID, "desc is NULL");
+    if (n_img < 1 || n_img > 65536) return fail(HOG_E_INVALID, "n_images must be in [1, 65536], got %d", n_img);
+    for (int i = 0; i < n_img; ++i) {
+        hog_status st = check_desc(&descs[i]);
+        if (st != HOG_OK) return st;
+        const hog_plan_desc &a = descs[0], &b = descs[i];
+        if (b.channels != a.channels || b.n_bins != a.n_bins || b.n_templates != a.n_templates ||
+            !same_scan(a.scan, b.scan))
+            return fail(HOG_E_INVALID, "image %d: channels, n_bins, n_templates and scan must match image 0", i);
+    }
+    const hog_plan_desc d0 = descs[0];
+    const hog_scan_params &sp = d0.scan;
+    const int nb = d0.n_bins, K = d0.n_templates;
     const int win_w = sp.cell * sp.win_cells_x, win_h = sp.cell * sp.win_cells_y;
     const int dim = sp.norm == HOG_NORM_RAW
                         ? sp.win_cells_x * sp.win_cells_y * nb
@@ -316,17 +333,28 @@ extern "C" hog_status hog_plan_create(const hog_plan_desc *desc, hog_plan **out)
 
     hog_plan *p = new (std::nothrow) hog_plan;
     if (!p) return fail(HOG_E_NOMEM, "host allocation failed");
-    p->desc = d;
+    p->desc = d0;
+    p->batch = batch;
     p->dev_mem = nullptr;
     std::vector<int32_t> mapx, mapy;
 
-    // Levels (nearest-neighbour pyramid): s_0 = 1, s_l = s_{l-1} * scale.
-    double s = 1.0;
     int64_t bins_off = 0, ii_off = 0, score_off = 0, cell_off = 0, block_off = 0, ws_off = 0;
-    int64_t tot_px = 0, tot_win = 0;
+    int64_t tot_px = 0, tot_win = 0, src_off = 0;
     const int n_chunks = (nb + hogk::kMaxBinChunk - 1) / hogk::kMaxBinChunk;
     const int chunk = (nb + n_chunks - 1) / n_chunks;
     int chunk_final = chunk;
+    for (int img = 0; img < n_img; ++img) {
+    const hog_plan_desc &d = descs[img];
+    hog_image_info ii_info;
+    std::memset(&ii_info, 0, sizeof ii_info);
+    ii_info.first_level = (int32_t)p->levels.size();
+    ii_info.width = d.width;
+    ii_info.height = d.height;
+    ii_info.img_offset = batch ? src_off : 0;
+    ii_info.img_pitch = batch ? (int64_t)d.width * d.channels : 0;
+    const int64_t img_px0 = tot_px, img_win0 = tot_win;
+    // Levels (nearest-neighbour pyramid): s_0 = 1, s_l = s_{l-1} * scale.
+    double s = 1.0;
     for (int l = 0;; ++l) {
         if (d.max_levels > 0 && l >= d.max_levels) break;
         if (l >= 256) break;
@@ -352,6 +380,10 @@ extern "C" hog_status hog_plan_create(const hog_plan_desc *desc, hog_plan **out)
         v.bm_gy = (lh + hogk::kBinRows - 1) / hogk::kBinRows;
         v.st_x = v.win_x ? (v.win_x + best_tw - 1) / best_tw : 0;
         v.st_y = v.win_y ? (v.win_y + best_th - 1) / best_th : 0;
+        v.src_w = d.width;
+        v.src_h = d.height;
+        v.src_off = ii_info.img_offset;
+        v.src_pitch = ii_info.img_pitch;
         v.mapx_off = (int64_t)mapx.size();
         v.mapy_off = (int64_t)mapy.size();
         for (int x = 0; x < lw; ++x) {
@@ -420,6 +452,12 @@ extern "C" hog_status hog_plan_create(const hog_plan_desc *desc, hog_plan **out)
         tot_win += (int64_t)v.win_x * v.win_y;
         s = s * d.scale;
         if (d.max_levels == 1) break;
+    }
+    ii_info.n_levels = (int32_t)p->levels.size() - ii_info.first_level;
+    ii_info.total_pixels = tot_px - img_px0;
+    ii_info.total_windows = tot_win - img_win0;
+    p->images.push_back(ii_info);
+    src_off += (int64_t)d.width * d.height * d.channels;
     }
     const int L = (int)p->levels.size();
     // Prepared template fragments of the matrix-core scorer (rewritten by
@@ -512,9 +550,7 @@ extern "C" hog_status hog_plan_create(const hog_plan_desc *desc, hog_plan **out)
     pd.mapy = (const int32_t *)(base + o_my);
     pd.n_levels = L;
     pd.n_bins = nb;
-    pd.channels = d.channels;
-    pd.src_w = d.width;
-    pd.src_h = d.height;
+    pd.channels = d0.channels;
     pd.n_templates = K;
     pd.cell = sp.cell;
     pd.win_cells_x = sp.win_cells_x;
@@ -558,6 +594,27 @@ extern "C" hog_status hog_plan_create(const hog_plan_desc *desc, hog_plan **out)
     return HOG_OK;
 }
 
+extern "C" hog_status hog_plan_create(const hog_plan_desc *desc, hog_plan **out)
+{
+    return create_plan(desc, 1, false, out);
+}
+
+extern "C" hog_status hog_plan_create_batch(const hog_plan_desc *descs, int n_images, hog_plan **out)
+{
+    return create_plan(descs, n_images, true, out);
+}
+
+extern "C" int hog_plan_images(const hog_plan *plan) { return plan ? (int)plan->images.size() : 0; }
+
+extern "C" hog_status hog_plan_get_image(const hog_plan *plan, int image, hog_image_info *out)
+{
+    if (!plan || !out) return fail(HOG_E_INVALID, "plan or out is NULL");
+    if (image < 0 || image >= (int)plan->images.size())
+        return fail(HOG_E_INVALID, "image %d outside [0, %d)", image, (int)plan->images.size());
+    *out = plan->images[image];
+    return HOG_OK;
+}
+
 extern "C" void hog_plan_destroy(hog_plan *plan)
 {
     if (!plan) return;
@@ -590,8 +647,11 @@ extern "C" hog_status hog_bin_map(const hog_plan *plan, const hog_lut *lut, cons
     if (!plan || !lut || !img || !bins) return fail(HOG_E_INVALID, "NULL argument");
     if (lut->n_bins != plan->desc.n_bins)
         return fail(HOG_E_INVALID, "lut has %d bins, plan has %d", lut->n_bins, plan->desc.n_bins);
-    if (img_pitch < (int64_t)plan->desc.width * plan->desc.channels)
+    if (plan->batch) {
+        if (img_pitch != 0) return fail(HOG_E_INVALID, "a batch plan takes img_pitch 0 (images are packed)");
+    } else if (img_pitch < (int64_t)plan->desc.width * plan->desc.channels) {
         return fail(HOG_E_INVALID, "img_pitch %lld < width*channels", (long long)img_pitch);
+    }
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = timed_launch("bin_map", s, [&] {
         return hogk::launch_bin_map(plan->dev, lut->dev_half, img, img_pitch, bins, s);

@@ -60,6 +60,9 @@ struct Level {
     int32_t bm_gx, bm_gy;      // bin-map waves
     int32_t st_x, st_y;        // scorer tiles
     int32_t cbx, cby;          // 8 x 8-cell blocks of the cell cache: ceil(cells / 8)
+    int32_t src_w, src_h;      // the level's source image (nearest-neighbour maps index it)
+    int64_t src_off;           // bytes: the source image in the input buffer
+    int64_t src_pitch;         // bytes per source row; 0: the pitch passed to the call
     int64_t mapx_off, mapy_off;
     int64_t bins_off, bins_pitch;
     int64_t ii_off, ii_pitch, ii_plane;
@@ -82,7 +85,6 @@ struct PlanDev {
     int32_t n_levels;
     int32_t n_bins;
     int32_t channels;
-    int32_t src_w, src_h;
     int32_t n_templates;
     int32_t cell, win_cells_x, win_cells_y, block, norm;
     float eps;

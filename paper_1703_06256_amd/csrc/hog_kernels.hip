@@ -103,8 +103,8 @@ __global__ __launch_bounds__(1024) void k_bin_map(const Level *__restrict__ lv,
                                                   const int32_t *__restrict__ first, int n_levels,
                                                   const int32_t *__restrict__ mapx,
                                                   const int32_t *__restrict__ mapy,
-                                                  const uint8_t *__restrict__ img, int64_t pitch,
-                                                  int src_w, int nb,
+                                                  const uint8_t *__restrict__ img, int64_t call_pitch,
+                                                  int nb,
                                                   const uint8_t *__restrict__ lut_half,
                                                   uint8_t *__restrict__ bins)
 {
@@ -127,6 +127,8 @@ __global__ __launch_bounds__(1024) void k_bin_map(const Level *__restrict__ lv,
         const int W = v.w, H = v.h;
         const int t = item - first[l];
         const int gx = t % v.bm_gx, gy = t / v.bm_gx;
+        const int src_w = v.src_w;
+        const int64_t pitch = v.src_pitch > 0 ? v.src_pitch : call_pitch;
         const int x = gx * kBinCols - 1 + lane;
         const bool col_ok = x >= 0 && x < W;
         const int32_t *my = mapy + v.mapy_off;
@@ -142,7 +144,7 @@ __global__ __launch_bounds__(1024) void k_bin_map(const Level *__restrict__ lv,
             shift = last ? 8u : 0u;
             can_load = col_ok && src_w >= 2;  // a 1-pixel-wide image has no interior
         }
-        const uint8_t *colp = img + coff;
+        const uint8_t *colp = img + v.src_off + coff;
         const int y0 = gy * kBinRows;
 
         uint32_t smp[kBinRows + 2];
@@ -1211,11 +1213,11 @@ hipError_t launch_bin_map(const PlanDev &p, const uint8_t *lut_half, const uint8
     if (p.channels == 1)
         hipLaunchKernelGGL(k_bin_map<1>, dim3(grid), dim3(1024), 0, stream, p.levels,
                            first_of(p, KB_BINMAP), p.n_levels, p.mapx, p.mapy, img, img_pitch,
-                           p.src_w, p.n_bins, lut_half, bins);
+                           p.n_bins, lut_half, bins);
     else
         hipLaunchKernelGGL(k_bin_map<3>, dim3(grid), dim3(1024), 0, stream, p.levels,
                            first_of(p, KB_BINMAP), p.n_levels, p.mapx, p.mapy, img, img_pitch,
-                           p.src_w, p.n_bins, lut_half, bins);
+                           p.n_bins, lut_half, bins);
     return hipGetLastError();
 }
 

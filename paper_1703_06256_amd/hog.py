@@ -23,7 +23,8 @@ LUT_SIDE = 511
 # Every symbol include/hog.h declares.
 EXPORTS = (
     "hog_last_error", "hog_lut_fill_host", "hog_lut_build", "hog_lut_free", "hog_lut_bins",
-    "hog_lut_host", "hog_plan_create", "hog_plan_destroy", "hog_plan_get_sizes",
+    "hog_lut_host", "hog_plan_create", "hog_plan_create_batch", "hog_plan_images",
+    "hog_plan_get_image", "hog_plan_destroy", "hog_plan_get_sizes",
     "hog_plan_get_level", "hog_bin_map", "hog_integral", "hog_scan_windows",
     "hog_timing_enable", "hog_timing_reset", "hog_timing_get",
 )
@@ -59,6 +60,13 @@ class LevelInfo(ctypes.Structure):
                 ("block_offset", ctypes.c_int64)]
 
 
+class ImageInfo(ctypes.Structure):
+    _fields_ = [("first_level", ctypes.c_int32), ("n_levels", ctypes.c_int32),
+                ("width", ctypes.c_int32), ("height", ctypes.c_int32),
+                ("img_offset", ctypes.c_int64), ("img_pitch", ctypes.c_int64),
+                ("total_pixels", ctypes.c_int64), ("total_windows", ctypes.c_int64)]
+
+
 class PlanSizes(ctypes.Structure):
     _fields_ = [("n_levels", ctypes.c_int32), ("bins_bytes", ctypes.c_int64),
                 ("ii_elems", ctypes.c_int64), ("score_elems", ctypes.c_int64),
@@ -88,6 +96,9 @@ def load_library():
         "hog_lut_bins": ([vp], i32),
         "hog_lut_host": ([vp], vp),
         "hog_plan_create": ([ctypes.POINTER(PlanDesc), ctypes.POINTER(vp)], i32),
+        "hog_plan_create_batch": ([ctypes.POINTER(PlanDesc), i32, ctypes.POINTER(vp)], i32),
+        "hog_plan_images": ([vp], i32),
+        "hog_plan_get_image": ([vp, i32, ctypes.POINTER(ImageInfo)], i32),
         "hog_plan_destroy": ([vp], None),
         "hog_plan_get_sizes": ([vp, ctypes.POINTER(PlanSizes)], i32),
         "hog_plan_get_level": ([vp, i32, ctypes.POINTER(LevelInfo)], i32),
@@ -180,13 +191,28 @@ def make_desc(width, height, channels=1, n_bins=8, max_levels=1, scale=1.0, n_te
 
 
 class Plan:
-    """Level geometry and buffer layout for one image shape."""
+    """Level geometry and buffer layout for one image shape, or (batch) for a
+    list of images packed in one input buffer."""
 
-    def __init__(self, desc: PlanDesc):
-        self.desc = desc
+    def __init__(self, desc, batch: bool = False):
         h = ctypes.c_void_p()
-        _check(load_library().hog_plan_create(ctypes.byref(desc), ctypes.byref(h)))
+        if batch:
+            descs = list(desc)
+            arr = (PlanDesc * len(descs))(*descs)
+            _check(load_library().hog_plan_create_batch(arr, len(descs), ctypes.byref(h)))
+            self.desc = descs[0]
+            self.descs = descs
+        else:
+            _check(load_library().hog_plan_create(ctypes.byref(desc), ctypes.byref(h)))
+            self.desc = desc
+            self.descs = [desc]
+        self.batch = batch
         self.handle = h
+        self.images = []
+        for i in range(load_library().hog_plan_images(h)):
+            ii = ImageInfo()
+            _check(load_library().hog_plan_get_image(h, i, ctypes.byref(ii)))
+            self.images.append(ii)
         sz = PlanSizes()
         _check(load_library().hog_plan_get_sizes(h, ctypes.byref(sz)))
         self.sizes = sz
@@ -211,8 +237,13 @@ class Plan:
 def hog_bin_map(plan: Plan, lut: Lut, img, bins, stream=None, img_pitch=None):
     import torch
     d = plan.desc
-    pitch = d.width * d.channels if img_pitch is None else int(img_pitch)
-    need = (d.height - 1) * pitch + d.width * d.channels
+    if plan.batch:
+        pitch = 0
+        last = plan.images[-1]
+        need = last.img_offset + last.height * last.img_pitch
+    else:
+        pitch = d.width * d.channels if img_pitch is None else int(img_pitch)
+        need = (d.height - 1) * pitch + d.width * d.channels
     _check(load_library().hog_bin_map(
         plan.handle, lut.handle, _dptr(img, torch.uint8, need, "img"), pitch,
         _dptr(bins, torch.uint8, plan.sizes.bins_bytes, "bins"), _stream(stream)))
@@ -255,6 +286,19 @@ def hog_timing_get(kernel: str):
     ms = ctypes.c_double()
     _check(load_library().hog_timing_get(kernel.encode(), ctypes.byref(n), ctypes.byref(ms)))
     return n.value, ms.value
+
+
+def pack_images(plan: Plan, images) -> np.ndarray:
+    """Host buffer holding a batch plan's images (uint8 HWC arrays) packed as
+    hog_bin_map reads them."""
+    assert plan.batch and len(images) == len(plan.images)
+    last = plan.images[-1]
+    out = np.zeros(last.img_offset + last.height * last.img_pitch, np.uint8)
+    for im, info in zip(images, plan.images):
+        a = np.ascontiguousarray(im).reshape(-1)
+        assert a.size == info.height * info.img_pitch
+        out[info.img_offset: info.img_offset + a.size] = a
+    return out
 
 
 class Buffers:

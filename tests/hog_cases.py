@@ -40,13 +40,34 @@ def run_gpu(desc: hog.PlanDesc, img: np.ndarray, tmpl: np.ndarray, bias: np.ndar
     return plan, (outs[0] if repeat == 1 else outs)
 
 
-def oracle_level_bins(img: np.ndarray, plan: hog.Plan, l: int) -> np.ndarray:
+def oracle_level_bins(img: np.ndarray, plan: hog.Plan, l: int, l0: int = 0) -> np.ndarray:
+    """Oracle bins of plan level l, which belongs to the image whose first
+    level is l0 (0 for single-image plans)."""
     li = plan.levels[l]
     nb = plan.desc.n_bins
-    if l == 0:
+    if l == l0:
         return oracle.bin_map(img, nb)
     lvl = oracle.resize_nn(img, li.scale, li.width, li.height)
     return oracle.bin_map(lvl, nb)
+
+
+def run_gpu_batch(descs, imgs, tmpl: np.ndarray, bias: np.ndarray, cell_hist=True):
+    """Run the three calls on one batch plan over imgs (packed as the plan
+    says); return the plan and host copies of every output."""
+    import torch
+    plan = hog.Plan(descs, batch=True)
+    lut = hog.hog_lut_build(plan.desc.n_bins)
+    l2 = plan.desc.scan.norm == hog.HOG_NORM_L2
+    buf = hog.Buffers(plan, cell_hist=cell_hist, block_feat=l2)
+    packed = torch.from_numpy(hog.pack_images(plan, imgs)).to("cuda")
+    tmpl_t = torch.from_numpy(np.ascontiguousarray(tmpl, np.float32).reshape(-1)).to("cuda")
+    bias_t = torch.from_numpy(np.ascontiguousarray(bias, np.float32).reshape(-1)).to("cuda")
+    hog.run_path(plan, lut, packed, tmpl_t, bias_t, buf)
+    torch.cuda.synchronize()
+    return plan, dict(bins=buf.bins.cpu().numpy(), ii=buf.ii.cpu().numpy(),
+                      scores=buf.scores.cpu().numpy(),
+                      cells=buf.cell_hist.cpu().numpy() if buf.cell_hist is not None else None,
+                      blocks=buf.block_feat.cpu().numpy() if buf.block_feat is not None else None)
 
 
 def oracle_params(desc: hog.PlanDesc) -> oracle.ScanParams:

@@ -99,3 +99,29 @@ def test_lut_mirror_rule_behind_the_half_table(nb):
     # an edge of the mirrored direction can only be an axis or a diagonal
     edge = (dxs == 0) | (np.abs(dxs) == dys)
     assert not f[~edge].any()
+
+
+@pytest.mark.parametrize("bad", [dict(n_bins=9), dict(channels=1), dict(n_templates=2),
+                                 dict(norm=hog.HOG_NORM_L2, cell=4)])
+def test_batch_plan_rejects_mismatched_images(bad):
+    base = dict(width=320, height=240, channels=3, n_bins=8)
+    other = dict(base, width=200, height=150)
+    other.update(bad)
+    descs = (hog.PlanDesc * 2)(hog.make_desc(**base), hog.make_desc(**other))
+    lib = hog.load_library()
+    h = ctypes.c_void_p()
+    assert lib.hog_plan_create_batch(descs, 2, ctypes.byref(h)) == hog.HOG_E_INVALID
+    assert not h.value
+    assert "match image 0" in lib.hog_last_error().decode()
+
+
+def test_batch_plan_rejects_bad_counts_and_bad_members():
+    lib = hog.load_library()
+    h = ctypes.c_void_p()
+    one = (hog.PlanDesc * 1)(hog.make_desc(320, 240))
+    assert lib.hog_plan_create_batch(one, 0, ctypes.byref(h)) == hog.HOG_E_INVALID
+    assert lib.hog_plan_create_batch(None, 1, ctypes.byref(h)) == hog.HOG_E_INVALID
+    bad = (hog.PlanDesc * 2)(hog.make_desc(320, 240), hog.make_desc(0, 240))
+    assert lib.hog_plan_create_batch(bad, 2, ctypes.byref(h)) == hog.HOG_E_INVALID
+    assert lib.hog_plan_images(None) == 0
+    assert lib.hog_plan_get_image(None, 0, None) == hog.HOG_E_INVALID

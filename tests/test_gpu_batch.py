@@ -1,0 +1,93 @@
+"""Batch plans: several images of different sizes, each with its own pyramid,
+in one launch per kernel. Every level of every image is compared with the
+oracle, and each image's results must equal, bit for bit, those of a
+single-image plan of the same image (alone and in the mix give the same
+result)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1703_06256_amd import hog
+from paper_1703_06256_amd import inputs
+
+from hog_cases import (check_scores, oracle_level_bins, oracle_params, run_gpu, run_gpu_batch,
+                       templates_for)
+
+pytestmark = pytest.mark.gpu
+
+
+def _check_image(plan, out, img, i, tmpl, bias):
+    info = plan.images[i]
+    d = plan.descs[i]
+    nb = d.n_bins
+    p = oracle_params(d)
+    for l in range(info.first_level, info.first_level + info.n_levels):
+        li = plan.levels[l]
+        want = oracle_level_bins(img, plan, l, info.first_level)
+        assert np.array_equal(hog.level_bins(plan, out["bins"], l), want), f"image {i} level {l} bins"
+        assert np.array_equal(hog.level_planes(plan, out["ii"], l),
+                              oracle.integral(want, nb)[:, 1:, 1:]), f"image {i} level {l} planes"
+        if li.cells_x and li.cells_y:
+            assert np.array_equal(hog.level_cells(plan, out["cells"], l),
+                                  oracle.cell_hist(want, nb, d.scan.cell)), f"image {i} level {l} cells"
+        if li.windows_x:
+            ref, absterm, _, _, _ = oracle.score_windows(want, nb, p, tmpl, bias)
+            got = hog.level_scores(plan, out["scores"], l).reshape(ref.shape)
+            check_scores(got, ref, absterm)
+
+
+def _same_as_alone(plan, out, imgs, tmpl, bias):
+    """Each image alone (single-image plan) gives bit-identical outputs."""
+    for i, img in enumerate(imgs):
+        info = plan.images[i]
+        p1, o1 = run_gpu(plan.descs[i], img, tmpl, bias)
+        assert p1.sizes.n_levels == info.n_levels
+        for k in range(info.n_levels):
+            l = info.first_level + k
+            assert np.array_equal(hog.level_bins(plan, out["bins"], l), hog.level_bins(p1, o1["bins"], k))
+            assert np.array_equal(hog.level_planes(plan, out["ii"], l), hog.level_planes(p1, o1["ii"], k))
+            a = hog.level_scores(plan, out["scores"], l)
+            b = hog.level_scores(p1, o1["scores"], k)
+            assert np.array_equal(a.view(np.uint32), b.view(np.uint32)), f"image {i} level {k} scores"
+
+
+RGB_SIZES = [(230, 300), (65, 129), (320, 240), (401, 183), (64, 128), (60, 100), (129, 257)]
+
+
+def test_rgb_l2_pyramid_batch():
+    """RGB, N_b = 8, 1.1 pyramids, 2x2-cell L2 blocks, two templates; one image
+    smaller than a window."""
+    descs = [hog.make_desc(w, h, channels=3, n_bins=8, max_levels=0, scale=1.1, n_templates=2,
+                           norm=hog.HOG_NORM_L2) for w, h in RGB_SIZES]
+    imgs = [inputs.synth_image(w, h, 3, inputs.SEED_BATCH_BASE + j) for j, (w, h) in enumerate(RGB_SIZES)]
+    tmpl, _ = templates_for(descs[0], 4100)
+    bias = np.array([0.25, -1.5], np.float32)
+    plan, out = run_gpu_batch(descs, imgs, tmpl, bias)
+    assert len(plan.images) == len(RGB_SIZES)
+    assert plan.sizes.n_levels == sum(im.n_levels for im in plan.images)
+    for i, img in enumerate(imgs):
+        _check_image(plan, out, img, i, tmpl, bias)
+    _same_as_alone(plan, out, imgs, tmpl, bias)
+
+
+def test_gray_raw_batch_single_levels():
+    sizes = [(320, 240), (70, 130), (200, 150), (3, 3)]
+    descs = [hog.make_desc(w, h, channels=1, n_bins=9) for w, h in sizes]
+    imgs = [inputs.synth_image(w, h, 1, 4200 + j) for j, (w, h) in enumerate(sizes)]
+    tmpl, bias = templates_for(descs[0], 4300)
+    plan, out = run_gpu_batch(descs, imgs, tmpl, bias)
+    for i, img in enumerate(imgs):
+        _check_image(plan, out, img[:, :, 0], i, tmpl, bias)
+    _same_as_alone(plan, out, [im[:, :, 0] for im in imgs], tmpl, bias)
+
+
+def test_batch_n18_mixed_pyramids():
+    """N_b = 18 (three 6-bin chunks), images with and without pyramids."""
+    sizes = [(300, 260, 0), (257, 140, 1), (150, 300, 3)]
+    descs = [hog.make_desc(w, h, channels=3, n_bins=18, max_levels=ml, scale=1.05,
+                           norm=hog.HOG_NORM_L2) for w, h, ml in sizes]
+    imgs = [inputs.synth_image(w, h, 3, 4400 + j) for j, (w, h, _) in enumerate(sizes)]
+    tmpl, bias = templates_for(descs[0], 4500)
+    plan, out = run_gpu_batch(descs, imgs, tmpl, bias)
+    for i, img in enumerate(imgs):
+        _check_image(plan, out, img, i, tmpl, bias)
