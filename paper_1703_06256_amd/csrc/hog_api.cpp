@@ -301,17 +301,26 @@ static hog_status create_plan(const hog_plan_desc *descs, int n_img, bool batch,
     // the vector scorer: tw x th windows per workgroup (<= 256 threads) with
     // the cells they use staged in LDS.
     const int nbp = (int)round_up(nb, 4);
-    int best_tw = 0, best_th = 0, mfma_ks = 0;
+    int best_tw = 0, best_th = 0, mfma_ks = 0, scorer = 0;
     int64_t best_lds = 0;
-    if (sp.norm == HOG_NORM_L2 && sp.win_cells_x - 1 == hogk::kStripMaxBX &&
-        sp.win_cells_y - 1 <= 16 && nb <= 20) {
+    const bool l2_8wide = sp.norm == HOG_NORM_L2 && sp.win_cells_x - 1 == hogk::kStripMaxBX &&
+                          sp.win_cells_y - 1 <= 16;
+    if (l2_8wide && nb <= 16 && K >= 16) {
+        // Many templates: the window GEMM, one workgroup per 64 x 8 windows
+        // and 32 templates.
+        scorer = 2;
+        mfma_ks = nb <= 8 ? 8 : 16;
+        best_tw = hogk::kWgW;
+        best_th = hogk::kWgTH;
+    } else if (l2_8wide && nb <= 20) {
+        scorer = 1;
         mfma_ks = nb <= 8 ? 8 : nb <= 16 ? 16 : 20;  // bin slots per cell
         best_tw = hogk::kStripW;
         best_th = hogk::kStripTH;
         const int64_t rowh = (int64_t)(hogk::kStripW + 8) * mfma_ks;  // halves per staged cell row
         best_lds = 4 * round_up(4 * rowh * 2 + 64 * 4 + (int64_t)hogk::kStripW * best_th * 4, 16);
     }
-    if (mfma_ks == 0) {
+    if (scorer == 0) {
         double best_cost = 1e30;
         for (int tw = 1; tw <= 64; tw *= 2)
             for (int th = 1; tw * th <= 256; th *= 2) {
@@ -463,10 +472,17 @@ static hog_status create_plan(const hog_plan_desc *descs, int n_img, bool batch,
     // Prepared template fragments of the matrix-core scorer (rewritten by
     // every hog_scan_windows call).
     int64_t tprep_off = 0, tprep_stride = 0;
-    if (mfma_ks > 0) {
+    if (scorer == 1) {
         tprep_stride = round_up(hogk::strip_prep_bytes(mfma_ks), 256);
         tprep_off = round_up(ws_off, 256);
         ws_off = tprep_off + tprep_stride * K;
+    } else if (scorer == 2) {
+        // per tile of 32 templates: fragments [by][bx][step][hi|lo][lane] of
+        // 16 bytes, then 32 scales
+        const int64_t frags = (int64_t)(sp.win_cells_y - 1) * hogk::kStripMaxBX * (mfma_ks / 4) * 2 * 64;
+        tprep_stride = round_up(frags * 16 + 32 * 4, 256);
+        tprep_off = round_up(ws_off, 256);
+        ws_off = tprep_off + tprep_stride * ((K + 31) / 32);
     }
     // The integral kernels address a chunk of planes (and a level's bins)
     // through one buffer descriptor with 31-bit byte offsets.
@@ -498,7 +514,8 @@ static hog_status create_plan(const hog_plan_desc *descs, int n_img, bool batch,
         items[hogk::KB_ESCAN] = (int64_t)v.h * nb;
         items[hogk::KB_PSCAN] = nb;
         items[hogk::KB_CELL] = (int64_t)v.cells_x * v.cells_y;
-        items[hogk::KB_STILE] = (int64_t)v.st_x * v.st_y * (mfma_ks ? K : 1);
+        items[hogk::KB_STILE] = (int64_t)v.st_x * v.st_y *
+                                (scorer == 1 ? K : scorer == 2 ? (K + 31) / 32 : 1);
         items[hogk::KB_BLOCK] = (sp.norm == HOG_NORM_L2 && v.cells_x >= 2 && v.cells_y >= 2)
                                     ? (int64_t)(v.cells_x - 1) * (v.cells_y - 1)
                                     : 0;
@@ -563,6 +580,7 @@ static hog_status create_plan(const hog_plan_desc *descs, int n_img, bool batch,
     pd.st_th = best_th;
     pd.st_lds_bytes = (int32_t)best_lds;
     pd.mfma_ks = mfma_ks;
+    pd.scorer = scorer;
     pd.cell_stride = nbp;
     pd.bin_chunk = chunk_final;  // bins per wave; a last, smaller chunk takes the rest
     pd.n_chunks = (nb + chunk_final - 1) / chunk_final;

@@ -29,6 +29,11 @@ constexpr int kStripW = 16;
 constexpr int kStripTH = 16;
 constexpr int kStripMaxBX = 7;
 
+// Many-template scorer (K >= 16): one workgroup per kWgW x kWgTH windows and
+// 32 templates.
+constexpr int kWgW = 64;
+constexpr int kWgTH = 8;
+
 // Workspace bytes of one template's prepared weights for nbp bin slots per
 // cell: fragments [bx][step][hi|lo][lane] of 16 bytes (one step per 32 or, at
 // the end, 16 features of the 4 nbp), then the column scales [lane] (float).
@@ -90,7 +95,8 @@ struct PlanDev {
     float eps;
     int32_t feat_dim;
     int32_t st_tw, st_th;      // scorer tile (windows)
-    int32_t mfma_ks;           // > 0: matrix-core scorer, bin slots per cell (8, 16 or 20)
+    int32_t scorer;            // 0: vector units; 1: strips (one template per wave); 2: window GEMM (K >= 16)
+    int32_t mfma_ks;           // matrix-core scorers: bin slots per cell (8, 16 or 20)
     int32_t st_lds_bytes;      // scorer dynamic LDS
     int32_t cell_stride;       // floats per staged cell in the scorer's LDS
     int32_t bin_chunk;         // bins per integral wave

@@ -1159,6 +1159,268 @@ __global__ __launch_bounds__(256, 2) void k_score_strip(const Level *__restrict_
     }
 }
 
+// ---------------------------------------------------------------------------
+// Sec. 3.1 / Fig. 4 + Sec. 4 for many templates (K >= 16, in tiles of 32): a
+// GEMM of windows x features by features x templates. For a window row wy
+// and block position p = (by, bx), v_mfma_f32_32x32x16_f16 gives
+//     D_p[k][m] = T_k[p] . v(B(m, p)),   B(m, p) = block (wy + by, wx0 + m + bx),
+// with 32 templates on the M axis and 32 windows on the N axis, so each lane
+// holds one window and the block's 1/sqrt(|v|^2 + eps^2) is one scale per
+// lane: S[k][m] += inv(B(m, p)) * D_p[k][m] (FP32). The counts are exact in
+// fp16; k_score_prep_wg scales each template by a power of two (its max |T|
+// into [2^14, 2^15)) and splits it into fp16 hi + lo.
+//
+// A workgroup covers kWgW window columns x kWgTH window rows for one tile of
+// 32 templates; wave w owns rows w and w + 4, each as two 32-window halves.
+// It walks by = 0 .. nby - 1: cell rows wy0 + by .. + kWgTH sit in an LDS
+// ring (one new row per by), the norms of the kWgTH block rows are
+// recomputed, and the template fragments of the positions (by, 0 .. 6) are in
+// LDS, double-buffered and fetched one by ahead.
+// ---------------------------------------------------------------------------
+constexpr int kWgCells = kWgW + 8;     // cell columns staged per row
+constexpr int kWgSlots = kWgTH + 1;    // cell-row ring
+
+struct WgArgs {
+    int nb, nby, k, dim;
+    int64_t tprep_off, tprep_stride;
+    float eps;
+};
+
+typedef float float16v_t __attribute__((ext_vector_type(16)));
+
+// One workgroup (1024 threads) per tile of 32 templates: per-template scales,
+// then the A fragments [p][s][hi|lo][lane] (lane: template kk0 + lane % 32,
+// features 16 s + 8 (lane / 32) .. + 7 of the block at position p).
+template <int NBP>
+__global__ __launch_bounds__(1024) void k_score_prep_wg(WgArgs a, const float *__restrict__ tmpl,
+                                                        uint8_t *__restrict__ ws)
+{
+    constexpr int KS = NBP / 4;  // 16-feature steps per block
+    __shared__ int sh_e[32];
+    const int kt = (int)blockIdx.x, kk0 = 32 * kt;
+    const int tid = threadIdx.x;
+    {
+        const int tk = tid >> 5, sub = tid & 31;  // 32 threads per template
+        float mx = 0.f;
+        if (kk0 + tk < a.k) {
+            const float *t = tmpl + (int64_t)(kk0 + tk) * a.dim;
+            for (int i = sub; i < a.dim; i += 32) mx = fmaxf(mx, fabsf(t[i]));
+        }
+#pragma unroll
+        for (int d = 16; d >= 1; d >>= 1) mx = fmaxf(mx, __shfl_xor(mx, d));
+        int ex = 0;
+        if (mx > 0.f) (void)frexpf(mx, &ex);  // mx = f 2^ex, f in [0.5, 1)
+        if (sub == 0) sh_e[tk] = mx > 0.f ? 15 - ex : 0;
+    }
+    __syncthreads();
+    uint8_t *tp = ws + a.tprep_off + (int64_t)kt * a.tprep_stride;
+    const int n_frag = a.nby * kStripMaxBX * KS * 2 * 64;
+    for (int f = tid; f < n_frag; f += 1024) {
+        const int lane = f & 63, rest = f >> 6;
+        const int hl = rest & 1, s = (rest >> 1) % KS, pos = (rest >> 1) / KS;
+        const int by = pos / kStripMaxBX, bx = pos % kStripMaxBX;
+        const int kk = kk0 + (lane & 31), h = lane >> 5;
+        const int e = sh_e[lane & 31];
+        half8_t out;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int kf = 16 * s + 8 * h + i;
+            const int w = kf / (2 * NBP), rem = kf % (2 * NBP);
+            const int u = rem / NBP, bin = rem % NBP;
+            float val = 0.f;
+            if (kk < a.k && bin < a.nb)
+                val = tmpl[(int64_t)kk * a.dim + ((by * kStripMaxBX + bx) * 4 + w * 2 + u) * a.nb + bin];
+            const float sv = ldexpf(val, e);
+            const _Float16 hi = (_Float16)sv;
+            out[i] = hl == 0 ? hi : (_Float16)(sv - (float)hi);
+        }
+        *reinterpret_cast<half8_t *>(tp + (int64_t)f * 16) = out;
+    }
+    if (tid < 32) reinterpret_cast<float *>(tp + (int64_t)n_frag * 16)[tid] = ldexpf(1.f, -sh_e[tid]);
+}
+
+template <int NBP>
+__global__ __launch_bounds__(256, NBP == 8 ? 2 : 1) void k_score_wgemm(const Level *__restrict__ lv,
+                                                                      const int32_t *__restrict__ first,
+                                                                      int n_levels, WgArgs a,
+                                                                      const uint8_t *__restrict__ ws,
+                                                                      const float *__restrict__ bias,
+                                                                      float *__restrict__ scores)
+{
+    constexpr int KS = NBP / 4;                  // 16-feature steps per block
+    constexpr int NFRAG = kStripMaxBX * KS * 2;  // fragments per block row offset: [bx][s][hi|lo]
+    constexpr int ROWH = kWgCells * NBP;         // halves per staged cell row
+    constexpr int NSEG = kWgCells / 8;           // 8-cell segments of the blocked cache
+    constexpr int PF = NFRAG * 64 / 256;         // 16-byte fragment loads per thread and by
+    typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+    __shared__ u32x4 bst[2][NFRAG * 64];
+    __shared__ __attribute__((aligned(16))) _Float16 ring[kWgSlots][ROWH];
+    __shared__ float sqr[kWgSlots][kWgCells];
+    __shared__ float invb[kWgTH][kWgCells];
+
+    const int wg = (int)blockIdx.x;
+    if (wg >= first[n_levels]) return;  // whole workgroup
+    const int l = find_level(first, n_levels, wg);
+    const Level &v = lv[l];
+    int rel = wg - first[l];
+    const int tx = rel % v.st_x;
+    rel /= v.st_x;
+    const int ty = rel % v.st_y, kt = rel / v.st_y;
+    const int wx0 = tx * kWgW, wy0 = ty * kWgTH, kk0 = 32 * kt;
+    const int tid = (int)threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int n = lane & 31, h = lane >> 5;
+    const int nb = a.nb, nby = a.nby;
+    const uint8_t *tp = ws + a.tprep_off + (int64_t)kt * a.tprep_stride;
+    const u32x4 *tfrag = reinterpret_cast<const u32x4 *>(tp);
+
+    for (int i = tid; i < kWgSlots * ROWH / 8; i += 256)
+        reinterpret_cast<u32x4 *>(&ring[0][0])[i] = u32x4{0u, 0u, 0u, 0u};
+
+    // Cell row cy: thread t < nb * NSEG loads bin t / NSEG of cells
+    // 8 (t % NSEG) .. + 7 (0 outside the level's cache).
+    const uint16_t *cache = reinterpret_cast<const uint16_t *>(ws + v.ws_cache);
+    const int f_bin = tid / NSEG, f_seg = tid - f_bin * NSEG;
+    const bool f_on = tid < nb * NSEG && (wx0 >> 3) + f_seg < v.cbx;
+    auto fetch_row = [&](int cy) -> u16x8_t {
+        u16x8_t val = {0, 0, 0, 0, 0, 0, 0, 0};
+        if (f_on && cy < v.cells_y)
+            val = *reinterpret_cast<const u16x8_t *>(
+                cache + (((int64_t)f_bin * v.cby + (cy >> 3)) * v.cbx + (wx0 >> 3) + f_seg) * 64 + (cy & 7) * 8);
+        return val;
+    };
+    auto store_row = [&](int cy, const u16x8_t &val) {
+        if (tid < nb * NSEG) {
+            _Float16 *rp = &ring[cy % kWgSlots][8 * f_seg * NBP + f_bin];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) rp[e * NBP] = (_Float16)val[e];
+        }
+    };
+    auto row_sq = [&](int cy) {  // threads < kWgCells
+        if (tid < kWgCells) {
+            const _Float16 *cp = &ring[cy % kWgSlots][tid * NBP];
+            typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
+            float s = 0.f;
+#pragma unroll
+            for (int j = 0; j < NBP / 2; ++j) {
+                const half2_t hv = {cp[2 * j], cp[2 * j + 1]};
+                s = __builtin_amdgcn_fdot2(hv, hv, s, false);
+            }
+            sqr[cy % kWgSlots][tid] = s;
+        }
+    };
+    auto fetch_frags = [&](int by, u32x4 (&pf)[PF]) {
+#pragma unroll
+        for (int i = 0; i < PF; ++i) pf[i] = tfrag[(int64_t)by * NFRAG * 64 + tid + 256 * i];
+    };
+    auto store_frags = [&](int buf, const u32x4 (&pf)[PF]) {
+#pragma unroll
+        for (int i = 0; i < PF; ++i) bst[buf][tid + 256 * i] = pf[i];
+    };
+
+    // Prologue: cell rows wy0 .. wy0 + kWgTH, fragments of by = 0, and the
+    // next row and fragments in flight.
+    u32x4 pf[PF];
+    fetch_frags(0, pf);
+    {
+        u16x8_t rows[kWgTH + 1];
+#pragma unroll
+        for (int i = 0; i <= kWgTH; ++i) rows[i] = fetch_row(wy0 + i);
+        __syncthreads();  // ring zeroed
+#pragma unroll
+        for (int i = 0; i <= kWgTH; ++i) store_row(wy0 + i, rows[i]);
+    }
+    store_frags(0, pf);
+    __syncthreads();
+    for (int i = 0; i <= kWgTH; ++i) row_sq(wy0 + i);
+    u16x8_t cpre = fetch_row(wy0 + kWgTH + 1);
+    if (nby > 1) fetch_frags(1, pf);
+
+    // Window rows of this wave: rho = wave, wave + 4; halves mu = 0, 1.
+    float16v_t S[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) S[q][r] = 0.f;
+
+    for (int by = 0; by < nby; ++by) {
+        __syncthreads();  // rows and their sums of squares are in place
+        for (int i = tid; i < kWgTH * (kWgCells - 1); i += 256) {
+            const int rho = i / (kWgCells - 1), c = i - rho * (kWgCells - 1);
+            const int s0 = (wy0 + by + rho) % kWgSlots, s1 = (wy0 + by + rho + 1) % kWgSlots;
+            invb[rho][c] = inv_block_norm((sqr[s0][c] + sqr[s0][c + 1]) + (sqr[s1][c] + sqr[s1][c + 1]), a.eps);
+        }
+        __syncthreads();
+        const half8_t *bf = reinterpret_cast<const half8_t *>(bst[by & 1]);
+#pragma unroll 1
+        for (int bx = 0; bx < kStripMaxBX; ++bx) {
+            half8_t bh[KS], bl[KS];
+#pragma unroll
+            for (int s2 = 0; s2 < KS; ++s2) {
+                bh[s2] = bf[((bx * KS + s2) * 2 + 0) * 64 + lane];
+                bl[s2] = bf[((bx * KS + s2) * 2 + 1) * 64 + lane];
+            }
+            half8_t wf[4][KS];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int rho = wave + 4 * (q >> 1), mu = q & 1;
+#pragma unroll
+                for (int s2 = 0; s2 < KS; ++s2) {
+                    const int kf = 16 * s2 + 8 * h;
+                    const int w = kf / (2 * NBP);
+                    wf[q][s2] = *reinterpret_cast<const half8_t *>(
+                        &ring[(wy0 + by + rho + w) % kWgSlots][(32 * mu + n + bx) * NBP + kf % (2 * NBP)]);
+                }
+            }
+            float16v_t d[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) d[q][r] = 0.f;
+#pragma unroll
+            for (int s2 = 0; s2 < KS; ++s2)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) d[q] = __builtin_amdgcn_mfma_f32_32x32x16_f16(bh[s2], wf[q][s2], d[q], 0, 0, 0);
+#pragma unroll
+            for (int s2 = 0; s2 < KS; ++s2)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) d[q] = __builtin_amdgcn_mfma_f32_32x32x16_f16(bl[s2], wf[q][s2], d[q], 0, 0, 0);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int rho = wave + 4 * (q >> 1), mu = q & 1;
+                const float iv = invb[rho][32 * mu + n + bx];
+#pragma unroll
+                for (int r = 0; r < 16; ++r) S[q][r] = fmaf(d[q][r], iv, S[q][r]);
+            }
+        }
+        __syncthreads();  // done with this by's ring slot, fragments and norms
+        if (by + 1 < nby) {
+            store_frags((by + 1) & 1, pf);
+            store_row(wy0 + by + kWgTH + 1, cpre);
+            __syncthreads();
+            row_sq(wy0 + by + kWgTH + 1);
+            cpre = fetch_row(wy0 + by + kWgTH + 2);
+            if (by + 2 < nby) fetch_frags(by + 2, pf);
+        }
+    }
+
+    // scores[(wy * win_x + wx) * K + k] = bias_k + cs_k * S[k][window].
+    const float *cs = reinterpret_cast<const float *>(tp + (int64_t)nby * NFRAG * 64 * 16);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int rho = wave + 4 * (q >> 1), mu = q & 1;
+        const int wx = wx0 + 32 * mu + n, wy = wy0 + rho;
+        if (wx < v.win_x && wy < v.win_y) {
+            float *out = scores + v.score_off + ((int64_t)wy * v.win_x + wx) * a.k;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int kr = 8 * (r >> 2) + 4 * h + (r & 3);
+                if (kk0 + kr < a.k)
+                    out[kk0 + kr] = (float)((double)bias[kk0 + kr] + (double)(cs[kr] * S[q][r]));
+            }
+        }
+    }
+}
+
 // Optional output: every normalised 2x2 block, f = h / sqrt(|v|^2 + eps^2).
 __global__ __launch_bounds__(256) void k_block_features(const Level *__restrict__ lv,
                                                         const int32_t *__restrict__ first,
@@ -1300,7 +1562,31 @@ hipError_t launch_score(const PlanDev &p, const uint8_t *ws, const float *tmpl, 
     if (n == 0) return hipSuccess;
     const dim3 grid((unsigned)n), block(256);
     const int32_t *f = first_of(p, KB_STILE);
-    if (p.mfma_ks > 0) {
+    if (p.scorer == 2) {
+        WgArgs m;
+        m.nb = p.n_bins;
+        m.nby = p.win_cells_y - 1;
+        m.k = p.n_templates;
+        m.dim = p.feat_dim;
+        m.tprep_off = p.tprep_off;
+        m.tprep_stride = p.tprep_stride;
+        m.eps = p.eps;
+        const unsigned ktiles = (unsigned)((m.k + 31) / 32);
+        uint8_t *wsw = const_cast<uint8_t *>(ws);
+        switch (p.mfma_ks) {
+        case 8:
+            hipLaunchKernelGGL(k_score_prep_wg<8>, dim3(ktiles), dim3(1024), 0, stream, m, tmpl, wsw);
+            hipLaunchKernelGGL(k_score_wgemm<8>, grid, block, 0, stream, p.levels, f, p.n_levels, m, ws, bias, scores);
+            break;
+        case 16:
+            hipLaunchKernelGGL(k_score_prep_wg<16>, dim3(ktiles), dim3(1024), 0, stream, m, tmpl, wsw);
+            hipLaunchKernelGGL(k_score_wgemm<16>, grid, block, 0, stream, p.levels, f, p.n_levels, m, ws, bias, scores);
+            break;
+        default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
+    if (p.scorer == 1) {
         StripArgs m;
         m.nb = p.n_bins;
         m.nby = p.win_cells_y - 1;

@@ -206,3 +206,18 @@ def test_l2_scores_with_extreme_template_scales():
     tmpl = (tmpl * np.float32(10.0) ** rng.integers(-20, 20, tmpl.shape)).astype(np.float32)
     plan, out = run_gpu(desc, img, tmpl, bias)
     _check_level(plan, out, img, 0, tmpl=tmpl, bias=bias)
+
+
+@pytest.mark.parametrize("nb,k,w,h,ml", [(8, 32, 260, 300, 1), (8, 16, 200, 170, 1), (12, 40, 230, 260, 1),
+                                         (16, 33, 150, 200, 1), (8, 32, 300, 270, 0)])
+def test_l2_many_templates_window_gemm(nb, k, w, h, ml):
+    """K >= 16 templates: the window GEMM (templates x windows on the matrix
+    cores, tiles of 32 templates, the last one partial), with a bias."""
+    desc = hog.make_desc(w, h, channels=3, n_bins=nb, n_templates=k, norm=hog.HOG_NORM_L2,
+                         max_levels=ml, scale=1.1)
+    img = inputs.synth_image(w, h, 3, 900 + nb + k)
+    tmpl, _ = templates_for(desc, 901 + nb + k)
+    bias = np.linspace(-3.0, 3.0, k).astype(np.float32)
+    plan, out = run_gpu(desc, img, tmpl, bias)
+    for l in range(plan.sizes.n_levels):
+        _check_level(plan, out, img, l, tmpl=tmpl, bias=bias)
