@@ -232,6 +232,31 @@ hog_status hog_scan_windows(const hog_plan *plan, const uint32_t *ii, const floa
                             float *block_feat, void *workspace, void *stream);
 
 /* ------------------------------------------------------------------------ */
+/* The whole path at once.                                                  */
+/* ------------------------------------------------------------------------ */
+
+/* hog_bin_map, hog_integral and hog_scan_windows (scores only; cells from the
+ * cache for 8-pixel cells, else from ii) in one call, on the same buffers and
+ * with the same layouts. Arguments are all checked before anything is
+ * enqueued. */
+hog_status hog_run(const hog_plan *plan, const hog_lut *lut, const uint8_t *img, int64_t img_pitch,
+                   uint8_t *bins, uint32_t *ii, const float *tmpl, const float *bias, float *scores,
+                   void *workspace, void *stream);
+
+/* hog_run captured once into a HIP graph for these exact buffers, replayed by
+ * hog_graph_launch with one launch: for callers that run the same plan on the
+ * same buffers again and again (a batch refilled in place, video frames).
+ * The buffers' contents are read at replay time; the pointers are fixed. The
+ * graph records no memset nodes. Creating it synchronises nothing and
+ * launches nothing; hog_graph_destroy frees it (library-owned). */
+typedef struct hog_graph hog_graph;
+hog_status hog_graph_create(const hog_plan *plan, const hog_lut *lut, const uint8_t *img,
+                            int64_t img_pitch, uint8_t *bins, uint32_t *ii, const float *tmpl,
+                            const float *bias, float *scores, void *workspace, hog_graph **out);
+hog_status hog_graph_launch(hog_graph *graph, void *stream);
+void hog_graph_destroy(hog_graph *graph);
+
+/* ------------------------------------------------------------------------ */
 /* Kernel timing. When enabled, every kernel launch of the calls above is   */
 /* bracketed by a pair of HIP events recorded on the launch stream; totals  */
 /* accumulate per kernel name until hog_timing_reset. Not thread-safe.      */

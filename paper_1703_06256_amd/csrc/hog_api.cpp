@@ -47,6 +47,7 @@ struct PendingTiming {
     hipEvent_t start, stop;
 };
 bool g_timing_on = false;
+thread_local bool g_capturing = false;  // inside hog_graph_create: no timing events
 std::vector<PendingTiming> g_pending;
 std::vector<hipEvent_t> g_event_pool;
 std::map<std::string, std::pair<int64_t, double>> g_timing_totals;
@@ -64,7 +65,7 @@ hipError_t take_event(hipEvent_t *ev)
 template <class F>
 hipError_t timed_launch(const char *name, hipStream_t stream, F &&launch)
 {
-    if (!g_timing_on) return launch();
+    if (!g_timing_on || g_capturing) return launch();
     hipEvent_t a = nullptr, b = nullptr;
     hipError_t e = take_event(&a);
     if (e == hipSuccess) e = take_event(&b);
@@ -736,6 +737,110 @@ extern "C" hog_status hog_scan_windows(const hog_plan *plan, const uint32_t *ii,
         if (e != hipSuccess) return device_fail(e, "score launch");
     }
     return HOG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// The whole path in one call, and captured into a HIP graph.
+// ---------------------------------------------------------------------------
+static hog_status check_run_args(const hog_plan *plan, const hog_lut *lut, const uint8_t *img,
+                                 int64_t img_pitch, uint8_t *bins, uint32_t *ii, const float *tmpl,
+                                 const float *bias, float *scores, void *workspace)
+{
+    if (!plan || !lut || !img || !bins || !ii || !workspace) return fail(HOG_E_INVALID, "NULL argument");
+    if (plan->sizes.score_elems > 0 && (!tmpl || !bias || !scores))
+        return fail(HOG_E_INVALID, "tmpl, bias and scores are required when the plan has windows");
+    if (lut->n_bins != plan->desc.n_bins)
+        return fail(HOG_E_INVALID, "lut has %d bins, plan has %d", lut->n_bins, plan->desc.n_bins);
+    if (plan->batch ? img_pitch != 0 : img_pitch < (int64_t)plan->desc.width * plan->desc.channels)
+        return fail(HOG_E_INVALID, "bad img_pitch %lld", (long long)img_pitch);
+    return HOG_OK;
+}
+
+static hog_status run_path(const hog_plan *plan, const hog_lut *lut, const uint8_t *img, int64_t img_pitch,
+                           uint8_t *bins, uint32_t *ii, const float *tmpl, const float *bias, float *scores,
+                           void *workspace, void *stream)
+{
+    hog_status st = hog_bin_map(plan, lut, img, img_pitch, bins, stream);
+    if (st != HOG_OK) return st;
+    st = hog_integral(plan, bins, ii, workspace, stream);
+    if (st != HOG_OK) return st;
+    const bool from_planes = plan->desc.scan.cell != 8;
+    return hog_scan_windows(plan, from_planes ? ii : nullptr, tmpl, bias, scores, nullptr, nullptr,
+                            workspace, stream);
+}
+
+extern "C" hog_status hog_run(const hog_plan *plan, const hog_lut *lut, const uint8_t *img, int64_t img_pitch,
+                              uint8_t *bins, uint32_t *ii, const float *tmpl, const float *bias,
+                              float *scores, void *workspace, void *stream)
+{
+    hog_status st = check_run_args(plan, lut, img, img_pitch, bins, ii, tmpl, bias, scores, workspace);
+    if (st != HOG_OK) return st;
+    return run_path(plan, lut, img, img_pitch, bins, ii, tmpl, bias, scores, workspace, stream);
+}
+
+struct hog_graph {
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+};
+
+extern "C" hog_status hog_graph_create(const hog_plan *plan, const hog_lut *lut, const uint8_t *img,
+                                       int64_t img_pitch, uint8_t *bins, uint32_t *ii, const float *tmpl,
+                                       const float *bias, float *scores, void *workspace, hog_graph **out)
+{
+    if (!out) return fail(HOG_E_INVALID, "out is NULL");
+    *out = nullptr;
+    hog_status st = check_run_args(plan, lut, img, img_pitch, bins, ii, tmpl, bias, scores, workspace);
+    if (st != HOG_OK) return st;
+    hipStream_t cs = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (e != hipSuccess) return device_fail(e, "hipStreamCreate (capture)");
+    e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+        (void)hipStreamDestroy(cs);
+        return device_fail(e, "hipStreamBeginCapture");
+    }
+    g_capturing = true;
+    st = run_path(plan, lut, img, img_pitch, bins, ii, tmpl, bias, scores, workspace, cs);
+    g_capturing = false;
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(cs, &graph);
+    (void)hipStreamDestroy(cs);
+    if (st != HOG_OK || e != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return st != HOG_OK ? st : device_fail(e, "hipStreamEndCapture");
+    }
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        return device_fail(e, "hipGraphInstantiate");
+    }
+    hog_graph *g = new (std::nothrow) hog_graph;
+    if (!g) {
+        (void)hipGraphExecDestroy(exec);
+        (void)hipGraphDestroy(graph);
+        return fail(HOG_E_NOMEM, "host allocation failed");
+    }
+    g->graph = graph;
+    g->exec = exec;
+    *out = g;
+    return HOG_OK;
+}
+
+extern "C" hog_status hog_graph_launch(hog_graph *g, void *stream)
+{
+    if (!g) return fail(HOG_E_INVALID, "graph is NULL");
+    hipError_t e = hipGraphLaunch(g->exec, (hipStream_t)stream);
+    if (e != hipSuccess) return device_fail(e, "hipGraphLaunch");
+    return HOG_OK;
+}
+
+extern "C" void hog_graph_destroy(hog_graph *g)
+{
+    if (!g) return;
+    (void)hipGraphExecDestroy(g->exec);
+    (void)hipGraphDestroy(g->graph);
+    delete g;
 }
 
 // ---------------------------------------------------------------------------

@@ -25,7 +25,8 @@ EXPORTS = (
     "hog_last_error", "hog_lut_fill_host", "hog_lut_build", "hog_lut_free", "hog_lut_bins",
     "hog_lut_host", "hog_plan_create", "hog_plan_create_batch", "hog_plan_images",
     "hog_plan_get_image", "hog_plan_destroy", "hog_plan_get_sizes",
-    "hog_plan_get_level", "hog_bin_map", "hog_integral", "hog_scan_windows",
+    "hog_plan_get_level", "hog_bin_map", "hog_integral", "hog_scan_windows", "hog_run",
+    "hog_graph_create", "hog_graph_launch", "hog_graph_destroy",
     "hog_timing_enable", "hog_timing_reset", "hog_timing_get",
 )
 
@@ -105,6 +106,10 @@ def load_library():
         "hog_bin_map": ([vp, vp, vp, i64, vp, vp], i32),
         "hog_integral": ([vp, vp, vp, vp, vp], i32),
         "hog_scan_windows": ([vp, vp, vp, vp, vp, vp, vp, vp, vp], i32),
+        "hog_run": ([vp, vp, vp, i64, vp, vp, vp, vp, vp, vp, vp], i32),
+        "hog_graph_create": ([vp, vp, vp, i64, vp, vp, vp, vp, vp, vp, ctypes.POINTER(vp)], i32),
+        "hog_graph_launch": ([vp, vp], i32),
+        "hog_graph_destroy": ([vp], None),
         "hog_timing_enable": ([i32], i32),
         "hog_timing_reset": ([], i32),
         "hog_timing_get": ([ctypes.c_char_p, ctypes.POINTER(i64),
@@ -329,6 +334,56 @@ def run_path(plan: Plan, lut: Lut, img, tmpl, bias, buf: Buffers, stream=None,
     from_planes = cells_from_planes or plan.desc.scan.cell != 8
     hog_scan_windows(plan, buf.ii if from_planes else None, tmpl, bias, buf.scores,
                      buf.workspace, buf.cell_hist, buf.block_feat, stream)
+
+
+def _run_args(plan: Plan, lut: Lut, img, tmpl, bias, buf: "Buffers", img_pitch=None):
+    import torch
+    d = plan.desc
+    if plan.batch:
+        pitch = 0
+        last = plan.images[-1]
+        need = last.img_offset + last.height * last.img_pitch
+    else:
+        pitch = d.width * d.channels if img_pitch is None else int(img_pitch)
+        need = (d.height - 1) * pitch + d.width * d.channels
+    k = d.n_templates
+    return (plan.handle, lut.handle, _dptr(img, torch.uint8, need, "img"), pitch,
+            _dptr(buf.bins, torch.uint8, plan.sizes.bins_bytes, "bins"),
+            _dptr(buf.ii, torch.int32, plan.sizes.ii_elems, "ii"),
+            _dptr(tmpl, torch.float32, k * plan.sizes.feature_dim, "tmpl"),
+            _dptr(bias, torch.float32, k, "bias"),
+            _dptr(buf.scores, torch.float32, plan.sizes.score_elems, "scores"),
+            _dptr(buf.workspace, torch.uint8, plan.sizes.workspace_bytes, "workspace"))
+
+
+def hog_run(plan: Plan, lut: Lut, img, tmpl, bias, buf: "Buffers", stream=None, img_pitch=None):
+    """The whole path in one C call (hog_run)."""
+    _check(load_library().hog_run(*_run_args(plan, lut, img, tmpl, bias, buf, img_pitch), _stream(stream)))
+
+
+class Graph:
+    """hog_run captured into a HIP graph for fixed buffers (hog_graph_*)."""
+
+    def __init__(self, plan: Plan, lut: Lut, img, tmpl, bias, buf: "Buffers", img_pitch=None):
+        h = ctypes.c_void_p()
+        _check(load_library().hog_graph_create(*_run_args(plan, lut, img, tmpl, bias, buf, img_pitch),
+                                               ctypes.byref(h)))
+        self.handle = h
+        self._keep = (plan, lut, img, tmpl, bias, buf)  # buffers must outlive the graph
+
+    def launch(self, stream=None):
+        _check(load_library().hog_graph_launch(self.handle, _stream(stream)))
+
+    def destroy(self):
+        if self.handle:
+            load_library().hog_graph_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
 
 
 # ----------------------------------------------------------------------------

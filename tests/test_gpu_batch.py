@@ -91,3 +91,71 @@ def test_batch_n18_mixed_pyramids():
     plan, out = run_gpu_batch(descs, imgs, tmpl, bias)
     for i, img in enumerate(imgs):
         _check_image(plan, out, img, i, tmpl, bias)
+
+
+def _batch_setup(sizes, k, seed):
+    import torch
+    descs = [hog.make_desc(w, h, channels=3, n_bins=8, max_levels=0, scale=1.1, n_templates=k,
+                           norm=hog.HOG_NORM_L2) for w, h in sizes]
+    plan = hog.Plan(descs, batch=True)
+    lut = hog.hog_lut_build(8)
+    imgs = [inputs.synth_image(w, h, 3, seed + j) for j, (w, h) in enumerate(sizes)]
+    packed = torch.from_numpy(hog.pack_images(plan, imgs)).cuda()
+    tmpl, bias = inputs.synth_templates(k, plan.sizes.feature_dim, seed + 99)
+    return (plan, lut, imgs, packed, torch.from_numpy(tmpl.reshape(-1)).cuda(),
+            torch.from_numpy(bias).cuda())
+
+
+def _snap(plan, buf):
+    """The defined part of every output: each level's bins and planes (row
+    padding is unspecified) and all scores."""
+    bins, ii = buf.bins.cpu().numpy(), buf.ii.cpu().numpy()
+    out = [buf.scores.cpu().numpy().view(np.uint32)]
+    for l in range(plan.sizes.n_levels):
+        out.append(hog.level_bins(plan, bins, l))
+        out.append(hog.level_planes(plan, ii, l))
+    return out
+
+
+def test_hog_run_equals_the_three_calls():
+    import torch
+    plan, lut, _, packed, tt, bt = _batch_setup([(300, 200), (130, 257)], 2, 4600)
+    b1, b2 = hog.Buffers(plan), hog.Buffers(plan)
+    hog.run_path(plan, lut, packed, tt, bt, b1)
+    hog.hog_run(plan, lut, packed, tt, bt, b2)
+    torch.cuda.synchronize()
+    for x, y in zip(_snap(plan, b1), _snap(plan, b2)):
+        assert np.array_equal(x, y)
+
+
+@pytest.mark.parametrize("k", [1, 32])
+def test_graph_replays_equal_eager(k):
+    """hog_graph: replays with eager work between them, and after the input
+    is refilled in place, give the eager results bit for bit."""
+    import torch
+    sizes = [(320, 240), (257, 301), (640, 360)]
+    plan, lut, imgs, packed, tt, bt = _batch_setup(sizes, k, 4700)
+    ref = hog.Buffers(plan)
+    hog.hog_run(plan, lut, packed, tt, bt, ref)
+    torch.cuda.synchronize()
+    want = _snap(plan, ref)
+    buf = hog.Buffers(plan)
+    g = hog.Graph(plan, lut, packed, tt, bt, buf)
+    other = hog.Buffers(plan)
+    for rep in range(3):
+        g.launch()
+        torch.cuda.synchronize()
+        for x, y in zip(want, _snap(plan, buf)):
+            assert np.array_equal(x, y), f"replay {rep}"
+        hog.hog_run(plan, lut, packed, tt, bt, other)  # eager work between replays
+        buf.scores.zero_()
+        torch.cuda.synchronize()
+    # New image contents in the same buffer: the replay reads them.
+    imgs2 = [inputs.synth_image(w, h, 3, 4800 + j) for j, (w, h) in enumerate(sizes)]
+    packed.copy_(torch.from_numpy(hog.pack_images(plan, imgs2)))
+    g.launch()
+    hog.hog_run(plan, lut, packed, tt, bt, other)
+    torch.cuda.synchronize()
+    for x, y in zip(_snap(plan, other), _snap(plan, buf)):
+        assert np.array_equal(x, y)
+    g.destroy()
