@@ -5,7 +5,10 @@
 A step is one pass of the whole path over one synthetic image:
 hog_bin_map (every pyramid level), hog_integral (one integral image per bin
 per level) and hog_scan_windows (cells, blocks, window scores), through the
-C ABI, with the image, templates and all buffers resident in HBM.
+C ABI, with the image, templates and all buffers resident in HBM. With
+--workload batch64 a step is one pass over a batch of 64 images (one batch
+plan, replayed as a captured HIP graph); the line then also gives the same
+images run through 64 single-image plans, one after another.
 
 Prints one JSON line: processed Mpixel/s (pixels summed over pyramid
 levels), per-step latency percentiles, per-kernel times, the roofline of the
@@ -40,6 +43,12 @@ WORKLOADS = {
     # 320x240 grey, N_b = 8, single level, raw 8x16x8 cell features.
     "gray_320x240": dict(width=320, height=240, channels=1, n_bins=8, max_levels=1, scale=1.0,
                          norm=0, seed=1000, tseed=9000),
+    # Batched: 64 RGB images, sizes uniform in 320..1920 x 240..1080 (seeded),
+    # each with a 1.1 pyramid, N_b = 8, L2 blocks (3360-dim), 32 templates; one
+    # batch plan replayed as a captured HIP graph, beside the same 64 images
+    # run through 64 single-image plans.
+    "batch64": dict(batch=64, size_seed=4000, channels=3, n_bins=8, max_levels=0, scale=1.1,
+                    norm=1, seed=4000, tseed=9003, templates=32),
 }
 KERNELS = ("bin_map", "integral_reduce", "integral_scan", "integral_emit", "cells", "score")
 
@@ -67,30 +76,52 @@ def measured_traffic(workload):
     return int(t.group(1))
 
 
-def cpu_baseline(wl, desc, tmpl, bias):
-    """The oracle (single thread) over one full step of the same workload."""
+def batch_sizes(wl):
+    import numpy as np
+    rng = np.random.default_rng(wl["size_seed"])
+    return [(int(rng.integers(320, 1921)), int(rng.integers(240, 1081))) for _ in range(wl["batch"])]
+
+
+def oracle_image(img, wl, w, h, tmpl, bias):
+    """The oracle over one image's whole pyramid; returns processed pixels."""
     import oracle
-    from paper_1703_06256_amd import inputs
-    img = inputs.synth_image(wl["width"], wl["height"], wl["channels"], wl["seed"])
     p = oracle.ScanParams(norm=wl["norm"])
     nb = wl["n_bins"]
-    levels = oracle.pyramid(wl["width"], wl["height"], wl["scale"], 64, 128,
-                            wl["max_levels"]) if wl["max_levels"] != 1 else \
-        [(wl["width"], wl["height"], 1.0)]
-    t0 = time.perf_counter()
+    levels = oracle.pyramid(w, h, wl["scale"], 64, 128, wl["max_levels"]) \
+        if wl["max_levels"] != 1 else [(w, h, 1.0)]
     px = 0
-    for l, (w, h, s) in enumerate(levels):
-        lvl = img if l == 0 else oracle.resize_nn(img, s, w, h)
+    for l, (lw, lh, s) in enumerate(levels):
+        lvl = img if l == 0 else oracle.resize_nn(img, s, lw, lh)
         bins = oracle.bin_map(lvl, nb)
         oracle.integral(bins, nb)
-        nwx, nwy = oracle.window_grid(w, h, p)
+        nwx, nwy = oracle.window_grid(lw, lh, p)
         if nwx:
             oracle.score_windows(bins, nb, p, tmpl, bias)
-        px += w * h
+        px += lw * lh
+    return px, len(levels)
+
+
+def cpu_baseline(wl, tmpl, bias):
+    """The oracle (single thread) over one full step of the same workload, or
+    (batches) over the first images of the batch."""
+    from paper_1703_06256_amd import inputs
+    t0 = time.perf_counter()
+    if "batch" in wl:
+        px = n_lv = 0
+        n_img = 2
+        for j, (w, h) in enumerate(batch_sizes(wl)[:n_img]):
+            img = inputs.synth_image(w, h, wl["channels"], wl["seed"] + j)
+            a, b = oracle_image(img, wl, w, h, tmpl, bias)
+            px += a
+            n_lv += b
+        what = f"the first {n_img} images of the batch ({n_lv} levels, {px} processed pixels"
+    else:
+        img = inputs.synth_image(wl["width"], wl["height"], wl["channels"], wl["seed"])
+        px, n_lv = oracle_image(img, wl, wl["width"], wl["height"], tmpl, bias)
+        what = f"one full step ({n_lv} levels, {px} processed pixels"
     dt = time.perf_counter() - t0
     return dict(value=px / dt / 1e6, unit="Mpixel/s", cores=1, kind="oracle",
-                sample=f"one full step ({len(levels)} levels, {px} processed pixels: FP64 bins, "
-                       f"Eq.5 integrals, brute-force window scores) in {dt:.2f} s")
+                sample=f"{what}: FP64 bins, Eq.5 integrals, brute-force window scores) in {dt:.2f} s")
 
 
 def main():
@@ -115,21 +146,39 @@ def main():
 
     torch.cuda.set_device(0)
     wl = WORKLOADS[args.workload]
-    desc = hog.make_desc(wl["width"], wl["height"], channels=wl["channels"], n_bins=wl["n_bins"],
-                         max_levels=wl["max_levels"], scale=wl["scale"], norm=wl["norm"])
-    plan = hog.Plan(desc)
+    batch = "batch" in wl
+    K = wl.get("templates", 1)
+    if batch:
+        sizes = batch_sizes(wl)
+        descs = [hog.make_desc(w, h, channels=wl["channels"], n_bins=wl["n_bins"],
+                               max_levels=wl["max_levels"], scale=wl["scale"], norm=wl["norm"],
+                               n_templates=K) for w, h in sizes]
+        plan = hog.Plan(descs, batch=True)
+        imgs = [inputs.synth_image(w, h, wl["channels"], wl["seed"] + j) for j, (w, h) in enumerate(sizes)]
+        img_t = torch.from_numpy(hog.pack_images(plan, imgs)).cuda()
+    else:
+        desc = hog.make_desc(wl["width"], wl["height"], channels=wl["channels"], n_bins=wl["n_bins"],
+                             max_levels=wl["max_levels"], scale=wl["scale"], norm=wl["norm"],
+                             n_templates=K)
+        plan = hog.Plan(desc)
+        img = inputs.synth_image(wl["width"], wl["height"], wl["channels"], wl["seed"])
+        img_t = torch.from_numpy(img.reshape(-1)).cuda()
     sz = plan.sizes
     lut = hog.hog_lut_build(wl["n_bins"])
-    img = inputs.synth_image(wl["width"], wl["height"], wl["channels"], wl["seed"])
-    tmpl, bias = inputs.synth_templates(1, sz.feature_dim, wl["tseed"])
-    img_t = torch.from_numpy(img.reshape(-1)).cuda()
+    tmpl, bias = inputs.synth_templates(K, sz.feature_dim, wl["tseed"])
     tmpl_t = torch.from_numpy(tmpl.reshape(-1)).cuda()
     bias_t = torch.from_numpy(bias).cuda()
     buf = hog.Buffers(plan)
     stream = torch.cuda.current_stream()
 
-    def step():
-        hog.run_path(plan, lut, img_t, tmpl_t, bias_t, buf, stream)
+    if batch:
+        graph = hog.Graph(plan, lut, img_t, tmpl_t, bias_t, buf)
+
+        def step():
+            graph.launch(stream)
+    else:
+        def step():
+            hog.run_path(plan, lut, img_t, tmpl_t, bias_t, buf, stream)
 
     for _ in range(args.warmup):
         step()
@@ -168,7 +217,7 @@ def main():
     hog.hog_timing_reset()
     n_k = min(args.steps, 50)
     for _ in range(n_k):
-        step()
+        hog.run_path(plan, lut, img_t, tmpl_t, bias_t, buf, stream)  # eager: a graph records no events
     torch.cuda.synchronize()
     kern_us = {}
     for k in KERNELS:
@@ -180,6 +229,39 @@ def main():
     # Roofline of the dominant kernel: the integral-image writer moves, per
     # processed pixel, 4*N_b bytes of planes (write) and 1 byte of bins (read).
     emit_bytes = sz.total_pixels * (4 * wl["n_bins"] + 1)
+    extra = {}
+    if batch:
+        # The same images through 64 single-image plans, launched one image
+        # after another (eager), and the batch plan launched eagerly.
+        singles = []
+        for j, (w, h) in enumerate(sizes):
+            p1 = hog.Plan(descs[j])
+            b1 = hog.Buffers(p1)
+            singles.append((p1, torch.from_numpy(imgs[j].reshape(-1)).cuda(), b1))
+
+        def per_image():
+            for p1, im1, b1 in singles:
+                hog.hog_run(p1, lut, im1, tmpl_t, bias_t, b1, stream)
+
+        def eager_batch():
+            hog.hog_run(plan, lut, img_t, tmpl_t, bias_t, buf, stream)
+
+        for name, fn in (("per_image", per_image), ("batch_eager", eager_batch)):
+            for _ in range(3):
+                fn()
+            torch.cuda.synchronize()
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            reps = max(3, min(args.steps, 20))
+            a.record(stream)
+            for _ in range(reps):
+                fn()
+            b.record(stream)
+            torch.cuda.synchronize()
+            t = a.elapsed_time(b) / reps
+            extra[name] = dict(ms=round(t, 4), mpixel_per_s=round(sz.total_pixels / (t * 1e3), 1))
+        extra["speedup_vs_per_image"] = round(extra["per_image"]["ms"] / ms_per_step, 3)
+        del singles
     emit_us = kern_us.get("integral_emit", float("nan"))
     achieved = emit_bytes / (emit_us * 1e-6) / 1e9
     roofline = dict(bound="hbm", kernel="integral_emit", achieved=round(achieved, 1),
@@ -199,7 +281,7 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(wl, desc, tmpl, bias)
+        cpu = cpu_baseline(wl, tmpl, bias)
 
     out = {
         "metric": METRIC,
@@ -216,7 +298,9 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": args.workload,
-            "image": f"{wl['width']}x{wl['height']}x{wl['channels']} uint8",
+            "image": (f"{wl['batch']} images {wl['channels']}ch uint8, sizes uniform 320..1920 x "
+                      f"240..1080 (seed {wl['size_seed']})") if batch else
+                     f"{wl['width']}x{wl['height']}x{wl['channels']} uint8",
             "n_bins": wl["n_bins"],
             "levels": sz.n_levels,
             "pyramid_scale": wl["scale"],
@@ -224,9 +308,11 @@ def main():
             "windows": sz.total_windows,
             "feature_dim": sz.feature_dim,
             "norm": "l2" if wl["norm"] else "raw",
-            "templates": 1,
+            "templates": K,
+            "launch": "captured HIP graph of the batch plan" if batch else "three calls per step",
         },
-        "base_mpixel_per_s": round(wl["width"] * wl["height"] / (ms_per_step * 1e3), 2),
+        "base_mpixel_per_s": round(sum(w * h for w, h in sizes) / (ms_per_step * 1e3), 2) if batch
+        else round(wl["width"] * wl["height"] / (ms_per_step * 1e3), 2),
         "p50_ms": round(float(np.percentile(lat, 50)), 4),
         "p99_ms": round(float(np.percentile(lat, 99)), 4),
         "wall_ms_timed": round(wall_ms, 2),
@@ -234,6 +320,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
+    out.update(extra)
     print(json.dumps(out), flush=True)
 
 
