@@ -171,6 +171,8 @@ def main():
     buf = hog.Buffers(plan)
     stream = torch.cuda.current_stream()
 
+    # Tile shapes picked by timing candidates on these buffers.
+    tiles = hog.autotune(plan, lut, img_t, tmpl_t, bias_t, buf, stream, reps=3)
     if batch:
         graph = hog.Graph(plan, lut, img_t, tmpl_t, bias_t, buf)
 
@@ -310,6 +312,7 @@ def main():
             "norm": "l2" if wl["norm"] else "raw",
             "templates": K,
             "launch": "captured HIP graph of the batch plan" if batch else "three calls per step",
+            "tiles": {"bin_chunk": tiles.bin_chunk, "score_rows": tiles.score_rows, "how": "autotuned"},
         },
         "base_mpixel_per_s": round(sum(w * h for w, h in sizes) / (ms_per_step * 1e3), 2) if batch
         else round(wl["width"] * wl["height"] / (ms_per_step * 1e3), 2),

@@ -232,6 +232,31 @@ hog_status hog_scan_windows(const hog_plan *plan, const uint32_t *ii, const floa
                             float *block_feat, void *workspace, void *stream);
 
 /* ------------------------------------------------------------------------ */
+/* Tile shapes.                                                             */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int32_t bin_chunk;  /* bins per integral wave, 1..6 (a last, shorter chunk takes the rest) */
+    int32_t score_rows; /* window rows per strip of the one-template matrix-core scorer
+                           (L2, 8-cell-wide windows, K < 16, n_bins <= 20); 0 otherwise */
+} hog_tiles;
+
+hog_status hog_plan_get_tiles(const hog_plan *plan, hog_tiles *out);
+/* Install tile shapes (validated: HOG_E_INVALID if out of range). Updates
+ * the plan's device tables (synchronous); not to be called while work that
+ * uses the plan is in flight. Results do not depend on the tile shapes. */
+hog_status hog_plan_set_tiles(hog_plan *plan, const hog_tiles *tiles);
+
+/* Autotuner: times the whole path (hog_run, reps runs per candidate) on the
+ * caller's buffers for each candidate tile shape -- bins per integral wave,
+ * then window rows per strip -- and installs the fastest; *chosen (nullable)
+ * receives it. Synchronises the stream; the buffers' contents after the call
+ * are those of a hog_run. */
+hog_status hog_plan_autotune(hog_plan *plan, const hog_lut *lut, const uint8_t *img,
+                             int64_t img_pitch, uint8_t *bins, uint32_t *ii, const float *tmpl,
+                             const float *bias, float *scores, void *workspace, void *stream,
+                             int reps, hog_tiles *chosen);
+
+/* ------------------------------------------------------------------------ */
 /* The whole path at once.                                                  */
 /* ------------------------------------------------------------------------ */
 

@@ -139,6 +139,8 @@ struct hog_plan {
     std::vector<hog_image_info> images;
     std::vector<Level> levels;
     std::vector<hog_level_info> info;
+    std::vector<int32_t> first;  // host copy of the per-kernel prefix tables
+    size_t first_off;            // their offset in dev_mem
     hog_plan_sizes sizes;
     PlanDev dev;
     void *dev_mem;
@@ -546,6 +548,8 @@ static hog_status create_plan(const hog_plan_desc *descs, int n_img, bool batch,
     std::vector<uint8_t> blob(total_bytes, 0);
     std::memcpy(blob.data(), p->levels.data(), lv_bytes);
     std::memcpy(blob.data() + o_first, first.data(), first_bytes);
+    p->first = first;
+    p->first_off = o_first;
     std::memcpy(blob.data() + o_mx, mapx.data(), mx_bytes);
     std::memcpy(blob.data() + o_my, mapy.data(), my_bytes);
     hipError_t e = hipMalloc(&p->dev_mem, total_bytes);
@@ -737,6 +741,137 @@ extern "C" hog_status hog_scan_windows(const hog_plan *plan, const uint32_t *ii,
         if (e != hipSuccess) return device_fail(e, "score launch");
     }
     return HOG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Tile shapes and their autotuner.
+// ---------------------------------------------------------------------------
+
+// Bins per integral wave: the cap c split evenly (chunks of ceil(nb / ceil(nb / c))).
+static int chunk_for(int nb, int c) { return (nb + (nb + c - 1) / c - 1) / ((nb + c - 1) / c); }
+
+// Installs bins per integral wave and (strip scorer) window rows per strip,
+// updating the level table and the scorer's prefix table on the device.
+static hog_status apply_tiles(hog_plan *p, int chunk, int rows)
+{
+    PlanDev &pd = p->dev;
+    const int L = pd.n_levels, K = pd.n_templates;
+    int64_t max_plane = 0;
+    for (const Level &v : p->levels) max_plane = std::max(max_plane, v.ii_plane);
+    if (chunk < 1 || chunk > hogk::kMaxBinChunk || (int64_t)chunk * max_plane * 4 > ((int64_t)1 << 31) - 1)
+        return fail(HOG_E_INVALID, "bins per integral wave must be in [1, %d] and fit 2 GiB", hogk::kMaxBinChunk);
+    pd.bin_chunk = chunk;
+    pd.n_chunks = (pd.n_bins + chunk - 1) / chunk;
+    if (pd.scorer == 1 && rows != pd.st_th) {
+        if (rows < 1 || rows > 64) return fail(HOG_E_INVALID, "window rows per strip must be in [1, 64]");
+        pd.st_th = rows;
+        const int64_t rowh = (int64_t)(hogk::kStripW + 8) * pd.mfma_ks;
+        pd.st_lds_bytes = (int32_t)(4 * round_up(4 * rowh * 2 + 64 * 4 + (int64_t)hogk::kStripW * rows * 4, 16));
+        int64_t tot = 0;
+        int32_t *f = p->first.data() + (size_t)hogk::KB_STILE * (L + 1);
+        for (int l = 0; l < L; ++l) {
+            Level &v = p->levels[l];
+            v.st_y = v.win_y ? (v.win_y + rows - 1) / rows : 0;
+            f[l] = (int32_t)tot;
+            tot += (int64_t)v.st_x * v.st_y * K;
+        }
+        f[L] = (int32_t)tot;
+        pd.total[hogk::KB_STILE] = tot;
+        hipError_t e = hipMemcpy(p->dev_mem, p->levels.data(), sizeof(Level) * L, hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = hipMemcpy((uint8_t *)p->dev_mem + p->first_off, p->first.data(), sizeof(int32_t) * p->first.size(),
+                          hipMemcpyHostToDevice);
+        if (e != hipSuccess) return device_fail(e, "hipMemcpy(plan tables)");
+    }
+    return HOG_OK;
+}
+
+extern "C" hog_status hog_plan_get_tiles(const hog_plan *plan, hog_tiles *out)
+{
+    if (!plan || !out) return fail(HOG_E_INVALID, "plan or out is NULL");
+    out->bin_chunk = plan->dev.bin_chunk;
+    out->score_rows = plan->dev.scorer == 1 ? plan->dev.st_th : 0;
+    return HOG_OK;
+}
+
+extern "C" hog_status hog_plan_set_tiles(hog_plan *plan, const hog_tiles *tiles)
+{
+    if (!plan || !tiles) return fail(HOG_E_INVALID, "plan or tiles is NULL");
+    return apply_tiles(plan, tiles->bin_chunk, plan->dev.scorer == 1 ? tiles->score_rows : plan->dev.st_th);
+}
+
+static hog_status check_run_args(const hog_plan *plan, const hog_lut *lut, const uint8_t *img,
+                                 int64_t img_pitch, uint8_t *bins, uint32_t *ii, const float *tmpl,
+                                 const float *bias, float *scores, void *workspace);
+static hog_status run_path(const hog_plan *plan, const hog_lut *lut, const uint8_t *img, int64_t img_pitch,
+                           uint8_t *bins, uint32_t *ii, const float *tmpl, const float *bias, float *scores,
+                           void *workspace, void *stream);
+
+extern "C" hog_status hog_plan_autotune(hog_plan *plan, const hog_lut *lut, const uint8_t *img,
+                                        int64_t img_pitch, uint8_t *bins, uint32_t *ii, const float *tmpl,
+                                        const float *bias, float *scores, void *workspace, void *stream,
+                                        int reps, hog_tiles *chosen)
+{
+    hog_status st = check_run_args(plan, lut, img, img_pitch, bins, ii, tmpl, bias, scores, workspace);
+    if (st != HOG_OK) return st;
+    if (reps < 1 || reps > 1000) return fail(HOG_E_INVALID, "reps must be in [1, 1000]");
+    hipStream_t s = (hipStream_t)stream;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        return device_fail(e, "hipEventCreate");
+    }
+    // Mean time of reps whole runs (after one untimed run) with these tiles.
+    auto time_with = [&](int chunk, int rows, float *ms) -> hog_status {
+        hog_status r = apply_tiles(plan, chunk, rows);
+        if (r != HOG_OK) return r;
+        r = run_path(plan, lut, img, img_pitch, bins, ii, tmpl, bias, scores, workspace, stream);
+        if (r != HOG_OK) return r;
+        hipError_t he = hipEventRecord(e0, s);
+        for (int i = 0; i < reps && r == HOG_OK; ++i)
+            r = run_path(plan, lut, img, img_pitch, bins, ii, tmpl, bias, scores, workspace, stream);
+        if (r != HOG_OK) return r;
+        if (he == hipSuccess) he = hipEventRecord(e1, s);
+        if (he == hipSuccess) he = hipEventSynchronize(e1);
+        if (he == hipSuccess) he = hipEventElapsedTime(ms, e0, e1);
+        return he == hipSuccess ? HOG_OK : device_fail(he, "autotune timing");
+    };
+    const int nb = plan->dev.n_bins;
+    int best_chunk = plan->dev.bin_chunk, best_rows = plan->dev.st_th;
+    float best = 1e30f;
+    // Bins per integral wave, then window rows per strip (strip scorer).
+    int64_t max_plane = 0;
+    for (const Level &v : plan->levels) max_plane = std::max(max_plane, v.ii_plane);
+    for (int c = 2; c <= hogk::kMaxBinChunk && st == HOG_OK; ++c) {
+        const int chunk = chunk_for(nb, c);
+        if (chunk != c || (int64_t)chunk * max_plane * 4 > ((int64_t)1 << 31) - 1) continue;
+        float ms = 0.f;
+        st = time_with(chunk, best_rows, &ms);
+        if (st == HOG_OK && ms < best) {
+            best = ms;
+            best_chunk = chunk;
+        }
+    }
+    if (st == HOG_OK && plan->dev.scorer == 1) {
+        const int cand[] = {8, 12, 16, 24, 32};
+        for (int rows : cand) {
+            float ms = 0.f;
+            st = time_with(best_chunk, rows, &ms);
+            if (st != HOG_OK) break;
+            if (ms < best) {
+                best = ms;
+                best_rows = rows;
+            }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != HOG_OK) return st;
+    st = apply_tiles(plan, best_chunk, best_rows);
+    if (st == HOG_OK && chosen) st = hog_plan_get_tiles(plan, chosen);
+    return st;
 }
 
 // ---------------------------------------------------------------------------

@@ -26,7 +26,8 @@ EXPORTS = (
     "hog_lut_host", "hog_plan_create", "hog_plan_create_batch", "hog_plan_images",
     "hog_plan_get_image", "hog_plan_destroy", "hog_plan_get_sizes",
     "hog_plan_get_level", "hog_bin_map", "hog_integral", "hog_scan_windows", "hog_run",
-    "hog_graph_create", "hog_graph_launch", "hog_graph_destroy",
+    "hog_graph_create", "hog_graph_launch", "hog_graph_destroy", "hog_plan_get_tiles",
+    "hog_plan_set_tiles", "hog_plan_autotune",
     "hog_timing_enable", "hog_timing_reset", "hog_timing_get",
 )
 
@@ -66,6 +67,10 @@ class ImageInfo(ctypes.Structure):
                 ("width", ctypes.c_int32), ("height", ctypes.c_int32),
                 ("img_offset", ctypes.c_int64), ("img_pitch", ctypes.c_int64),
                 ("total_pixels", ctypes.c_int64), ("total_windows", ctypes.c_int64)]
+
+
+class Tiles(ctypes.Structure):
+    _fields_ = [("bin_chunk", ctypes.c_int32), ("score_rows", ctypes.c_int32)]
 
 
 class PlanSizes(ctypes.Structure):
@@ -110,6 +115,10 @@ def load_library():
         "hog_graph_create": ([vp, vp, vp, i64, vp, vp, vp, vp, vp, vp, ctypes.POINTER(vp)], i32),
         "hog_graph_launch": ([vp, vp], i32),
         "hog_graph_destroy": ([vp], None),
+        "hog_plan_get_tiles": ([vp, ctypes.POINTER(Tiles)], i32),
+        "hog_plan_set_tiles": ([vp, ctypes.POINTER(Tiles)], i32),
+        "hog_plan_autotune": ([vp, vp, vp, i64, vp, vp, vp, vp, vp, vp, vp, i32,
+                               ctypes.POINTER(Tiles)], i32),
         "hog_timing_enable": ([i32], i32),
         "hog_timing_reset": ([], i32),
         "hog_timing_get": ([ctypes.c_char_p, ctypes.POINTER(i64),
@@ -359,6 +368,25 @@ def _run_args(plan: Plan, lut: Lut, img, tmpl, bias, buf: "Buffers", img_pitch=N
 def hog_run(plan: Plan, lut: Lut, img, tmpl, bias, buf: "Buffers", stream=None, img_pitch=None):
     """The whole path in one C call (hog_run)."""
     _check(load_library().hog_run(*_run_args(plan, lut, img, tmpl, bias, buf, img_pitch), _stream(stream)))
+
+
+def plan_tiles(plan: Plan) -> Tiles:
+    t = Tiles()
+    _check(load_library().hog_plan_get_tiles(plan.handle, ctypes.byref(t)))
+    return t
+
+
+def set_plan_tiles(plan: Plan, bin_chunk: int, score_rows: int = 0):
+    t = Tiles(bin_chunk, score_rows)
+    _check(load_library().hog_plan_set_tiles(plan.handle, ctypes.byref(t)))
+
+
+def autotune(plan: Plan, lut: Lut, img, tmpl, bias, buf: "Buffers", stream=None, reps=3,
+             img_pitch=None) -> Tiles:
+    t = Tiles()
+    _check(load_library().hog_plan_autotune(*_run_args(plan, lut, img, tmpl, bias, buf, img_pitch),
+                                            _stream(stream), int(reps), ctypes.byref(t)))
+    return t
 
 
 class Graph:
