@@ -47,8 +47,8 @@ typedef enum {
     HOG_E_INVALID = 1,   /* bad argument; nothing was enqueued */
     HOG_E_NOMEM = 2,     /* a host or device allocation failed */
     HOG_E_DEVICE = 3,    /* a HIP call or kernel launch failed */
-    HOG_E_BUSY = 4,      /* reserved for the request queue */
-    HOG_E_NOT_READY = 5  /* reserved for the request queue */
+    HOG_E_BUSY = 4,      /* the request queue is full (hog_submit) */
+    HOG_E_NOT_READY = 5  /* the request has not finished (hog_poll) */
 } hog_status;
 
 #define HOG_NO_BIN 255
@@ -280,6 +280,56 @@ hog_status hog_graph_create(const hog_plan *plan, const hog_lut *lut, const uint
                             const float *bias, float *scores, void *workspace, hog_graph **out);
 hog_status hog_graph_launch(hog_graph *graph, void *stream);
 void hog_graph_destroy(hog_graph *graph);
+
+/* ------------------------------------------------------------------------ */
+/* Serving: a request queue with continuous batching.                       */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int32_t channels, n_bins, n_templates;
+    int32_t max_levels;      /* each request's pyramid: 1 = the image only (hog_plan_desc) */
+    double scale;
+    hog_scan_params scan;
+    int32_t max_width, max_height; /* largest image accepted */
+    int64_t memory_budget;   /* device bytes for the requests on the device */
+    int32_t max_slots;       /* requests on the device at once */
+    int32_t max_batch;       /* requests per launch (<= max_slots) */
+    int32_t max_queue;       /* requests waiting; hog_submit returns HOG_E_BUSY beyond */
+    int32_t streams;         /* batches in flight at once, 1..8 */
+} hog_server_config;
+
+typedef struct hog_server hog_server;
+
+/* A server for one detector: the lookup table and the K templates (host,
+ * float[K][D], float[K]; copied) stay on the current device, which also holds
+ * an arena of memory_budget bytes for the requests' buffers. A worker thread
+ * admits waiting requests, oldest first, into a batch while slots and arena
+ * memory allow -- a request's footprint is that of its plan's buffers (bins,
+ * N_b uint32 integral images per level, workspace, scores, image) -- and
+ * runs the batch as one batch plan (hog_plan_create_batch) on one of
+ * `streams` non-blocking streams: copy in from pinned memory, hog_run, scores
+ * out. Requests that arrive while batches are running are admitted into the
+ * next batch as memory frees up, and run concurrently with them. Each
+ * request's scores equal those of running its image alone with
+ * hog_plan_create (bit for bit). Library-owned; hog_server_destroy waits for
+ * the batches on the device and drops requests that never started. */
+hog_status hog_server_create(const hog_server_config *cfg, const float *tmpl_host,
+                             const float *bias_host, hog_server **out);
+void hog_server_destroy(hog_server *server);
+
+/* Queue an image (host, w x h x channels uint8, rows packed; copied before
+ * returning) and get its ticket. HOG_E_INVALID if the image is larger than
+ * max_width x max_height or alone needs more than memory_budget; HOG_E_BUSY if
+ * max_queue requests are waiting. Thread-safe. */
+hog_status hog_submit(hog_server *server, const uint8_t *host_img, int w, int h, uint64_t *ticket);
+
+/* HOG_E_NOT_READY while the request is waiting or running. Once it is done:
+ * copies its scores (every level of its pyramid, in level order, each as
+ * hog_scan_windows lays them out: [wy][wx][K]) into scores (cap floats;
+ * HOG_E_INVALID if too small, the request is kept), sets the level-0 window
+ * grid and the latency from hog_submit to completion (seconds, host clock),
+ * and forgets the ticket. HOG_E_INVALID for an unknown ticket. Thread-safe. */
+hog_status hog_poll(hog_server *server, uint64_t ticket, float *scores, size_t cap, int *nwx,
+                    int *nwy, double *latency_s);
 
 /* ------------------------------------------------------------------------ */
 /* Kernel timing. When enabled, every kernel launch of the calls above is   */

@@ -2,8 +2,9 @@
 
     python -m paper_1703_06256_amd.build
 
-Compiles csrc/hog_kernels.hip for gfx950 and csrc/hog_api.cpp for the host,
-and links them into paper_1703_06256_amd/libhog.so. Packed-FP32 instructions
+Compiles csrc/hog_kernels.hip for gfx950 and csrc/hog_api.cpp and
+csrc/hog_server.cpp for the host, and links them into
+paper_1703_06256_amd/libhog.so. Packed-FP32 instructions
 are disabled for the device code.
 """
 from __future__ import annotations
@@ -37,16 +38,18 @@ def build(verbose: bool = False) -> str:
     os.makedirs(BUILD_DIR, exist_ok=True)
     k_obj = os.path.join(BUILD_DIR, "hog_kernels.o")
     a_obj = os.path.join(BUILD_DIR, "hog_api.o")
+    s_obj = os.path.join(BUILD_DIR, "hog_server.o")
     steps = [
         [HIPCC, *COMMON, *DEVICE, "-c", os.path.join(CSRC, "hog_kernels.hip"), "-o", k_obj],
         [HIPCC, *COMMON, *DEVICE, "-x", "hip", "-c", os.path.join(CSRC, "hog_api.cpp"), "-o", a_obj],
+        [HIPCC, *COMMON, *DEVICE, "-x", "hip", "-c", os.path.join(CSRC, "hog_server.cpp"), "-o", s_obj],
     ]
     for cmd in steps:
         out = _run(cmd)
         if verbose and out:
             print(out)
     tmp = LIB + ".tmp"
-    _run([HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp, k_obj, a_obj])
+    _run([HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-pthread", "-o", tmp, k_obj, a_obj, s_obj])
     os.replace(tmp, LIB)
     return LIB
 

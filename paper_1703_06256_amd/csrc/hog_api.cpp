@@ -146,6 +146,10 @@ struct hog_plan {
     void *dev_mem;
 };
 
+namespace hogk {
+void set_last_error(const char *msg) { g_last_error = msg ? msg : ""; }
+}  // namespace hogk
+
 extern "C" {
 
 const char *hog_last_error(void) { return g_last_error.c_str(); }

@@ -107,6 +107,9 @@ struct PlanDev {
     int64_t total[KB_COUNT];   // totals (= first[k][n_levels])
 };
 
+// Sets the calling thread's hog_last_error() message (hog_api.cpp).
+void set_last_error(const char *msg);
+
 // Launchers (hog_kernels.hip). Each enqueues one kernel on `stream` and
 // returns the launch status.
 hipError_t launch_bin_map(const PlanDev &p, const uint8_t *lut_half, const uint8_t *img,

@@ -27,7 +27,8 @@ EXPORTS = (
     "hog_plan_get_image", "hog_plan_destroy", "hog_plan_get_sizes",
     "hog_plan_get_level", "hog_bin_map", "hog_integral", "hog_scan_windows", "hog_run",
     "hog_graph_create", "hog_graph_launch", "hog_graph_destroy", "hog_plan_get_tiles",
-    "hog_plan_set_tiles", "hog_plan_autotune",
+    "hog_plan_set_tiles", "hog_plan_autotune", "hog_server_create", "hog_server_destroy",
+    "hog_submit", "hog_poll",
     "hog_timing_enable", "hog_timing_reset", "hog_timing_get",
 )
 
@@ -73,6 +74,16 @@ class Tiles(ctypes.Structure):
     _fields_ = [("bin_chunk", ctypes.c_int32), ("score_rows", ctypes.c_int32)]
 
 
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("channels", ctypes.c_int32), ("n_bins", ctypes.c_int32),
+                ("n_templates", ctypes.c_int32), ("max_levels", ctypes.c_int32),
+                ("scale", ctypes.c_double), ("scan", ScanParams),
+                ("max_width", ctypes.c_int32), ("max_height", ctypes.c_int32),
+                ("memory_budget", ctypes.c_int64), ("max_slots", ctypes.c_int32),
+                ("max_batch", ctypes.c_int32), ("max_queue", ctypes.c_int32),
+                ("streams", ctypes.c_int32)]
+
+
 class PlanSizes(ctypes.Structure):
     _fields_ = [("n_levels", ctypes.c_int32), ("bins_bytes", ctypes.c_int64),
                 ("ii_elems", ctypes.c_int64), ("score_elems", ctypes.c_int64),
@@ -116,6 +127,11 @@ def load_library():
         "hog_graph_launch": ([vp, vp], i32),
         "hog_graph_destroy": ([vp], None),
         "hog_plan_get_tiles": ([vp, ctypes.POINTER(Tiles)], i32),
+        "hog_server_create": ([ctypes.POINTER(ServerConfig), vp, vp, ctypes.POINTER(vp)], i32),
+        "hog_server_destroy": ([vp], None),
+        "hog_submit": ([vp, vp, i32, i32, ctypes.POINTER(ctypes.c_uint64)], i32),
+        "hog_poll": ([vp, ctypes.c_uint64, vp, ctypes.c_size_t, ctypes.POINTER(i32),
+                      ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double)], i32),
         "hog_plan_set_tiles": ([vp, ctypes.POINTER(Tiles)], i32),
         "hog_plan_autotune": ([vp, vp, vp, i64, vp, vp, vp, vp, vp, vp, vp, i32,
                                ctypes.POINTER(Tiles)], i32),
@@ -387,6 +403,65 @@ def autotune(plan: Plan, lut: Lut, img, tmpl, bias, buf: "Buffers", stream=None,
     _check(load_library().hog_plan_autotune(*_run_args(plan, lut, img, tmpl, bias, buf, img_pitch),
                                             _stream(stream), int(reps), ctypes.byref(t)))
     return t
+
+
+class Server:
+    """hog_server_*: a request queue with continuous batching on the current
+    device. tmpl float32 [K][D] and bias float32 [K] are host arrays."""
+
+    def __init__(self, tmpl: np.ndarray, bias: np.ndarray, channels=3, n_bins=8, max_levels=1,
+                 scale=1.0, cell=8, win_cells_x=8, win_cells_y=16, block=2, norm=HOG_NORM_L2,
+                 eps=1e-3, max_width=1920, max_height=1080, memory_budget=1 << 30, max_slots=16,
+                 max_batch=8, max_queue=1024, streams=3):
+        self._tmpl = np.ascontiguousarray(tmpl, np.float32)
+        self._bias = np.ascontiguousarray(bias, np.float32)
+        self.k = self._bias.size
+        self.channels = channels
+        self.max_levels = max_levels
+        cfg = ServerConfig(channels, n_bins, self.k, max_levels, scale,
+                           ScanParams(cell, win_cells_x, win_cells_y, block, norm, eps),
+                           max_width, max_height, memory_budget, max_slots, max_batch, max_queue,
+                           streams)
+        h = ctypes.c_void_p()
+        _check(load_library().hog_server_create(
+            ctypes.byref(cfg), self._tmpl.ctypes.data_as(ctypes.c_void_p),
+            self._bias.ctypes.data_as(ctypes.c_void_p), ctypes.byref(h)))
+        self.handle = h
+
+    def submit(self, img: np.ndarray) -> int:
+        a = np.ascontiguousarray(img, np.uint8)
+        h, w = a.shape[0], a.shape[1]
+        t = ctypes.c_uint64()
+        _check(load_library().hog_submit(self.handle, a.ctypes.data_as(ctypes.c_void_p), w, h,
+                                         ctypes.byref(t)))
+        return t.value
+
+    def poll(self, ticket: int, cap: int):
+        """None while not ready; else (scores, nwx, nwy, latency_s): scores is
+        float32[nwy * nwx * K] for single-level servers, else the cap floats
+        written (every level, in order)."""
+        out = np.empty(max(cap, 1), np.float32)
+        nwx, nwy, lat = ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
+        st = load_library().hog_poll(self.handle, ctypes.c_uint64(ticket),
+                                     out.ctypes.data_as(ctypes.c_void_p), cap, ctypes.byref(nwx),
+                                     ctypes.byref(nwy), ctypes.byref(lat))
+        if st == HOG_E_NOT_READY:
+            return None
+        _check(st)
+        if self.max_levels == 1:
+            out = out[:nwx.value * nwy.value * self.k]
+        return out, nwx.value, nwy.value, lat.value
+
+    def close(self):
+        if self.handle:
+            load_library().hog_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Graph:
