@@ -8,7 +8,11 @@ per level) and hog_scan_windows (cells, blocks, window scores), through the
 C ABI, with the image, templates and all buffers resident in HBM. With
 --workload batch64 a step is one pass over a batch of 64 images (one batch
 plan, replayed as a captured HIP graph); the line then also gives the same
-images run through 64 single-image plans, one after another.
+images run through 64 single-image plans, one after another. With
+--workload serve [--rate R] [--requests N] a Poisson stream of mixed-size
+requests goes through the request server (hog_submit / hog_wait_any /
+hog_poll) and, for comparison, through the per-image path; the value is the
+server's throughput at that offered load, with its latency percentiles.
 
 Prints one JSON line: processed Mpixel/s (pixels summed over pyramid
 levels), per-step latency percentiles, per-kernel times, the roofline of the
@@ -129,7 +133,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="pyramid_1920x1080", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="pyramid_1920x1080", choices=sorted(WORKLOADS) + ["serve"])
+    ap.add_argument("--rate", type=float, default=2000.0,
+                    help="serve: offered load in requests per second (Poisson)")
+    ap.add_argument("--requests", type=int, default=400, help="serve: requests in the stream")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 1 GiB device-to-device copy (for counter calibration)")
@@ -145,6 +152,25 @@ def main():
     from paper_1703_06256_amd import hog, inputs
 
     torch.cuda.set_device(0)
+    if args.workload == "serve":
+        from paper_1703_06256_amd import serving_bench
+        r = serving_bench.measure(args.rate, args.requests)
+        srv = r["server"]
+        plain = r["per_image"]
+        print(json.dumps({
+            "metric": METRIC, "value": srv["mpixel_per_s"], "unit": "Mpixel/s", "n_gpus": 1,
+            "steps": args.requests, "warmup": 0, "ms_per_step": None, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+            "config": {"workload": "serve", "requests": args.requests,
+                       "offered_requests_per_s": args.rate,
+                       "sizes": "320x240:800x600:1920x1080:3840x2160 = 4:3:2:1 (seed 5000)",
+                       "n_bins": 8, "templates": serving_bench.K, "levels": 1, "norm": "l2",
+                       "streams": r["streams"], "max_batch": r["max_batch"],
+                       "copy_threads": r["copy_threads"]},
+            "p50_ms": srv["p50_ms"], "p99_ms": srv["p99_ms"], "server": srv, "per_image": plain,
+            "speedup_vs_per_image": round(srv["mpixel_per_s"] / plain["mpixel_per_s"], 3)}),
+            flush=True)
+        return
     wl = WORKLOADS[args.workload]
     batch = "batch" in wl
     K = wl.get("templates", 1)

@@ -291,10 +291,13 @@ typedef struct {
     hog_scan_params scan;
     int32_t max_width, max_height; /* largest image accepted */
     int64_t memory_budget;   /* device bytes for the requests on the device */
+    int64_t host_budget;     /* pinned host bytes for the images of queued requests */
     int32_t max_slots;       /* requests on the device at once */
     int32_t max_batch;       /* requests per launch (<= max_slots) */
     int32_t max_queue;       /* requests waiting; hog_submit returns HOG_E_BUSY beyond */
     int32_t streams;         /* batches in flight at once, 1..8 */
+    int32_t copy_threads;    /* helper threads that split hog_submit's copies of large
+                                images with the caller, 0..32 (0: the caller alone) */
 } hog_server_config;
 
 typedef struct hog_server hog_server;
@@ -302,13 +305,18 @@ typedef struct hog_server hog_server;
 /* A server for one detector: the lookup table and the K templates (host,
  * float[K][D], float[K]; copied) stay on the current device, which also holds
  * an arena of memory_budget bytes for the requests' buffers. A worker thread
- * admits waiting requests, oldest first, into a batch while slots and arena
- * memory allow -- a request's footprint is that of its plan's buffers (bins,
- * N_b uint32 integral images per level, workspace, scores, image) -- and
- * runs the batch as one batch plan (hog_plan_create_batch) on one of
- * `streams` non-blocking streams: copy in from pinned memory, hog_run, scores
- * out. Requests that arrive while batches are running are admitted into the
- * next batch as memory frees up, and run concurrently with them. Each
+ * forms a batch from the oldest waiting request and the waiting requests of
+ * the same image size behind it, while slots and arena memory allow -- a
+ * request's footprint is that of its plan's buffers (bins, N_b uint32
+ * integral images per level, workspace, scores, image) -- and runs it as one
+ * batch plan (hog_plan_create_batch, cached per size and count) on one of
+ * `streams` non-blocking streams: copy in from the pinned host arena
+ * (host_budget bytes), hog_run, each request's scores out into its own
+ * region of a pinned output arena (room for 2 * max_slots results of the
+ * largest image; a finished request holds its region until hog_poll takes
+ * it, and admission waits while the arena is full). Requests that arrive while
+ * batches are running form the next batches as slots and memory free up,
+ * and run concurrently with them. Each
  * request's scores equal those of running its image alone with
  * hog_plan_create (bit for bit). Library-owned; hog_server_destroy waits for
  * the batches on the device and drops requests that never started. */
@@ -316,10 +324,17 @@ hog_status hog_server_create(const hog_server_config *cfg, const float *tmpl_hos
                              const float *bias_host, hog_server **out);
 void hog_server_destroy(hog_server *server);
 
-/* Queue an image (host, w x h x channels uint8, rows packed; copied before
- * returning) and get its ticket. HOG_E_INVALID if the image is larger than
- * max_width x max_height or alone needs more than memory_budget; HOG_E_BUSY if
- * max_queue requests are waiting. Thread-safe. */
+/* Builds the batch plans for 1..max_batch images of w x h now, so that the
+ * first batches of that size do not wait for them (a plan's tables are
+ * allocated and copied synchronously). Optional. HOG_E_INVALID if w x h is
+ * outside max_width x max_height or cannot be planned. Thread-safe. */
+hog_status hog_server_warm(hog_server *server, int w, int h);
+
+/* Queue an image (host, w x h x channels uint8, rows packed; copied into the
+ * server's pinned host memory before returning) and get its ticket.
+ * HOG_E_INVALID if the image is larger than max_width x max_height or alone
+ * needs more than memory_budget; HOG_E_BUSY if max_queue requests are waiting
+ * or host_budget is in use by queued and running requests. Thread-safe. */
 hog_status hog_submit(hog_server *server, const uint8_t *host_img, int w, int h, uint64_t *ticket);
 
 /* HOG_E_NOT_READY while the request is waiting or running. Once it is done:
@@ -330,6 +345,16 @@ hog_status hog_submit(hog_server *server, const uint8_t *host_img, int w, int h,
  * and forgets the ticket. HOG_E_INVALID for an unknown ticket. Thread-safe. */
 hog_status hog_poll(hog_server *server, uint64_t ticket, float *scores, size_t cap, int *nwx,
                     int *nwy, double *latency_s);
+
+/* Completion queue: writes into tickets[] (cap >= 1 entries) the tickets of
+ * requests that finished, succeeded or failed, since the last call, in the
+ * order they finished, and their number into *count; waits up to timeout_us
+ * microseconds (0: no wait) while there are none. Each ticket is reported
+ * once, and not at all if hog_poll has already taken it; take its result
+ * with hog_poll. HOG_E_INVALID for NULL pointers, cap <
+ * 1 or a negative timeout. Thread-safe. */
+hog_status hog_wait_any(hog_server *server, uint64_t *tickets, int cap, int64_t timeout_us,
+                        int *count);
 
 /* ------------------------------------------------------------------------ */
 /* Kernel timing. When enabled, every kernel launch of the calls above is   */

@@ -1,20 +1,24 @@
 // Request serving with continuous batching (hog_server_*, hog_submit,
 // hog_poll): the scan of Sec. 4 applied to a stream of images.
 //
-// hog_submit copies a host image into the server and returns a ticket. A
-// worker thread admits pending requests, oldest first, into a batch while
-// in-flight slots and device memory allow; admission is by the device
+// hog_submit copies a host image into the server's pinned host arena and
+// returns a ticket. A worker thread forms batches: the oldest waiting
+// request and the waiting requests of the same image size behind it, as many
+// as in-flight slots and device memory allow. Admission is by the device
 // footprint of the batch's buffers (bins, integral images, workspace,
-// scores), carved from one arena allocated at creation. The batch is packed
-// into pinned host memory, copied in, run through hog_run on a batch plan
-// (one launch per kernel for all its images), and its scores copied back,
-// all on one of several non-blocking streams; requests that arrive while
-// batches are on the device form the next batch on another stream, so their
-// work overlaps. Batch plans are cached by composition; the lookup table and
-// the templates stay resident. hog_poll returns a finished request's scores
-// and its latency (submit to ready, host clock).
+// scores), carved from one arena allocated at creation. The batch's images
+// are copied in from pinned memory, run through hog_run on a batch plan (one
+// launch per kernel for all its images), and its scores copied back, all on
+// one of several non-blocking streams; requests that arrive while batches
+// are on the device form the next batch on another stream. Batches of one
+// size keep the plan cache to (sizes seen) x max_batch entries, each built
+// once (building one allocates and copies its tables synchronously, too slow
+// to do per batch). The lookup table and the templates stay resident.
+// hog_wait_any reports finished tickets as they complete; hog_poll returns a
+// finished request's scores and its latency (submit to ready, host clock).
 #include "hog.h"
 #include "hog_internal.h"
+#include "copy_pool.h"
 
 #include <hip/hip_runtime.h>
 
@@ -54,12 +58,12 @@ int64_t align256(int64_t x) { return (x + 255) & ~(int64_t)255; }
 struct Request {
     uint64_t ticket = 0;
     int w = 0, h = 0;
-    std::vector<uint8_t> img;  // host copy, rows of w * channels bytes
-    int64_t footprint = 0;     // device bytes of the image alone
+    int64_t img_off = 0, img_bytes = 0;  // the image in the pinned host arena
+    int64_t footprint = 0;               // device bytes of the image alone
     Clock::time_point t_submit;
     bool ready = false;
     hog_status status = HOG_OK;
-    std::vector<float> scores;
+    int64_t out_off = -1, n_scores = 0;  // the scores in the pinned output arena
     int nwx = 0, nwy = 0;
     double latency = 0.0;
 };
@@ -132,10 +136,6 @@ Layout layout_of(const hog_plan_sizes &z, int64_t img_bytes)
 struct Slot {
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
-    uint8_t *pin_in = nullptr;  // packed images (pinned)
-    size_t in_cap = 0;
-    float *pin_out = nullptr;  // scores (pinned)
-    size_t out_cap = 0;
     bool busy = false;
     std::vector<ReqPtr> reqs;
     hog_plan *plan = nullptr;
@@ -151,13 +151,21 @@ struct hog_server {
     float *d_tmpl = nullptr, *d_bias = nullptr;
     uint8_t *arena_base = nullptr;
     Arena arena;
+    uint8_t *host_base = nullptr;  // pinned host arena for queued images
+    Arena host_arena;
+    uint8_t *out_base = nullptr;   // pinned arena for finished requests' scores
+    Arena out_arena;
+    hogk::CopyPool copies;
     std::vector<Slot> slots;
     std::map<std::vector<std::pair<int, int>>, hog_plan *> plans;  // by batch composition
     std::mutex mu;                                                 // guards the fields below
-    std::condition_variable cv;
+    std::condition_variable cv;       // wakes the worker
+    std::condition_variable done_cv;  // wakes hog_wait_any
     std::deque<ReqPtr> pending;
+    std::deque<uint64_t> done_q;      // finished, not yet reported by hog_wait_any
     std::map<uint64_t, ReqPtr> live;  // submitted and not yet returned by hog_poll
     int in_flight = 0;                // requests on the device
+    uint64_t events = 0;              // bumped by every change that may let the worker admit
     uint64_t next_ticket = 1;
     bool stop = false;
     std::mutex plan_mu;  // guards plans
@@ -203,62 +211,56 @@ int64_t batch_bytes(hog_plan *p, int64_t img_bytes)
     return layout_of(z, img_bytes).total;
 }
 
-// Finished batch in slot i: scores to the requests, memory back to the arena.
+// Finished batch: its requests become ready (their scores are already in
+// their output regions), its device memory goes back to the arena. Copies
+// nothing.
 void finish(hog_server *s, Slot &sl, hipError_t err)
 {
-    hog_plan_sizes z;
-    hog_plan_get_sizes(sl.plan, &z);
-    const int K = s->cfg.n_templates;
     const auto now = Clock::now();
     std::lock_guard<std::mutex> lk(s->mu);
-    for (size_t i = 0; i < sl.reqs.size(); ++i) {
-        Request &r = *sl.reqs[i];
+    for (auto &rp : sl.reqs) {
+        Request &r = *rp;
         if (err != hipSuccess) {
             r.status = HOG_E_DEVICE;
-        } else {
-            hog_image_info im;
-            hog_plan_get_image(sl.plan, (int)i, &im);
-            hog_level_info first, last;
-            hog_plan_get_level(sl.plan, im.first_level, &first);
-            hog_plan_get_level(sl.plan, im.first_level + im.n_levels - 1, &last);
-            const int64_t a = first.score_offset;
-            const int64_t b = last.score_offset + (int64_t)last.windows_x * last.windows_y * K;
-            r.scores.assign(sl.pin_out + a, sl.pin_out + b);
-            r.nwx = first.windows_x;
-            r.nwy = first.windows_y;
+            if (r.out_off >= 0) s->out_arena.release(r.out_off, align256(r.n_scores * 4));
+            r.out_off = -1;
         }
         r.latency = std::chrono::duration<double>(now - r.t_submit).count();
         r.ready = true;
+        s->host_arena.release(r.img_off, align256(r.img_bytes));
+        s->done_q.push_back(r.ticket);
     }
+    s->done_cv.notify_all();
     s->arena.release(sl.off, sl.bytes);
     s->in_flight -= (int)sl.reqs.size();
     sl.reqs.clear();
     sl.busy = false;
-    s->cv.notify_all();
+    ++s->events;
 }
 
-// Launches one batch into a free slot if requests and memory allow.
+// Launches one batch into a free slot if requests and memory allow: the
+// oldest waiting request and those of its size behind it, in arrival order.
 bool admit(hog_server *s, Slot &sl)
 {
     std::vector<ReqPtr> take;
     {
         std::lock_guard<std::mutex> lk(s->mu);
         const int room = std::min(s->cfg.max_batch, s->cfg.max_slots - s->in_flight);
-        for (auto it = s->pending.begin(); it != s->pending.end() && (int)take.size() < room; ++it)
-            take.push_back(*it);
+        if (room > 0 && !s->pending.empty()) {
+            const int w = s->pending.front()->w, h = s->pending.front()->h;
+            for (auto it = s->pending.begin(); it != s->pending.end() && (int)take.size() < room; ++it)
+                if ((*it)->w == w && (*it)->h == h) take.push_back(*it);
+        }
     }
     if (take.empty()) return false;
     // Largest batch (oldest first) whose buffers fit the arena now.
     while (!take.empty()) {
-        std::vector<ReqPtr> order(take);
-        std::stable_sort(order.begin(), order.end(), [](const ReqPtr &a, const ReqPtr &b) {
-            return std::make_pair(a->w, a->h) < std::make_pair(b->w, b->h);
-        });
+        const std::vector<ReqPtr> &order = take;
         std::vector<std::pair<int, int>> key;
         int64_t img_bytes = 0;
         for (auto &r : order) {
             key.emplace_back(r->w, r->h);
-            img_bytes += (int64_t)r->img.size();
+            img_bytes += r->img_bytes;
         }
         hog_plan *p = plan_for(s, key);
         if (!p) {  // cannot plan this batch: fail its oldest request
@@ -266,19 +268,44 @@ bool admit(hog_server *s, Slot &sl)
             ReqPtr r = take.front();
             r->status = HOG_E_INVALID;
             r->ready = true;
+            s->host_arena.release(r->img_off, align256(r->img_bytes));
             s->pending.erase(std::find(s->pending.begin(), s->pending.end(), r));
+            s->done_q.push_back(r->ticket);
+            s->done_cv.notify_all();
             return true;
         }
         const int64_t bytes = batch_bytes(p, img_bytes);
         hog_plan_sizes z;
         hog_plan_get_sizes(p, &z);
+        // Each request's scores: [a, b) of the batch's score buffer.
+        const int K = s->cfg.n_templates;
+        std::vector<int64_t> sc_a(order.size()), sc_n(order.size());
+        for (size_t i = 0; i < order.size(); ++i) {
+            hog_image_info im;
+            hog_plan_get_image(p, (int)i, &im);
+            hog_level_info first, last;
+            hog_plan_get_level(p, im.first_level, &first);
+            hog_plan_get_level(p, im.first_level + im.n_levels - 1, &last);
+            sc_a[i] = first.score_offset;
+            sc_n[i] = last.score_offset + (int64_t)last.windows_x * last.windows_y * K - sc_a[i];
+            order[i]->nwx = first.windows_x;
+            order[i]->nwy = first.windows_y;
+            order[i]->n_scores = sc_n[i];
+        }
         int64_t off = 0;
         bool ok;
         {
             std::lock_guard<std::mutex> lk(s->mu);
-            ok = (size_t)img_bytes <= sl.in_cap && (size_t)z.score_elems <= sl.out_cap &&
-                 s->arena.alloc(bytes, &off);
-            if (ok) {
+            ok = s->arena.alloc(bytes, &off);
+            size_t i = 0;
+            for (; ok && i < order.size(); ++i)
+                if (sc_n[i] > 0 && !s->out_arena.alloc(align256(sc_n[i] * 4), &order[i]->out_off)) ok = false;
+            if (!ok) {  // undo
+                for (size_t j = 0; j + 1 < i; ++j)
+                    if (sc_n[j] > 0) s->out_arena.release(order[j]->out_off, align256(sc_n[j] * 4));
+                if (i > 0) s->arena.release(off, bytes);
+                for (auto &r : order) r->out_off = -1;
+            } else {
                 for (auto &r : take) s->pending.erase(std::find(s->pending.begin(), s->pending.end(), r));
                 s->in_flight += (int)take.size();
             }
@@ -287,22 +314,25 @@ bool admit(hog_server *s, Slot &sl)
             take.pop_back();
             continue;
         }
-        // Pack, copy in, run, copy the scores out.
+        // Copy the images in (packed as the batch plan reads them), run, copy
+        // the scores out.
         const Layout L = layout_of(z, img_bytes);
-        for (int i = 0; i < (int)order.size(); ++i) {
+        uint8_t *base = s->arena_base + off;
+        hipError_t e = hipSuccess;
+        for (int i = 0; i < (int)order.size() && e == hipSuccess; ++i) {
             hog_image_info im;
             hog_plan_get_image(p, i, &im);
-            std::memcpy(sl.pin_in + im.img_offset, order[i]->img.data(), order[i]->img.size());
+            e = hipMemcpyAsync(base + L.img + im.img_offset, s->host_base + order[i]->img_off,
+                               (size_t)order[i]->img_bytes, hipMemcpyHostToDevice, sl.stream);
         }
-        uint8_t *base = s->arena_base + off;
-        hipError_t e = hipMemcpyAsync(base + L.img, sl.pin_in, (size_t)img_bytes, hipMemcpyHostToDevice, sl.stream);
         hog_status st = HOG_OK;
         if (e == hipSuccess)
             st = hog_run(p, s->lut, base + L.img, 0, base + L.bins, (uint32_t *)(base + L.ii), s->d_tmpl,
                          s->d_bias, (float *)(base + L.scores), base + L.ws, sl.stream);
-        if (e == hipSuccess && st == HOG_OK && z.score_elems > 0)
-            e = hipMemcpyAsync(sl.pin_out, base + L.scores, (size_t)z.score_elems * 4, hipMemcpyDeviceToHost,
-                               sl.stream);
+        for (size_t i = 0; i < order.size() && e == hipSuccess && st == HOG_OK; ++i)
+            if (sc_n[i] > 0)
+                e = hipMemcpyAsync(s->out_base + order[i]->out_off, base + L.scores + sc_a[i] * 4,
+                                   (size_t)sc_n[i] * 4, hipMemcpyDeviceToHost, sl.stream);
         if (e == hipSuccess && st == HOG_OK) e = hipEventRecord(sl.done, sl.stream);
         sl.reqs = order;
         sl.plan = p;
@@ -319,6 +349,11 @@ void worker_main(hog_server *s)
 {
     (void)hipSetDevice(s->device);
     for (;;) {
+        uint64_t seen;
+        {
+            std::lock_guard<std::mutex> lk(s->mu);
+            seen = s->events;
+        }
         bool progress = false;
         for (Slot &sl : s->slots) {
             if (!sl.busy) continue;
@@ -334,13 +369,27 @@ void worker_main(hog_server *s)
         for (Slot &sl : s->slots) any_busy = any_busy || sl.busy;
         if (s->stop && !any_busy) break;
         if (!progress) {
+            // Batches on the device: poll their events again soon. Otherwise
+            // sleep until a submission, a poll that frees output space, or
+            // stop (events counts them, so none is missed).
             if (any_busy)
                 s->cv.wait_for(lk, std::chrono::microseconds(20));
             else
-                s->cv.wait_for(lk, std::chrono::milliseconds(5),
-                               [&] { return s->stop || !s->pending.empty(); });
+                s->cv.wait_for(lk, std::chrono::milliseconds(50),
+                               [&] { return s->stop || s->events != seen; });
         }
     }
+}
+
+// Callers that only poll never drain the completion queue: drop the tickets
+// hog_poll has taken once they outnumber the live ones (caller holds mu).
+void forget_done(hog_server *s)
+{
+    if (s->done_q.size() <= 2 * s->live.size() + 64) return;
+    std::deque<uint64_t> keep;
+    for (uint64_t t : s->done_q)
+        if (s->live.count(t)) keep.push_back(t);
+    s->done_q.swap(keep);
 }
 
 }  // namespace
@@ -359,6 +408,9 @@ extern "C" hog_status hog_server_create(const hog_server_config *cfg, const floa
         return srv_fail(HOG_E_INVALID, "max_width / max_height outside [1, 32767]");
     if (c.memory_budget < 1) return srv_fail(HOG_E_INVALID, "memory_budget must be positive");
     if (c.max_queue < 1) return srv_fail(HOG_E_INVALID, "max_queue must be positive");
+    if (c.copy_threads < 0 || c.copy_threads > 32) return srv_fail(HOG_E_INVALID, "copy_threads outside [0, 32]");
+    const int64_t max_img = (int64_t)c.max_width * c.max_height * c.channels;
+    if (c.host_budget < max_img) return srv_fail(HOG_E_INVALID, "host_budget must hold the largest image");
     // Validate the description through a plan of the largest image.
     hog_plan_desc d = desc_for(c, c.max_width, c.max_height);
     hog_plan *probe = nullptr;
@@ -389,17 +441,22 @@ extern "C" hog_status hog_server_create(const hog_server_config *cfg, const floa
     if (hipMalloc(&s->arena_base, (size_t)c.memory_budget) != hipSuccess)
         return cleanup(HOG_E_NOMEM, "arena of memory_budget bytes");
     s->arena.reset(c.memory_budget);
-    const size_t in_cap = (size_t)c.max_batch * c.max_width * c.max_height * c.channels;
+    if (hipHostMalloc((void **)&s->host_base, (size_t)c.host_budget, hipHostMallocDefault) != hipSuccess)
+        return cleanup(HOG_E_NOMEM, "pinned host arena of host_budget bytes");
+    s->host_arena.reset(c.host_budget);
+    // Scores of the requests on the device and of finished ones not yet
+    // polled: twice max_slots requests of the largest image.
+    const int64_t out_bytes = 2 * (int64_t)c.max_slots * align256(std::max<int64_t>(z.score_elems, 1) * 4);
+    if (hipHostMalloc((void **)&s->out_base, (size_t)out_bytes, hipHostMallocDefault) != hipSuccess)
+        return cleanup(HOG_E_NOMEM, "pinned output arena");
+    s->out_arena.reset(out_bytes);
     s->slots.resize(c.streams);
     for (Slot &sl : s->slots) {
-        sl.in_cap = in_cap;
-        sl.out_cap = (size_t)c.max_batch * (size_t)std::max<int64_t>(z.score_elems, 1);
         if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess ||
-            hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess ||
-            hipHostMalloc((void **)&sl.pin_in, in_cap, hipHostMallocDefault) != hipSuccess ||
-            hipHostMalloc((void **)&sl.pin_out, sl.out_cap * 4, hipHostMallocDefault) != hipSuccess)
+            hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess)
             return cleanup(HOG_E_NOMEM, "stream slot");
     }
+    s->copies.start(c.copy_threads);
     s->worker = std::thread(worker_main, s);
     *out = s;
     return HOG_OK;
@@ -412,6 +469,7 @@ extern "C" void hog_server_destroy(hog_server *s)
         {
             std::lock_guard<std::mutex> lk(s->mu);
             s->stop = true;
+            ++s->events;
             s->pending.clear();  // queued, never started
         }
         s->cv.notify_all();
@@ -421,9 +479,9 @@ extern "C" void hog_server_destroy(hog_server *s)
         if (sl.stream) (void)hipStreamSynchronize(sl.stream);
         if (sl.done) (void)hipEventDestroy(sl.done);
         if (sl.stream) (void)hipStreamDestroy(sl.stream);
-        if (sl.pin_in) (void)hipHostFree(sl.pin_in);
-        if (sl.pin_out) (void)hipHostFree(sl.pin_out);
     }
+    if (s->host_base) (void)hipHostFree(s->host_base);
+    if (s->out_base) (void)hipHostFree(s->out_base);
     for (auto &kv : s->plans) hog_plan_destroy(kv.second);
     if (s->arena_base) (void)hipFree(s->arena_base);
     if (s->d_tmpl) (void)hipFree(s->d_tmpl);
@@ -455,15 +513,23 @@ extern "C" hog_status hog_submit(hog_server *s, const uint8_t *host_img, int w, 
     auto r = std::make_shared<Request>();
     r->w = w;
     r->h = h;
-    r->img.assign(host_img, host_img + (size_t)w * h * s->cfg.channels);
+    r->img_bytes = (int64_t)w * h * s->cfg.channels;
     r->footprint = fp;
     r->t_submit = Clock::now();
     {
         std::lock_guard<std::mutex> lk(s->mu);
         if ((int)s->pending.size() >= s->cfg.max_queue) return srv_fail(HOG_E_BUSY, "queue full");
+        if (!s->host_arena.alloc(align256(r->img_bytes), &r->img_off))
+            return srv_fail(HOG_E_BUSY, "pinned host arena full");
+    }
+    // The region is this request's alone until its batch finishes.
+    s->copies.copy(s->host_base + r->img_off, host_img, (size_t)r->img_bytes);
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
         r->ticket = s->next_ticket++;
         s->pending.push_back(r);
         s->live[r->ticket] = r;
+        ++s->events;
     }
     s->cv.notify_all();
     *ticket = r->ticket;
@@ -474,22 +540,64 @@ extern "C" hog_status hog_poll(hog_server *s, uint64_t ticket, float *scores, si
                                double *latency_s)
 {
     if (!s) return srv_fail(HOG_E_INVALID, "server is NULL");
-    std::lock_guard<std::mutex> lk(s->mu);
-    auto it = s->live.find(ticket);
-    if (it == s->live.end()) return srv_fail(HOG_E_INVALID, "unknown ticket %llu", (unsigned long long)ticket);
-    Request &r = *it->second;
-    if (!r.ready) return HOG_E_NOT_READY;
-    if (r.status != HOG_OK) {
-        const hog_status st = r.status;
-        s->live.erase(it);
-        return srv_fail(st, "request failed on the device");
+    ReqPtr r;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        auto it = s->live.find(ticket);
+        if (it == s->live.end())
+            return srv_fail(HOG_E_INVALID, "unknown ticket %llu", (unsigned long long)ticket);
+        r = it->second;
+        if (!r->ready) return HOG_E_NOT_READY;
+        if (r->status == HOG_OK && ((size_t)r->n_scores > cap || (!scores && r->n_scores > 0)))
+            return srv_fail(HOG_E_INVALID, "scores needs %lld floats", (long long)r->n_scores);
+        s->live.erase(it);  // the request is the caller's alone from here
+        forget_done(s);
     }
-    if (r.scores.size() > cap || (!scores && !r.scores.empty()))
-        return srv_fail(HOG_E_INVALID, "scores needs %zu floats", r.scores.size());
-    if (!r.scores.empty()) std::memcpy(scores, r.scores.data(), r.scores.size() * 4);
-    if (nwx) *nwx = r.nwx;
-    if (nwy) *nwy = r.nwy;
-    if (latency_s) *latency_s = r.latency;
-    s->live.erase(it);
+    if (r->status != HOG_OK) return srv_fail(r->status, "request failed on the device");
+    if (r->n_scores > 0) std::memcpy(scores, s->out_base + r->out_off, (size_t)r->n_scores * 4);
+    if (nwx) *nwx = r->nwx;
+    if (nwy) *nwy = r->nwy;
+    if (latency_s) *latency_s = r->latency;
+    if (r->out_off >= 0) {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->out_arena.release(r->out_off, align256(r->n_scores * 4));
+        ++s->events;
+        s->cv.notify_all();  // output space for the worker
+    }
+    return HOG_OK;
+}
+
+extern "C" hog_status hog_wait_any(hog_server *s, uint64_t *tickets, int cap, int64_t timeout_us, int *count)
+{
+    if (count) *count = 0;
+    if (!s || !tickets || !count) return srv_fail(HOG_E_INVALID, "NULL argument");
+    if (cap < 1 || timeout_us < 0) return srv_fail(HOG_E_INVALID, "need cap >= 1 and timeout_us >= 0");
+    std::unique_lock<std::mutex> lk(s->mu);
+    if (s->done_q.empty() && timeout_us > 0)
+        s->done_cv.wait_for(lk, std::chrono::microseconds(timeout_us), [&] { return !s->done_q.empty(); });
+    int n = 0;
+    while (n < cap && !s->done_q.empty()) {
+        const uint64_t t = s->done_q.front();
+        s->done_q.pop_front();
+        if (s->live.count(t)) tickets[n++] = t;  // not yet taken by hog_poll
+    }
+    *count = n;
+    return HOG_OK;
+}
+
+extern "C" hog_status hog_server_warm(hog_server *s, int w, int h)
+{
+    if (!s) return srv_fail(HOG_E_INVALID, "server is NULL");
+    if (w < 1 || h < 1 || w > s->cfg.max_width || h > s->cfg.max_height)
+        return srv_fail(HOG_E_INVALID, "image %dx%d outside [1, %d] x [1, %d]", w, h, s->cfg.max_width,
+                        s->cfg.max_height);
+    std::vector<std::pair<int, int>> key;
+    for (int n = 1; n <= s->cfg.max_batch; ++n) {
+        key.emplace_back(w, h);
+        if (!plan_for(s, key)) {
+            const std::string why = hog_last_error();
+            return srv_fail(HOG_E_INVALID, "cannot plan %d images of %dx%d: %s", n, w, h, why.c_str());
+        }
+    }
     return HOG_OK;
 }

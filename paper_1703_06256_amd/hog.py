@@ -28,7 +28,7 @@ EXPORTS = (
     "hog_plan_get_level", "hog_bin_map", "hog_integral", "hog_scan_windows", "hog_run",
     "hog_graph_create", "hog_graph_launch", "hog_graph_destroy", "hog_plan_get_tiles",
     "hog_plan_set_tiles", "hog_plan_autotune", "hog_server_create", "hog_server_destroy",
-    "hog_submit", "hog_poll",
+    "hog_server_warm", "hog_submit", "hog_poll", "hog_wait_any",
     "hog_timing_enable", "hog_timing_reset", "hog_timing_get",
 )
 
@@ -79,9 +79,10 @@ class ServerConfig(ctypes.Structure):
                 ("n_templates", ctypes.c_int32), ("max_levels", ctypes.c_int32),
                 ("scale", ctypes.c_double), ("scan", ScanParams),
                 ("max_width", ctypes.c_int32), ("max_height", ctypes.c_int32),
-                ("memory_budget", ctypes.c_int64), ("max_slots", ctypes.c_int32),
+                ("memory_budget", ctypes.c_int64), ("host_budget", ctypes.c_int64),
+                ("max_slots", ctypes.c_int32),
                 ("max_batch", ctypes.c_int32), ("max_queue", ctypes.c_int32),
-                ("streams", ctypes.c_int32)]
+                ("streams", ctypes.c_int32), ("copy_threads", ctypes.c_int32)]
 
 
 class PlanSizes(ctypes.Structure):
@@ -132,6 +133,8 @@ def load_library():
         "hog_submit": ([vp, vp, i32, i32, ctypes.POINTER(ctypes.c_uint64)], i32),
         "hog_poll": ([vp, ctypes.c_uint64, vp, ctypes.c_size_t, ctypes.POINTER(i32),
                       ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double)], i32),
+        "hog_server_warm": ([vp, i32, i32], i32),
+        "hog_wait_any": ([vp, ctypes.POINTER(ctypes.c_uint64), i32, i64, ctypes.POINTER(i32)], i32),
         "hog_plan_set_tiles": ([vp, ctypes.POINTER(Tiles)], i32),
         "hog_plan_autotune": ([vp, vp, vp, i64, vp, vp, vp, vp, vp, vp, vp, i32,
                                ctypes.POINTER(Tiles)], i32),
@@ -411,8 +414,10 @@ class Server:
 
     def __init__(self, tmpl: np.ndarray, bias: np.ndarray, channels=3, n_bins=8, max_levels=1,
                  scale=1.0, cell=8, win_cells_x=8, win_cells_y=16, block=2, norm=HOG_NORM_L2,
-                 eps=1e-3, max_width=1920, max_height=1080, memory_budget=1 << 30, max_slots=16,
-                 max_batch=8, max_queue=1024, streams=3):
+                 eps=1e-3, max_width=1920, max_height=1080, memory_budget=1 << 30, host_budget=None,
+                 max_slots=16, max_batch=8, max_queue=1024, streams=3, copy_threads=4):
+        if host_budget is None:
+            host_budget = 4 * max_batch * max_width * max_height * channels
         self._tmpl = np.ascontiguousarray(tmpl, np.float32)
         self._bias = np.ascontiguousarray(bias, np.float32)
         self.k = self._bias.size
@@ -420,13 +425,17 @@ class Server:
         self.max_levels = max_levels
         cfg = ServerConfig(channels, n_bins, self.k, max_levels, scale,
                            ScanParams(cell, win_cells_x, win_cells_y, block, norm, eps),
-                           max_width, max_height, memory_budget, max_slots, max_batch, max_queue,
-                           streams)
+                           max_width, max_height, memory_budget, host_budget, max_slots, max_batch,
+                           max_queue, streams, copy_threads)
         h = ctypes.c_void_p()
         _check(load_library().hog_server_create(
             ctypes.byref(cfg), self._tmpl.ctypes.data_as(ctypes.c_void_p),
             self._bias.ctypes.data_as(ctypes.c_void_p), ctypes.byref(h)))
         self.handle = h
+
+    def warm(self, w: int, h: int):
+        """Build the batch plans for 1..max_batch images of w x h now."""
+        _check(load_library().hog_server_warm(self.handle, w, h))
 
     def submit(self, img: np.ndarray) -> int:
         a = np.ascontiguousarray(img, np.uint8)
@@ -436,11 +445,13 @@ class Server:
                                          ctypes.byref(t)))
         return t.value
 
-    def poll(self, ticket: int, cap: int):
+    def poll(self, ticket: int, cap: int, out: np.ndarray = None):
         """None while not ready; else (scores, nwx, nwy, latency_s): scores is
         float32[nwy * nwx * K] for single-level servers, else the cap floats
-        written (every level, in order)."""
-        out = np.empty(max(cap, 1), np.float32)
+        written (every level, in order). `out` (float32, >= cap) avoids an
+        allocation per call."""
+        if out is None:
+            out = np.empty(max(cap, 1), np.float32)
         nwx, nwy, lat = ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
         st = load_library().hog_poll(self.handle, ctypes.c_uint64(ticket),
                                      out.ctypes.data_as(ctypes.c_void_p), cap, ctypes.byref(nwx),
@@ -451,6 +462,14 @@ class Server:
         if self.max_levels == 1:
             out = out[:nwx.value * nwy.value * self.k]
         return out, nwx.value, nwy.value, lat.value
+
+    def wait_any(self, timeout_us: int = 0, cap: int = 256) -> list:
+        """Tickets finished since the last call (hog_wait_any), waiting up to
+        timeout_us while there are none."""
+        buf = (ctypes.c_uint64 * cap)()
+        n = ctypes.c_int()
+        _check(load_library().hog_wait_any(self.handle, buf, cap, int(timeout_us), ctypes.byref(n)))
+        return list(buf[:n.value])
 
     def close(self):
         if self.handle:

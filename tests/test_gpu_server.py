@@ -1,4 +1,4 @@
-"""Serving (hog_server_*, hog_submit, hog_poll): requests of mixed sizes,
+"""Serving (hog_server_*, hog_submit, hog_poll, hog_wait_any): requests of mixed sizes,
 submitted while others run, each give the scores of their image run alone
 (bit for bit) and of the oracle (within tolerance); a memory budget that
 fits one request at a time still completes every request; bad calls fail
@@ -138,3 +138,110 @@ def test_server_errors():
     srv.close()
     with pytest.raises(hog.HogError):
         hog.Server(tmpl, bias, max_batch=0)
+
+
+def test_wait_any_reports_each_ticket_once():
+    tmpl, bias = _templates()
+    srv = hog.Server(tmpl, bias, channels=3, n_bins=8, max_width=800, max_height=600,
+                     memory_budget=512 << 20, max_slots=8, max_batch=4, streams=2)
+    srv.warm(320, 240)
+    sizes = [SIZES[j % 3] for j in range(12)]
+    imgs = [inputs.synth_image(w, h, 3, 5400 + j) for j, (w, h) in enumerate(sizes)]
+    tickets = [srv.submit(im) for im in imgs]
+    seen = []
+    t0 = time.time()
+    while len(seen) < len(tickets):
+        seen += srv.wait_any(2000)
+        assert time.time() - t0 < 60, "requests did not finish"
+    assert sorted(seen) == sorted(tickets)
+    assert srv.wait_any(0) == []
+    for t, im, (w, h) in zip(tickets, imgs, sizes):
+        r = srv.poll(t, _cap(w, h))
+        assert r is not None
+        want, _, _ = _alone(im, tmpl, bias)
+        assert np.array_equal(r[0].view(np.uint32), want.view(np.uint32))
+    with pytest.raises(hog.HogError) as e:
+        srv.warm(801, 600)
+    assert e.value.status == hog.HOG_E_INVALID
+    srv.close()
+
+
+def test_host_budget_rejects_with_busy_and_accepted_requests_finish():
+    tmpl, bias = _templates()
+    one = 320 * 240 * 3
+    with pytest.raises(hog.HogError) as e:
+        hog.Server(tmpl, bias, max_width=320, max_height=240, memory_budget=64 << 20,
+                   host_budget=one - 1)
+    assert e.value.status == hog.HOG_E_INVALID
+    srv = hog.Server(tmpl, bias, max_width=320, max_height=240, memory_budget=64 << 20,
+                     host_budget=2 * 256 * ((one + 255) // 256), max_slots=4, max_batch=2)
+    imgs = [inputs.synth_image(320, 240, 3, 5500 + j) for j in range(16)]
+    accepted = []
+    for im in imgs:
+        try:
+            accepted.append((srv.submit(im), im))
+        except hog.HogError as err:
+            assert err.status == hog.HOG_E_BUSY
+    assert accepted
+    res = _wait(srv, [t for t, _ in accepted], [_cap(320, 240)] * len(accepted))
+    for t, im in accepted:
+        want, _, _ = _alone(im, tmpl, bias)
+        assert np.array_equal(res[t][0].view(np.uint32), want.view(np.uint32))
+    srv.close()
+
+
+def test_unpolled_results_hold_output_space_until_polled():
+    """Finished results wait in a pinned output arena of 2 * max_slots
+    results: a client that lets 4 pile up sees admission pause, never more
+    than 4 unpolled, and every request finishes once it polls."""
+    tmpl, bias = _templates()
+    srv = hog.Server(tmpl, bias, max_width=320, max_height=240, memory_budget=256 << 20,
+                     max_slots=2, max_batch=2, streams=2)
+    imgs = [inputs.synth_image(320, 240, 3, 5600 + j) for j in range(10)]
+    tickets = [srv.submit(im) for im in imgs]
+    unpolled, res = [], {}
+    t0 = time.time()
+    while len(res) < len(tickets):
+        unpolled += srv.wait_any(2000)
+        assert len(unpolled) <= 4
+        if len(unpolled) == 4 or len(unpolled) + len(res) == len(tickets):
+            time.sleep(0.02)  # no room for another result meanwhile
+            unpolled += srv.wait_any(0)
+            assert len(unpolled) <= 4
+            for t in unpolled:
+                res[t] = srv.poll(t, _cap(320, 240))
+            unpolled = []
+        assert time.time() - t0 < 60, "requests did not finish"
+    for t, im in zip(tickets, imgs):
+        want, _, _ = _alone(im, tmpl, bias)
+        assert np.array_equal(res[t][0].view(np.uint32), want.view(np.uint32))
+    srv.close()
+
+
+def test_large_images_copied_in_pieces_equal_alone():
+    """Images above 2 MiB are copied into the server by the caller and
+    helper threads together (copy_threads); two submitting threads share
+    the helpers."""
+    tmpl, bias = _templates()
+    with pytest.raises(hog.HogError) as e:
+        hog.Server(tmpl, bias, copy_threads=33)
+    assert e.value.status == hog.HOG_E_INVALID
+    srv = hog.Server(tmpl, bias, max_width=1920, max_height=1080, memory_budget=1 << 30,
+                     max_slots=8, max_batch=4, streams=2, copy_threads=3)
+    sizes = [(1920, 1080), (1000, 700), (1283, 721), (1920, 1080)]
+    imgs = [inputs.synth_image(w, h, 3, 5700 + j) for j, (w, h) in enumerate(sizes * 2)]
+    got = [None] * len(imgs)
+
+    def submit(idx):
+        for j in idx:
+            got[j] = srv.submit(imgs[j])
+    th = [threading.Thread(target=submit, args=(range(k, len(imgs), 2),)) for k in range(2)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    res = _wait(srv, got, [_cap(im.shape[1], im.shape[0]) for im in imgs])
+    for t, im in zip(got, imgs):
+        want, _, _ = _alone(im, tmpl, bias)
+        assert np.array_equal(res[t][0].view(np.uint32), want.view(np.uint32))
+    srv.close()
