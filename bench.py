@@ -65,16 +65,17 @@ def kernel_sources_sha256():
     return h.hexdigest()
 
 
-def measured_traffic(workload):
-    """HBM bytes per integral_emit launch from the committed FETCH_SIZE /
-    WRITE_SIZE summary of this workload (copy-calibrated), or None when there
-    is none or the kernel sources have changed since it was taken."""
+def measured_traffic(workload, bin_chunk):
+    """HBM bytes per integral_emit launch with `bin_chunk` bins per wave from
+    the committed FETCH_SIZE / WRITE_SIZE summary of this workload
+    (copy-calibrated), or None when there is none or the kernel sources have
+    changed since it was taken."""
     path = os.path.join(ROOT, "profiles", f"hbm_traffic_{workload}.txt")
     if not os.path.exists(path):
         return None
     text = open(path).read()
     h = re.search(r"kernel sources sha256 \(hog_kernels.hip \+ hog_internal.h\): ([0-9a-f]{64})", text)
-    t = re.search(r"integral_emit traffic per launch: (\d+) bytes", text)
+    t = re.search(r"integral_emit<%d> traffic per launch: (\d+) bytes" % bin_chunk, text)
     if not h or not t or h.group(1) != kernel_sources_sha256():
         return None
     return int(t.group(1))
@@ -294,7 +295,7 @@ def main():
     achieved = emit_bytes / (emit_us * 1e-6) / 1e9
     roofline = dict(bound="hbm", kernel="integral_emit", achieved=round(achieved, 1),
                     peak=HBM_PEAK_GBS, unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4),
-                    traffic=measured_traffic(args.workload),
+                    traffic=measured_traffic(args.workload, tiles.bin_chunk),
                     algorithmic_bytes_per_launch=emit_bytes)
 
     if args.copy_calibration:
