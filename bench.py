@@ -53,6 +53,13 @@ WORKLOADS = {
     # run through 64 single-image plans.
     "batch64": dict(batch=64, size_seed=4000, channels=3, n_bins=8, max_levels=0, scale=1.1,
                     norm=1, seed=4000, tseed=9003, templates=32),
+    # The pyramid workload with narrow integral images: uint16 / uint8 planes
+    # holding the counts mod 2^16 / 2^8 (exact four-corner sums for areas
+    # below 2^16 / 2^8 pixels; the 8x8 cells and the scores are unchanged).
+    "pyramid_1920x1080_u16": dict(width=1920, height=1080, channels=3, n_bins=18, max_levels=0,
+                                  scale=1.05, norm=1, seed=1002, tseed=9002, plane_bits=16),
+    "pyramid_1920x1080_u8": dict(width=1920, height=1080, channels=3, n_bins=18, max_levels=0,
+                                 scale=1.05, norm=1, seed=1002, tseed=9002, plane_bits=8),
 }
 KERNELS = ("bin_map", "integral_reduce", "integral_scan", "integral_emit", "cells", "score")
 
@@ -179,14 +186,14 @@ def main():
         sizes = batch_sizes(wl)
         descs = [hog.make_desc(w, h, channels=wl["channels"], n_bins=wl["n_bins"],
                                max_levels=wl["max_levels"], scale=wl["scale"], norm=wl["norm"],
-                               n_templates=K) for w, h in sizes]
+                               n_templates=K, plane_bits=wl.get("plane_bits", 32)) for w, h in sizes]
         plan = hog.Plan(descs, batch=True)
         imgs = [inputs.synth_image(w, h, wl["channels"], wl["seed"] + j) for j, (w, h) in enumerate(sizes)]
         img_t = torch.from_numpy(hog.pack_images(plan, imgs)).cuda()
     else:
         desc = hog.make_desc(wl["width"], wl["height"], channels=wl["channels"], n_bins=wl["n_bins"],
                              max_levels=wl["max_levels"], scale=wl["scale"], norm=wl["norm"],
-                             n_templates=K)
+                             n_templates=K, plane_bits=wl.get("plane_bits", 32))
         plan = hog.Plan(desc)
         img = inputs.synth_image(wl["width"], wl["height"], wl["channels"], wl["seed"])
         img_t = torch.from_numpy(img.reshape(-1)).cuda()
@@ -256,8 +263,9 @@ def main():
     hog.hog_timing_enable(False)
 
     # Roofline of the dominant kernel: the integral-image writer moves, per
-    # processed pixel, 4*N_b bytes of planes (write) and 1 byte of bins (read).
-    emit_bytes = sz.total_pixels * (4 * wl["n_bins"] + 1)
+    # processed pixel, N_b plane elements of ii_elem_bytes (4 for uint32
+    # planes) written and 1 byte of bins read.
+    emit_bytes = sz.total_pixels * (sz.ii_elem_bytes * wl["n_bins"] + 1)
     extra = {}
     if batch:
         # The same images through 64 single-image plans, launched one image
@@ -323,7 +331,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "u32",
+        "dtype": {4: "u32", 2: "u16", 1: "u8"}[sz.ii_elem_bytes],
         "data": "synthetic",
         "config": {
             "workload": args.workload,
@@ -338,6 +346,7 @@ def main():
             "feature_dim": sz.feature_dim,
             "norm": "l2" if wl["norm"] else "raw",
             "templates": K,
+            "plane_bits": 8 * sz.ii_elem_bytes,
             "launch": "captured HIP graph of the batch plan" if batch else "three calls per step",
             "tiles": {"bin_chunk": tiles.bin_chunk, "score_rows": tiles.score_rows, "how": "autotuned"},
         },

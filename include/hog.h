@@ -107,6 +107,9 @@ typedef struct {
     double scale;          /* pyramid step (> 1) when max_levels != 1 */
     int32_t n_templates;   /* K >= 1 linear templates */
     hog_scan_params scan;
+    int32_t plane_bits;    /* integral-image element: 32 (or 0) uint32; 16 uint16; 8 uint8.
+                              Narrow planes hold ii mod 2^plane_bits (Sec. 4: 16-bit
+                              integral images); see hog_integral. 8 needs cell^2 < 256. */
 } hog_plan_desc;
 
 typedef struct hog_plan hog_plan;
@@ -124,8 +127,8 @@ typedef struct {
     int64_t bins_pitch;      /* bytes */
     int64_t ii_offset;       /* elements; ii(x, y) of bin n at ii[ii_offset +
                                 n*ii_plane_stride + y*ii_pitch + x] (hog_integral) */
-    int64_t ii_pitch;        /* elements between rows, multiple of 32 */
-    int64_t ii_plane_stride; /* elements between bins' planes, multiple of 32 */
+    int64_t ii_pitch;        /* elements between rows; rows are whole 128-byte lines */
+    int64_t ii_plane_stride; /* elements between bins' planes */
     int32_t cells_x, cells_y;    /* whole cells: floor(width / cell), ... */
     int32_t windows_x, windows_y;/* window grid; 0 x 0 if the level is smaller than a window */
     int64_t score_offset;    /* elements; scores[score_offset + (wy*windows_x + wx)*K + k] */
@@ -137,7 +140,7 @@ typedef struct {
 typedef struct {
     int32_t n_levels;
     int64_t bins_bytes;       /* size of the bins buffer */
-    int64_t ii_elems;         /* uint32 elements of the integral-image buffer */
+    int64_t ii_elems;         /* elements (ii_elem_bytes each) of the integral-image buffer */
     int64_t score_elems;      /* float elements of the score buffer */
     int64_t cell_elems;       /* uint32 elements of the optional cell_hist buffer */
     int64_t block_elems;      /* float elements of the optional block_feat buffer */
@@ -145,6 +148,7 @@ typedef struct {
     int32_t feature_dim;      /* window feature length D */
     int64_t total_pixels;     /* sum of level areas */
     int64_t total_windows;    /* sum of window counts */
+    int32_t ii_elem_bytes;    /* plane_bits / 8: 4, 2 or 1 */
 } hog_plan_sizes;
 
 /* One image of a plan: its levels, and where hog_bin_map reads it. */
@@ -196,21 +200,26 @@ hog_status hog_bin_map(const hog_plan *plan, const hog_lut *lut, const uint8_t *
  * Writes, for every level and bin n, the integral image
  *   ii[ii_offset + n*ii_plane_stride + y*ii_pitch + x]
  *       = #{ (x', y') : x' <= x, y' <= y, bin(x', y') = n }
- * for 0 <= x < width, 0 <= y < height (uint32, exact). Values at x < 0 or
+ * for 0 <= x < width, 0 <= y < height (uint32, exact). With plane_bits 16
+ * or 8 the planes are uint16 / uint8 and hold that count mod 2^plane_bits;
+ * since the four-corner sum of Eq. 6 is a sum with signs, taking it mod
+ * 2^plane_bits still gives the exact count of any rectangle of fewer than
+ * 2^plane_bits pixels, whatever the image size. Values at x < 0 or
  * y < 0 are zero by definition and not stored: a rectangle touching row or
  * column 0 takes them as 0 in the four-corner sum. Elements of a row beyond
  * column width - 1 hold unspecified values. As a by-product it caches every
  * 8 x 8-pixel cell histogram (Eq. 6, the four-corner sums of the planes it
  * writes) in the workspace for hog_scan_windows. workspace: device, at least
  * workspace_bytes, contents on entry ignored. */
-hog_status hog_integral(const hog_plan *plan, const uint8_t *bins, uint32_t *ii,
+hog_status hog_integral(const hog_plan *plan, const uint8_t *bins, void *ii,
                         void *workspace, void *stream);
 
 /* Eq. 6, Sec. 3.3, Sec. 4. For every level: the histogram of cell (cx, cy),
  * the cell x cell square at (cx*cell, cy*cell), is ii(4) + ii(1) - ii(2) -
  * ii(3) on each bin's plane, computed once per cell and cached. If ii is
- * non-NULL (device, layout as written by hog_integral) the cells are
- * computed from it; if ii is NULL the histograms cached by the last
+ * non-NULL (device, layout and element type as written by hog_integral) the
+ * cells are computed from it (mod 2^plane_bits for narrow planes, exact as
+ * cell^2 < 2^plane_bits); if ii is NULL the histograms cached by the last
  * hog_integral call on this plan and workspace are used (Sec. 3.3: areas
  * visited more than once are cached before evaluation); that needs 8-pixel
  * cells, otherwise ii is required.
@@ -227,7 +236,7 @@ hog_status hog_integral(const hog_plan *plan, const uint8_t *bins, uint32_t *ii,
  * cell_hist (nullable): device, uint32, receives every cell histogram.
  * block_feat (nullable, L2 only): device, float, receives every normalised
  * block. workspace: the one passed to hog_integral. */
-hog_status hog_scan_windows(const hog_plan *plan, const uint32_t *ii, const float *tmpl,
+hog_status hog_scan_windows(const hog_plan *plan, const void *ii, const float *tmpl,
                             const float *bias, float *scores, uint32_t *cell_hist,
                             float *block_feat, void *workspace, void *stream);
 
@@ -252,7 +261,7 @@ hog_status hog_plan_set_tiles(hog_plan *plan, const hog_tiles *tiles);
  * receives it. Synchronises the stream; the buffers' contents after the call
  * are those of a hog_run. */
 hog_status hog_plan_autotune(hog_plan *plan, const hog_lut *lut, const uint8_t *img,
-                             int64_t img_pitch, uint8_t *bins, uint32_t *ii, const float *tmpl,
+                             int64_t img_pitch, uint8_t *bins, void *ii, const float *tmpl,
                              const float *bias, float *scores, void *workspace, void *stream,
                              int reps, hog_tiles *chosen);
 
@@ -265,7 +274,7 @@ hog_status hog_plan_autotune(hog_plan *plan, const hog_lut *lut, const uint8_t *
  * with the same layouts. Arguments are all checked before anything is
  * enqueued. */
 hog_status hog_run(const hog_plan *plan, const hog_lut *lut, const uint8_t *img, int64_t img_pitch,
-                   uint8_t *bins, uint32_t *ii, const float *tmpl, const float *bias, float *scores,
+                   uint8_t *bins, void *ii, const float *tmpl, const float *bias, float *scores,
                    void *workspace, void *stream);
 
 /* hog_run captured once into a HIP graph for these exact buffers, replayed by
@@ -276,7 +285,7 @@ hog_status hog_run(const hog_plan *plan, const hog_lut *lut, const uint8_t *img,
  * launches nothing; hog_graph_destroy frees it (library-owned). */
 typedef struct hog_graph hog_graph;
 hog_status hog_graph_create(const hog_plan *plan, const hog_lut *lut, const uint8_t *img,
-                            int64_t img_pitch, uint8_t *bins, uint32_t *ii, const float *tmpl,
+                            int64_t img_pitch, uint8_t *bins, void *ii, const float *tmpl,
                             const float *bias, float *scores, void *workspace, hog_graph **out);
 hog_status hog_graph_launch(hog_graph *graph, void *stream);
 void hog_graph_destroy(hog_graph *graph);

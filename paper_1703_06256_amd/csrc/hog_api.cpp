@@ -270,8 +270,17 @@ static hog_status check_desc(const hog_plan_desc *d)
             return fail(HOG_E_INVALID, "an L2 window needs at least 2x2 cells");
         if (!(s.eps >= 0.f) || !std::isfinite(s.eps)) return fail(HOG_E_INVALID, "eps must be finite and >= 0");
     }
+    const int pbits = d->plane_bits == 0 ? 32 : d->plane_bits;
+    if (pbits != 32 && pbits != 16 && pbits != 8)
+        return fail(HOG_E_INVALID, "plane_bits must be 32, 16 or 8 (0 = 32), got %d", d->plane_bits);
+    // A cell's four-corner sum taken mod 2^bits is exact below 2^bits pixels.
+    if ((int64_t)s.cell * s.cell >= ((int64_t)1 << pbits))
+        return fail(HOG_E_INVALID, "%d-pixel cells hold up to %d pixels, too many for %d-bit planes", s.cell,
+                    s.cell * s.cell, pbits);
     return HOG_OK;
 }
+
+static int plane_bytes_of(const hog_plan_desc &d) { return (d.plane_bits == 0 ? 32 : d.plane_bits) / 8; }
 
 static bool same_scan(const hog_scan_params &a, const hog_scan_params &b)
 {
@@ -291,12 +300,14 @@ static hog_status create_plan(const hog_plan_desc *descs, int n_img, bool batch,
         if (st != HOG_OK) return st;
         const hog_plan_desc &a = descs[0], &b = descs[i];
         if (b.channels != a.channels || b.n_bins != a.n_bins || b.n_templates != a.n_templates ||
-            !same_scan(a.scan, b.scan))
-            return fail(HOG_E_INVALID, "image %d: channels, n_bins, n_templates and scan must match image 0", i);
+            !same_scan(a.scan, b.scan) || plane_bytes_of(a) != plane_bytes_of(b))
+            return fail(HOG_E_INVALID,
+                        "image %d: channels, n_bins, n_templates, scan and plane_bits must match image 0", i);
     }
     const hog_plan_desc d0 = descs[0];
     const hog_scan_params &sp = d0.scan;
     const int nb = d0.n_bins, K = d0.n_templates;
+    const int pb = plane_bytes_of(d0);  // bytes per plane element
     const int win_w = sp.cell * sp.win_cells_x, win_h = sp.cell * sp.win_cells_y;
     const int dim = sp.norm == HOG_NORM_RAW
                         ? sp.win_cells_x * sp.win_cells_y * nb
@@ -414,10 +425,11 @@ static hog_status create_plan(const hog_plan_desc *descs, int n_img, bool batch,
         v.bins_off = bins_off;
         bins_off = round_up(bins_off + v.bins_pitch * lh, 256);
         // Planes: ii(x, y) at [y * pitch + x]; rows are whole 128-byte lines
-        // (pitch a multiple of 32), so every row store is whole lines.
-        v.ii_pitch = round_up(lw, 32);
+        // (pitch a multiple of 128 / element bytes), so every row store is
+        // whole lines; levels start 256-byte aligned.
+        v.ii_pitch = round_up(lw, 128 / pb);
         v.ii_plane = v.ii_pitch * lh;
-        v.ii_off = round_up(ii_off, 64);
+        v.ii_off = round_up(ii_off, 256 / pb);
         ii_off = v.ii_off + v.ii_plane * nb;
         v.score_off = score_off;
         score_off += (int64_t)v.win_x * v.win_y * K;
@@ -501,8 +513,8 @@ static hog_status create_plan(const hog_plan_desc *descs, int n_img, bool batch,
         }
         const int64_t lim = ((int64_t)1 << 31) - 1;
         int c = chunk;
-        while (c > 1 && (int64_t)c * max_plane * 4 > lim) --c;
-        if ((int64_t)c * max_plane * 4 > lim || max_bins > lim) {
+        while (c > 1 && (int64_t)c * max_plane * pb > lim) --c;
+        if ((int64_t)c * max_plane * pb > lim || max_bins > lim) {
             delete p;
             return fail(HOG_E_INVALID, "image too large: one integral image exceeds 2 GiB");
         }
@@ -591,6 +603,7 @@ static hog_status create_plan(const hog_plan_desc *descs, int n_img, bool batch,
     pd.mfma_ks = mfma_ks;
     pd.scorer = scorer;
     pd.cell_stride = nbp;
+    pd.plane_bytes = pb;
     pd.bin_chunk = chunk_final;  // bins per wave; a last, smaller chunk takes the rest
     pd.n_chunks = (nb + chunk_final - 1) / chunk_final;
     for (int k = 0; k < hogk::KB_COUNT; ++k) pd.total[k] = totals[k];
@@ -617,6 +630,7 @@ static hog_status create_plan(const hog_plan_desc *descs, int n_img, bool batch,
     z.feature_dim = dim;
     z.total_pixels = tot_px;
     z.total_windows = tot_win;
+    z.ii_elem_bytes = pb;
     *out = p;
     return HOG_OK;
 }
@@ -687,7 +701,7 @@ extern "C" hog_status hog_bin_map(const hog_plan *plan, const hog_lut *lut, cons
     return HOG_OK;
 }
 
-extern "C" hog_status hog_integral(const hog_plan *plan, const uint8_t *bins, uint32_t *ii,
+extern "C" hog_status hog_integral(const hog_plan *plan, const uint8_t *bins, void *ii,
                                    void *workspace, void *stream)
 {
     if (!plan || !bins || !ii || !workspace) return fail(HOG_E_INVALID, "NULL argument");
@@ -708,7 +722,7 @@ extern "C" hog_status hog_integral(const hog_plan *plan, const uint8_t *bins, ui
     return HOG_OK;
 }
 
-extern "C" hog_status hog_scan_windows(const hog_plan *plan, const uint32_t *ii, const float *tmpl,
+extern "C" hog_status hog_scan_windows(const hog_plan *plan, const void *ii, const float *tmpl,
                                        const float *bias, float *scores, uint32_t *cell_hist,
                                        float *block_feat, void *workspace, void *stream)
 {
@@ -762,7 +776,7 @@ static hog_status apply_tiles(hog_plan *p, int chunk, int rows)
     const int L = pd.n_levels, K = pd.n_templates;
     int64_t max_plane = 0;
     for (const Level &v : p->levels) max_plane = std::max(max_plane, v.ii_plane);
-    if (chunk < 1 || chunk > hogk::kMaxBinChunk || (int64_t)chunk * max_plane * 4 > ((int64_t)1 << 31) - 1)
+    if (chunk < 1 || chunk > hogk::kMaxBinChunk || (int64_t)chunk * max_plane * p->dev.plane_bytes > ((int64_t)1 << 31) - 1)
         return fail(HOG_E_INVALID, "bins per integral wave must be in [1, %d] and fit 2 GiB", hogk::kMaxBinChunk);
     pd.bin_chunk = chunk;
     pd.n_chunks = (pd.n_bins + chunk - 1) / chunk;
@@ -805,14 +819,14 @@ extern "C" hog_status hog_plan_set_tiles(hog_plan *plan, const hog_tiles *tiles)
 }
 
 static hog_status check_run_args(const hog_plan *plan, const hog_lut *lut, const uint8_t *img,
-                                 int64_t img_pitch, uint8_t *bins, uint32_t *ii, const float *tmpl,
+                                 int64_t img_pitch, uint8_t *bins, void *ii, const float *tmpl,
                                  const float *bias, float *scores, void *workspace);
 static hog_status run_path(const hog_plan *plan, const hog_lut *lut, const uint8_t *img, int64_t img_pitch,
-                           uint8_t *bins, uint32_t *ii, const float *tmpl, const float *bias, float *scores,
+                           uint8_t *bins, void *ii, const float *tmpl, const float *bias, float *scores,
                            void *workspace, void *stream);
 
 extern "C" hog_status hog_plan_autotune(hog_plan *plan, const hog_lut *lut, const uint8_t *img,
-                                        int64_t img_pitch, uint8_t *bins, uint32_t *ii, const float *tmpl,
+                                        int64_t img_pitch, uint8_t *bins, void *ii, const float *tmpl,
                                         const float *bias, float *scores, void *workspace, void *stream,
                                         int reps, hog_tiles *chosen)
 {
@@ -850,7 +864,7 @@ extern "C" hog_status hog_plan_autotune(hog_plan *plan, const hog_lut *lut, cons
     for (const Level &v : plan->levels) max_plane = std::max(max_plane, v.ii_plane);
     for (int c = 2; c <= hogk::kMaxBinChunk && st == HOG_OK; ++c) {
         const int chunk = chunk_for(nb, c);
-        if (chunk != c || (int64_t)chunk * max_plane * 4 > ((int64_t)1 << 31) - 1) continue;
+        if (chunk != c || (int64_t)chunk * max_plane * plan->dev.plane_bytes > ((int64_t)1 << 31) - 1) continue;
         float ms = 0.f;
         st = time_with(chunk, best_rows, &ms);
         if (st == HOG_OK && ms < best) {
@@ -882,7 +896,7 @@ extern "C" hog_status hog_plan_autotune(hog_plan *plan, const hog_lut *lut, cons
 // The whole path in one call, and captured into a HIP graph.
 // ---------------------------------------------------------------------------
 static hog_status check_run_args(const hog_plan *plan, const hog_lut *lut, const uint8_t *img,
-                                 int64_t img_pitch, uint8_t *bins, uint32_t *ii, const float *tmpl,
+                                 int64_t img_pitch, uint8_t *bins, void *ii, const float *tmpl,
                                  const float *bias, float *scores, void *workspace)
 {
     if (!plan || !lut || !img || !bins || !ii || !workspace) return fail(HOG_E_INVALID, "NULL argument");
@@ -896,7 +910,7 @@ static hog_status check_run_args(const hog_plan *plan, const hog_lut *lut, const
 }
 
 static hog_status run_path(const hog_plan *plan, const hog_lut *lut, const uint8_t *img, int64_t img_pitch,
-                           uint8_t *bins, uint32_t *ii, const float *tmpl, const float *bias, float *scores,
+                           uint8_t *bins, void *ii, const float *tmpl, const float *bias, float *scores,
                            void *workspace, void *stream)
 {
     hog_status st = hog_bin_map(plan, lut, img, img_pitch, bins, stream);
@@ -909,7 +923,7 @@ static hog_status run_path(const hog_plan *plan, const hog_lut *lut, const uint8
 }
 
 extern "C" hog_status hog_run(const hog_plan *plan, const hog_lut *lut, const uint8_t *img, int64_t img_pitch,
-                              uint8_t *bins, uint32_t *ii, const float *tmpl, const float *bias,
+                              uint8_t *bins, void *ii, const float *tmpl, const float *bias,
                               float *scores, void *workspace, void *stream)
 {
     hog_status st = check_run_args(plan, lut, img, img_pitch, bins, ii, tmpl, bias, scores, workspace);
@@ -923,7 +937,7 @@ struct hog_graph {
 };
 
 extern "C" hog_status hog_graph_create(const hog_plan *plan, const hog_lut *lut, const uint8_t *img,
-                                       int64_t img_pitch, uint8_t *bins, uint32_t *ii, const float *tmpl,
+                                       int64_t img_pitch, uint8_t *bins, void *ii, const float *tmpl,
                                        const float *bias, float *scores, void *workspace, hog_graph **out)
 {
     if (!out) return fail(HOG_E_INVALID, "out is NULL");

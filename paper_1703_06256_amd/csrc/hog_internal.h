@@ -99,6 +99,7 @@ struct PlanDev {
     int32_t mfma_ks;           // matrix-core scorers: bin slots per cell (8, 16 or 20)
     int32_t st_lds_bytes;      // scorer dynamic LDS
     int32_t cell_stride;       // floats per staged cell in the scorer's LDS
+    int32_t plane_bytes;       // bytes per integral-image element: 4, 2 or 1 (ii mod 2^(8 bytes))
     int32_t bin_chunk;         // bins per integral wave
     int32_t n_chunks;
     int32_t n_cu;              // compute units of the device (persistent grids)
@@ -117,9 +118,9 @@ hipError_t launch_bin_map(const PlanDev &p, const uint8_t *lut_half, const uint8
 hipError_t launch_int_reduce(const PlanDev &p, const uint8_t *bins, uint8_t *ws,
                              hipStream_t stream);
 hipError_t launch_int_scan(const PlanDev &p, uint8_t *ws, hipStream_t stream);
-hipError_t launch_int_emit(const PlanDev &p, const uint8_t *bins, uint8_t *ws, uint32_t *ii,
+hipError_t launch_int_emit(const PlanDev &p, const uint8_t *bins, uint8_t *ws, void *ii,
                            hipStream_t stream);
-hipError_t launch_cells(const PlanDev &p, const uint32_t *ii, uint8_t *ws, uint32_t *cell_hist,
+hipError_t launch_cells(const PlanDev &p, const void *ii, uint8_t *ws, uint32_t *cell_hist,
                         hipStream_t stream);
 hipError_t launch_cache_export(const PlanDev &p, const uint8_t *ws, uint32_t *cell_hist,
                                hipStream_t stream);

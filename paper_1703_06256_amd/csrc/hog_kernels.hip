@@ -456,16 +456,21 @@ __global__ __launch_bounds__(256) void k_int_scan(const Level *__restrict__ lv,
 // previous corner row. Their four-corner sum (Eq. 6) is the cell's
 // histogram entry, cached here once per cell (uint16 [n][cy][cx]).
 //
-// The planes hold ii(x, y) at [y * pitch + x] (Eq. 5, one value per pixel).
+// The planes hold ii(x, y) at [y * pitch + x] (Eq. 5, one value per pixel),
+// as PB-byte elements: the low 8 PB bits of the count (Sec. 4's 16-bit
+// integral images, taken mod 2^(8 PB) so that four-corner sums of areas below
+// 2^(8 PB) pixels stay exact). The running values in registers are full
+// 32-bit counts either way, so the cell cache is the same for every PB.
 // ---------------------------------------------------------------------------
-template <int NBC, bool CELLS>
+template <int NBC, bool CELLS, int PB>
 __global__ __launch_bounds__(256) void k_int_emit(const Level *__restrict__ lv,
                                                   const int32_t *__restrict__ first, int n_levels,
                                                   int nb, int n_chunk,
                                                   const uint8_t *__restrict__ bins,
                                                   uint8_t *__restrict__ ws,
-                                                  uint32_t *__restrict__ ii)
+                                                  uint8_t *__restrict__ ii)
 {
+    static_assert(PB == 4 || PB == 2 || PB == 1, "plane element bytes");
     // Consecutive waves take the chunks of one tile.
     const int gw = (int)blockIdx.x * 4 + wave_id_in_block();
     const int lane = threadIdx.x & 63;
@@ -486,7 +491,7 @@ __global__ __launch_bounds__(256) void k_int_emit(const Level *__restrict__ lv,
     // row pitch store at its last element: right of the level every lane
     // holds the value of column w - 1, so those duplicate stores write the
     // same value and every row store covers whole lines.
-    const uint32_t col4 = (uint32_t)min(x, (int)v.ii_pitch - 1) * 4u;
+    const uint32_t colb = (uint32_t)min(x, (int)v.ii_pitch - 1) * (uint32_t)PB;
 
     // Carries (k_int_scan): the plane value at (x, 64 ty - 1) is P (pixels
     // above and left of the tile) plus the tile's columns' counts above it up
@@ -517,12 +522,17 @@ __global__ __launch_bounds__(256) void k_int_emit(const Level *__restrict__ lv,
     stage_bin_tile(tb, buffer_rsrc(bins + v.bins_off, (uint32_t)(v.bins_pitch * v.h)),
                    (int)v.bins_pitch, tx, y0, lane);
 
-    // The chunk's nbc planes as one buffer; the plan keeps NBC * plane * 4 < 2^31.
-    const int plane4 = (int)(v.ii_plane * 4), pitch4 = (int)(v.ii_pitch * 4);
+    // The chunk's nbc planes as one buffer; the plan keeps NBC * plane * PB < 2^31.
+    const int planeb = (int)(v.ii_plane * PB), pitchb = (int)(v.ii_pitch * PB);
     const __amdgpu_buffer_rsrc_t isrc =
-        buffer_rsrc(ii + v.ii_off + (int64_t)b0 * v.ii_plane, (uint32_t)(nbc * plane4));
+        buffer_rsrc(ii + (v.ii_off + (int64_t)b0 * v.ii_plane) * PB, (uint32_t)(nbc * planeb));
     auto store_row = [&](int j, int y, uint32_t val) {
-        __builtin_amdgcn_raw_buffer_store_b32(val, isrc, (int)col4, j * plane4 + y * pitch4, 0);
+        if constexpr (PB == 4)
+            __builtin_amdgcn_raw_buffer_store_b32(val, isrc, (int)colb, j * planeb + y * pitchb, 0);
+        else if constexpr (PB == 2)
+            __builtin_amdgcn_raw_buffer_store_b16((uint16_t)val, isrc, (int)colb, j * planeb + y * pitchb, 0);
+        else
+            __builtin_amdgcn_raw_buffer_store_b8((uint8_t)val, isrc, (int)colb, j * planeb + y * pitchb, 0);
     };
 
     auto do_row = [&](int bin, int y) {
@@ -600,20 +610,24 @@ __global__ __launch_bounds__(256) void k_int_emit(const Level *__restrict__ lv,
 // P(r1, c1) + P(r0, c0) - P(r0, c1) - P(r1, c0) with (r0, c0) = cell * (cy, cx)
 // and (r1, c1) = (r0, c0) + cell in padded coordinates. Computed once per
 // cell and cached (uint16, [bin][cy][cx]) for every window that uses it.
+// Narrow planes (T = uint16 / uint8) hold the counts mod 2^bits; the sum is
+// taken mod 2^bits too and is exact, a cell having fewer than 2^bits pixels.
 // ---------------------------------------------------------------------------
+template <typename T>
 __global__ __launch_bounds__(256) void k_cells(const Level *__restrict__ lv,
                                                const int32_t *__restrict__ first, int n_levels,
-                                               int nb, int cell, const uint32_t *__restrict__ ii,
+                                               int nb, int cell, const T *__restrict__ ii,
                                                uint8_t *__restrict__ ws,
                                                uint32_t *__restrict__ cell_hist)
 {
+    constexpr uint32_t kMask = sizeof(T) == 4 ? 0xffffffffu : (1u << (8 * sizeof(T))) - 1u;
     const int g = (int)(blockIdx.x * 256 + threadIdx.x);
     if (g >= first[n_levels]) return;
     const int l = find_level(first, n_levels, g);
     const Level &v = lv[l];
     const int rel = g - first[l];
     const int cy = rel / v.cells_x, cx = rel % v.cells_x;
-    const uint32_t *P = ii + v.ii_off;
+    const T *P = ii + v.ii_off;
     // Corners: ii at the cell's last row/column and at the row/column just
     // before it; ii(-1, .) = ii(., -1) = 0.
     const int64_t y1 = (int64_t)(cy + 1) * cell - 1, x1 = (int64_t)(cx + 1) * cell - 1;
@@ -622,12 +636,12 @@ __global__ __launch_bounds__(256) void k_cells(const Level *__restrict__ lv,
     uint16_t *cache = reinterpret_cast<uint16_t *>(ws + v.ws_cache);
     uint32_t *ch = cell_hist ? cell_hist + v.cell_off + (int64_t)rel * nb : nullptr;
     for (int n = 0; n < nb; ++n) {
-        const uint32_t *p = P + (int64_t)n * v.ii_plane;
+        const T *p = P + (int64_t)n * v.ii_plane;
         const uint32_t a = p[r1 + x1];
-        const uint32_t b = y0 >= 0 ? p[r0 + x1] : 0u;
-        const uint32_t c = x0 >= 0 ? p[r1 + x0] : 0u;
-        const uint32_t d = (y0 >= 0 && x0 >= 0) ? p[r0 + x0] : 0u;
-        const uint32_t h = a - b - c + d;
+        const uint32_t b = y0 >= 0 ? (uint32_t)p[r0 + x1] : 0u;
+        const uint32_t c = x0 >= 0 ? (uint32_t)p[r1 + x0] : 0u;
+        const uint32_t d = (y0 >= 0 && x0 >= 0) ? (uint32_t)p[r0 + x0] : 0u;
+        const uint32_t h = (a - b - c + d) & kMask;
         cache[cache_index(v, n, cy, cx)] = (uint16_t)h;
         if (ch) ch[n] = h;
     }
@@ -1507,23 +1521,23 @@ hipError_t launch_int_scan(const PlanDev &p, uint8_t *ws, hipStream_t stream)
 }
 
 // k_int_emit for chunks of NBC bins (the last one possibly shorter), with or
-// without the fused cell cache.
-#define HOG_EMIT_CASE(NBC)                                                                        \
-    case NBC:                                                                                     \
-        if (cells)                                                                                \
-            hipLaunchKernelGGL((k_int_emit<NBC, true>), grid, dim3(256), 0, stream, p.levels,     \
-                               first_of(p, KB_ITILE), p.n_levels, p.n_bins, p.n_chunks, bins, ws, \
-                               ii);                                                               \
-        else                                                                                      \
-            hipLaunchKernelGGL((k_int_emit<NBC, false>), grid, dim3(256), 0, stream, p.levels,    \
-                               first_of(p, KB_ITILE), p.n_levels, p.n_bins, p.n_chunks, bins, ws, \
-                               ii);                                                               \
+// without the fused cell cache, for PB-byte plane elements.
+#define HOG_EMIT_CASE(NBC)                                                                          \
+    case NBC:                                                                                       \
+        if (cells)                                                                                  \
+            hipLaunchKernelGGL((k_int_emit<NBC, true, PB>), grid, dim3(256), 0, stream, p.levels,   \
+                               first_of(p, KB_ITILE), p.n_levels, p.n_bins, p.n_chunks, bins, ws,   \
+                               ii);                                                                 \
+        else                                                                                        \
+            hipLaunchKernelGGL((k_int_emit<NBC, false, PB>), grid, dim3(256), 0, stream, p.levels,  \
+                               first_of(p, KB_ITILE), p.n_levels, p.n_bins, p.n_chunks, bins, ws,   \
+                               ii);                                                                 \
         break;
 
-hipError_t launch_int_emit(const PlanDev &p, const uint8_t *bins, uint8_t *ws, uint32_t *ii,
-                           hipStream_t stream)
+template <int PB>
+static hipError_t launch_int_emit_pb(const PlanDev &p, const uint8_t *bins, uint8_t *ws, uint8_t *ii,
+                                     hipStream_t stream)
 {
-    if (p.total[KB_ITILE] == 0) return hipSuccess;
     const bool cells = p.cell == 8;
     const dim3 grid(blocks_for(p.total[KB_ITILE] * p.n_chunks, 4));
     static_assert(kMaxBinChunk == 6, "one case per chunk size");
@@ -1535,13 +1549,41 @@ hipError_t launch_int_emit(const PlanDev &p, const uint8_t *bins, uint8_t *ws, u
     return hipGetLastError();
 }
 
-hipError_t launch_cells(const PlanDev &p, const uint32_t *ii, uint8_t *ws, uint32_t *cell_hist,
+hipError_t launch_int_emit(const PlanDev &p, const uint8_t *bins, uint8_t *ws, void *ii,
+                           hipStream_t stream)
+{
+    if (p.total[KB_ITILE] == 0) return hipSuccess;
+    uint8_t *iib = static_cast<uint8_t *>(ii);
+    switch (p.plane_bytes) {
+    case 4: return launch_int_emit_pb<4>(p, bins, ws, iib, stream);
+    case 2: return launch_int_emit_pb<2>(p, bins, ws, iib, stream);
+    case 1: return launch_int_emit_pb<1>(p, bins, ws, iib, stream);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_cells(const PlanDev &p, const void *ii, uint8_t *ws, uint32_t *cell_hist,
                         hipStream_t stream)
 {
     const int64_t n = p.total[KB_CELL];
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_cells, dim3(blocks_for(n, 256)), dim3(256), 0, stream, p.levels,
-                       first_of(p, KB_CELL), p.n_levels, p.n_bins, p.cell, ii, ws, cell_hist);
+    const dim3 grid(blocks_for(n, 256));
+    const int32_t *f = first_of(p, KB_CELL);
+    switch (p.plane_bytes) {
+    case 4:
+        hipLaunchKernelGGL(k_cells<uint32_t>, grid, dim3(256), 0, stream, p.levels, f, p.n_levels, p.n_bins, p.cell,
+                           static_cast<const uint32_t *>(ii), ws, cell_hist);
+        break;
+    case 2:
+        hipLaunchKernelGGL(k_cells<uint16_t>, grid, dim3(256), 0, stream, p.levels, f, p.n_levels, p.n_bins, p.cell,
+                           static_cast<const uint16_t *>(ii), ws, cell_hist);
+        break;
+    case 1:
+        hipLaunchKernelGGL(k_cells<uint8_t>, grid, dim3(256), 0, stream, p.levels, f, p.n_levels, p.n_bins, p.cell,
+                           static_cast<const uint8_t *>(ii), ws, cell_hist);
+        break;
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

@@ -122,7 +122,7 @@ Layout layout_of(const hog_plan_sizes &z, int64_t img_bytes)
     L.bins = o;
     o = align256(o + z.bins_bytes);
     L.ii = o;
-    o = align256(o + z.ii_elems * 4);
+    o = align256(o + z.ii_elems * z.ii_elem_bytes);
     L.scores = o;
     o = align256(o + std::max<int64_t>(z.score_elems, 1) * 4);
     L.ws = o;
@@ -327,7 +327,7 @@ bool admit(hog_server *s, Slot &sl)
         }
         hog_status st = HOG_OK;
         if (e == hipSuccess)
-            st = hog_run(p, s->lut, base + L.img, 0, base + L.bins, (uint32_t *)(base + L.ii), s->d_tmpl,
+            st = hog_run(p, s->lut, base + L.img, 0, base + L.bins, base + L.ii, s->d_tmpl,
                          s->d_bias, (float *)(base + L.scores), base + L.ws, sl.stream);
         for (size_t i = 0; i < order.size() && e == hipSuccess && st == HOG_OK; ++i)
             if (sc_n[i] > 0)

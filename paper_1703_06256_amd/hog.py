@@ -49,7 +49,8 @@ class PlanDesc(ctypes.Structure):
     _fields_ = [("width", ctypes.c_int32), ("height", ctypes.c_int32),
                 ("channels", ctypes.c_int32), ("n_bins", ctypes.c_int32),
                 ("max_levels", ctypes.c_int32), ("scale", ctypes.c_double),
-                ("n_templates", ctypes.c_int32), ("scan", ScanParams)]
+                ("n_templates", ctypes.c_int32), ("scan", ScanParams),
+                ("plane_bits", ctypes.c_int32)]
 
 
 class LevelInfo(ctypes.Structure):
@@ -90,7 +91,8 @@ class PlanSizes(ctypes.Structure):
                 ("ii_elems", ctypes.c_int64), ("score_elems", ctypes.c_int64),
                 ("cell_elems", ctypes.c_int64), ("block_elems", ctypes.c_int64),
                 ("workspace_bytes", ctypes.c_int64), ("feature_dim", ctypes.c_int32),
-                ("total_pixels", ctypes.c_int64), ("total_windows", ctypes.c_int64)]
+                ("total_pixels", ctypes.c_int64), ("total_windows", ctypes.c_int64),
+                ("ii_elem_bytes", ctypes.c_int32)]
 
 
 _lib = None
@@ -218,9 +220,16 @@ def hog_lut_build(n_bins: int) -> Lut:
 
 def make_desc(width, height, channels=1, n_bins=8, max_levels=1, scale=1.0, n_templates=1,
               cell=8, win_cells_x=8, win_cells_y=16, block=2, norm=HOG_NORM_RAW,
-              eps=1e-3) -> PlanDesc:
+              eps=1e-3, plane_bits=32) -> PlanDesc:
     return PlanDesc(width, height, channels, n_bins, max_levels, scale, n_templates,
-                    ScanParams(cell, win_cells_x, win_cells_y, block, norm, eps))
+                    ScanParams(cell, win_cells_x, win_cells_y, block, norm, eps), plane_bits)
+
+
+def ii_dtype(plan: "Plan"):
+    """torch dtype holding the plan's plane elements (same bits: int32 for
+    uint32, int16 for uint16, uint8)."""
+    import torch
+    return {4: torch.int32, 2: torch.int16, 1: torch.uint8}[plan.sizes.ii_elem_bytes]
 
 
 class Plan:
@@ -286,7 +295,7 @@ def hog_integral(plan: Plan, bins, ii, workspace, stream=None):
     import torch
     _check(load_library().hog_integral(
         plan.handle, _dptr(bins, torch.uint8, plan.sizes.bins_bytes, "bins"),
-        _dptr(ii, torch.int32, plan.sizes.ii_elems, "ii"),
+        _dptr(ii, ii_dtype(plan), plan.sizes.ii_elems, "ii"),
         _dptr(workspace, torch.uint8, plan.sizes.workspace_bytes, "workspace"),
         _stream(stream)))
 
@@ -296,7 +305,7 @@ def hog_scan_windows(plan: Plan, ii, tmpl, bias, scores, workspace, cell_hist=No
     import torch
     k = plan.desc.n_templates
     _check(load_library().hog_scan_windows(
-        plan.handle, _dptr(ii, torch.int32, plan.sizes.ii_elems, "ii") if ii is not None else None,
+        plan.handle, _dptr(ii, ii_dtype(plan), plan.sizes.ii_elems, "ii") if ii is not None else None,
         _dptr(tmpl, torch.float32, k * plan.sizes.feature_dim, "tmpl"),
         _dptr(bias, torch.float32, k, "bias"),
         _dptr(scores, torch.float32, plan.sizes.score_elems, "scores"),
@@ -342,7 +351,7 @@ class Buffers:
         import torch
         s = plan.sizes
         self.bins = torch.empty(max(s.bins_bytes, 1), dtype=torch.uint8, device=device)
-        self.ii = torch.empty(max(s.ii_elems, 1), dtype=torch.int32, device=device)
+        self.ii = torch.empty(max(s.ii_elems, 1), dtype=ii_dtype(plan), device=device)
         self.scores = torch.empty(max(s.score_elems, 1), dtype=torch.float32, device=device)
         self.workspace = torch.empty(max(s.workspace_bytes, 1), dtype=torch.uint8, device=device)
         self.cell_hist = (torch.empty(max(s.cell_elems, 1), dtype=torch.int32, device=device)
@@ -377,7 +386,7 @@ def _run_args(plan: Plan, lut: Lut, img, tmpl, bias, buf: "Buffers", img_pitch=N
     k = d.n_templates
     return (plan.handle, lut.handle, _dptr(img, torch.uint8, need, "img"), pitch,
             _dptr(buf.bins, torch.uint8, plan.sizes.bins_bytes, "bins"),
-            _dptr(buf.ii, torch.int32, plan.sizes.ii_elems, "ii"),
+            _dptr(buf.ii, ii_dtype(plan), plan.sizes.ii_elems, "ii"),
             _dptr(tmpl, torch.float32, k * plan.sizes.feature_dim, "tmpl"),
             _dptr(bias, torch.float32, k, "bias"),
             _dptr(buf.scores, torch.float32, plan.sizes.score_elems, "scores"),
@@ -517,10 +526,12 @@ def level_bins(plan: Plan, bins_host: np.ndarray, l: int) -> np.ndarray:
 
 
 def level_planes(plan: Plan, ii_host: np.ndarray, l: int) -> np.ndarray:
-    """uint32[n_bins][h][w] of level l: [n][y][x] = ii_n(x, y)."""
+    """uint32 / uint16 / uint8 [n_bins][h][w] of level l: [n][y][x] = ii_n(x, y)
+    (mod 2^plane_bits)."""
     li = plan.levels[l]
     nb = plan.desc.n_bins
-    a = ii_host.view(np.uint32)[li.ii_offset: li.ii_offset + li.ii_plane_stride * nb]
+    et = {4: np.uint32, 2: np.uint16, 1: np.uint8}[plan.sizes.ii_elem_bytes]
+    a = ii_host.view(et)[li.ii_offset: li.ii_offset + li.ii_plane_stride * nb]
     a = a.reshape(nb, li.ii_plane_stride)[:, :li.ii_pitch * li.height]
     return a.reshape(nb, li.height, li.ii_pitch)[:, :, :li.width]
 

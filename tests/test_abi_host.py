@@ -54,6 +54,8 @@ BAD_DESCS = [
     dict(win_cells_x=0), dict(win_cells_y=65), dict(norm=2),
     dict(norm=hog.HOG_NORM_L2, block=3), dict(norm=hog.HOG_NORM_L2, win_cells_x=1),
     dict(norm=hog.HOG_NORM_L2, eps=float("nan")),
+    dict(plane_bits=12), dict(plane_bits=64), dict(plane_bits=-8),
+    dict(plane_bits=8, cell=16), dict(plane_bits=8, cell=32),
 ]
 
 
@@ -102,7 +104,7 @@ def test_lut_mirror_rule_behind_the_half_table(nb):
 
 
 @pytest.mark.parametrize("bad", [dict(n_bins=9), dict(channels=1), dict(n_templates=2),
-                                 dict(norm=hog.HOG_NORM_L2, cell=4)])
+                                 dict(norm=hog.HOG_NORM_L2, cell=4), dict(plane_bits=16)])
 def test_batch_plan_rejects_mismatched_images(bad):
     base = dict(width=320, height=240, channels=3, n_bins=8)
     other = dict(base, width=200, height=150)

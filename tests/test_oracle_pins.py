@@ -219,6 +219,53 @@ def test_integral_invariants():
     assert np.all(np.diff(p, axis=1) >= 0) and np.all(np.diff(p, axis=2) >= 0)
 
 
+@pytest.mark.parametrize("bits", [16, 8])
+def test_narrow_integral_closed_form_wraps(bits):
+    """One bin everywhere: ii(x, y) = (x + 1)(y + 1), so the narrow planes
+    hold that product mod 2^bits -- here it wraps (up to 400 x 300 pixels)."""
+    w, h = 400, 300
+    bins = np.full((h, w), 2, np.uint8)
+    p = oracle.integral_mod(bins, 3, bits)
+    assert p.dtype == (np.uint16 if bits == 16 else np.uint8)
+    x = np.arange(w + 1, dtype=np.int64)[None, :]
+    y = np.arange(h + 1, dtype=np.int64)[:, None]
+    assert np.array_equal(p[2].astype(np.int64), (x * y) % (1 << bits))
+    assert int((x * y).max()) >= 1 << bits  # the case does wrap
+    assert not p[0].any() and not p[1].any()
+
+
+@pytest.mark.parametrize("bits", [16, 8])
+def test_narrow_integral_four_corners_count_small_rectangles(bits):
+    """The reading behind narrow planes: on the planes mod 2^bits, the
+    four-corner sum of Eq. 6 taken mod 2^bits equals the brute-force count of
+    any rectangle with fewer than 2^bits pixels, wherever it lies (values far
+    beyond 2^bits below and left of it); at exactly 2^bits pixels of one bin
+    it reads 0, so the bound is tight."""
+    rng = np.random.default_rng(100 + bits)
+    h, w, nb = 700, 500, 3  # 350,000 pixels: every plane wraps mod 2^16 and 2^8
+    bins = rng.integers(0, nb, (h, w)).astype(np.uint8)
+    bins[rng.random((h, w)) < 0.05] = NO_BIN
+    p = oracle.integral_mod(bins, nb, bits).astype(np.int64)
+    m = 1 << bits
+    for _ in range(300):
+        rh = int(rng.integers(1, min(h, m - 1) + 1))
+        rw = int(rng.integers(1, min(w, (m - 1) // rh) + 1))
+        y0 = int(rng.integers(0, h - rh + 1))
+        x0 = int(rng.integers(0, w - rw + 1))
+        y1, x1 = y0 + rh, x0 + rw
+        assert rh * rw < m
+        four = (p[:, y1, x1] + p[:, y0, x0] - p[:, y0, x1] - p[:, y1, x0]) % m
+        brute = [(bins[y0:y1, x0:x1] == n).sum() for n in range(nb)]
+        assert list(four) == brute
+    # tightness: 2^bits pixels, all of bin 0
+    side = 1 << (bits // 2)
+    one = np.zeros((side + 3, side + 5), np.uint8)
+    q = oracle.integral_mod(one, 1, bits).astype(np.int64)
+    y0, x0 = 2, 3
+    four = (q[0, y0 + side, x0 + side] + q[0, y0, x0] - q[0, y0, x0 + side] - q[0, y0 + side, x0]) % m
+    assert four == 0
+
+
 # --------------------------------------------------------------------------
 # Eq. 3 / Eq. 6: area histograms.
 # --------------------------------------------------------------------------
