@@ -57,6 +57,11 @@ typedef enum {
 
 enum { HOG_NORM_RAW = 0, HOG_NORM_L2 = 1 };
 
+/* Orientation of the table's bins: signed over [0, 2 pi) (the default), or
+ * unsigned over [0, pi), where a gradient and its opposite share a bin (the
+ * 9-bin, 0..180 degree histograms of Fig. 4's example). */
+enum { HOG_ORIENT_SIGNED = 0, HOG_ORIENT_UNSIGNED = 1 };
+
 /* Message for the calling thread's last failing call ("" if none). */
 const char *hog_last_error(void);
 
@@ -75,10 +80,20 @@ typedef struct hog_lut hog_lut;
  * caller-owned host buffer of 511*511 bytes. No device call is made. */
 hog_status hog_lut_fill_host(int n_bins, uint8_t *table);
 
+/* As hog_lut_fill_host for either orientation. HOG_ORIENT_UNSIGNED: the
+ * angle of (dx, dy) is taken mod pi, into [0, pi), and falls in the sector
+ * [k pi/n, (k+1) pi/n); axes and diagonals (directions m pi/4) get
+ * floor((m mod 4) n / 4), in integers. HOG_E_INVALID for another value. */
+hog_status hog_lut_fill_host_ex(int n_bins, int orientation, uint8_t *table);
+
 /* Build the table for n_bins once and upload it to the current device.
  * *out is library-owned (host copy + device copy); free with hog_lut_free.
  * Synchronous. */
 hog_status hog_lut_build(int n_bins, hog_lut **out);
+/* hog_lut_build for either orientation (hog_lut_fill_host_ex). The plans and
+ * kernels are the same for both: the orientation lives in the table only. */
+hog_status hog_lut_build_ex(int n_bins, int orientation, hog_lut **out);
+int hog_lut_orientation(const hog_lut *lut);
 void hog_lut_free(hog_lut *lut);
 int hog_lut_bins(const hog_lut *lut);
 /* Host copy of the table (511*511 bytes, layout as hog_lut_fill_host),
@@ -305,6 +320,7 @@ typedef struct {
     int32_t max_batch;       /* requests per launch (<= max_slots) */
     int32_t max_queue;       /* requests waiting; hog_submit returns HOG_E_BUSY beyond */
     int32_t streams;         /* batches in flight at once, 1..8 */
+    int32_t orientation;     /* HOG_ORIENT_SIGNED or HOG_ORIENT_UNSIGNED */
     int32_t copy_threads;    /* helper threads that split hog_submit's copies of large
                                 images with the caller, 0..32 (0: the caller alone) */
 } hog_server_config;

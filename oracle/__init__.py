@@ -44,6 +44,12 @@ def _load():
         lib.orc_bin_table.argtypes = [i32, p]
         lib.orc_bin_table.restype = i32
         lib.orc_bin_map.argtypes = [p, i32, i32, i32, i64, i32, p]
+        lib.orc_bin_unsigned.argtypes = [i32, i32, i32]
+        lib.orc_bin_unsigned.restype = i32
+        lib.orc_bin_table_ex.argtypes = [i32, i32, p]
+        lib.orc_bin_table_ex.restype = i32
+        lib.orc_bin_map_ex.argtypes = [p, i32, i32, i32, i64, i32, i32, p]
+        lib.orc_bin_map_ex.restype = i32
         lib.orc_pyramid.argtypes = [i32, i32, dbl, i32, i32, i32, i32, p, p, p]
         lib.orc_resize_nn.argtypes = [p, i32, i32, i32, i64, dbl, i32, i32, p]
         lib.orc_integral.argtypes = [p, i32, i32, i32, p]
@@ -73,28 +79,31 @@ def _check(rc: int, what: str):
 
 
 # --------------------------------------------------------------------------
-def bin_of(dx: int, dy: int, n_bins: int) -> int:
-    """Orientation bin of one gradient (FP64 atan2; 255 for a zero gradient)."""
-    r = _load().orc_bin(int(dx), int(dy), int(n_bins))
+def bin_of(dx: int, dy: int, n_bins: int, unsigned: bool = False) -> int:
+    """Orientation bin of one gradient (FP64 atan2; 255 for a zero gradient);
+    unsigned: the angle mod pi."""
+    fn = _load().orc_bin_unsigned if unsigned else _load().orc_bin
+    r = fn(int(dx), int(dy), int(n_bins))
     _check(r, "bin")
     return r
 
 
-def bin_table(n_bins: int) -> np.ndarray:
+def bin_table(n_bins: int, unsigned: bool = False) -> np.ndarray:
     """bin_of over every (dx, dy) in [-255, 255]^2, as uint8[dy+255][dx+255]."""
     out = np.empty((511, 511), dtype=np.uint8)
-    _check(_load().orc_bin_table(int(n_bins), _ptr(out)), "bin_table")
+    _check(_load().orc_bin_table_ex(int(n_bins), int(unsigned), _ptr(out)), "bin_table")
     return out
 
 
-def bin_map(img: np.ndarray, n_bins: int) -> np.ndarray:
+def bin_map(img: np.ndarray, n_bins: int, unsigned: bool = False) -> np.ndarray:
     """Bin map (uint8, h x w) of an image of shape (h, w) or (h, w, c)."""
     img = np.ascontiguousarray(img, dtype=np.uint8)
     if img.ndim == 2:
         img = img[:, :, None]
     h, w, c = img.shape
     out = np.empty((h, w), dtype=np.uint8)
-    _check(_load().orc_bin_map(_ptr(img), w, h, c, w * c, n_bins, _ptr(out)), "bin_map")
+    _check(_load().orc_bin_map_ex(_ptr(img), w, h, c, w * c, n_bins, int(unsigned), _ptr(out)),
+           "bin_map")
     return out
 
 

@@ -74,15 +74,49 @@ int orc_bin(int dx, int dy, int n_bins)
     return b;
 }
 
-/* orc_bin for every (dx, dy) in [-255, 255]^2: out[(dy+255)*511 + dx+255]. */
-int orc_bin_table(int n_bins, uint8_t *out)
+/* ---------------------------------------------------------------------- */
+/* Unsigned orientation: the variant Fig. 4's example uses (9 bins over   */
+/* 0..180 degrees), where a gradient and its opposite share a bin.  The   */
+/* angle is taken mod pi, into [0, pi), and split into n_bins half-open   */
+/* sectors [k pi/n, (k+1) pi/n).  On the axes and diagonals the direction */
+/* m pi/4 folds to (m mod 4) pi/4, sector floor((m mod 4) n / 4), taken   */
+/* in integers for the same reason as above.                              */
+/* ---------------------------------------------------------------------- */
+int orc_bin_unsigned(int dx, int dy, int n_bins)
+{
+    if (n_bins < 1 || n_bins > 64) return -1;
+    if (dx == 0 && dy == 0) return ORC_NO_BIN;
+    int m = -1;
+    if (dy == 0) m = 0;                 /* 0 or pi */
+    else if (dx == 0) m = 2;            /* pi/2 or 3 pi/2 */
+    else if (dx == dy) m = 1;           /* pi/4 or 5 pi/4 */
+    else if (dx == -dy) m = 3;          /* 3 pi/4 or 7 pi/4 */
+    if (m >= 0) return (m * n_bins) / 4;
+    double theta = atan2((double)dy, (double)dx); /* (-pi, pi] */
+    if (theta < 0.0) theta += M_PI;                /* [0, pi) */
+    int b = (int)floor((theta * (double)n_bins) / M_PI);
+    if (b < 0 || b >= n_bins) return -2; /* cannot happen for |dx|,|dy| <= 255 */
+    return b;
+}
+
+static int orc_bin_oriented(int dx, int dy, int n_bins, int unsigned_orientation)
+{
+    return unsigned_orientation ? orc_bin_unsigned(dx, dy, n_bins) : orc_bin(dx, dy, n_bins);
+}
+
+/* orc_bin (or orc_bin_unsigned) for every (dx, dy) in [-255, 255]^2:     */
+/* out[(dy+255)*511 + dx+255].                                            */
+int orc_bin_table_ex(int n_bins, int unsigned_orientation, uint8_t *out)
 {
     if (n_bins < 1 || n_bins > 64) return -1;
     for (int dy = -255; dy <= 255; ++dy)
         for (int dx = -255; dx <= 255; ++dx)
-            out[(dy + 255) * 511 + (dx + 255)] = (uint8_t)orc_bin(dx, dy, n_bins);
+            out[(dy + 255) * 511 + (dx + 255)] =
+                (uint8_t)orc_bin_oriented(dx, dy, n_bins, unsigned_orientation);
     return 0;
 }
+
+int orc_bin_table(int n_bins, uint8_t *out) { return orc_bin_table_ex(n_bins, 0, out); }
 
 /* ---------------------------------------------------------------------- */
 /* Eq. 1 + Sec. 2: bin map of one image.                                  */
@@ -95,8 +129,8 @@ int orc_bin_table(int n_bins, uint8_t *out)
 /* one-pixel border, where Eq. 1 has no neighbour, gets no bin.           */
 /* out is w*h bytes, row-major, no padding.                               */
 /* ---------------------------------------------------------------------- */
-int orc_bin_map(const uint8_t *img, int w, int h, int channels, int64_t pitch,
-                int n_bins, uint8_t *out)
+int orc_bin_map_ex(const uint8_t *img, int w, int h, int channels, int64_t pitch,
+                   int n_bins, int unsigned_orientation, uint8_t *out)
 {
     if (w < 1 || h < 1 || channels < 1 || n_bins < 1 || n_bins > 64) return -1;
     for (int y = 0; y < h; ++y) {
@@ -114,12 +148,18 @@ int orc_bin_map(const uint8_t *img, int w, int h, int channels, int64_t pitch,
                     int mag = dx * dx + dy * dy;
                     if (mag > best) { best = mag; bdx = dx; bdy = dy; }
                 }
-                if (best > 0) bin = (uint8_t)orc_bin(bdx, bdy, n_bins);
+                if (best > 0) bin = (uint8_t)orc_bin_oriented(bdx, bdy, n_bins, unsigned_orientation);
             }
             out[(int64_t)y * w + x] = bin;
         }
     }
     return 0;
+}
+
+int orc_bin_map(const uint8_t *img, int w, int h, int channels, int64_t pitch,
+                int n_bins, uint8_t *out)
+{
+    return orc_bin_map_ex(img, w, h, channels, pitch, n_bins, 0, out);
 }
 
 /* ---------------------------------------------------------------------- */

@@ -104,7 +104,9 @@ hipError_t drain_timing()
 // floor(m n / 8) for the direction m pi/4, computed in integers. Elsewhere
 // the FP64 angle is far (> 1e-9 of a sector) from every edge.
 // ---------------------------------------------------------------------------
-uint8_t lut_entry(int dx, int dy, int n)
+// Unsigned orientation folds the angle into [0, pi): sectors of pi / n, and
+// on the axes and diagonals floor((m mod 4) n / 4).
+uint8_t lut_entry(int dx, int dy, int n, bool folded)
 {
     if (dx == 0 && dy == 0) return HOG_NO_BIN;
     if (dx == 0 || dy == 0 || dx == dy || dx == -dy) {
@@ -113,12 +115,14 @@ uint8_t lut_entry(int dx, int dy, int n)
         else if (dx == 0) m = dy > 0 ? 2 : 6;
         else if (dx > 0) m = dy > 0 ? 1 : 7;
         else m = dy > 0 ? 3 : 5;
-        return (uint8_t)((m * n) / 8);
+        return folded ? (uint8_t)(((m % 4) * n) / 4) : (uint8_t)((m * n) / 8);
     }
-    const double two_pi = 6.283185307179586476925286766559;
+    const double pi = 3.14159265358979323846264338327950;
+    const double range = folded ? pi : 2.0 * pi;
     double a = std::atan2((double)dy, (double)dx);
-    if (a < 0.0) a += two_pi;
-    int k = (int)std::floor(a * (double)n / two_pi);
+    if (a < 0.0) a += 2.0 * pi;
+    if (folded && a >= pi) a -= pi;
+    int k = (int)std::floor(a * (double)n / range);
     if (k >= n) k = n - 1;
     return (uint8_t)k;
 }
@@ -128,6 +132,7 @@ uint8_t lut_entry(int dx, int dy, int n)
 // ---------------------------------------------------------------------------
 struct hog_lut {
     int n_bins;
+    int orientation;
     std::vector<uint8_t> host;
     uint8_t *dev;       // full table, 511 * 511 bytes
     uint8_t *dev_half;  // dy >= 0 half with mirror flags, as the kernels stage it in LDS
@@ -154,24 +159,38 @@ extern "C" {
 
 const char *hog_last_error(void) { return g_last_error.c_str(); }
 
-hog_status hog_lut_fill_host(int n_bins, uint8_t *table)
+hog_status hog_lut_fill_host_ex(int n_bins, int orientation, uint8_t *table)
 {
     if (n_bins < 1 || n_bins > HOG_MAX_BINS)
         return fail(HOG_E_INVALID, "n_bins must be in [1, %d], got %d", HOG_MAX_BINS, n_bins);
+    if (orientation != HOG_ORIENT_SIGNED && orientation != HOG_ORIENT_UNSIGNED)
+        return fail(HOG_E_INVALID, "orientation must be HOG_ORIENT_SIGNED or HOG_ORIENT_UNSIGNED, got %d",
+                    orientation);
     if (!table) return fail(HOG_E_INVALID, "table is NULL");
+    const bool folded = orientation == HOG_ORIENT_UNSIGNED;
     for (int dy = -255; dy <= 255; ++dy)
         for (int dx = -255; dx <= 255; ++dx)
-            table[(dy + 255) * HOG_LUT_SIDE + (dx + 255)] = lut_entry(dx, dy, n_bins);
+            table[(dy + 255) * HOG_LUT_SIDE + (dx + 255)] = lut_entry(dx, dy, n_bins, folded);
     return HOG_OK;
 }
 
-hog_status hog_lut_build(int n_bins, hog_lut **out)
+hog_status hog_lut_fill_host(int n_bins, uint8_t *table)
+{
+    return hog_lut_fill_host_ex(n_bins, HOG_ORIENT_SIGNED, table);
+}
+
+hog_status hog_lut_build(int n_bins, hog_lut **out) { return hog_lut_build_ex(n_bins, HOG_ORIENT_SIGNED, out); }
+
+int hog_lut_orientation(const hog_lut *lut) { return lut ? lut->orientation : -1; }
+
+hog_status hog_lut_build_ex(int n_bins, int orientation, hog_lut **out)
 {
     if (!out) return fail(HOG_E_INVALID, "out is NULL");
     *out = nullptr;
     hog_lut *lut = new (std::nothrow) hog_lut;
     if (!lut) return fail(HOG_E_NOMEM, "host allocation failed");
     lut->n_bins = n_bins;
+    lut->orientation = orientation;
     lut->dev = nullptr;
     lut->dev_half = nullptr;
     try {
@@ -180,15 +199,16 @@ hog_status hog_lut_build(int n_bins, hog_lut **out)
         delete lut;
         return fail(HOG_E_NOMEM, "host allocation failed");
     }
-    hog_status st = hog_lut_fill_host(n_bins, lut->host.data());
+    hog_status st = hog_lut_fill_host_ex(n_bins, orientation, lut->host.data());
     if (st != HOG_OK) {
         delete lut;
         return st;
     }
     // Half table: entry (dx, dy >= 0) = bin(dx, dy) | f << 6, where
     // bin(dx, -dy) = n - 1 - bin(dx, dy) + f. Mirroring dy maps the angle t to
-    // 2 pi - t, so off the sector edges the bin becomes n - 1 - bin and on an
-    // edge n - bin; f is read off the full table and checked.
+    // 2 pi - t (unsigned: t mod pi to pi - t mod pi), so off the sector edges
+    // the bin becomes n - 1 - bin and on an edge n - bin; f is read off the
+    // full table and checked.
     std::vector<uint8_t> half((size_t)hogk::kLutHalfBytes, 0);
     for (int dy = 0; dy <= 255; ++dy)
         for (int dx = -255; dx <= 255; ++dx) {

@@ -409,6 +409,8 @@ extern "C" hog_status hog_server_create(const hog_server_config *cfg, const floa
     if (c.memory_budget < 1) return srv_fail(HOG_E_INVALID, "memory_budget must be positive");
     if (c.max_queue < 1) return srv_fail(HOG_E_INVALID, "max_queue must be positive");
     if (c.copy_threads < 0 || c.copy_threads > 32) return srv_fail(HOG_E_INVALID, "copy_threads outside [0, 32]");
+    if (c.orientation != HOG_ORIENT_SIGNED && c.orientation != HOG_ORIENT_UNSIGNED)
+        return srv_fail(HOG_E_INVALID, "orientation must be HOG_ORIENT_SIGNED or HOG_ORIENT_UNSIGNED");
     const int64_t max_img = (int64_t)c.max_width * c.max_height * c.channels;
     if (c.host_budget < max_img) return srv_fail(HOG_E_INVALID, "host_budget must hold the largest image");
     // Validate the description through a plan of the largest image.
@@ -431,7 +433,7 @@ extern "C" hog_status hog_server_create(const hog_server_config *cfg, const floa
         return srv_fail(st, "%s", what);
     };
     if (e != hipSuccess) return cleanup(HOG_E_DEVICE, "hipGetDevice");
-    if (hog_lut_build(c.n_bins, &s->lut) != HOG_OK) return cleanup(HOG_E_DEVICE, "lookup table");
+    if (hog_lut_build_ex(c.n_bins, c.orientation, &s->lut) != HOG_OK) return cleanup(HOG_E_DEVICE, "lookup table");
     const size_t tb = (size_t)c.n_templates * z.feature_dim * 4, bb = (size_t)c.n_templates * 4;
     if (hipMalloc(&s->d_tmpl, tb) != hipSuccess || hipMalloc(&s->d_bias, bb) != hipSuccess)
         return cleanup(HOG_E_NOMEM, "templates");

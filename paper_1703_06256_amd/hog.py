@@ -18,12 +18,13 @@ LIB_PATH = os.path.join(_PKG, "libhog.so")
 HOG_OK, HOG_E_INVALID, HOG_E_NOMEM, HOG_E_DEVICE, HOG_E_BUSY, HOG_E_NOT_READY = range(6)
 HOG_NO_BIN = 255
 HOG_NORM_RAW, HOG_NORM_L2 = 0, 1
+HOG_ORIENT_SIGNED, HOG_ORIENT_UNSIGNED = 0, 1
 LUT_SIDE = 511
 
 # Every symbol include/hog.h declares.
 EXPORTS = (
     "hog_last_error", "hog_lut_fill_host", "hog_lut_build", "hog_lut_free", "hog_lut_bins",
-    "hog_lut_host", "hog_plan_create", "hog_plan_create_batch", "hog_plan_images",
+    "hog_lut_host", "hog_lut_fill_host_ex", "hog_lut_build_ex", "hog_lut_orientation", "hog_plan_create", "hog_plan_create_batch", "hog_plan_images",
     "hog_plan_get_image", "hog_plan_destroy", "hog_plan_get_sizes",
     "hog_plan_get_level", "hog_bin_map", "hog_integral", "hog_scan_windows", "hog_run",
     "hog_graph_create", "hog_graph_launch", "hog_graph_destroy", "hog_plan_get_tiles",
@@ -83,7 +84,8 @@ class ServerConfig(ctypes.Structure):
                 ("memory_budget", ctypes.c_int64), ("host_budget", ctypes.c_int64),
                 ("max_slots", ctypes.c_int32),
                 ("max_batch", ctypes.c_int32), ("max_queue", ctypes.c_int32),
-                ("streams", ctypes.c_int32), ("copy_threads", ctypes.c_int32)]
+                ("streams", ctypes.c_int32), ("orientation", ctypes.c_int32),
+                ("copy_threads", ctypes.c_int32)]
 
 
 class PlanSizes(ctypes.Structure):
@@ -106,12 +108,25 @@ def load_library():
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing: build it with "
                            "`python -m paper_1703_06256_amd.build` (there is no fallback path)")
+    # One HIP runtime per process. PyTorch ships its own copy of the HIP
+    # runtime under the same soname as the system's; with torch loaded first
+    # the dynamic linker binds libhog to that copy, so torch's device memory
+    # and stream handles belong to the runtime libhog calls. Loaded the other
+    # way round, the process would hold two runtimes and torch's would find
+    # no GPU.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(LIB_PATH)
     vp, i32, i64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64
     sig = {
         "hog_last_error": ([], ctypes.c_char_p),
         "hog_lut_fill_host": ([i32, vp], i32),
         "hog_lut_build": ([i32, ctypes.POINTER(vp)], i32),
+        "hog_lut_fill_host_ex": ([i32, i32, vp], i32),
+        "hog_lut_build_ex": ([i32, i32, ctypes.POINTER(vp)], i32),
+        "hog_lut_orientation": ([vp], i32),
         "hog_lut_free": ([vp], None),
         "hog_lut_bins": ([vp], i32),
         "hog_lut_host": ([vp], vp),
@@ -181,10 +196,11 @@ def _dptr(t, dtype, min_elems: int, name: str):
 
 
 # ----------------------------------------------------------------------------
-def hog_lut_fill_host(n_bins: int) -> np.ndarray:
+def hog_lut_fill_host(n_bins: int, orientation: int = HOG_ORIENT_SIGNED) -> np.ndarray:
     """Host-only table: uint8[dy+255][dx+255]."""
     out = np.empty((LUT_SIDE, LUT_SIDE), np.uint8)
-    _check(load_library().hog_lut_fill_host(int(n_bins), out.ctypes.data_as(ctypes.c_void_p)))
+    _check(load_library().hog_lut_fill_host_ex(int(n_bins), int(orientation),
+                                               out.ctypes.data_as(ctypes.c_void_p)))
     return out
 
 
@@ -212,9 +228,9 @@ class Lut:
             pass
 
 
-def hog_lut_build(n_bins: int) -> Lut:
+def hog_lut_build(n_bins: int, orientation: int = HOG_ORIENT_SIGNED) -> Lut:
     h = ctypes.c_void_p()
-    _check(load_library().hog_lut_build(int(n_bins), ctypes.byref(h)))
+    _check(load_library().hog_lut_build_ex(int(n_bins), int(orientation), ctypes.byref(h)))
     return Lut(h, int(n_bins))
 
 
@@ -424,7 +440,8 @@ class Server:
     def __init__(self, tmpl: np.ndarray, bias: np.ndarray, channels=3, n_bins=8, max_levels=1,
                  scale=1.0, cell=8, win_cells_x=8, win_cells_y=16, block=2, norm=HOG_NORM_L2,
                  eps=1e-3, max_width=1920, max_height=1080, memory_budget=1 << 30, host_budget=None,
-                 max_slots=16, max_batch=8, max_queue=1024, streams=3, copy_threads=4):
+                 max_slots=16, max_batch=8, max_queue=1024, streams=3, copy_threads=4,
+                 orientation=HOG_ORIENT_SIGNED):
         if host_budget is None:
             host_budget = 4 * max_batch * max_width * max_height * channels
         self._tmpl = np.ascontiguousarray(tmpl, np.float32)
@@ -435,7 +452,7 @@ class Server:
         cfg = ServerConfig(channels, n_bins, self.k, max_levels, scale,
                            ScanParams(cell, win_cells_x, win_cells_y, block, norm, eps),
                            max_width, max_height, memory_budget, host_budget, max_slots, max_batch,
-                           max_queue, streams, copy_threads)
+                           max_queue, streams, orientation, copy_threads)
         h = ctypes.c_void_p()
         _check(load_library().hog_server_create(
             ctypes.byref(cfg), self._tmpl.ctypes.data_as(ctypes.c_void_p),

@@ -15,11 +15,12 @@ SCORE_RTOL = 1e-5
 
 
 def run_gpu(desc: hog.PlanDesc, img: np.ndarray, tmpl: np.ndarray, bias: np.ndarray,
-            cell_hist=True, block_feat=None, repeat=1, cells_from_planes=False):
+            cell_hist=True, block_feat=None, repeat=1, cells_from_planes=False,
+            orientation=hog.HOG_ORIENT_SIGNED):
     """Run the three calls on cuda:0; return host copies of every output."""
     import torch
     plan = hog.Plan(desc)
-    lut = hog.hog_lut_build(desc.n_bins)
+    lut = hog.hog_lut_build(desc.n_bins, orientation)
     if block_feat is None:
         block_feat = desc.scan.norm == hog.HOG_NORM_L2
     buf = hog.Buffers(plan, cell_hist=cell_hist, block_feat=block_feat)
@@ -40,15 +41,16 @@ def run_gpu(desc: hog.PlanDesc, img: np.ndarray, tmpl: np.ndarray, bias: np.ndar
     return plan, (outs[0] if repeat == 1 else outs)
 
 
-def oracle_level_bins(img: np.ndarray, plan: hog.Plan, l: int, l0: int = 0) -> np.ndarray:
+def oracle_level_bins(img: np.ndarray, plan: hog.Plan, l: int, l0: int = 0,
+                      unsigned: bool = False) -> np.ndarray:
     """Oracle bins of plan level l, which belongs to the image whose first
     level is l0 (0 for single-image plans)."""
     li = plan.levels[l]
     nb = plan.desc.n_bins
     if l == l0:
-        return oracle.bin_map(img, nb)
+        return oracle.bin_map(img, nb, unsigned)
     lvl = oracle.resize_nn(img, li.scale, li.width, li.height)
-    return oracle.bin_map(lvl, nb)
+    return oracle.bin_map(lvl, nb, unsigned)
 
 
 def run_gpu_batch(descs, imgs, tmpl: np.ndarray, bias: np.ndarray, cell_hist=True):

@@ -5,6 +5,7 @@ import ctypes
 import os
 import re
 import subprocess
+import sys
 
 import numpy as np
 import pytest
@@ -86,12 +87,14 @@ def test_calls_reject_null_arguments():
     lib.hog_lut_free(None)
 
 
+@pytest.mark.parametrize("orientation", [hog.HOG_ORIENT_SIGNED, hog.HOG_ORIENT_UNSIGNED])
 @pytest.mark.parametrize("nb", list(range(1, 65)))
-def test_lut_mirror_rule_behind_the_half_table(nb):
+def test_lut_mirror_rule_behind_the_half_table(nb, orientation):
     """The kernels keep only the dy >= 0 half of the table plus one flag:
     bin(dx, -dy) = nb - 1 - bin(dx, dy) + f with f in {0, 1}, f = 1 exactly on
-    sector edges (where the mirrored angle 2 pi - t is a multiple of 2 pi/nb)."""
-    t = hog.hog_lut_fill_host(nb).astype(np.int64)
+    sector edges (where the mirrored angle 2 pi - t, or pi - t for unsigned
+    orientation, is a multiple of the sector width)."""
+    t = hog.hog_lut_fill_host(nb, orientation).astype(np.int64)
     up = t[255 + 1:, :]          # dy = 1..255
     dn = t[255 - 1::-1, :]       # dy = -1..-255
     f = dn - (nb - 1 - up)
@@ -127,3 +130,35 @@ def test_batch_plan_rejects_bad_counts_and_bad_members():
     assert lib.hog_plan_create_batch(bad, 2, ctypes.byref(h)) == hog.HOG_E_INVALID
     assert lib.hog_plan_images(None) == 0
     assert lib.hog_plan_get_image(None, 0, None) == hog.HOG_E_INVALID
+
+
+@pytest.mark.parametrize("nb", list(range(1, 65)))
+def test_unsigned_host_table_equals_oracle(nb):
+    assert np.array_equal(hog.hog_lut_fill_host(nb, hog.HOG_ORIENT_UNSIGNED),
+                          oracle.bin_table(nb, unsigned=True))
+
+
+def test_lut_rejects_unknown_orientation():
+    lib = hog.load_library()
+    out = np.empty((511, 511), np.uint8)
+    assert lib.hog_lut_fill_host_ex(8, 2, out.ctypes.data_as(ctypes.c_void_p)) == hog.HOG_E_INVALID
+    h = ctypes.c_void_p()
+    assert lib.hog_lut_build_ex(8, -1, ctypes.byref(h)) == hog.HOG_E_INVALID
+    assert not h.value
+    assert lib.hog_lut_orientation(None) == -1
+
+
+def test_binding_leaves_one_hip_runtime_in_the_process():
+    """PyTorch carries its own HIP runtime under the system one's soname.
+    Loading libhog through the binding, even before anything else imports
+    torch, must leave exactly one runtime mapped, so torch's device memory and
+    streams belong to the runtime libhog calls."""
+    code = ("import re, sys; sys.path.insert(0, %r)\n"
+            "from paper_1703_06256_amd import hog\n"
+            "hog.load_library()\n"
+            "m = open('/proc/self/maps').read()\n"
+            "print(len(set(re.findall(r'\\S*libamdhip64\\S*', m))))\n") % os.path.dirname(os.path.dirname(
+                os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stderr
+    assert r.stdout.strip() == "1"

@@ -104,6 +104,62 @@ def test_bins_off_boundary_match_long_double(n_bins):
     assert np.array_equal(got[~tie], want[~tie])
 
 
+@pytest.mark.parametrize("n_bins", list(range(1, 33)))
+def test_unsigned_bins_are_signed_bins_of_twice_as_many_mod_n(n_bins):
+    """Folding the angle into [0, pi) with n sectors of pi/n is the signed
+    binning with 2n sectors of 2pi/(2n), taken mod n: floor(t 2n / 2pi) mod n
+    = floor((t mod pi) n / pi), on the edges too. So the unsigned table is
+    pinned to the signed one, itself pinned above."""
+    u = oracle.bin_table(n_bins, unsigned=True).astype(np.int64)
+    s2 = oracle.bin_table(2 * n_bins).astype(np.int64)
+    want = np.where(s2 == NO_BIN, NO_BIN, s2 % n_bins)
+    assert np.array_equal(u, want)
+
+
+@pytest.mark.parametrize("n_bins", [9, 33, 47, 64])
+def test_unsigned_bins_off_edges_match_long_double(n_bins):
+    """n > 32 has no signed table of 2n bins to compare with: off the axes and
+    diagonals the unsigned bin must equal floor((theta mod pi) n / pi) in x87
+    long double, with a margin to the edges far above both precisions."""
+    ld = np.longdouble
+    pi = np.arctan(ld(1)) * 4
+    theta = np.arctan2(DY.astype(ld), DX.astype(ld))
+    theta = np.where(theta < 0, theta + pi, theta)
+    pos = theta * n_bins / pi
+    tie = (DX == 0) | (DY == 0) | (np.abs(DX) == np.abs(DY))
+    frac = pos - np.floor(pos)
+    assert np.minimum(frac, 1 - frac)[~tie].min() > 1e-9
+    got = oracle.bin_table(n_bins, unsigned=True)
+    assert np.array_equal(got[~tie], np.floor(pos).astype(np.int64)[~tie])
+    # axes and diagonals: (m mod 4) n / 4 for the direction m pi / 4
+    for (dx, dy), m in [((7, 0), 0), ((-7, 0), 0), ((0, 7), 2), ((0, -7), 2), ((7, 7), 1),
+                        ((-7, -7), 1), ((-7, 7), 3), ((7, -7), 3)]:
+        assert oracle.bin_of(dx, dy, n_bins, unsigned=True) == (m * n_bins) // 4
+
+
+def test_unsigned_bins_opposite_gradients_share_a_bin_and_9_bin_examples():
+    u = oracle.bin_table(9, unsigned=True)
+    assert np.array_equal(u, u[::-1, ::-1])  # (dx, dy) and (-dx, -dy)
+    # 9 bins of 20 degrees over 0..180
+    cases = {(1, 0): 0, (-1, 0): 0, (0, 1): 4, (0, -1): 4, (1, 1): 2, (-1, -1): 2, (-1, 1): 6,
+             (1, -1): 6, (5, -3): 7, (-5, 3): 7, (10, 1): 0, (1, 10): 4, (-10, 1): 8}
+    for (dx, dy), want in cases.items():
+        assert oracle.bin_of(dx, dy, 9, unsigned=True) == want, (dx, dy)
+
+
+def test_unsigned_bin_map_is_signed_map_of_twice_the_bins_mod_n():
+    """Through the whole bin map (Eq. 1, channel choice, border): unsigned
+    with n bins equals signed with 2n bins mod n; an inverted image (every
+    gradient negated) has the same unsigned map."""
+    rng = np.random.default_rng(77)
+    img = rng.integers(0, 256, (37, 53, 3)).astype(np.uint8)
+    for n in (4, 9, 16):
+        u = oracle.bin_map(img, n, unsigned=True).astype(np.int64)
+        s2 = oracle.bin_map(img, 2 * n).astype(np.int64)
+        assert np.array_equal(u, np.where(s2 == NO_BIN, NO_BIN, s2 % n))
+        assert np.array_equal(u, oracle.bin_map(255 - img, n, unsigned=True))
+
+
 @pytest.mark.parametrize("n_bins", [8, 18])
 def test_bins_reflection(n_bins):
     """Mirroring dy mirrors the angle: bin(dx,-dy) = n-1-bin(dx,dy) off edges."""
