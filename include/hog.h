@@ -62,6 +62,18 @@ enum { HOG_NORM_RAW = 0, HOG_NORM_L2 = 1 };
  * 9-bin, 0..180 degree histograms of Fig. 4's example). */
 enum { HOG_ORIENT_SIGNED = 0, HOG_ORIENT_UNSIGNED = 1 };
 
+/* Votes per pixel. HOG_VOTES_HARD: the pixel counts 1 in its bin (Sec. 2's
+ * simplest case, which the paper keeps). HOG_VOTES_SOFT: the two-bin vote
+ * Sec. 2 attributes to OpenCV, which the paper sets aside -- with a the
+ * angle in bin widths minus 1/2, the pixel votes 1 - frac(a) to bin
+ * floor(a) mod n and frac(a) to the next bin -- here quantised to whole
+ * units of 1/HOG_SOFT_QUANTUM: w1 = floor(frac(a) HOG_SOFT_QUANTUM + 1/2)
+ * to the next bin and HOG_SOFT_QUANTUM - w1 to floor(a) mod n, so that the
+ * per-bin integral images stay exact integers (in units of
+ * 1/HOG_SOFT_QUANTUM) and Eq. 6 stays exact. */
+enum { HOG_VOTES_HARD = 0, HOG_VOTES_SOFT = 1 };
+#define HOG_SOFT_QUANTUM 32
+
 /* Message for the calling thread's last failing call ("" if none). */
 const char *hog_last_error(void);
 
@@ -86,13 +98,20 @@ hog_status hog_lut_fill_host(int n_bins, uint8_t *table);
  * floor((m mod 4) n / 4), in integers. HOG_E_INVALID for another value. */
 hog_status hog_lut_fill_host_ex(int n_bins, int orientation, uint8_t *table);
 
+/* The soft-vote table (HOG_VOTES_SOFT) for either orientation, host-only:
+ * table[(dy+255)*511 + (dx+255)] = b0 | w1 << 8 (uint16), b0 the lower of
+ * the two bins and w1 the units (0..HOG_SOFT_QUANTUM) that go to bin
+ * (b0 + 1) mod n_bins; (0, 0) gives 255 (no vote). Angles as in
+ * hog_lut_fill_host_ex, in FP64. */
+hog_status hog_lut_fill_soft_host(int n_bins, int orientation, uint16_t *table);
+
 /* Build the table for n_bins once and upload it to the current device.
  * *out is library-owned (host copy + device copy); free with hog_lut_free.
  * Synchronous. */
 hog_status hog_lut_build(int n_bins, hog_lut **out);
 /* hog_lut_build for either orientation (hog_lut_fill_host_ex). The plans and
  * kernels are the same for both: the orientation lives in the table only. */
-hog_status hog_lut_build_ex(int n_bins, int orientation, hog_lut **out);
+hog_status hog_lut_build_ex(int n_bins, int orientation, hog_lut **out);  /* holds both tables */
 int hog_lut_orientation(const hog_lut *lut);
 void hog_lut_free(hog_lut *lut);
 int hog_lut_bins(const hog_lut *lut);
@@ -125,6 +144,8 @@ typedef struct {
     int32_t plane_bits;    /* integral-image element: 32 (or 0) uint32; 16 uint16; 8 uint8.
                               Narrow planes hold ii mod 2^plane_bits (Sec. 4: 16-bit
                               integral images); see hog_integral. 8 needs cell^2 < 256. */
+    int32_t votes;         /* HOG_VOTES_HARD (0) or HOG_VOTES_SOFT; soft needs 32-bit planes
+                              and width * height * HOG_SOFT_QUANTUM < 2^32 */
 } hog_plan_desc;
 
 typedef struct hog_plan hog_plan;
@@ -138,7 +159,9 @@ typedef struct hog_plan hog_plan;
 typedef struct {
     int32_t width, height;
     double scale;
-    int64_t bins_offset;     /* bytes; bin (x, y) at bins[bins_offset + y*bins_pitch + x] */
+    int64_t bins_offset;     /* bytes; bin (x, y) at bins[bins_offset + y*bins_pitch + x]
+                                (soft votes: the uint16 b0 | w1 << 8 at byte offset
+                                bins_offset + y*bins_pitch + 2x) */
     int64_t bins_pitch;      /* bytes */
     int64_t ii_offset;       /* elements; ii(x, y) of bin n at ii[ii_offset +
                                 n*ii_plane_stride + y*ii_pitch + x] (hog_integral) */
@@ -207,7 +230,9 @@ hog_status hog_plan_get_level(const hog_plan *plan, int level, hog_level_info *o
  * dx = P[x+1][y] - P[x-1][y], dy = P[x][y+1] - P[x][y-1] (on the level's
  * nearest-neighbour image); the channel with the largest dx^2 + dy^2 wins
  * (ties to the lowest index); the bin is lut[(dy+255)*511 + dx+255]. Border
- * pixels and zero gradients get 255. lut must have the plan's n_bins. */
+ * pixels and zero gradients get 255. lut must have the plan's n_bins. Soft
+ * votes: each pixel gets the uint16 soft-table entry b0 | w1 << 8 instead
+ * (255 for no vote). */
 hog_status hog_bin_map(const hog_plan *plan, const hog_lut *lut, const uint8_t *img,
                        int64_t img_pitch, uint8_t *bins, void *stream);
 
@@ -225,7 +250,10 @@ hog_status hog_bin_map(const hog_plan *plan, const hog_lut *lut, const uint8_t *
  * column width - 1 hold unspecified values. As a by-product it caches every
  * 8 x 8-pixel cell histogram (Eq. 6, the four-corner sums of the planes it
  * writes) in the workspace for hog_scan_windows. workspace: device, at least
- * workspace_bytes, contents on entry ignored. */
+ * workspace_bytes, contents on entry ignored. Soft votes: the count becomes
+ * the sum of the votes for bin n, in units of 1/HOG_SOFT_QUANTUM (a pixel
+ * gives HOG_SOFT_QUANTUM - w1 to b0 and w1 to b0 + 1 mod n_bins), and the
+ * cell histograms of every cell size are cached. */
 hog_status hog_integral(const hog_plan *plan, const uint8_t *bins, void *ii,
                         void *workspace, void *stream);
 
@@ -250,7 +278,9 @@ hog_status hog_integral(const hog_plan *plan, const uint8_t *bins, void *ii,
  * tmpl: device, float[K][D]; bias: device, float[K]; scores: device, float.
  * cell_hist (nullable): device, uint32, receives every cell histogram.
  * block_feat (nullable, L2 only): device, float, receives every normalised
- * block. workspace: the one passed to hog_integral. */
+ * block. workspace: the one passed to hog_integral. Soft votes: cells hold
+ * vote sums in units of 1/HOG_SOFT_QUANTUM (so does cell_hist); the feature
+ * uses them divided by HOG_SOFT_QUANTUM, so a pixel's votes sum to 1. */
 hog_status hog_scan_windows(const hog_plan *plan, const void *ii, const float *tmpl,
                             const float *bias, float *scores, uint32_t *cell_hist,
                             float *block_feat, void *workspace, void *stream);

@@ -50,6 +50,16 @@ def _load():
         lib.orc_bin_table_ex.restype = i32
         lib.orc_bin_map_ex.argtypes = [p, i32, i32, i32, i64, i32, i32, p]
         lib.orc_bin_map_ex.restype = i32
+        lib.orc_soft_vote.argtypes = [i32, i32, i32, i32, p, p]
+        lib.orc_soft_vote.restype = i32
+        lib.orc_soft_table.argtypes = [i32, i32, p, p]
+        lib.orc_soft_table.restype = i32
+        lib.orc_soft_bin_map.argtypes = [p, i32, i32, i32, i64, i32, i32, p, p]
+        lib.orc_soft_bin_map.restype = i32
+        lib.orc_soft_integral.argtypes = [p, p, i32, i32, i32, p]
+        lib.orc_soft_integral.restype = i32
+        lib.orc_soft_cell_hist.argtypes = [p, p, i32, i32, i32, i32, p]
+        lib.orc_soft_cell_hist.restype = i32
         lib.orc_pyramid.argtypes = [i32, i32, dbl, i32, i32, i32, i32, p, p, p]
         lib.orc_resize_nn.argtypes = [p, i32, i32, i32, i64, dbl, i32, i32, p]
         lib.orc_integral.argtypes = [p, i32, i32, i32, p]
@@ -105,6 +115,97 @@ def bin_map(img: np.ndarray, n_bins: int, unsigned: bool = False) -> np.ndarray:
     _check(_load().orc_bin_map_ex(_ptr(img), w, h, c, w * c, n_bins, int(unsigned), _ptr(out)),
            "bin_map")
     return out
+
+
+SOFT_Q = 32  # vote units per pixel (soft votes)
+
+
+def soft_vote(dx: int, dy: int, n_bins: int, unsigned: bool = False):
+    """(b0, w1) of one gradient: w1 units to bin b0 + 1 mod n, SOFT_Q - w1 to
+    b0; (255, 0) for a zero gradient."""
+    b0, w1 = ctypes.c_int(), ctypes.c_int()
+    _check(_load().orc_soft_vote(int(dx), int(dy), int(n_bins), int(unsigned), ctypes.byref(b0),
+                                 ctypes.byref(w1)), "soft_vote")
+    return b0.value, w1.value
+
+
+def soft_table(n_bins: int, unsigned: bool = False):
+    """soft_vote over every (dx, dy) in [-255, 255]^2: (b0, w1) uint8[dy+255][dx+255]."""
+    b0 = np.empty((511, 511), np.uint8)
+    w1 = np.empty((511, 511), np.uint8)
+    _check(_load().orc_soft_table(int(n_bins), int(unsigned), _ptr(b0), _ptr(w1)), "soft_table")
+    return b0, w1
+
+
+def soft_bin_map(img: np.ndarray, n_bins: int, unsigned: bool = False):
+    """(b0, w1) maps, uint8 h x w each, of an image of shape (h, w) or (h, w, c)."""
+    img = np.ascontiguousarray(img, dtype=np.uint8)
+    if img.ndim == 2:
+        img = img[:, :, None]
+    h, w, c = img.shape
+    b0 = np.empty((h, w), np.uint8)
+    w1 = np.empty((h, w), np.uint8)
+    _check(_load().orc_soft_bin_map(_ptr(img), w, h, c, w * c, n_bins, int(unsigned), _ptr(b0), _ptr(w1)),
+           "soft_bin_map")
+    return b0, w1
+
+
+def soft_integral(b0: np.ndarray, w1: np.ndarray, n_bins: int) -> np.ndarray:
+    """uint32[n_bins][h+1][w+1]: Eq. 5 over the soft votes (units of 1/SOFT_Q)."""
+    b0 = np.ascontiguousarray(b0, np.uint8)
+    w1 = np.ascontiguousarray(w1, np.uint8)
+    h, w = b0.shape
+    out = np.empty((n_bins, h + 1, w + 1), np.uint32)
+    _check(_load().orc_soft_integral(_ptr(b0), _ptr(w1), w, h, n_bins, _ptr(out)), "soft_integral")
+    return out
+
+
+def soft_cell_hist(b0: np.ndarray, w1: np.ndarray, n_bins: int, cell: int = 8) -> np.ndarray:
+    """uint32[h//cell][w//cell][n_bins]: brute-force vote sums (units of 1/SOFT_Q)."""
+    b0 = np.ascontiguousarray(b0, np.uint8)
+    w1 = np.ascontiguousarray(w1, np.uint8)
+    h, w = b0.shape
+    out = np.empty((h // cell, w // cell, n_bins), np.uint32)
+    _check(_load().orc_soft_cell_hist(_ptr(b0), _ptr(w1), w, h, n_bins, cell, _ptr(out)),
+           "soft_cell_hist")
+    return out
+
+
+def features_from_cells(cells: np.ndarray, p: "ScanParams", wx: int, wy: int) -> np.ndarray:
+    """Window feature (Sec. 3.1 / Fig. 4) from a cell-histogram array
+    [cy][cx][n] in FP64, in the order of window_feature: raw, the cells in
+    row-major order; L2, each 2x2-cell block v / sqrt(|v|^2 + eps^2)."""
+    c = cells.astype(np.float64)
+    win = c[wy:wy + p.wcy, wx:wx + p.wcx]  # [cy][cx][n]
+    if p.norm == 0:
+        return win.reshape(-1)
+    out = []
+    for by in range(p.wcy - 1):
+        for bx in range(p.wcx - 1):
+            v = np.concatenate([win[by + vv, bx + uu] for vv in (0, 1) for uu in (0, 1)])
+            out.append(v / np.sqrt(np.dot(v, v) + p.eps * p.eps))
+    return np.concatenate(out)
+
+
+def soft_score_windows(b0, w1, n_bins, p, tmpl, bias, wxs=None, wys=None):
+    """Scores (FP64) of the listed windows under soft votes: features from the
+    brute-force vote sums divided by SOFT_Q (a pixel's votes sum to 1).
+    Returns (scores [n][K], sum_d |T_d f_d| + |b| [n][K], wxs, wys)."""
+    cells = soft_cell_hist(b0, w1, n_bins, p.cell).astype(np.float64) / SOFT_Q
+    h, w = b0.shape
+    nwx = (w // p.cell) - p.wcx + 1
+    nwy = (h // p.cell) - p.wcy + 1
+    if wxs is None:
+        wys, wxs = np.divmod(np.arange(max(nwx, 0) * max(nwy, 0)), max(nwx, 1))
+    T = np.asarray(tmpl, np.float64).reshape(len(bias), -1)
+    b = np.asarray(bias, np.float64)
+    s = np.empty((len(wxs), len(b)))
+    a = np.empty((len(wxs), len(b)))
+    for i, (wx, wy) in enumerate(zip(wxs, wys)):
+        f = features_from_cells(cells, p, int(wx), int(wy))
+        s[i] = T @ f + b
+        a[i] = np.abs(T * f[None, :]).sum(axis=1) + np.abs(b)
+    return s, a, np.asarray(wxs), np.asarray(wys)
 
 
 def pyramid(w: int, h: int, scale: float, min_w: int, min_h: int, max_levels: int = 0):

@@ -295,6 +295,144 @@ int orc_cell_hist(const uint8_t *bins, int w, int h, int n_bins, int cell, uint3
 }
 
 /* ---------------------------------------------------------------------- */
+/* Soft votes.  Sec. 2 notes that OpenCV shares each pixel's vote between */
+/* two bins, and that the paper keeps to one bin per pixel because the    */
+/* shared vote does not fit the one-hot decomposition.  The variant here  */
+/* quantises the shared vote so that integral images stay exact: with t   */
+/* the angle (signed [0, 2 pi) or unsigned [0, pi)), the bin width        */
+/* range / n and a = t / width - 1/2, the pixel gives                      */
+/*     w1 = floor(frac(a) * ORC_SOFT_Q + 1/2)                              */
+/* units to bin (floor(a) + 1) mod n and ORC_SOFT_Q - w1 to floor(a) mod n */
+/* (ORC_SOFT_Q units = one pixel).  On the axes and diagonals t / width   */
+/* is the rational m n / 8 (signed) or (m mod 4) n / 4 (unsigned), and a  */
+/* is taken in integers there; elsewhere a is FP64.                        */
+/* ---------------------------------------------------------------------- */
+#define ORC_SOFT_Q 32
+
+int orc_soft_vote(int dx, int dy, int n_bins, int unsigned_orientation, int *b0, int *w1)
+{
+    if (n_bins < 1 || n_bins > 64 || !b0 || !w1) return -1;
+    if (dx == 0 && dy == 0) { *b0 = ORC_NO_BIN; *w1 = 0; return ORC_NO_BIN; }
+    int m = -1;
+    if (dy == 0) m = dx > 0 ? 0 : 4;
+    else if (dx == 0) m = dy > 0 ? 2 : 6;
+    else if (dx == dy) m = dx > 0 ? 1 : 5;
+    else if (dx == -dy) m = dx < 0 ? 3 : 7;
+    long fl;
+    double frac_q; /* frac(a) * ORC_SOFT_Q */
+    if (m >= 0) {
+        /* a * den = num exactly */
+        const long den = unsigned_orientation ? 4 : 8;
+        const long num = unsigned_orientation ? (long)(m % 4) * n_bins - 2 : (long)m * n_bins - 4;
+        fl = num >= 0 ? num / den : -((-num + den - 1) / den);
+        frac_q = (double)((num - fl * den) * ORC_SOFT_Q) / (double)den;
+    } else {
+        double t = atan2((double)dy, (double)dx);
+        const double range = unsigned_orientation ? M_PI : 2.0 * M_PI;
+        if (t < 0.0) t += range;
+        const double a = (t * (double)n_bins) / range - 0.5;
+        const double f = floor(a);
+        fl = (long)f;
+        frac_q = (a - f) * ORC_SOFT_Q;
+    }
+    *b0 = (int)(((fl % n_bins) + n_bins) % n_bins);
+    *w1 = (int)floor(frac_q + 0.5);
+    return 0;
+}
+
+/* The soft vote of every (dx, dy) in [-255, 255]^2, as b0 and w1 tables. */
+int orc_soft_table(int n_bins, int unsigned_orientation, uint8_t *b0_out, uint8_t *w1_out)
+{
+    if (n_bins < 1 || n_bins > 64) return -1;
+    for (int dy = -255; dy <= 255; ++dy)
+        for (int dx = -255; dx <= 255; ++dx) {
+            int b0, w1;
+            orc_soft_vote(dx, dy, n_bins, unsigned_orientation, &b0, &w1);
+            b0_out[(dy + 255) * 511 + (dx + 255)] = (uint8_t)b0;
+            w1_out[(dy + 255) * 511 + (dx + 255)] = (uint8_t)w1;
+        }
+    return 0;
+}
+
+/* Eq. 1 and the channel choice as in orc_bin_map, then the soft vote.    */
+int orc_soft_bin_map(const uint8_t *img, int w, int h, int channels, int64_t pitch, int n_bins,
+                     int unsigned_orientation, uint8_t *b0_out, uint8_t *w1_out)
+{
+    if (w < 1 || h < 1 || channels < 1 || n_bins < 1 || n_bins > 64) return -1;
+    for (int y = 0; y < h; ++y)
+        for (int x = 0; x < w; ++x) {
+            int b0 = ORC_NO_BIN, w1 = 0;
+            if (x > 0 && x < w - 1 && y > 0 && y < h - 1) {
+                int best = -1, bdx = 0, bdy = 0;
+                for (int c = 0; c < channels; ++c) {
+                    int dx = img[(int64_t)y * pitch + (int64_t)(x + 1) * channels + c] -
+                             img[(int64_t)y * pitch + (int64_t)(x - 1) * channels + c];
+                    int dy = img[(int64_t)(y + 1) * pitch + (int64_t)x * channels + c] -
+                             img[(int64_t)(y - 1) * pitch + (int64_t)x * channels + c];
+                    int mag = dx * dx + dy * dy;
+                    if (mag > best) { best = mag; bdx = dx; bdy = dy; }
+                }
+                if (best > 0) orc_soft_vote(bdx, bdy, n_bins, unsigned_orientation, &b0, &w1);
+            }
+            b0_out[(int64_t)y * w + x] = (uint8_t)b0;
+            w1_out[(int64_t)y * w + x] = (uint8_t)w1;
+        }
+    return 0;
+}
+
+/* The votes pixel (x, y) gives bin n, in units of 1 / ORC_SOFT_Q.         */
+static uint32_t soft_votes_for(const uint8_t *b0, const uint8_t *w1, int64_t i, int n, int n_bins)
+{
+    if (b0[i] == ORC_NO_BIN) return 0;
+    const int lo = b0[i], hi = (b0[i] + 1) % n_bins;
+    uint32_t v = 0;
+    if (lo == n) v += ORC_SOFT_Q - w1[i];
+    if (hi == n) v += w1[i];
+    return v;
+}
+
+/* Eq. 5 over the soft votes: out[n][y+1][x+1] = sum of bin n's votes over */
+/* x' <= x, y' <= y (64-bit running sums; guard row and column are 0).     */
+int orc_soft_integral(const uint8_t *b0, const uint8_t *w1, int w, int h, int n_bins, uint32_t *out)
+{
+    if (w < 1 || h < 1 || n_bins < 1 || n_bins > 64) return -1;
+    const int64_t W1 = w + 1, plane = W1 * (h + 1);
+    for (int n = 0; n < n_bins; ++n) {
+        uint32_t *P = out + n * plane;
+        for (int x = 0; x <= w; ++x) P[x] = 0;
+        for (int y = 0; y < h; ++y) {
+            uint64_t row = 0;
+            P[(y + 1) * W1] = 0;
+            for (int x = 0; x < w; ++x) {
+                row += soft_votes_for(b0, w1, (int64_t)y * w + x, n, n_bins);
+                P[(y + 1) * W1 + x + 1] = (uint32_t)(P[y * W1 + x + 1] + row);
+            }
+        }
+    }
+    return 0;
+}
+
+/* Brute-force vote sums of every cell, in units of 1 / ORC_SOFT_Q.        */
+int orc_soft_cell_hist(const uint8_t *b0, const uint8_t *w1, int w, int h, int n_bins, int cell,
+                       uint32_t *out)
+{
+    if (w < 1 || h < 1 || n_bins < 1 || n_bins > 64 || cell < 1) return -1;
+    const int wc = w / cell, hc = h / cell;
+    for (int cy = 0; cy < hc; ++cy)
+        for (int cx = 0; cx < wc; ++cx) {
+            uint32_t *hist = out + ((int64_t)cy * wc + cx) * n_bins;
+            for (int n = 0; n < n_bins; ++n) {
+                uint32_t sum = 0;
+                for (int y = cy * cell; y < cy * cell + cell; ++y)
+                    for (int x = cx * cell; x < cx * cell + cell; ++x)
+                        sum += soft_votes_for(b0, w1, (int64_t)y * w + x, n, n_bins);
+                hist[n] = sum;
+            }
+        }
+    return 0;
+}
+
+/* ---------------------------------------------------------------------- */
 /* Sec. 3.1 / Fig. 4: feature of one detection window.                    */
 /*                                                                        */
 /* The window has its top-left corner at pixel (wx*cell, wy*cell) and     */

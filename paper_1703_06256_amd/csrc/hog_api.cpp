@@ -127,6 +127,41 @@ uint8_t lut_entry(int dx, int dy, int n, bool folded)
     return (uint8_t)k;
 }
 
+// Soft vote (Sec. 2's two-bin split, quantised): with a the angle in bin
+// widths minus 1/2, b0 = floor(a) mod n and w1 = floor(frac(a) Q + 1/2)
+// units go to b0 + 1. On the axes and diagonals a is the rational
+// (m n - 4) / 8 (signed) or ((m mod 4) n - 2) / 4 (unsigned) and is taken in
+// integers; elsewhere in FP64. Returns b0 | w1 << 8, or 255.
+uint16_t soft_entry(int dx, int dy, int n, bool folded)
+{
+    constexpr int Q = HOG_SOFT_QUANTUM;
+    if (dx == 0 && dy == 0) return HOG_NO_BIN;
+    int b0, w1;
+    if (dx == 0 || dy == 0 || dx == dy || dx == -dy) {
+        int m;
+        if (dy == 0) m = dx > 0 ? 0 : 4;
+        else if (dx == 0) m = dy > 0 ? 2 : 6;
+        else if (dx > 0) m = dy > 0 ? 1 : 7;
+        else m = dy > 0 ? 3 : 5;
+        const int den = folded ? 4 : 8;
+        const int num = folded ? (m % 4) * n - 2 : m * n - 4;
+        const int fl = (num >= 0 ? num : num - den + 1) / den;  // floor
+        const int r = num - fl * den;                            // 0 .. den - 1
+        b0 = ((fl % n) + n) % n;
+        w1 = r * Q / den;
+    } else {
+        const double pi = 3.14159265358979323846264338327950;
+        const double range = folded ? pi : 2.0 * pi;
+        double t = std::atan2((double)dy, (double)dx);
+        if (t < 0.0) t += folded ? pi : 2.0 * pi;
+        const double a = t * (double)n / range - 0.5;
+        const double fl = std::floor(a);
+        w1 = (int)std::floor((a - fl) * Q + 0.5);
+        b0 = (((int)fl % n) + n) % n;
+    }
+    return (uint16_t)(b0 | w1 << 8);
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -136,6 +171,7 @@ struct hog_lut {
     std::vector<uint8_t> host;
     uint8_t *dev;       // full table, 511 * 511 bytes
     uint8_t *dev_half;  // dy >= 0 half with mirror flags, as the kernels stage it in LDS
+    uint16_t *dev_soft; // soft-vote table, 511 * 511 entries b0 | w1 << 8
 };
 
 struct hog_plan {
@@ -174,6 +210,21 @@ hog_status hog_lut_fill_host_ex(int n_bins, int orientation, uint8_t *table)
     return HOG_OK;
 }
 
+hog_status hog_lut_fill_soft_host(int n_bins, int orientation, uint16_t *table)
+{
+    if (n_bins < 1 || n_bins > HOG_MAX_BINS)
+        return fail(HOG_E_INVALID, "n_bins must be in [1, %d], got %d", HOG_MAX_BINS, n_bins);
+    if (orientation != HOG_ORIENT_SIGNED && orientation != HOG_ORIENT_UNSIGNED)
+        return fail(HOG_E_INVALID, "orientation must be HOG_ORIENT_SIGNED or HOG_ORIENT_UNSIGNED, got %d",
+                    orientation);
+    if (!table) return fail(HOG_E_INVALID, "table is NULL");
+    const bool folded = orientation == HOG_ORIENT_UNSIGNED;
+    for (int dy = -255; dy <= 255; ++dy)
+        for (int dx = -255; dx <= 255; ++dx)
+            table[(dy + 255) * HOG_LUT_SIDE + (dx + 255)] = soft_entry(dx, dy, n_bins, folded);
+    return HOG_OK;
+}
+
 hog_status hog_lut_fill_host(int n_bins, uint8_t *table)
 {
     return hog_lut_fill_host_ex(n_bins, HOG_ORIENT_SIGNED, table);
@@ -193,6 +244,7 @@ hog_status hog_lut_build_ex(int n_bins, int orientation, hog_lut **out)
     lut->orientation = orientation;
     lut->dev = nullptr;
     lut->dev_half = nullptr;
+    lut->dev_soft = nullptr;
     try {
         lut->host.resize((size_t)HOG_LUT_SIDE * HOG_LUT_SIDE);
     } catch (...) {
@@ -225,23 +277,20 @@ hog_status hog_lut_build_ex(int n_bins, int orientation, hog_lut **out)
             }
             half[(size_t)dy * HOG_LUT_SIDE + (dx + 255)] = e;
         }
+    std::vector<uint16_t> soft((size_t)HOG_LUT_SIDE * HOG_LUT_SIDE);
+    (void)hog_lut_fill_soft_host(n_bins, orientation, soft.data());  // arguments checked above
     hipError_t e = hipMalloc((void **)&lut->dev, lut->host.size());
+    if (e == hipSuccess) e = hipMalloc((void **)&lut->dev_half, half.size());
+    if (e == hipSuccess) e = hipMalloc((void **)&lut->dev_soft, soft.size() * 2);
     if (e != hipSuccess) {
-        delete lut;
+        hog_lut_free(lut);
         return device_fail(e, "hipMalloc(lut)");
-    }
-    e = hipMalloc((void **)&lut->dev_half, half.size());
-    if (e != hipSuccess) {
-        (void)hipFree(lut->dev);
-        delete lut;
-        return device_fail(e, "hipMalloc(lut half)");
     }
     e = hipMemcpy(lut->dev, lut->host.data(), lut->host.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(lut->dev_half, half.data(), half.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(lut->dev_soft, soft.data(), soft.size() * 2, hipMemcpyHostToDevice);
     if (e != hipSuccess) {
-        (void)hipFree(lut->dev);
-        (void)hipFree(lut->dev_half);
-        delete lut;
+        hog_lut_free(lut);
         return device_fail(e, "hipMemcpy(lut)");
     }
     *out = lut;
@@ -253,6 +302,7 @@ void hog_lut_free(hog_lut *lut)
     if (!lut) return;
     if (lut->dev) (void)hipFree(lut->dev);
     if (lut->dev_half) (void)hipFree(lut->dev_half);
+    if (lut->dev_soft) (void)hipFree(lut->dev_soft);
     delete lut;
 }
 
@@ -293,6 +343,13 @@ static hog_status check_desc(const hog_plan_desc *d)
     const int pbits = d->plane_bits == 0 ? 32 : d->plane_bits;
     if (pbits != 32 && pbits != 16 && pbits != 8)
         return fail(HOG_E_INVALID, "plane_bits must be 32, 16 or 8 (0 = 32), got %d", d->plane_bits);
+    if (d->votes != HOG_VOTES_HARD && d->votes != HOG_VOTES_SOFT)
+        return fail(HOG_E_INVALID, "votes must be HOG_VOTES_HARD or HOG_VOTES_SOFT, got %d", d->votes);
+    if (d->votes == HOG_VOTES_SOFT) {
+        if (pbits != 32) return fail(HOG_E_INVALID, "soft votes need 32-bit planes");
+        if ((int64_t)d->width * d->height * HOG_SOFT_QUANTUM >= ((int64_t)1 << 32))
+            return fail(HOG_E_INVALID, "soft votes: width * height * %d must stay below 2^32", HOG_SOFT_QUANTUM);
+    }
     // A cell's four-corner sum taken mod 2^bits is exact below 2^bits pixels.
     if ((int64_t)s.cell * s.cell >= ((int64_t)1 << pbits))
         return fail(HOG_E_INVALID, "%d-pixel cells hold up to %d pixels, too many for %d-bit planes", s.cell,
@@ -320,14 +377,16 @@ static hog_status create_plan(const hog_plan_desc *descs, int n_img, bool batch,
         if (st != HOG_OK) return st;
         const hog_plan_desc &a = descs[0], &b = descs[i];
         if (b.channels != a.channels || b.n_bins != a.n_bins || b.n_templates != a.n_templates ||
-            !same_scan(a.scan, b.scan) || plane_bytes_of(a) != plane_bytes_of(b))
+            !same_scan(a.scan, b.scan) || plane_bytes_of(a) != plane_bytes_of(b) || a.votes != b.votes)
             return fail(HOG_E_INVALID,
-                        "image %d: channels, n_bins, n_templates, scan and plane_bits must match image 0", i);
+                        "image %d: channels, n_bins, n_templates, scan, plane_bits and votes must match image 0",
+                        i);
     }
     const hog_plan_desc d0 = descs[0];
     const hog_scan_params &sp = d0.scan;
     const int nb = d0.n_bins, K = d0.n_templates;
     const int pb = plane_bytes_of(d0);  // bytes per plane element
+    const bool soft = d0.votes == HOG_VOTES_SOFT;
     const int win_w = sp.cell * sp.win_cells_x, win_h = sp.cell * sp.win_cells_y;
     const int dim = sp.norm == HOG_NORM_RAW
                         ? sp.win_cells_x * sp.win_cells_y * nb
@@ -343,14 +402,18 @@ static hog_status create_plan(const hog_plan_desc *descs, int n_img, bool batch,
     int64_t best_lds = 0;
     const bool l2_8wide = sp.norm == HOG_NORM_L2 && sp.win_cells_x - 1 == hogk::kStripMaxBX &&
                           sp.win_cells_y - 1 <= 16;
-    if (l2_8wide && nb <= 16 && K >= 16) {
+    // The matrix-core scorers take cell values exactly in fp16 (integers up to
+    // 2048): every hard-vote cell (at most 32 x 32 pixels), soft-vote cells
+    // of up to 8 x 8 pixels.
+    const bool fp16_exact = !soft || (int64_t)sp.cell * sp.cell * HOG_SOFT_QUANTUM <= 2048;
+    if (l2_8wide && fp16_exact && nb <= 16 && K >= 16) {
         // Many templates: the window GEMM, one workgroup per 64 x 8 windows
         // and 32 templates.
         scorer = 2;
         mfma_ks = nb <= 8 ? 8 : 16;
         best_tw = hogk::kWgW;
         best_th = hogk::kWgTH;
-    } else if (l2_8wide && nb <= 20) {
+    } else if (l2_8wide && fp16_exact && nb <= 20) {
         scorer = 1;
         mfma_ks = nb <= 8 ? 8 : nb <= 16 ? 16 : 20;  // bin slots per cell
         best_tw = hogk::kStripW;
@@ -441,7 +504,7 @@ static hog_status create_plan(const hog_plan_desc *descs, int n_img, bool batch,
             int64_t sy = (int64_t)std::floor((double)y * s);
             mapy.push_back((int32_t)std::min<int64_t>(sy, d.height - 1));
         }
-        v.bins_pitch = round_up(lw, 64);
+        v.bins_pitch = soft ? round_up(2 * (int64_t)lw, 128) : round_up(lw, 64);
         v.bins_off = bins_off;
         bins_off = round_up(bins_off + v.bins_pitch * lh, 256);
         // Planes: ii(x, y) at [y * pitch + x]; rows are whole 128-byte lines
@@ -558,6 +621,9 @@ static hog_status create_plan(const hog_plan_desc *descs, int n_img, bool batch,
         items[hogk::KB_BLOCK] = (sp.norm == HOG_NORM_L2 && v.cells_x >= 2 && v.cells_y >= 2)
                                     ? (int64_t)(v.cells_x - 1) * (v.cells_y - 1)
                                     : 0;
+        items[hogk::KB_SPIX] = soft ? (int64_t)v.w * v.h : 0;
+        items[hogk::KB_SROW] = soft ? (int64_t)nb * v.h : 0;
+        items[hogk::KB_SCOL] = soft ? (int64_t)nb * v.ii_pitch : 0;
         for (int k = 0; k < hogk::KB_COUNT; ++k) {
             first[(size_t)k * (L + 1) + l] = (int32_t)totals[k];
             totals[k] += items[k];
@@ -616,6 +682,9 @@ static hog_status create_plan(const hog_plan_desc *descs, int n_img, bool batch,
     pd.block = sp.block;
     pd.norm = sp.norm;
     pd.eps = sp.eps;
+    pd.votes = d0.votes;
+    pd.eps_counts = soft ? sp.eps * HOG_SOFT_QUANTUM : sp.eps;
+    pd.vscale = soft ? 1.0f / HOG_SOFT_QUANTUM : 1.0f;
     pd.feat_dim = dim;
     pd.st_tw = best_tw;
     pd.st_th = best_th;
@@ -715,7 +784,9 @@ extern "C" hog_status hog_bin_map(const hog_plan *plan, const hog_lut *lut, cons
     }
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = timed_launch("bin_map", s, [&] {
-        return hogk::launch_bin_map(plan->dev, lut->dev_half, img, img_pitch, bins, s);
+        return plan->dev.votes == HOG_VOTES_SOFT
+                   ? hogk::launch_bin_map_soft(plan->dev, lut->dev_soft, img, img_pitch, bins, s)
+                   : hogk::launch_bin_map(plan->dev, lut->dev_half, img, img_pitch, bins, s);
     });
     if (e != hipSuccess) return device_fail(e, "bin_map launch");
     return HOG_OK;
@@ -727,6 +798,16 @@ extern "C" hog_status hog_integral(const hog_plan *plan, const uint8_t *bins, vo
     if (!plan || !bins || !ii || !workspace) return fail(HOG_E_INVALID, "NULL argument");
     hipStream_t s = (hipStream_t)stream;
     uint8_t *ws = (uint8_t *)workspace;
+    if (plan->dev.votes == HOG_VOTES_SOFT) {
+        // Weighted planes (row pass, column pass), then every cell cached.
+        hipError_t e = timed_launch("integral_soft", s, [&] {
+            return hogk::launch_soft_integral(plan->dev, bins, (uint32_t *)ii, s);
+        });
+        if (e != hipSuccess) return device_fail(e, "integral_soft launch");
+        e = timed_launch("cells", s, [&] { return hogk::launch_cells(plan->dev, ii, ws, nullptr, s); });
+        if (e != hipSuccess) return device_fail(e, "cells launch");
+        return HOG_OK;
+    }
     hipError_t e = timed_launch("integral_reduce", s, [&] {
         return hogk::launch_int_reduce(plan->dev, bins, ws, s);
     });
@@ -759,7 +840,7 @@ extern "C" hog_status hog_scan_windows(const hog_plan *plan, const void *ii, con
         // Cell histograms from the given planes (four-corner sums).
         e = timed_launch("cells", s, [&] { return hogk::launch_cells(plan->dev, ii, ws, cell_hist, s); });
         if (e != hipSuccess) return device_fail(e, "cells launch");
-    } else if (plan->desc.scan.cell != 8) {
+    } else if (plan->desc.scan.cell != 8 && plan->dev.votes != HOG_VOTES_SOFT) {
         return fail(HOG_E_INVALID, "hog_integral caches cells only for 8-pixel cells; pass ii");
     } else if (cell_hist) {
         // Cell histograms cached by hog_integral in this workspace.
@@ -937,7 +1018,8 @@ static hog_status run_path(const hog_plan *plan, const hog_lut *lut, const uint8
     if (st != HOG_OK) return st;
     st = hog_integral(plan, bins, ii, workspace, stream);
     if (st != HOG_OK) return st;
-    const bool from_planes = plan->desc.scan.cell != 8;
+    // hog_integral caches 8-pixel cells (every cell size with soft votes).
+    const bool from_planes = plan->desc.scan.cell != 8 && plan->dev.votes != HOG_VOTES_SOFT;
     return hog_scan_windows(plan, from_planes ? ii : nullptr, tmpl, bias, scores, nullptr, nullptr,
                             workspace, stream);
 }

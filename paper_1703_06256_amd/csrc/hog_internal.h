@@ -52,6 +52,9 @@ enum {
     KB_CELL,        // threads of the cell kernel: cells
     KB_STILE,       // workgroups of the scorer: window tiles
     KB_BLOCK,       // threads of the block-feature kernel: blocks
+    KB_SPIX,        // soft votes: threads of the bin map, one per pixel
+    KB_SROW,        // soft votes: waves of the row pass, one per (bin, row)
+    KB_SCOL,        // soft votes: threads of the column pass, one per (bin, plane column)
     KB_COUNT
 };
 
@@ -92,7 +95,10 @@ struct PlanDev {
     int32_t channels;
     int32_t n_templates;
     int32_t cell, win_cells_x, win_cells_y, block, norm;
-    float eps;
+    float eps;                 // L2 epsilon in feature units
+    float eps_counts;          // the same in units of the cached cell values
+    float vscale;              // feature units per cached cell unit: 1, or 1 / HOG_SOFT_QUANTUM
+    int32_t votes;             // HOG_VOTES_HARD or HOG_VOTES_SOFT
     int32_t feat_dim;
     int32_t st_tw, st_th;      // scorer tile (windows)
     int32_t scorer;            // 0: vector units; 1: strips (one template per wave); 2: window GEMM (K >= 16)
@@ -117,6 +123,12 @@ hipError_t launch_bin_map(const PlanDev &p, const uint8_t *lut_half, const uint8
                           int64_t img_pitch, uint8_t *bins, hipStream_t stream);
 hipError_t launch_int_reduce(const PlanDev &p, const uint8_t *bins, uint8_t *ws,
                              hipStream_t stream);
+// Soft votes: bin map from the uint16 soft table, and the weighted integral
+// images (row pass, then column pass over the planes).
+hipError_t launch_bin_map_soft(const PlanDev &p, const uint16_t *soft_lut, const uint8_t *img,
+                               int64_t img_pitch, uint8_t *bins, hipStream_t stream);
+hipError_t launch_soft_integral(const PlanDev &p, const uint8_t *bins, uint32_t *ii,
+                                hipStream_t stream);
 hipError_t launch_int_scan(const PlanDev &p, uint8_t *ws, hipStream_t stream);
 hipError_t launch_int_emit(const PlanDev &p, const uint8_t *bins, uint8_t *ws, void *ii,
                            hipStream_t stream);

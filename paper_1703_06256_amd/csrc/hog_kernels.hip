@@ -13,6 +13,7 @@
 //   k_cells           Eq. 6, Sec. 3.3   four-corner cell histograms, cached
 //   k_score           Sec. 3.1, Sec. 4  window features and inner products
 //   k_block_features  (optional output) normalised block vectors
+#include "hog.h"
 #include "hog_internal.h"
 
 #define HOG_MAX_BINS_K 64
@@ -647,6 +648,116 @@ __global__ __launch_bounds__(256) void k_cells(const Level *__restrict__ lv,
     }
 }
 
+// ---------------------------------------------------------------------------
+// Soft votes (Sec. 2's two-bin split, quantised to 1/HOG_SOFT_QUANTUM).
+//
+// Bin map: one thread per pixel of every level. Eq. 1 and the channel choice
+// as in k_bin_map, on the level's nearest-neighbour samples; the soft table
+// entry b0 | w1 << 8 (uint16, read from global memory: 522 KB, L2-resident)
+// is stored for the pixel, 255 for the border and zero gradients.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_bin_map_soft(const Level *__restrict__ lv,
+                                                      const int32_t *__restrict__ first, int n_levels,
+                                                      const int32_t *__restrict__ mapx,
+                                                      const int32_t *__restrict__ mapy,
+                                                      const uint8_t *__restrict__ img, int64_t call_pitch,
+                                                      int channels, const uint16_t *__restrict__ soft,
+                                                      uint8_t *__restrict__ bins)
+{
+    const int g = (int)(blockIdx.x * 256 + threadIdx.x);
+    if (g >= first[n_levels]) return;
+    const int l = find_level(first, n_levels, g);
+    const Level &v = lv[l];
+    const int rel = g - first[l];
+    const int x = rel % v.w, y = rel / v.w;
+    uint16_t e = (uint16_t)kNoBin;
+    if (x >= 1 && x <= v.w - 2 && y >= 1 && y <= v.h - 2) {
+        const int64_t pitch = v.src_pitch > 0 ? v.src_pitch : call_pitch;
+        const uint8_t *src = img + v.src_off;
+        const int32_t *mx = mapx + v.mapx_off, *my = mapy + v.mapy_off;
+        const int64_t xl = (int64_t)mx[x - 1] * channels, xc = (int64_t)mx[x] * channels,
+                      xr = (int64_t)mx[x + 1] * channels;
+        const int64_t ru = (int64_t)my[y - 1] * pitch, rc = (int64_t)my[y] * pitch,
+                      rd = (int64_t)my[y + 1] * pitch;
+        int best = 0, bdx = 0, bdy = 0;
+        for (int c = 0; c < channels; ++c) {
+            const int dx = (int)src[rc + xr + c] - (int)src[rc + xl + c];
+            const int dy = (int)src[rd + xc + c] - (int)src[ru + xc + c];
+            const int m = dx * dx + dy * dy;
+            if (m > best) { best = m; bdx = dx; bdy = dy; }  // ties keep the lower channel
+        }
+        if (best > 0) e = soft[(bdy + 255) * 511 + (bdx + 255)];
+    }
+    *reinterpret_cast<uint16_t *>(bins + v.bins_off + (int64_t)y * v.bins_pitch + 2 * x) = e;
+}
+
+// Weighted integral images, row pass: one wave per (bin n, row y) of every
+// level. A pixel's vote for n is Q - w1 if n = b0, w1 if n = b0 + 1 mod nb
+// (both when nb = 1); the row's inclusive prefix of the votes is stored as
+// plane row y (every column of the pitch: right of the level the prefix
+// stays at its value at column w - 1).
+__global__ __launch_bounds__(256) void k_soft_rows(const Level *__restrict__ lv,
+                                                   const int32_t *__restrict__ first, int n_levels,
+                                                   int nb, const uint8_t *__restrict__ bins,
+                                                   uint32_t *__restrict__ ii)
+{
+    constexpr uint32_t Q = HOG_SOFT_QUANTUM;
+    const int gw = (int)blockIdx.x * 4 + wave_id_in_block();
+    if (gw >= first[n_levels]) return;
+    const int lane = threadIdx.x & 63;
+    const int l = find_level(first, n_levels, gw);
+    const Level &v = lv[l];
+    const int rel = gw - first[l];
+    const int n = rel / v.h, y = rel % v.h;
+    const uint16_t *row = reinterpret_cast<const uint16_t *>(bins + v.bins_off + (int64_t)y * v.bins_pitch);
+    uint32_t *out = ii + v.ii_off + (int64_t)n * v.ii_plane + (int64_t)y * v.ii_pitch;
+    uint32_t carry = 0;
+    for (int x0 = 0; x0 < v.ii_pitch; x0 += 64) {
+        const int x = x0 + lane;
+        const uint32_t e = x < v.w ? (uint32_t)row[x] : (uint32_t)kNoBin;
+        const uint32_t b0 = e & 255u, w1 = e >> 8;
+        uint32_t vote = 0;
+        if (b0 != (uint32_t)kNoBin) {
+            const uint32_t b1 = b0 + 1 == (uint32_t)nb ? 0u : b0 + 1;
+            vote = (b0 == (uint32_t)n ? Q - w1 : 0u) + (b1 == (uint32_t)n ? w1 : 0u);
+        }
+        const uint32_t incl = wave_incl_scan(vote, lane) + carry;
+        if (x < v.ii_pitch) out[x] = incl;
+        carry = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
+    }
+}
+
+// Column pass: one thread per (bin, plane column) of every level adds each
+// row's value to the running column sum and stores it back: Eq. 5.
+__global__ __launch_bounds__(256) void k_soft_cols(const Level *__restrict__ lv,
+                                                   const int32_t *__restrict__ first, int n_levels,
+                                                   uint32_t *__restrict__ ii)
+{
+    const int g = (int)(blockIdx.x * 256 + threadIdx.x);
+    if (g >= first[n_levels]) return;
+    const int l = find_level(first, n_levels, g);
+    const Level &v = lv[l];
+    const int rel = g - first[l];
+    const int n = rel / (int)v.ii_pitch, x = rel % (int)v.ii_pitch;
+    uint32_t *p = ii + v.ii_off + (int64_t)n * v.ii_plane + x;
+    uint32_t acc = 0;
+    int y = 0;
+    for (; y + 8 <= v.h; y += 8) {  // 8 independent loads in flight
+        uint32_t r[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) r[i] = p[(int64_t)(y + i) * v.ii_pitch];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            acc += r[i];
+            p[(int64_t)(y + i) * v.ii_pitch] = acc;
+        }
+    }
+    for (; y < v.h; ++y) {
+        acc += p[(int64_t)y * v.ii_pitch];
+        p[(int64_t)y * v.ii_pitch] = acc;
+    }
+}
+
 // Cell histograms cached by k_int_emit, exported as uint32 [cy][cx][n].
 __global__ __launch_bounds__(256) void k_cache_export(const Level *__restrict__ lv,
                                                       const int32_t *__restrict__ first,
@@ -668,6 +779,7 @@ __global__ __launch_bounds__(256) void k_cache_export(const Level *__restrict__ 
 struct ScoreArgs {
     int nb, wcx, wcy, norm, k, dim, tw, th, nbp;
     float eps;
+    float vscale;  // feature units per cached cell unit
 };
 
 // Load one staged cell (nb floats at hp) into registers.
@@ -731,7 +843,7 @@ __global__ __launch_bounds__(256) void k_score(const Level *__restrict__ lv,
         const int cy = wy0 + r, cx = wx0 + j;
         float val = 0.f;
         if (cy < v.cells_y && cx < v.cells_x)
-            val = (float)cache[cache_index(v, n, cy, cx)];
+            val = (float)cache[cache_index(v, n, cy, cx)] * a.vscale;  // exact: a power of two
         hc[(r * CW + j) * nbp + n] = val;
     }
     __syncthreads();
@@ -1497,6 +1609,29 @@ hipError_t launch_bin_map(const PlanDev &p, const uint8_t *lut_half, const uint8
     return hipGetLastError();
 }
 
+hipError_t launch_bin_map_soft(const PlanDev &p, const uint16_t *soft_lut, const uint8_t *img,
+                               int64_t img_pitch, uint8_t *bins, hipStream_t stream)
+{
+    const int64_t n = p.total[KB_SPIX];
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_bin_map_soft, dim3(blocks_for(n, 256)), dim3(256), 0, stream, p.levels,
+                       first_of(p, KB_SPIX), p.n_levels, p.mapx, p.mapy, img, img_pitch, p.channels, soft_lut,
+                       bins);
+    return hipGetLastError();
+}
+
+hipError_t launch_soft_integral(const PlanDev &p, const uint8_t *bins, uint32_t *ii, hipStream_t stream)
+{
+    if (p.total[KB_SROW] == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_soft_rows, dim3(blocks_for(p.total[KB_SROW], 4)), dim3(256), 0, stream, p.levels,
+                       first_of(p, KB_SROW), p.n_levels, p.n_bins, bins, ii);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_soft_cols, dim3(blocks_for(p.total[KB_SCOL], 256)), dim3(256), 0, stream, p.levels,
+                       first_of(p, KB_SCOL), p.n_levels, ii);
+    return hipGetLastError();
+}
+
 hipError_t launch_int_reduce(const PlanDev &p, const uint8_t *bins, uint8_t *ws, hipStream_t stream)
 {
     const int64_t tiles = p.total[KB_ITILE];
@@ -1612,7 +1747,7 @@ hipError_t launch_score(const PlanDev &p, const uint8_t *ws, const float *tmpl, 
         m.dim = p.feat_dim;
         m.tprep_off = p.tprep_off;
         m.tprep_stride = p.tprep_stride;
-        m.eps = p.eps;
+        m.eps = p.eps_counts;  // the matrix-core scorers work on cell counts
         const unsigned ktiles = (unsigned)((m.k + 31) / 32);
         uint8_t *wsw = const_cast<uint8_t *>(ws);
         switch (p.mfma_ks) {
@@ -1638,7 +1773,7 @@ hipError_t launch_score(const PlanDev &p, const uint8_t *ws, const float *tmpl, 
         m.lds_wave = p.st_lds_bytes / 4;
         m.tprep_off = p.tprep_off;
         m.tprep_stride = p.tprep_stride;
-        m.eps = p.eps;
+        m.eps = p.eps_counts;  // the matrix-core scorers work on cell counts
         const dim3 pgrid((unsigned)m.k), pblock(64 * kStripMaxBX), sgrid(blocks_for(n, 4));
         // The prepared weights are rewritten in the workspace by every call.
         uint8_t *wsw = const_cast<uint8_t *>(ws);
@@ -1671,6 +1806,7 @@ hipError_t launch_score(const PlanDev &p, const uint8_t *ws, const float *tmpl, 
     a.th = p.st_th;
     a.nbp = p.cell_stride;
     a.eps = p.eps;
+    a.vscale = p.vscale;
     const size_t lds = (size_t)p.st_lds_bytes;
     const bool w8 = p.win_cells_x == 8 && p.norm == 1;
     if (w8 && p.n_bins == 8)
@@ -1694,7 +1830,7 @@ hipError_t launch_block_features(const PlanDev &p, const uint8_t *ws, float *blo
     const int64_t n = p.total[KB_BLOCK];
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_block_features, dim3(blocks_for(n, 256)), dim3(256), 0, stream, p.levels,
-                       first_of(p, KB_BLOCK), p.n_levels, p.n_bins, p.eps, ws, block_feat);
+                       first_of(p, KB_BLOCK), p.n_levels, p.n_bins, p.eps_counts, ws, block_feat);
     return hipGetLastError();
 }
 

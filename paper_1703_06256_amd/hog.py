@@ -19,12 +19,15 @@ HOG_OK, HOG_E_INVALID, HOG_E_NOMEM, HOG_E_DEVICE, HOG_E_BUSY, HOG_E_NOT_READY = 
 HOG_NO_BIN = 255
 HOG_NORM_RAW, HOG_NORM_L2 = 0, 1
 HOG_ORIENT_SIGNED, HOG_ORIENT_UNSIGNED = 0, 1
+HOG_VOTES_HARD, HOG_VOTES_SOFT = 0, 1
+HOG_SOFT_QUANTUM = 32
 LUT_SIDE = 511
 
 # Every symbol include/hog.h declares.
 EXPORTS = (
     "hog_last_error", "hog_lut_fill_host", "hog_lut_build", "hog_lut_free", "hog_lut_bins",
-    "hog_lut_host", "hog_lut_fill_host_ex", "hog_lut_build_ex", "hog_lut_orientation", "hog_plan_create", "hog_plan_create_batch", "hog_plan_images",
+    "hog_lut_host", "hog_lut_fill_host_ex", "hog_lut_build_ex", "hog_lut_orientation",
+    "hog_lut_fill_soft_host", "hog_plan_create", "hog_plan_create_batch", "hog_plan_images",
     "hog_plan_get_image", "hog_plan_destroy", "hog_plan_get_sizes",
     "hog_plan_get_level", "hog_bin_map", "hog_integral", "hog_scan_windows", "hog_run",
     "hog_graph_create", "hog_graph_launch", "hog_graph_destroy", "hog_plan_get_tiles",
@@ -51,7 +54,7 @@ class PlanDesc(ctypes.Structure):
                 ("channels", ctypes.c_int32), ("n_bins", ctypes.c_int32),
                 ("max_levels", ctypes.c_int32), ("scale", ctypes.c_double),
                 ("n_templates", ctypes.c_int32), ("scan", ScanParams),
-                ("plane_bits", ctypes.c_int32)]
+                ("plane_bits", ctypes.c_int32), ("votes", ctypes.c_int32)]
 
 
 class LevelInfo(ctypes.Structure):
@@ -127,6 +130,7 @@ def load_library():
         "hog_lut_fill_host_ex": ([i32, i32, vp], i32),
         "hog_lut_build_ex": ([i32, i32, ctypes.POINTER(vp)], i32),
         "hog_lut_orientation": ([vp], i32),
+        "hog_lut_fill_soft_host": ([i32, i32, vp], i32),
         "hog_lut_free": ([vp], None),
         "hog_lut_bins": ([vp], i32),
         "hog_lut_host": ([vp], vp),
@@ -204,6 +208,14 @@ def hog_lut_fill_host(n_bins: int, orientation: int = HOG_ORIENT_SIGNED) -> np.n
     return out
 
 
+def hog_lut_fill_soft_host(n_bins: int, orientation: int = HOG_ORIENT_SIGNED):
+    """Host-only soft-vote table: (b0, w1) as two uint8[dy+255][dx+255]."""
+    out = np.empty((LUT_SIDE, LUT_SIDE), np.uint16)
+    _check(load_library().hog_lut_fill_soft_host(int(n_bins), int(orientation),
+                                                 out.ctypes.data_as(ctypes.c_void_p)))
+    return (out & 255).astype(np.uint8), (out >> 8).astype(np.uint8)
+
+
 class Lut:
     """Library-owned lookup table (host + device copies)."""
 
@@ -236,9 +248,9 @@ def hog_lut_build(n_bins: int, orientation: int = HOG_ORIENT_SIGNED) -> Lut:
 
 def make_desc(width, height, channels=1, n_bins=8, max_levels=1, scale=1.0, n_templates=1,
               cell=8, win_cells_x=8, win_cells_y=16, block=2, norm=HOG_NORM_RAW,
-              eps=1e-3, plane_bits=32) -> PlanDesc:
+              eps=1e-3, plane_bits=32, votes=HOG_VOTES_HARD) -> PlanDesc:
     return PlanDesc(width, height, channels, n_bins, max_levels, scale, n_templates,
-                    ScanParams(cell, win_cells_x, win_cells_y, block, norm, eps), plane_bits)
+                    ScanParams(cell, win_cells_x, win_cells_y, block, norm, eps), plane_bits, votes)
 
 
 def ii_dtype(plan: "Plan"):
@@ -536,10 +548,15 @@ class Graph:
 
 # ----------------------------------------------------------------------------
 # Views of one level inside the plan-layout buffers (host numpy arrays).
-def level_bins(plan: Plan, bins_host: np.ndarray, l: int) -> np.ndarray:
+def level_bins(plan: Plan, bins_host: np.ndarray, l: int):
+    """uint8[h][w] bins of level l; soft votes: the pair (b0, w1) of uint8[h][w]."""
     li = plan.levels[l]
     a = bins_host[li.bins_offset: li.bins_offset + li.bins_pitch * li.height]
-    return a.reshape(li.height, li.bins_pitch)[:, :li.width]
+    a = a.reshape(li.height, li.bins_pitch)
+    if plan.desc.votes == HOG_VOTES_SOFT:
+        e = a[:, :2 * li.width].reshape(li.height, li.width, 2)
+        return e[:, :, 0].copy(), e[:, :, 1].copy()
+    return a[:, :li.width]
 
 
 def level_planes(plan: Plan, ii_host: np.ndarray, l: int) -> np.ndarray:

@@ -57,6 +57,8 @@ BAD_DESCS = [
     dict(norm=hog.HOG_NORM_L2, eps=float("nan")),
     dict(plane_bits=12), dict(plane_bits=64), dict(plane_bits=-8),
     dict(plane_bits=8, cell=16), dict(plane_bits=8, cell=32),
+    dict(votes=2), dict(votes=-1), dict(votes=1, plane_bits=16), dict(votes=1, plane_bits=8),
+    dict(votes=1, width=32767, height=32767),
 ]
 
 
@@ -107,7 +109,7 @@ def test_lut_mirror_rule_behind_the_half_table(nb, orientation):
 
 
 @pytest.mark.parametrize("bad", [dict(n_bins=9), dict(channels=1), dict(n_templates=2),
-                                 dict(norm=hog.HOG_NORM_L2, cell=4), dict(plane_bits=16)])
+                                 dict(norm=hog.HOG_NORM_L2, cell=4), dict(plane_bits=16), dict(votes=1)])
 def test_batch_plan_rejects_mismatched_images(bad):
     base = dict(width=320, height=240, channels=3, n_bins=8)
     other = dict(base, width=200, height=150)
@@ -162,3 +164,11 @@ def test_binding_leaves_one_hip_runtime_in_the_process():
     r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
     assert r.returncode == 0, r.stderr
     assert r.stdout.strip() == "1"
+
+
+@pytest.mark.parametrize("orientation", [hog.HOG_ORIENT_SIGNED, hog.HOG_ORIENT_UNSIGNED])
+@pytest.mark.parametrize("nb", list(range(1, 65)))
+def test_soft_host_table_equals_oracle(nb, orientation):
+    b0, w1 = hog.hog_lut_fill_soft_host(nb, orientation)
+    ob0, ow1 = oracle.soft_table(nb, orientation == hog.HOG_ORIENT_UNSIGNED)
+    assert np.array_equal(b0, ob0) and np.array_equal(w1, ow1)

@@ -1,0 +1,89 @@
+"""Soft votes (Sec. 2's two-bin split, quantised to 1/32 of a pixel): the
+soft bin maps, the weighted integral images and the cell vote sums equal the
+oracle's bit for bit on every level; block features and window scores (from
+the vote sums divided by 32) are within the stated tolerance, on the vector
+scorer (raw features, 12-pixel cells), the strip and the window-GEMM matrix-core
+scorers (whose fp16 inputs stay exact: 8 x 8 cells hold at most 2048 units)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1703_06256_amd import hog
+from paper_1703_06256_amd import inputs
+
+from hog_cases import check_features, check_scores, oracle_params, run_gpu, templates_for
+
+pytestmark = pytest.mark.gpu
+
+CASES = [
+    dict(width=320, height=240, channels=1, n_bins=8),
+    dict(width=800, height=600, channels=3, n_bins=9, norm=hog.HOG_NORM_L2),
+    dict(width=333, height=277, channels=3, n_bins=18, max_levels=0, scale=1.2, norm=hog.HOG_NORM_L2),
+    dict(width=640, height=480, channels=3, n_bins=8, n_templates=32, norm=hog.HOG_NORM_L2),
+    dict(width=300, height=260, channels=3, n_bins=9, cell=12, win_cells_x=5, win_cells_y=8,
+         norm=hog.HOG_NORM_L2),
+    dict(width=200, height=170, channels=1, n_bins=1),
+]
+
+
+def _level_img(img, plan, l):
+    li = plan.levels[l]
+    return img if l == 0 else oracle.resize_nn(img, li.scale, li.width, li.height)
+
+
+@pytest.mark.parametrize("case", range(len(CASES)))
+@pytest.mark.parametrize("orientation", [hog.HOG_ORIENT_SIGNED, hog.HOG_ORIENT_UNSIGNED])
+def test_soft_votes_equal_oracle(case, orientation):
+    kw = CASES[case]
+    unsigned = orientation == hog.HOG_ORIENT_UNSIGNED
+    desc = hog.make_desc(votes=hog.HOG_VOTES_SOFT, **kw)
+    img = inputs.synth_image(kw["width"], kw["height"], kw["channels"], 7900 + case)
+    tmpl, bias = templates_for(desc, 7950 + case)
+    l2 = desc.scan.norm == hog.HOG_NORM_L2
+    plan, out = run_gpu(desc, img, tmpl, bias, cell_hist=True, block_feat=l2, orientation=orientation)
+    nb, p = desc.n_bins, oracle_params(desc)
+    for l in range(plan.sizes.n_levels):
+        li = plan.levels[l]
+        b0, w1 = oracle.soft_bin_map(_level_img(img, plan, l), nb, unsigned)
+        gb0, gw1 = hog.level_bins(plan, out["bins"], l)
+        assert np.array_equal(gb0, b0) and np.array_equal(gw1, w1), f"soft bins, level {l}"
+        planes = hog.level_planes(plan, out["ii"], l)
+        assert np.array_equal(planes, oracle.soft_integral(b0, w1, nb)[:, 1:, 1:]), f"planes, level {l}"
+        if li.cells_x and li.cells_y:
+            want_cells = oracle.soft_cell_hist(b0, w1, nb, desc.scan.cell)
+            assert np.array_equal(hog.level_cells(plan, out["cells"], l), want_cells), f"cells, level {l}"
+        if not li.windows_x:
+            continue
+        rng = np.random.default_rng(l + 10 * case)
+        n = min(50, li.windows_x * li.windows_y)
+        idx = rng.choice(li.windows_x * li.windows_y, size=n, replace=False)
+        ref, absterm, wxs, wys = oracle.soft_score_windows(b0, w1, nb, p, tmpl, bias,
+                                                           idx % li.windows_x, idx // li.windows_x)
+        check_scores(hog.level_scores(plan, out["scores"], l)[wys, wxs, :], ref, absterm)
+        if l2 and l == 0:
+            cells = oracle.soft_cell_hist(b0, w1, nb, desc.scan.cell) / oracle.SOFT_Q
+            blocks = hog.level_blocks(plan, out["blocks"], l)  # [by][bx][4][nb]
+            nbx, nby = desc.scan.win_cells_x - 1, desc.scan.win_cells_y - 1
+            for i in range(min(len(wxs), 16)):
+                g = blocks[wys[i]:wys[i] + nby, wxs[i]:wxs[i] + nbx].reshape(-1)
+                check_features(g, oracle.features_from_cells(cells, p, int(wxs[i]), int(wys[i])))
+
+
+def test_soft_votes_with_cells_from_planes_and_hog_run():
+    """hog_run on a soft plan, and cells recomputed from the planes, give the
+    same scores as the three calls with the cache."""
+    import torch
+    kw = CASES[1]
+    desc = hog.make_desc(votes=hog.HOG_VOTES_SOFT, **kw)
+    img = inputs.synth_image(kw["width"], kw["height"], kw["channels"], 7990)
+    tmpl, bias = templates_for(desc, 7991)
+    plan, out = run_gpu(desc, img, tmpl, bias, cell_hist=False, block_feat=False)
+    _, out2 = run_gpu(desc, img, tmpl, bias, cell_hist=False, block_feat=False, cells_from_planes=True)
+    assert np.array_equal(out["scores"].view(np.uint32), out2["scores"].view(np.uint32))
+    lut = hog.hog_lut_build(desc.n_bins)
+    buf = hog.Buffers(plan)
+    img_t = torch.from_numpy(img.reshape(-1)).cuda()
+    hog.hog_run(plan, lut, img_t, torch.from_numpy(tmpl.reshape(-1)).cuda(), torch.from_numpy(bias).cuda(), buf)
+    torch.cuda.synchronize()
+    n = plan.sizes.score_elems
+    assert np.array_equal(buf.scores.cpu().numpy()[:n].view(np.uint32), out["scores"][:n].view(np.uint32))

@@ -476,3 +476,112 @@ def test_resize_nn_closed_forms():
     assert np.array_equal(oracle.resize_nn(img, 2.0, 30, 20), img[::2, ::2])
     out = oracle.resize_nn(img, 1.5, 40, 26)
     assert np.array_equal(out[5, 7], img[7, 10])  # floor(5*1.5)=7, floor(7*1.5)=10
+
+
+# --------------------------------------------------------------------------
+# Soft votes (Sec. 2's two-bin split, quantised).
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("n_bins,unsigned", [(1, False), (4, False), (8, False), (9, True), (18, False),
+                                             (18, True), (64, False)])
+def test_soft_vote_centre_of_mass_is_the_angle(n_bins, unsigned):
+    """Independent of the oracle's arithmetic: the two shares sum to one
+    pixel, and their centre of mass (b0 + 1/2 + w1/Q bin widths) is the
+    gradient's angle, within the quantisation (half a unit) -- checked
+    against x87 long double atan2 over the whole table."""
+    q = oracle.SOFT_Q
+    b0, w1 = oracle.soft_table(n_bins, unsigned)
+    zero = (DX == 0) & (DY == 0)
+    assert np.all(b0[zero] == NO_BIN) and np.all(w1[zero] == 0)
+    assert np.all(b0[~zero] < n_bins) and np.all(w1[~zero] <= q)
+    ld = np.longdouble
+    pi = np.arctan(ld(1)) * 4
+    rng_ = pi if unsigned else 2 * pi
+    t = np.arctan2(DY.astype(ld), DX.astype(ld))
+    t = np.where(t < 0, t + rng_, t)
+    width = rng_ / n_bins
+    centre = (b0.astype(ld) + ld(0.5) + w1.astype(ld) / q) * width
+    d = np.mod(centre - t + rng_ / 2, rng_) - rng_ / 2  # signed difference mod the range
+    assert np.abs(d[~zero]).max() <= width / (2 * q) + ld(1e-12)
+
+
+def test_soft_vote_axes_and_centres():
+    # a gradient on a bin centre gives all of its vote to that bin
+    assert oracle.soft_vote(1, 1, 4) == (0, 0)            # 45 deg, centre of bin 0 of 4
+    assert oracle.soft_vote(-1, 1, 4) == (1, 0)
+    # on a sector edge it is split evenly
+    assert oracle.soft_vote(1, 0, 8) == (7, 16)            # 0 deg: between bins 7 and 0
+    assert oracle.soft_vote(0, 1, 4) == (0, 16)            # 90 deg: between bins 0 and 1
+    # 90 of 180 degrees with 9 bins of 20: the centre of bin 4, whole vote there
+    assert oracle.soft_vote(0, 5, 9, unsigned=True) == (4, 0)
+    assert oracle.soft_vote(0, -5, 9, unsigned=True) == (4, 0)
+    # 0 degrees unsigned: between the last bin and bin 0
+    assert oracle.soft_vote(-3, 0, 9, unsigned=True) == (8, 16)
+    assert oracle.soft_vote(0, 0, 8) == (NO_BIN, 0)
+
+
+def test_soft_integral_closed_form_and_invariants():
+    q = oracle.SOFT_Q
+    h, w, nb = 13, 21, 5
+    b0 = np.full((h, w), 3, np.uint8)
+    w1 = np.full((h, w), 10, np.uint8)
+    p = oracle.soft_integral(b0, w1, nb).astype(np.int64)
+    x = np.arange(w + 1)[None, :]
+    y = np.arange(h + 1)[:, None]
+    assert np.array_equal(p[3], (q - 10) * x * y) and np.array_equal(p[4], 10 * x * y)
+    assert not p[[0, 1, 2]].any()
+    rng = np.random.default_rng(5)
+    b0 = rng.integers(0, nb, (h, w)).astype(np.uint8)
+    w1 = rng.integers(0, q + 1, (h, w)).astype(np.uint8)
+    b0[rng.random((h, w)) < 0.2] = NO_BIN
+    p = oracle.soft_integral(b0, w1, nb).astype(np.int64)
+    assert p[:, h, w].sum() == q * np.count_nonzero(b0 != NO_BIN)
+    d = p[:, 1:, 1:] - p[:, :-1, 1:] - p[:, 1:, :-1] + p[:, :-1, :-1]  # per-pixel votes
+    for n in range(nb):
+        want = np.where(b0 == n, q - w1.astype(np.int64), 0) + np.where((b0 + 1) % nb == n, w1, 0)
+        want = np.where(b0 == NO_BIN, 0, want)
+        assert np.array_equal(d[n], want)
+
+
+def test_soft_cell_hist_equals_four_corners_and_centred_votes_equal_hard_counts():
+    rng = np.random.default_rng(9)
+    h, w, nb = 48, 72, 7
+    b0 = rng.integers(0, nb, (h, w)).astype(np.uint8)
+    w1 = rng.integers(0, oracle.SOFT_Q + 1, (h, w)).astype(np.uint8)
+    b0[rng.random((h, w)) < 0.1] = NO_BIN
+    p = oracle.soft_integral(b0, w1, nb).astype(np.int64)
+    ch = oracle.soft_cell_hist(b0, w1, nb, 8).astype(np.int64)
+    c = p[:, ::8][:, :, ::8]
+    four = c[:, 1:, 1:] + c[:, :-1, :-1] - c[:, :-1, 1:] - c[:, 1:, :-1]
+    assert np.array_equal(four.transpose(1, 2, 0), ch)
+    # a diagonal ramp puts every interior gradient on the 45-degree centre of bin 0 of 4
+    yy, xx = np.mgrid[0:40, 0:48]
+    img = (2 * xx + 2 * yy).astype(np.uint8)
+    sb0, sw1 = oracle.soft_bin_map(img, 4)
+    hard = oracle.bin_map(img, 4)
+    assert np.array_equal(oracle.soft_cell_hist(sb0, sw1, 4, 8),
+                          oracle.SOFT_Q * oracle.cell_hist(hard, 4, 8))
+
+
+@pytest.mark.parametrize("norm,cell,wcx,wcy", [(0, 8, 8, 16), (1, 8, 8, 16), (1, 6, 5, 7), (0, 4, 3, 9)])
+def test_features_from_cells_equal_the_brute_force_window_feature(norm, cell, wcx, wcy):
+    """The numpy feature builder the soft-vote scores use, fed hard cell
+    counts, equals the C oracle's brute-force window feature (pinned above)
+    element for element; and soft votes that all sit on bin centres (a
+    diagonal ramp, 4 bins) give Q times the hard counts, hence the same
+    features once divided by Q."""
+    p = ScanParams(cell=cell, win_cells_x=wcx, win_cells_y=wcy, norm=norm)
+    rng = np.random.default_rng(norm * 10 + cell)
+    h, w, nb = 140, 90, 6
+    bins = rng.integers(0, nb, (h, w)).astype(np.uint8)
+    bins[rng.random((h, w)) < 0.2] = NO_BIN
+    cells = oracle.cell_hist(bins, nb, cell)
+    mx, my = (w // cell) - wcx, (h // cell) - wcy
+    for wx, wy in [(0, 0), (min(1, mx), min(2, my)), (mx, my)]:
+        assert np.allclose(oracle.features_from_cells(cells, p, wx, wy),
+                           oracle.window_feature(bins, nb, p, wx, wy), rtol=1e-14, atol=0)
+    yy, xx = np.mgrid[0:140, 0:90]
+    img = (2 * xx + 2 * yy).astype(np.uint8)
+    sb0, sw1 = oracle.soft_bin_map(img, 4)
+    soft_cells = oracle.soft_cell_hist(sb0, sw1, 4, cell) / oracle.SOFT_Q
+    assert np.allclose(oracle.features_from_cells(soft_cells, p, 1, 1),
+                       oracle.window_feature(oracle.bin_map(img, 4), 4, p, 1, 1), rtol=1e-14, atol=0)
