@@ -60,8 +60,12 @@ WORKLOADS = {
                                   scale=1.05, norm=1, seed=1002, tseed=9002, plane_bits=16),
     "pyramid_1920x1080_u8": dict(width=1920, height=1080, channels=3, n_bins=18, max_levels=0,
                                  scale=1.05, norm=1, seed=1002, tseed=9002, plane_bits=8),
+    # The pyramid workload with two-bin soft votes (quantised to 1/32 pixel):
+    # weighted uint32 planes from a row pass and a column pass.
+    "pyramid_1920x1080_soft": dict(width=1920, height=1080, channels=3, n_bins=18, max_levels=0,
+                                   scale=1.05, norm=1, seed=1002, tseed=9002, votes=1),
 }
-KERNELS = ("bin_map", "integral_reduce", "integral_scan", "integral_emit", "cells", "score")
+KERNELS = ("bin_map", "integral_reduce", "integral_scan", "integral_emit", "integral_soft", "cells", "score")
 
 
 def kernel_sources_sha256():
@@ -186,14 +190,15 @@ def main():
         sizes = batch_sizes(wl)
         descs = [hog.make_desc(w, h, channels=wl["channels"], n_bins=wl["n_bins"],
                                max_levels=wl["max_levels"], scale=wl["scale"], norm=wl["norm"],
-                               n_templates=K, plane_bits=wl.get("plane_bits", 32)) for w, h in sizes]
+                               n_templates=K, plane_bits=wl.get("plane_bits", 32),
+                               votes=wl.get("votes", 0)) for w, h in sizes]
         plan = hog.Plan(descs, batch=True)
         imgs = [inputs.synth_image(w, h, wl["channels"], wl["seed"] + j) for j, (w, h) in enumerate(sizes)]
         img_t = torch.from_numpy(hog.pack_images(plan, imgs)).cuda()
     else:
         desc = hog.make_desc(wl["width"], wl["height"], channels=wl["channels"], n_bins=wl["n_bins"],
                              max_levels=wl["max_levels"], scale=wl["scale"], norm=wl["norm"],
-                             n_templates=K, plane_bits=wl.get("plane_bits", 32))
+                             n_templates=K, plane_bits=wl.get("plane_bits", 32), votes=wl.get("votes", 0))
         plan = hog.Plan(desc)
         img = inputs.synth_image(wl["width"], wl["height"], wl["channels"], wl["seed"])
         img_t = torch.from_numpy(img.reshape(-1)).cuda()
@@ -265,7 +270,12 @@ def main():
     # Roofline of the dominant kernel: the integral-image writer moves, per
     # processed pixel, N_b plane elements of ii_elem_bytes (4 for uint32
     # planes) written and 1 byte of bins read.
-    emit_bytes = sz.total_pixels * (sz.ii_elem_bytes * wl["n_bins"] + 1)
+    # With soft votes the writer is the weighted integral (two passes over
+    # the planes); its algorithmic bytes are the planes written once and the
+    # 2-byte soft bins read.
+    soft = wl.get("votes", 0) == 1
+    emit_kernel = "integral_soft" if soft else "integral_emit"
+    emit_bytes = sz.total_pixels * (sz.ii_elem_bytes * wl["n_bins"] + (2 if soft else 1))
     extra = {}
     if batch:
         # The same images through 64 single-image plans, launched one image
@@ -299,11 +309,11 @@ def main():
             extra[name] = dict(ms=round(t, 4), mpixel_per_s=round(sz.total_pixels / (t * 1e3), 1))
         extra["speedup_vs_per_image"] = round(extra["per_image"]["ms"] / ms_per_step, 3)
         del singles
-    emit_us = kern_us.get("integral_emit", float("nan"))
+    emit_us = kern_us.get(emit_kernel, float("nan"))
     achieved = emit_bytes / (emit_us * 1e-6) / 1e9
-    roofline = dict(bound="hbm", kernel="integral_emit", achieved=round(achieved, 1),
+    roofline = dict(bound="hbm", kernel=emit_kernel, achieved=round(achieved, 1),
                     peak=HBM_PEAK_GBS, unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4),
-                    traffic=measured_traffic(args.workload, tiles.bin_chunk),
+                    traffic=None if soft else measured_traffic(args.workload, tiles.bin_chunk),
                     algorithmic_bytes_per_launch=emit_bytes)
 
     if args.copy_calibration:
@@ -347,6 +357,7 @@ def main():
             "norm": "l2" if wl["norm"] else "raw",
             "templates": K,
             "plane_bits": 8 * sz.ii_elem_bytes,
+            "votes": "soft (1/32)" if soft else "hard",
             "launch": "captured HIP graph of the batch plan" if batch else "three calls per step",
             "tiles": {"bin_chunk": tiles.bin_chunk, "score_rows": tiles.score_rows, "how": "autotuned"},
         },

@@ -416,6 +416,7 @@ hog_status hog_wait_any(hog_server *server, uint64_t *tickets, int cap, int64_t 
 /* bracketed by a pair of HIP events recorded on the launch stream; totals  */
 /* accumulate per kernel name until hog_timing_reset. Not thread-safe.      */
 /* Names: "bin_map", "integral_reduce", "integral_scan", "integral_emit",   */
+/* "integral_soft" (soft votes),                                             */
 /* "cells", "score", "block_features".                                       */
 /* ------------------------------------------------------------------------ */
 hog_status hog_timing_enable(int on);
