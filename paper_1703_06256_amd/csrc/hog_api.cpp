@@ -580,9 +580,9 @@ static hog_status create_plan(const hog_plan_desc *descs, int n_img, bool batch,
         ws_off = tprep_off + tprep_stride * K;
     } else if (scorer == 2) {
         // per tile of 32 templates: fragments [by][bx][step][hi|lo][lane] of
-        // 16 bytes, then 32 scales
+        // 16 bytes, then 32 scales (float), then their exponents (int)
         const int64_t frags = (int64_t)(sp.win_cells_y - 1) * hogk::kStripMaxBX * (mfma_ks / 4) * 2 * 64;
-        tprep_stride = round_up(frags * 16 + 32 * 4, 256);
+        tprep_stride = round_up(frags * 16 + 32 * 8, 256);
         tprep_off = round_up(ws_off, 256);
         ws_off = tprep_off + tprep_stride * ((K + 31) / 32);
     }

@@ -1317,52 +1317,65 @@ typedef float float16v_t __attribute__((ext_vector_type(16)));
 // One workgroup (1024 threads) per tile of 32 templates: per-template scales,
 // then the A fragments [p][s][hi|lo][lane] (lane: template kk0 + lane % 32,
 // features 16 s + 8 (lane / 32) .. + 7 of the block at position p).
+// Per template of the tile: the power of two that brings its max |T| into
+// [2^14, 2^15) -- exponent e (int) and scale 2^-e (float), stored after the
+// fragments. One workgroup of 1024 threads (32 per template) per tile.
+__global__ __launch_bounds__(1024) void k_score_prep_wg_scale(WgArgs a, const float *__restrict__ tmpl,
+                                                              uint8_t *__restrict__ ws, int64_t frag_bytes)
+{
+    const int kt = (int)blockIdx.x, kk0 = 32 * kt;
+    const int tid = threadIdx.x, tk = tid >> 5, sub = tid & 31;  // 32 threads per template
+    float mx = 0.f;
+    if (kk0 + tk < a.k) {
+        const float *t = tmpl + (int64_t)(kk0 + tk) * a.dim;
+        for (int i = sub; i < a.dim; i += 32) mx = fmaxf(mx, fabsf(t[i]));
+    }
+#pragma unroll
+    for (int d = 16; d >= 1; d >>= 1) mx = fmaxf(mx, __shfl_xor(mx, d));
+    int ex = 0;
+    if (mx > 0.f) (void)frexpf(mx, &ex);  // mx = f 2^ex, f in [0.5, 1)
+    const int e = mx > 0.f ? 15 - ex : 0;
+    uint8_t *tp = ws + a.tprep_off + (int64_t)kt * a.tprep_stride + frag_bytes;
+    if (sub == 0) {
+        reinterpret_cast<float *>(tp)[tk] = ldexpf(1.f, -e);
+        reinterpret_cast<int *>(tp + 32 * 4)[tk] = e;
+    }
+}
+
+// The A fragments [p][s][hi|lo][lane] of a tile (lane: template kk0 + lane %
+// 32, features 16 s + 8 (lane / 32) .. + 7 of the block at position p),
+// scaled by 2^e and split into fp16 hi + lo: one fragment per thread, over
+// as many workgroups as the tile has fragments / 256.
 template <int NBP>
-__global__ __launch_bounds__(1024) void k_score_prep_wg(WgArgs a, const float *__restrict__ tmpl,
-                                                        uint8_t *__restrict__ ws)
+__global__ __launch_bounds__(256) void k_score_prep_wg(WgArgs a, const float *__restrict__ tmpl,
+                                                       uint8_t *__restrict__ ws)
 {
     constexpr int KS = NBP / 4;  // 16-feature steps per block
-    __shared__ int sh_e[32];
-    const int kt = (int)blockIdx.x, kk0 = 32 * kt;
-    const int tid = threadIdx.x;
-    {
-        const int tk = tid >> 5, sub = tid & 31;  // 32 threads per template
-        float mx = 0.f;
-        if (kk0 + tk < a.k) {
-            const float *t = tmpl + (int64_t)(kk0 + tk) * a.dim;
-            for (int i = sub; i < a.dim; i += 32) mx = fmaxf(mx, fabsf(t[i]));
-        }
-#pragma unroll
-        for (int d = 16; d >= 1; d >>= 1) mx = fmaxf(mx, __shfl_xor(mx, d));
-        int ex = 0;
-        if (mx > 0.f) (void)frexpf(mx, &ex);  // mx = f 2^ex, f in [0.5, 1)
-        if (sub == 0) sh_e[tk] = mx > 0.f ? 15 - ex : 0;
-    }
-    __syncthreads();
+    const int kt = (int)blockIdx.y, kk0 = 32 * kt;
     uint8_t *tp = ws + a.tprep_off + (int64_t)kt * a.tprep_stride;
     const int n_frag = a.nby * kStripMaxBX * KS * 2 * 64;
-    for (int f = tid; f < n_frag; f += 1024) {
-        const int lane = f & 63, rest = f >> 6;
-        const int hl = rest & 1, s = (rest >> 1) % KS, pos = (rest >> 1) / KS;
-        const int by = pos / kStripMaxBX, bx = pos % kStripMaxBX;
-        const int kk = kk0 + (lane & 31), h = lane >> 5;
-        const int e = sh_e[lane & 31];
-        half8_t out;
+    const int f = (int)(blockIdx.x * 256 + threadIdx.x);
+    if (f >= n_frag) return;
+    const int *ex = reinterpret_cast<const int *>(tp + (int64_t)n_frag * 16 + 32 * 4);
+    const int lane = f & 63, rest = f >> 6;
+    const int hl = rest & 1, s = (rest >> 1) % KS, pos = (rest >> 1) / KS;
+    const int by = pos / kStripMaxBX, bx = pos % kStripMaxBX;
+    const int kk = kk0 + (lane & 31), h = lane >> 5;
+    const int e = ex[lane & 31];
+    half8_t out;
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            const int kf = 16 * s + 8 * h + i;
-            const int w = kf / (2 * NBP), rem = kf % (2 * NBP);
-            const int u = rem / NBP, bin = rem % NBP;
-            float val = 0.f;
-            if (kk < a.k && bin < a.nb)
-                val = tmpl[(int64_t)kk * a.dim + ((by * kStripMaxBX + bx) * 4 + w * 2 + u) * a.nb + bin];
-            const float sv = ldexpf(val, e);
-            const _Float16 hi = (_Float16)sv;
-            out[i] = hl == 0 ? hi : (_Float16)(sv - (float)hi);
-        }
-        *reinterpret_cast<half8_t *>(tp + (int64_t)f * 16) = out;
+    for (int i = 0; i < 8; ++i) {
+        const int kf = 16 * s + 8 * h + i;
+        const int w = kf / (2 * NBP), rem = kf % (2 * NBP);
+        const int u = rem / NBP, bin = rem % NBP;
+        float val = 0.f;
+        if (kk < a.k && bin < a.nb)
+            val = tmpl[(int64_t)kk * a.dim + ((by * kStripMaxBX + bx) * 4 + w * 2 + u) * a.nb + bin];
+        const float sv = ldexpf(val, e);
+        const _Float16 hi = (_Float16)sv;
+        out[i] = hl == 0 ? hi : (_Float16)(sv - (float)hi);
     }
-    if (tid < 32) reinterpret_cast<float *>(tp + (int64_t)n_frag * 16)[tid] = ldexpf(1.f, -sh_e[tid]);
+    *reinterpret_cast<half8_t *>(tp + (int64_t)f * 16) = out;
 }
 
 template <int NBP>
@@ -1750,13 +1763,17 @@ hipError_t launch_score(const PlanDev &p, const uint8_t *ws, const float *tmpl, 
         m.eps = p.eps_counts;  // the matrix-core scorers work on cell counts
         const unsigned ktiles = (unsigned)((m.k + 31) / 32);
         uint8_t *wsw = const_cast<uint8_t *>(ws);
+        // Fragments per tile: [by][bx][step][hi|lo][lane].
+        const int64_t n_frag = (int64_t)m.nby * kStripMaxBX * (p.mfma_ks / 4) * 2 * 64;
+        const dim3 fgrid(blocks_for(n_frag, 256), ktiles);
+        hipLaunchKernelGGL(k_score_prep_wg_scale, dim3(ktiles), dim3(1024), 0, stream, m, tmpl, wsw, n_frag * 16);
         switch (p.mfma_ks) {
         case 8:
-            hipLaunchKernelGGL(k_score_prep_wg<8>, dim3(ktiles), dim3(1024), 0, stream, m, tmpl, wsw);
+            hipLaunchKernelGGL(k_score_prep_wg<8>, fgrid, dim3(256), 0, stream, m, tmpl, wsw);
             hipLaunchKernelGGL(k_score_wgemm<8>, grid, block, 0, stream, p.levels, f, p.n_levels, m, ws, bias, scores);
             break;
         case 16:
-            hipLaunchKernelGGL(k_score_prep_wg<16>, dim3(ktiles), dim3(1024), 0, stream, m, tmpl, wsw);
+            hipLaunchKernelGGL(k_score_prep_wg<16>, fgrid, dim3(256), 0, stream, m, tmpl, wsw);
             hipLaunchKernelGGL(k_score_wgemm<16>, grid, block, 0, stream, p.levels, f, p.n_levels, m, ws, bias, scores);
             break;
         default: return hipErrorInvalidValue;
