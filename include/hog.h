@@ -351,6 +351,10 @@ typedef struct {
     int32_t max_queue;       /* requests waiting; hog_submit returns HOG_E_BUSY beyond */
     int32_t streams;         /* batches in flight at once, 1..8 */
     int32_t orientation;     /* HOG_ORIENT_SIGNED or HOG_ORIENT_UNSIGNED */
+    int32_t votes;           /* HOG_VOTES_HARD or HOG_VOTES_SOFT (hog_plan_desc) */
+    int32_t plane_bits;      /* integral-image element of the server's own buffers
+                                (hog_plan_desc; 0 = 32). The scores do not depend on it:
+                                8 or 16 cut the device footprint per request. */
     int32_t copy_threads;    /* helper threads that split hog_submit's copies of large
                                 images with the caller, 0..32 (0: the caller alone) */
 } hog_server_config;

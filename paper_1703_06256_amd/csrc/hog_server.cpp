@@ -186,6 +186,8 @@ hog_plan_desc desc_for(const hog_server_config &c, int w, int h)
     d.scale = c.scale;
     d.n_templates = c.n_templates;
     d.scan = c.scan;
+    d.votes = c.votes;
+    d.plane_bits = c.plane_bits;
     return d;
 }
 

@@ -88,6 +88,7 @@ class ServerConfig(ctypes.Structure):
                 ("max_slots", ctypes.c_int32),
                 ("max_batch", ctypes.c_int32), ("max_queue", ctypes.c_int32),
                 ("streams", ctypes.c_int32), ("orientation", ctypes.c_int32),
+                ("votes", ctypes.c_int32), ("plane_bits", ctypes.c_int32),
                 ("copy_threads", ctypes.c_int32)]
 
 
@@ -453,7 +454,7 @@ class Server:
                  scale=1.0, cell=8, win_cells_x=8, win_cells_y=16, block=2, norm=HOG_NORM_L2,
                  eps=1e-3, max_width=1920, max_height=1080, memory_budget=1 << 30, host_budget=None,
                  max_slots=16, max_batch=8, max_queue=1024, streams=3, copy_threads=4,
-                 orientation=HOG_ORIENT_SIGNED):
+                 orientation=HOG_ORIENT_SIGNED, votes=HOG_VOTES_HARD, plane_bits=32):
         if host_budget is None:
             host_budget = 4 * max_batch * max_width * max_height * channels
         self._tmpl = np.ascontiguousarray(tmpl, np.float32)
@@ -464,7 +465,7 @@ class Server:
         cfg = ServerConfig(channels, n_bins, self.k, max_levels, scale,
                            ScanParams(cell, win_cells_x, win_cells_y, block, norm, eps),
                            max_width, max_height, memory_budget, host_budget, max_slots, max_batch,
-                           max_queue, streams, orientation, copy_threads)
+                           max_queue, streams, orientation, votes, plane_bits, copy_threads)
         h = ctypes.c_void_p()
         _check(load_library().hog_server_create(
             ctypes.byref(cfg), self._tmpl.ctypes.data_as(ctypes.c_void_p),

@@ -159,3 +159,57 @@ def test_graph_replays_equal_eager(k):
     for x, y in zip(_snap(plan, other), _snap(plan, buf)):
         assert np.array_equal(x, y)
     g.destroy()
+
+
+def test_full_batch64_in_the_benchmarked_launch():
+    """The batched workload at full size, launched as the benchmark launches
+    it: 64 RGB images of seeded uniform sizes in 320..1920 x 240..1080 with
+    1.1 pyramids (1,088 levels), N_b = 8, L2, K = 32, tiles autotuned, one
+    captured graph replayed. Sampled images and levels: bins, planes and
+    cells bit for bit; scores on sampled windows within tolerance. Only the
+    checked levels are copied back."""
+    import os
+    import sys
+    import torch
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    import bench
+    wl = bench.WORKLOADS["batch64"]
+    sizes = bench.batch_sizes(wl)
+    descs = [hog.make_desc(w, h, channels=3, n_bins=8, max_levels=0, scale=1.1, n_templates=32,
+                           norm=hog.HOG_NORM_L2) for w, h in sizes]
+    plan = hog.Plan(descs, batch=True)
+    assert plan.sizes.n_levels == 1088
+    imgs = [inputs.synth_image(w, h, 3, wl["seed"] + j) for j, (w, h) in enumerate(sizes)]
+    packed = torch.from_numpy(hog.pack_images(plan, imgs)).cuda()
+    tmpl, bias = inputs.synth_templates(32, plan.sizes.feature_dim, wl["tseed"])
+    tt, bt = torch.from_numpy(tmpl.reshape(-1)).cuda(), torch.from_numpy(bias).cuda()
+    lut = hog.hog_lut_build(8)
+    buf = hog.Buffers(plan, cell_hist=False, block_feat=False)
+    hog.autotune(plan, lut, packed, tt, bt, buf)
+    buf.scores.zero_()
+    g = hog.Graph(plan, lut, packed, tt, bt, buf)
+    g.launch()
+    torch.cuda.synchronize()
+    scores = buf.scores.cpu().numpy()
+    p = oracle_params(descs[0])
+    rng = np.random.default_rng(64)
+    for i in sorted(rng.choice(64, size=4, replace=False)):
+        info = plan.images[i]
+        ls = sorted({info.first_level, info.first_level + info.n_levels // 2,
+                     info.first_level + info.n_levels - 1})
+        for l in ls:
+            li = plan.levels[l]
+            want = oracle_level_bins(imgs[i], plan, l, info.first_level)
+            bins = buf.bins[li.bins_offset: li.bins_offset + li.bins_pitch * li.height].cpu().numpy()
+            assert np.array_equal(bins.reshape(li.height, li.bins_pitch)[:, :li.width], want), f"image {i} level {l}"
+            ii = buf.ii[li.ii_offset: li.ii_offset + li.ii_plane_stride * 8].cpu().numpy().view(np.uint32)
+            planes = ii.reshape(8, li.ii_plane_stride)[:, :li.ii_pitch * li.height]
+            planes = planes.reshape(8, li.height, li.ii_pitch)[:, :, :li.width]
+            assert np.array_equal(planes, oracle.integral(want, 8)[:, 1:, 1:]), f"image {i} level {l} planes"
+            if li.windows_x:
+                n = min(40, li.windows_x * li.windows_y)
+                idx = rng.choice(li.windows_x * li.windows_y, size=n, replace=False)
+                ref, absterm, _, wxs, wys = oracle.score_windows(want, 8, p, tmpl, bias, idx % li.windows_x,
+                                                                 idx // li.windows_x)
+                check_scores(hog.level_scores(plan, scores, l)[wys, wxs, :], ref, absterm)
+    g.destroy()

@@ -245,3 +245,27 @@ def test_large_images_copied_in_pieces_equal_alone():
         want, _, _ = _alone(im, tmpl, bias)
         assert np.array_equal(res[t][0].view(np.uint32), want.view(np.uint32))
     srv.close()
+
+
+@pytest.mark.parametrize("votes,plane_bits", [(hog.HOG_VOTES_HARD, 8), (hog.HOG_VOTES_SOFT, 32)])
+def test_server_votes_and_plane_bits(votes, plane_bits):
+    """The server's plans take the configured votes and plane element; the
+    scores equal a single-image plan of the same description (and, for
+    8-bit planes, the uint32 plan: the scores never read the planes)."""
+    import torch
+    tmpl, bias = _templates()
+    srv = hog.Server(tmpl, bias, max_width=800, max_height=600, memory_budget=512 << 20,
+                     votes=votes, plane_bits=plane_bits)
+    sizes = [(320, 240), (641, 480), (800, 600)]
+    imgs = [inputs.synth_image(w, h, 3, 5800 + j) for j, (w, h) in enumerate(sizes)]
+    tickets = [srv.submit(im) for im in imgs]
+    res = _wait(srv, tickets, [_cap(w, h) for w, h in sizes])
+    srv.close()
+    for t, im, (w, h) in zip(tickets, imgs, sizes):
+        for pb in {plane_bits, 32}:
+            desc = hog.make_desc(w, h, channels=3, n_bins=8, n_templates=K, norm=hog.HOG_NORM_L2,
+                                 votes=votes, plane_bits=pb)
+            plan, out = run_gpu(desc, im, tmpl, bias, cell_hist=False, block_feat=False)
+            want = hog.level_scores(plan, out["scores"], 0).reshape(-1)
+            assert np.array_equal(res[t][0].view(np.uint32), want.view(np.uint32)), (w, h, pb)
+    torch.cuda.synchronize()
