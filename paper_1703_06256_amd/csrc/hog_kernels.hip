@@ -231,8 +231,10 @@ __global__ __launch_bounds__(64) void k_int_reduce(const Level *__restrict__ lv,
 {
     // One wave per tile, every bin at once. LDS: the tile's bins (row stride
     // kRedStride bytes, 17 dwords, so lane-per-row reads hit distinct banks),
-    // then per-lane histograms colh[n][lane] and rowh[n][lane]: each lane
-    // only ever adds to its own slots.
+    // then per-lane histograms colh and rowh: each lane only ever adds to its
+    // own slots. A count never exceeds 64, so four bins share a dword, one
+    // byte each (bin n: dword n / 4, byte n % 4), which halves the LDS and
+    // lets more tiles run at once.
     constexpr int kRedStride = 68;
     extern __shared__ __attribute__((aligned(16))) uint32_t red_smem[];
     const int tile = (int)blockIdx.x;
@@ -243,12 +245,16 @@ __global__ __launch_bounds__(64) void k_int_reduce(const Level *__restrict__ lv,
     const int t = tile - first[l];
     const int tx = t % v.tiles_x, ty = t / v.tiles_x;
     uint8_t *tb = reinterpret_cast<uint8_t *>(red_smem);
+    const int nw = (nb + 3) >> 2;  // dwords per lane and histogram
     uint32_t *colh = red_smem + kTile * kRedStride / 4;
-    uint32_t *rowh = colh + nb * 64;
-    for (int n = 0; n < nb; ++n) {
+    uint32_t *rowh = colh + nw * 64;
+    for (int n = 0; n < nw; ++n) {
         colh[n * 64 + lane] = 0u;
         rowh[n * 64 + lane] = 0u;
     }
+    auto slot = [](int b) { return (b >> 2) * 64; };
+    auto one = [](int b) { return 1u << (8 * (b & 3)); };
+    auto count = [&](const uint32_t *h, int b, int ln) { return (h[slot(b) + ln] >> (8 * (b & 3))) & 255u; };
     {
         typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
         const __amdgpu_buffer_rsrc_t bsrc = buffer_rsrc(bins + v.bins_off, (uint32_t)(v.bins_pitch * v.h));
@@ -275,7 +281,7 @@ __global__ __launch_bounds__(64) void k_int_reduce(const Level *__restrict__ lv,
     if (xin) {
         for (int r = 0; r < nrows; ++r) {
             const int b = tb[r * kRedStride + lane];
-            if (b < nb) atomicAdd(&colh[b * 64 + lane], 1u);
+            if (b < nb) atomicAdd(&colh[slot(b) + lane], one(b));
         }
     }
     // Row counts: lane = row.
@@ -286,7 +292,7 @@ __global__ __launch_bounds__(64) void k_int_reduce(const Level *__restrict__ lv,
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const int b = (int)((d >> (8 * e)) & 255u);
-                if (4 * k + e < ncols && b < nb) atomicAdd(&rowh[b * 64 + lane], 1u);
+                if (4 * k + e < ncols && b < nb) atomicAdd(&rowh[slot(b) + lane], one(b));
             }
         }
     }
@@ -298,18 +304,19 @@ __global__ __launch_bounds__(64) void k_int_reduce(const Level *__restrict__ lv,
     uint8_t *coltot = ws + v.ws_coltot + (int64_t)ty * nb * wp + x;
     uint32_t *tiletot = reinterpret_cast<uint32_t *>(ws + v.ws_tiletot) + ((int64_t)ty * v.tiles_x + tx) * nb;
     for (int n = 0; n < nb; ++n) {
-        if (lane < nrows) rowtot[(int64_t)n * hp] = (uint8_t)rowh[n * 64 + lane];
-        coltot[(int64_t)n * wp] = (uint8_t)colh[n * 64 + lane];
+        if (lane < nrows) rowtot[(int64_t)n * hp] = (uint8_t)count(rowh, n, lane);
+        coltot[(int64_t)n * wp] = (uint8_t)count(colh, n, lane);
     }
     // Lane n < nb sums bin n's 64 column counts.
     if (lane < nb) {
         typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
-        const u32x4 *cp = reinterpret_cast<const u32x4 *>(colh + lane * 64);
+        const u32x4 *cp = reinterpret_cast<const u32x4 *>(colh + slot(lane));
+        const uint32_t sh = 8u * (lane & 3);
         uint32_t t = 0;
 #pragma unroll
         for (int k = 0; k < 16; ++k) {
             const u32x4 q4 = cp[k];
-            t += (q4[0] + q4[1]) + (q4[2] + q4[3]);
+            t += (((q4[0] >> sh) & 255u) + ((q4[1] >> sh) & 255u)) + (((q4[2] >> sh) & 255u) + ((q4[3] >> sh) & 255u));
         }
         tiletot[lane] = t;
     }
@@ -1649,7 +1656,7 @@ hipError_t launch_int_reduce(const PlanDev &p, const uint8_t *bins, uint8_t *ws,
 {
     const int64_t tiles = p.total[KB_ITILE];
     if (tiles == 0) return hipSuccess;
-    const size_t lds = (size_t)kTile * 68 + (size_t)p.n_bins * 64 * 4 * 2;
+    const size_t lds = (size_t)kTile * 68 + (size_t)((p.n_bins + 3) / 4) * 64 * 4 * 2;
     hipLaunchKernelGGL(k_int_reduce, dim3((unsigned)tiles), dim3(64), lds, stream, p.levels,
                        first_of(p, KB_ITILE), p.n_levels, p.n_bins, bins, ws);
     return hipGetLastError();
