@@ -133,39 +133,47 @@ __global__ __launch_bounds__(1024) void k_bin_map(const Level *__restrict__ lv,
         const int x = gx * kBinCols - 1 + lane;
         const bool col_ok = x >= 0 && x < W;
         const int32_t *my = mapy + v.mapy_off;
-        const int sx = col_ok ? mapx[v.mapx_off + x] : 0;
+        const int y0 = gy * kBinRows;
+        if (C == 3 && src_w < 2) {  // wave-uniform: a 1-pixel-wide image has no interior
+            if (lane >= 1 && lane <= kBinCols && col_ok)
+                for (int i = 0; i < kBinRows && y0 + i < H; ++i)
+                    bins[v.bins_off + (int64_t)(y0 + i) * v.bins_pitch + x] = (uint8_t)kNoBin;
+            continue;
+        }
+        // Every lane and row loads from a clamped, valid position, so the
+        // loads carry no condition and are all in flight at once; samples
+        // outside the level are zeroed afterwards.
+        const int sx = mapx[v.mapx_off + min(max(x, 0), W - 1)];
         // Byte offset of the sample in a source row; for RGB a 4-byte read that
         // stays inside the row (it starts one byte early at the last column).
         int64_t coff = sx;
         uint32_t shift = 0;
-        bool can_load = col_ok;
         if constexpr (C == 3) {
             const bool last = sx >= src_w - 1;
             coff = last ? 3 * (int64_t)sx - 1 : 3 * (int64_t)sx;
             shift = last ? 8u : 0u;
-            can_load = col_ok && src_w >= 2;  // a 1-pixel-wide image has no interior
         }
         const uint8_t *colp = img + v.src_off + coff;
-        const int y0 = gy * kBinRows;
 
         uint32_t smp[kBinRows + 2];
 #pragma unroll
         for (int i = 0; i < kBinRows + 2; ++i) {
-            const int r = y0 - 1 + i;
-            uint32_t val = 0;
-            if (r >= 0 && r < H) {
-                const uint8_t *p = colp + (int64_t)my[r] * pitch;
-                if (can_load) {
-                    if constexpr (C == 1) {
-                        val = *p;
-                    } else {
-                        uint32_t w4;
-                        __builtin_memcpy(&w4, p, 4);
-                        val = (w4 >> shift) & 0xFFFFFFu;
-                    }
-                }
+            const int r = min(max(y0 - 1 + i, 0), H - 1);
+            const uint8_t *p = colp + (int64_t)my[r] * pitch;
+            if constexpr (C == 1) {
+                smp[i] = *p;
+            } else {
+                uint32_t w4;
+                __builtin_memcpy(&w4, p, 4);
+                smp[i] = w4;
             }
-            smp[i] = val;
+        }
+#pragma unroll
+        for (int i = 0; i < kBinRows + 2; ++i) {
+            const int r = y0 - 1 + i;
+            uint32_t val = smp[i];
+            if constexpr (C == 3) val = (val >> shift) & 0xFFFFFFu;
+            smp[i] = (col_ok && r >= 0 && r < H) ? val : 0u;
         }
         const bool col_interior = x >= 1 && x <= W - 2;
         uint8_t b[kBinRows];
