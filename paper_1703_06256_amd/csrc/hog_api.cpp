@@ -541,6 +541,11 @@ static hog_status create_plan(const hog_plan_desc *descs, int n_img, bool batch,
         }
         v.ws_cache = ws_off;
         ws_off = round_up(ws_off + (int64_t)nb * v.cby * v.cbx * 64 * 2, 256);
+        v.ws_stot = 0;
+        if (soft) {  // segment vote totals, uint32 [nb][h][tiles_x]
+            v.ws_stot = ws_off;
+            ws_off = round_up(ws_off + (int64_t)nb * v.h * v.tiles_x * 4, 256);
+        }
 
         info.width = lw;
         info.height = lh;
@@ -621,9 +626,9 @@ static hog_status create_plan(const hog_plan_desc *descs, int n_img, bool batch,
         items[hogk::KB_BLOCK] = (sp.norm == HOG_NORM_L2 && v.cells_x >= 2 && v.cells_y >= 2)
                                     ? (int64_t)(v.cells_x - 1) * (v.cells_y - 1)
                                     : 0;
-        items[hogk::KB_SPIX] = soft ? (int64_t)v.w * v.h : 0;
-        items[hogk::KB_SROW] = soft ? (int64_t)nb * v.h : 0;
-        items[hogk::KB_SCOL] = soft ? (int64_t)nb * v.ii_pitch : 0;
+        items[hogk::KB_SSEG] = soft ? (int64_t)v.h * v.tiles_x : 0;
+        items[hogk::KB_SSCAN] = soft ? (int64_t)nb * v.h : 0;
+        items[hogk::KB_SEMIT] = soft ? (int64_t)nb * v.tiles_x : 0;
         for (int k = 0; k < hogk::KB_COUNT; ++k) {
             first[(size_t)k * (L + 1) + l] = (int32_t)totals[k];
             totals[k] += items[k];
@@ -801,7 +806,7 @@ extern "C" hog_status hog_integral(const hog_plan *plan, const uint8_t *bins, vo
     if (plan->dev.votes == HOG_VOTES_SOFT) {
         // Weighted planes (row pass, column pass), then every cell cached.
         hipError_t e = timed_launch("integral_soft", s, [&] {
-            return hogk::launch_soft_integral(plan->dev, bins, (uint32_t *)ii, s);
+            return hogk::launch_soft_integral(plan->dev, bins, ws, (uint32_t *)ii, s);
         });
         if (e != hipSuccess) return device_fail(e, "integral_soft launch");
         e = timed_launch("cells", s, [&] { return hogk::launch_cells(plan->dev, ii, ws, nullptr, s); });

@@ -19,6 +19,7 @@
 #define HOG_MAX_BINS_K 64
 
 #include <algorithm>
+#include <type_traits>
 
 namespace hogk {
 namespace {
@@ -99,7 +100,11 @@ __device__ __forceinline__ uint32_t from_right_lane(uint32_t v)
 // the rows above and below. All samples are loaded first, then every lookup
 // is made, then lanes 1..62 store their bins.
 // ---------------------------------------------------------------------------
-template <int C>
+//
+// Soft votes (SOFT): the same walk; the lookup is the uint16 soft-table
+// entry b0 | w1 << 8 (522 KB, read through L2; no LDS table), stored as two
+// bytes per pixel.
+template <int C, bool SOFT>
 __global__ __launch_bounds__(1024) void k_bin_map(const Level *__restrict__ lv,
                                                   const int32_t *__restrict__ first, int n_levels,
                                                   const int32_t *__restrict__ mapx,
@@ -107,16 +112,19 @@ __global__ __launch_bounds__(1024) void k_bin_map(const Level *__restrict__ lv,
                                                   const uint8_t *__restrict__ img, int64_t call_pitch,
                                                   int nb,
                                                   const uint8_t *__restrict__ lut_half,
+                                                  const uint16_t *__restrict__ soft,
                                                   uint8_t *__restrict__ bins)
 {
-    __shared__ __attribute__((aligned(16))) uint8_t lut[kLutHalfBytes];
-    {
+    const uint8_t *lut = nullptr;
+    if constexpr (!SOFT) {
+        __shared__ __attribute__((aligned(16))) uint8_t lut_lds[kLutHalfBytes];
         typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
         const u32x4 *src = reinterpret_cast<const u32x4 *>(lut_half);
-        u32x4 *dst = reinterpret_cast<u32x4 *>(lut);
+        u32x4 *dst = reinterpret_cast<u32x4 *>(lut_lds);
         for (int i = threadIdx.x; i < kLutHalfBytes / 16; i += blockDim.x) dst[i] = src[i];
+        __syncthreads();
+        lut = lut_lds;
     }
-    __syncthreads();
 
     const int lane = threadIdx.x & 63;
     const int n_items = first[n_levels];
@@ -136,8 +144,13 @@ __global__ __launch_bounds__(1024) void k_bin_map(const Level *__restrict__ lv,
         const int y0 = gy * kBinRows;
         if (C == 3 && src_w < 2) {  // wave-uniform: a 1-pixel-wide image has no interior
             if (lane >= 1 && lane <= kBinCols && col_ok)
-                for (int i = 0; i < kBinRows && y0 + i < H; ++i)
-                    bins[v.bins_off + (int64_t)(y0 + i) * v.bins_pitch + x] = (uint8_t)kNoBin;
+                for (int i = 0; i < kBinRows && y0 + i < H; ++i) {
+                    if constexpr (SOFT)
+                        *reinterpret_cast<uint16_t *>(bins + v.bins_off + (int64_t)(y0 + i) * v.bins_pitch + 2 * x) =
+                            (uint16_t)kNoBin;
+                    else
+                        bins[v.bins_off + (int64_t)(y0 + i) * v.bins_pitch + x] = (uint8_t)kNoBin;
+                }
             continue;
         }
         // Every lane and row loads from a clamped, valid position, so the
@@ -176,7 +189,8 @@ __global__ __launch_bounds__(1024) void k_bin_map(const Level *__restrict__ lv,
             smp[i] = (col_ok && r >= 0 && r < H) ? val : 0u;
         }
         const bool col_interior = x >= 1 && x <= W - 2;
-        uint8_t b[kBinRows];
+        typedef typename std::conditional<SOFT, uint16_t, uint8_t>::type bin_t;
+        bin_t b[kBinRows];
 #pragma unroll
         for (int i = 0; i < kBinRows; ++i) {
             const int y = y0 + i;
@@ -191,17 +205,23 @@ __global__ __launch_bounds__(1024) void k_bin_map(const Level *__restrict__ lv,
                 if (m > best) { best = m; bdx = dx; bdy = dy; }  // ties keep the lower channel
             }
             const bool ok = col_interior && y >= 1 && y <= H - 2 && best > 0;
-            const int ady = bdy < 0 ? -bdy : bdy;
-            const uint32_t e = lut[ok ? ady * 511 + (bdx + 255) : 0];
-            const uint32_t half_bin = e & 63u;
-            const uint32_t bin = bdy < 0 ? (uint32_t)(nb - 1) - half_bin + (e >> 6) : half_bin;
-            b[i] = ok ? (uint8_t)bin : (uint8_t)kNoBin;
+            if constexpr (SOFT) {
+                const uint16_t e = soft[ok ? (bdy + 255) * 511 + (bdx + 255) : 0];
+                b[i] = ok ? e : (uint16_t)kNoBin;
+            } else {
+                const int ady = bdy < 0 ? -bdy : bdy;
+                const uint32_t e = lut[ok ? ady * 511 + (bdx + 255) : 0];
+                const uint32_t half_bin = e & 63u;
+                const uint32_t bin = bdy < 0 ? (uint32_t)(nb - 1) - half_bin + (e >> 6) : half_bin;
+                b[i] = ok ? (uint8_t)bin : (uint8_t)kNoBin;
+            }
         }
         const bool writer = lane >= 1 && lane <= kBinCols && col_ok;
-        uint8_t *out = bins + v.bins_off + x;
+        bin_t *out = reinterpret_cast<bin_t *>(bins + v.bins_off) + x;
+        const int64_t pitch_e = v.bins_pitch / (int64_t)sizeof(bin_t);
 #pragma unroll
         for (int i = 0; i < kBinRows; ++i)
-            if (writer && y0 + i < H) out[(int64_t)(y0 + i) * v.bins_pitch] = b[i];
+            if (writer && y0 + i < H) out[(int64_t)(y0 + i) * pitch_e] = b[i];
     }
 }
 
@@ -340,6 +360,13 @@ __global__ __launch_bounds__(64) void k_int_reduce(const Level *__restrict__ lv,
 struct ScanRanges {
     int rows_blocks, cols_blocks;  // blocks of the first two kinds; the rest are tiles
 };
+
+// Compiler-only ordering point for wave-private LDS traffic.
+__device__ __forceinline__ void lds_order()
+{
+    __builtin_amdgcn_wave_barrier();
+    asm volatile("" ::: "memory");
+}
 
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v, int lane)
 {
@@ -664,112 +691,132 @@ __global__ __launch_bounds__(256) void k_cells(const Level *__restrict__ lv,
 }
 
 // ---------------------------------------------------------------------------
-// Soft votes (Sec. 2's two-bin split, quantised to 1/HOG_SOFT_QUANTUM).
-//
-// Bin map: one thread per pixel of every level. Eq. 1 and the channel choice
-// as in k_bin_map, on the level's nearest-neighbour samples; the soft table
-// entry b0 | w1 << 8 (uint16, read from global memory: 522 KB, L2-resident)
-// is stored for the pixel, 255 for the border and zero gradients.
+// Soft votes (Sec. 2's two-bin split, quantised to 1/HOG_SOFT_QUANTUM):
+// weighted integral images in three passes, the hard path's structure with
+// vote weights in place of unit counts. A pixel with soft entry b0 | w1 << 8
+// gives Q - w1 to bin b0 and w1 to bin b0 + 1 mod nb (both to bin 0 when
+// nb = 1).
+//   1. k_soft_segtot: per 64-column segment s of row y, each bin's vote total
+//      (an LDS histogram per wave), into the workspace [n][y][s];
+//   2. k_soft_rowscan: per (bin, row), those totals become their exclusive
+//      prefix along the row: the votes left of each segment;
+//   3. k_soft_emit: per (bin, segment), one wave walks the rows top down;
+//      lane = column. Row y's prefix inside the segment is a wave scan of the
+//      votes, plus the votes left of the segment; adding it to the lane's
+//      running column sum gives ii(x, y), written once.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_bin_map_soft(const Level *__restrict__ lv,
+__device__ __forceinline__ uint32_t soft_vote_for(uint32_t e, int n, int nb)
+{
+    constexpr uint32_t Q = HOG_SOFT_QUANTUM;
+    const uint32_t b0 = e & 255u, w1 = e >> 8;
+    if (b0 == (uint32_t)kNoBin) return 0u;
+    const uint32_t b1 = b0 + 1 == (uint32_t)nb ? 0u : b0 + 1;
+    return (b0 == (uint32_t)n ? Q - w1 : 0u) + (b1 == (uint32_t)n ? w1 : 0u);
+}
+
+__global__ __launch_bounds__(256) void k_soft_segtot(const Level *__restrict__ lv,
+                                                     const int32_t *__restrict__ first, int n_levels,
+                                                     int nb, const uint8_t *__restrict__ bins,
+                                                     uint8_t *__restrict__ ws)
+{
+    constexpr uint32_t Q = HOG_SOFT_QUANTUM;
+    __shared__ uint32_t hist[4][64];
+    const int wid = wave_id_in_block(), lane = threadIdx.x & 63;
+    const int gw = (int)blockIdx.x * 4 + wid;
+    if (gw >= first[n_levels]) return;  // whole wave; no workgroup barrier below
+    const int l = find_level(first, n_levels, gw);
+    const Level &v = lv[l];
+    const int rel = gw - first[l];
+    const int sg = rel % v.tiles_x, y = rel / v.tiles_x;
+    uint32_t *h = hist[wid];
+    h[lane] = 0u;
+    lds_order();
+    const int x = sg * kTile + lane;
+    const uint16_t *row = reinterpret_cast<const uint16_t *>(bins + v.bins_off + (int64_t)y * v.bins_pitch);
+    const uint32_t e = x < v.w ? (uint32_t)row[x] : (uint32_t)kNoBin;
+    const uint32_t b0 = e & 255u, w1 = e >> 8;
+    if (b0 != (uint32_t)kNoBin) {
+        const uint32_t b1 = b0 + 1 == (uint32_t)nb ? 0u : b0 + 1;
+        if (w1 < Q) atomicAdd(&h[b0], Q - w1);
+        if (w1 > 0) atomicAdd(&h[b1], w1);
+    }
+    lds_order();
+    uint32_t *tot = reinterpret_cast<uint32_t *>(ws + v.ws_stot);
+    if (lane < nb) tot[((int64_t)lane * v.h + y) * v.tiles_x + sg] = h[lane];
+}
+
+__global__ __launch_bounds__(256) void k_soft_rowscan(const Level *__restrict__ lv,
                                                       const int32_t *__restrict__ first, int n_levels,
-                                                      const int32_t *__restrict__ mapx,
-                                                      const int32_t *__restrict__ mapy,
-                                                      const uint8_t *__restrict__ img, int64_t call_pitch,
-                                                      int channels, const uint16_t *__restrict__ soft,
-                                                      uint8_t *__restrict__ bins)
+                                                      uint8_t *__restrict__ ws)
 {
     const int g = (int)(blockIdx.x * 256 + threadIdx.x);
     if (g >= first[n_levels]) return;
     const int l = find_level(first, n_levels, g);
     const Level &v = lv[l];
-    const int rel = g - first[l];
-    const int x = rel % v.w, y = rel / v.w;
-    uint16_t e = (uint16_t)kNoBin;
-    if (x >= 1 && x <= v.w - 2 && y >= 1 && y <= v.h - 2) {
-        const int64_t pitch = v.src_pitch > 0 ? v.src_pitch : call_pitch;
-        const uint8_t *src = img + v.src_off;
-        const int32_t *mx = mapx + v.mapx_off, *my = mapy + v.mapy_off;
-        const int64_t xl = (int64_t)mx[x - 1] * channels, xc = (int64_t)mx[x] * channels,
-                      xr = (int64_t)mx[x + 1] * channels;
-        const int64_t ru = (int64_t)my[y - 1] * pitch, rc = (int64_t)my[y] * pitch,
-                      rd = (int64_t)my[y + 1] * pitch;
-        int best = 0, bdx = 0, bdy = 0;
-        for (int c = 0; c < channels; ++c) {
-            const int dx = (int)src[rc + xr + c] - (int)src[rc + xl + c];
-            const int dy = (int)src[rd + xc + c] - (int)src[ru + xc + c];
-            const int m = dx * dx + dy * dy;
-            if (m > best) { best = m; bdx = dx; bdy = dy; }  // ties keep the lower channel
+    const int rel = g - first[l];  // = n * h + y
+    uint32_t *t = reinterpret_cast<uint32_t *>(ws + v.ws_stot) + (int64_t)rel * v.tiles_x;
+    uint32_t acc = 0;
+    int sg = 0;
+    for (; sg + 8 <= v.tiles_x; sg += 8) {
+        uint32_t c[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) c[i] = t[sg + i];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            t[sg + i] = acc;
+            acc += c[i];
         }
-        if (best > 0) e = soft[(bdy + 255) * 511 + (bdx + 255)];
     }
-    *reinterpret_cast<uint16_t *>(bins + v.bins_off + (int64_t)y * v.bins_pitch + 2 * x) = e;
+    for (; sg < v.tiles_x; ++sg) {
+        const uint32_t c = t[sg];
+        t[sg] = acc;
+        acc += c;
+    }
 }
 
-// Weighted integral images, row pass: one wave per (bin n, row y) of every
-// level. A pixel's vote for n is Q - w1 if n = b0, w1 if n = b0 + 1 mod nb
-// (both when nb = 1); the row's inclusive prefix of the votes is stored as
-// plane row y (every column of the pitch: right of the level the prefix
-// stays at its value at column w - 1).
-__global__ __launch_bounds__(256) void k_soft_rows(const Level *__restrict__ lv,
+__global__ __launch_bounds__(256) void k_soft_emit(const Level *__restrict__ lv,
                                                    const int32_t *__restrict__ first, int n_levels,
                                                    int nb, const uint8_t *__restrict__ bins,
+                                                   const uint8_t *__restrict__ ws,
                                                    uint32_t *__restrict__ ii)
 {
-    constexpr uint32_t Q = HOG_SOFT_QUANTUM;
+    constexpr int kRows = 16;  // bin rows loaded ahead
     const int gw = (int)blockIdx.x * 4 + wave_id_in_block();
     if (gw >= first[n_levels]) return;
     const int lane = threadIdx.x & 63;
     const int l = find_level(first, n_levels, gw);
     const Level &v = lv[l];
     const int rel = gw - first[l];
-    const int n = rel / v.h, y = rel % v.h;
-    const uint16_t *row = reinterpret_cast<const uint16_t *>(bins + v.bins_off + (int64_t)y * v.bins_pitch);
-    uint32_t *out = ii + v.ii_off + (int64_t)n * v.ii_plane + (int64_t)y * v.ii_pitch;
-    uint32_t carry = 0;
-    for (int x0 = 0; x0 < v.ii_pitch; x0 += 64) {
-        const int x = x0 + lane;
-        const uint32_t e = x < v.w ? (uint32_t)row[x] : (uint32_t)kNoBin;
-        const uint32_t b0 = e & 255u, w1 = e >> 8;
-        uint32_t vote = 0;
-        if (b0 != (uint32_t)kNoBin) {
-            const uint32_t b1 = b0 + 1 == (uint32_t)nb ? 0u : b0 + 1;
-            vote = (b0 == (uint32_t)n ? Q - w1 : 0u) + (b1 == (uint32_t)n ? w1 : 0u);
-        }
-        const uint32_t incl = wave_incl_scan(vote, lane) + carry;
-        if (x < v.ii_pitch) out[x] = incl;
-        carry = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
-    }
-}
-
-// Column pass: one thread per (bin, plane column) of every level adds each
-// row's value to the running column sum and stores it back: Eq. 5.
-__global__ __launch_bounds__(256) void k_soft_cols(const Level *__restrict__ lv,
-                                                   const int32_t *__restrict__ first, int n_levels,
-                                                   uint32_t *__restrict__ ii)
-{
-    const int g = (int)(blockIdx.x * 256 + threadIdx.x);
-    if (g >= first[n_levels]) return;
-    const int l = find_level(first, n_levels, g);
-    const Level &v = lv[l];
-    const int rel = g - first[l];
-    const int n = rel / (int)v.ii_pitch, x = rel % (int)v.ii_pitch;
-    uint32_t *p = ii + v.ii_off + (int64_t)n * v.ii_plane + x;
+    const int n = rel / v.tiles_x, sg = rel % v.tiles_x;
+    const int x = sg * kTile + lane;
+    const bool xin = x < v.w, store = x < v.ii_pitch;
+    const int xc = min(x, v.w - 1);
+    const uint32_t *tot = reinterpret_cast<const uint32_t *>(ws + v.ws_stot) + (int64_t)n * v.h * v.tiles_x + sg;
+    const uint8_t *brow = bins + v.bins_off + 2 * (int64_t)xc;
+    uint32_t *out = ii + v.ii_off + (int64_t)n * v.ii_plane + x;
     uint32_t acc = 0;
-    int y = 0;
-    for (; y + 8 <= v.h; y += 8) {  // 8 independent loads in flight
-        uint32_t r[8];
+    for (int y0 = 0; y0 < v.h; y0 += kTile) {
+        // Lane i holds the votes left of the segment in row y0 + i.
+        const uint32_t cv = y0 + lane < v.h ? tot[(int64_t)(y0 + lane) * v.tiles_x] : 0u;
+        const int y1 = min(y0 + kTile, v.h);
+        int y = y0;
+        for (; y + kRows <= y1; y += kRows) {
+            uint32_t e[kRows];
 #pragma unroll
-        for (int i = 0; i < 8; ++i) r[i] = p[(int64_t)(y + i) * v.ii_pitch];
+            for (int i = 0; i < kRows; ++i) e[i] = *reinterpret_cast<const uint16_t *>(brow + (int64_t)(y + i) * v.bins_pitch);
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            acc += r[i];
-            p[(int64_t)(y + i) * v.ii_pitch] = acc;
+            for (int i = 0; i < kRows; ++i) {
+                const uint32_t vote = xin ? soft_vote_for(e[i], n, nb) : 0u;
+                acc += wave_incl_scan(vote, lane) + (uint32_t)__builtin_amdgcn_readlane((int)cv, y + i - y0);
+                if (store) out[(int64_t)(y + i) * v.ii_pitch] = acc;
+            }
         }
-    }
-    for (; y < v.h; ++y) {
-        acc += p[(int64_t)y * v.ii_pitch];
-        p[(int64_t)y * v.ii_pitch] = acc;
+        for (; y < y1; ++y) {
+            const uint32_t e = *reinterpret_cast<const uint16_t *>(brow + (int64_t)y * v.bins_pitch);
+            const uint32_t vote = xin ? soft_vote_for(e, n, nb) : 0u;
+            acc += wave_incl_scan(vote, lane) + (uint32_t)__builtin_amdgcn_readlane((int)cv, y - y0);
+            if (store) out[(int64_t)y * v.ii_pitch] = acc;
+        }
     }
 }
 
@@ -1001,13 +1048,6 @@ struct StripShape {
     static constexpr int S = K32 + K16;                // prepared fragments per (bx, hi|lo)
     static_assert(4 * NBP == 32 * K32 + 16 * K16, "bin padding must fill the steps");
 };
-
-// Compiler-only ordering point for wave-private LDS traffic.
-__device__ __forceinline__ void lds_order()
-{
-    __builtin_amdgcn_wave_barrier();
-    asm volatile("" ::: "memory");
-}
 
 // Lane i of each 16-lane row takes lane i-1's value; lane 0 of a row takes 0.
 __device__ __forceinline__ double shift_row_right(double x)
@@ -1627,36 +1667,48 @@ hipError_t launch_bin_map(const PlanDev &p, const uint8_t *lut_half, const uint8
     const int64_t per_block = 16;  // waves of a 1024-thread workgroup
     const unsigned grid = (unsigned)std::min<int64_t>((items + per_block - 1) / per_block, p.n_cu);
     if (p.channels == 1)
-        hipLaunchKernelGGL(k_bin_map<1>, dim3(grid), dim3(1024), 0, stream, p.levels,
+        hipLaunchKernelGGL((k_bin_map<1, false>), dim3(grid), dim3(1024), 0, stream, p.levels,
                            first_of(p, KB_BINMAP), p.n_levels, p.mapx, p.mapy, img, img_pitch,
-                           p.n_bins, lut_half, bins);
+                           p.n_bins, lut_half, nullptr, bins);
     else
-        hipLaunchKernelGGL(k_bin_map<3>, dim3(grid), dim3(1024), 0, stream, p.levels,
+        hipLaunchKernelGGL((k_bin_map<3, false>), dim3(grid), dim3(1024), 0, stream, p.levels,
                            first_of(p, KB_BINMAP), p.n_levels, p.mapx, p.mapy, img, img_pitch,
-                           p.n_bins, lut_half, bins);
+                           p.n_bins, lut_half, nullptr, bins);
     return hipGetLastError();
 }
 
 hipError_t launch_bin_map_soft(const PlanDev &p, const uint16_t *soft_lut, const uint8_t *img,
                                int64_t img_pitch, uint8_t *bins, hipStream_t stream)
 {
-    const int64_t n = p.total[KB_SPIX];
-    if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_bin_map_soft, dim3(blocks_for(n, 256)), dim3(256), 0, stream, p.levels,
-                       first_of(p, KB_SPIX), p.n_levels, p.mapx, p.mapy, img, img_pitch, p.channels, soft_lut,
-                       bins);
+    const int64_t items = p.total[KB_BINMAP];
+    if (items == 0) return hipSuccess;
+    const int64_t per_block = 16;  // waves of a 1024-thread workgroup; no LDS table: two per CU
+    const unsigned grid = (unsigned)std::min<int64_t>((items + per_block - 1) / per_block, 2 * (int64_t)p.n_cu);
+    if (p.channels == 1)
+        hipLaunchKernelGGL((k_bin_map<1, true>), dim3(grid), dim3(1024), 0, stream, p.levels,
+                           first_of(p, KB_BINMAP), p.n_levels, p.mapx, p.mapy, img, img_pitch,
+                           p.n_bins, nullptr, soft_lut, bins);
+    else
+        hipLaunchKernelGGL((k_bin_map<3, true>), dim3(grid), dim3(1024), 0, stream, p.levels,
+                           first_of(p, KB_BINMAP), p.n_levels, p.mapx, p.mapy, img, img_pitch,
+                           p.n_bins, nullptr, soft_lut, bins);
     return hipGetLastError();
 }
 
-hipError_t launch_soft_integral(const PlanDev &p, const uint8_t *bins, uint32_t *ii, hipStream_t stream)
+hipError_t launch_soft_integral(const PlanDev &p, const uint8_t *bins, uint8_t *ws, uint32_t *ii,
+                                hipStream_t stream)
 {
-    if (p.total[KB_SROW] == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_soft_rows, dim3(blocks_for(p.total[KB_SROW], 4)), dim3(256), 0, stream, p.levels,
-                       first_of(p, KB_SROW), p.n_levels, p.n_bins, bins, ii);
+    if (p.total[KB_SSEG] == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_soft_segtot, dim3(blocks_for(p.total[KB_SSEG], 4)), dim3(256), 0, stream, p.levels,
+                       first_of(p, KB_SSEG), p.n_levels, p.n_bins, bins, ws);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_soft_cols, dim3(blocks_for(p.total[KB_SCOL], 256)), dim3(256), 0, stream, p.levels,
-                       first_of(p, KB_SCOL), p.n_levels, ii);
+    hipLaunchKernelGGL(k_soft_rowscan, dim3(blocks_for(p.total[KB_SSCAN], 256)), dim3(256), 0, stream, p.levels,
+                       first_of(p, KB_SSCAN), p.n_levels, ws);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_soft_emit, dim3(blocks_for(p.total[KB_SEMIT], 4)), dim3(256), 0, stream, p.levels,
+                       first_of(p, KB_SEMIT), p.n_levels, p.n_bins, bins, ws, ii);
     return hipGetLastError();
 }
 
