@@ -1372,26 +1372,35 @@ typedef float float16v_t __attribute__((ext_vector_type(16)));
 // One workgroup (1024 threads) per tile of 32 templates: per-template scales,
 // then the A fragments [p][s][hi|lo][lane] (lane: template kk0 + lane % 32,
 // features 16 s + 8 (lane / 32) .. + 7 of the block at position p).
-// Per template of the tile: the power of two that brings its max |T| into
-// [2^14, 2^15) -- exponent e (int) and scale 2^-e (float), stored after the
-// fragments. One workgroup of 1024 threads (32 per template) per tile.
-__global__ __launch_bounds__(1024) void k_score_prep_wg_scale(WgArgs a, const float *__restrict__ tmpl,
-                                                              uint8_t *__restrict__ ws, int64_t frag_bytes)
+// Per template: the power of two that brings its max |T| into [2^14, 2^15)
+// -- exponent e (int) and scale 2^-e (float), stored after its tile's
+// fragments. One wave per template slot of every tile (0 past the last
+// template), 8 loads in flight per lane.
+__global__ __launch_bounds__(64) void k_score_prep_wg_scale(WgArgs a, const float *__restrict__ tmpl,
+                                                            uint8_t *__restrict__ ws, int64_t frag_bytes)
 {
-    const int kt = (int)blockIdx.x, kk0 = 32 * kt;
-    const int tid = threadIdx.x, tk = tid >> 5, sub = tid & 31;  // 32 threads per template
+    const int kk = (int)blockIdx.x, kt = kk >> 5, tk = kk & 31;
+    const int lane = threadIdx.x;
     float mx = 0.f;
-    if (kk0 + tk < a.k) {
-        const float *t = tmpl + (int64_t)(kk0 + tk) * a.dim;
-        for (int i = sub; i < a.dim; i += 32) mx = fmaxf(mx, fabsf(t[i]));
+    if (kk < a.k) {
+        const float *t = tmpl + (int64_t)kk * a.dim;
+        int i = lane;
+        for (; i + 7 * 64 < a.dim; i += 8 * 64) {
+            float r[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) r[j] = t[i + 64 * j];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) mx = fmaxf(mx, fabsf(r[j]));
+        }
+        for (; i < a.dim; i += 64) mx = fmaxf(mx, fabsf(t[i]));
     }
 #pragma unroll
-    for (int d = 16; d >= 1; d >>= 1) mx = fmaxf(mx, __shfl_xor(mx, d));
+    for (int d = 32; d >= 1; d >>= 1) mx = fmaxf(mx, __shfl_xor(mx, d));
     int ex = 0;
     if (mx > 0.f) (void)frexpf(mx, &ex);  // mx = f 2^ex, f in [0.5, 1)
     const int e = mx > 0.f ? 15 - ex : 0;
     uint8_t *tp = ws + a.tprep_off + (int64_t)kt * a.tprep_stride + frag_bytes;
-    if (sub == 0) {
+    if (lane == 0) {
         reinterpret_cast<float *>(tp)[tk] = ldexpf(1.f, -e);
         reinterpret_cast<int *>(tp + 32 * 4)[tk] = e;
     }
@@ -1833,7 +1842,7 @@ hipError_t launch_score(const PlanDev &p, const uint8_t *ws, const float *tmpl, 
         // Fragments per tile: [by][bx][step][hi|lo][lane].
         const int64_t n_frag = (int64_t)m.nby * kStripMaxBX * (p.mfma_ks / 4) * 2 * 64;
         const dim3 fgrid(blocks_for(n_frag, 256), ktiles);
-        hipLaunchKernelGGL(k_score_prep_wg_scale, dim3(ktiles), dim3(1024), 0, stream, m, tmpl, wsw, n_frag * 16);
+        hipLaunchKernelGGL(k_score_prep_wg_scale, dim3(32 * ktiles), dim3(64), 0, stream, m, tmpl, wsw, n_frag * 16);
         switch (p.mfma_ks) {
         case 8:
             hipLaunchKernelGGL(k_score_prep_wg<8>, fgrid, dim3(256), 0, stream, m, tmpl, wsw);
