@@ -6,12 +6,21 @@
 // its level by a binary search over that table.
 //
 //   k_bin_map         Eq. 1 + Sec. 2    gradients, channel choice, table lookup
+//                                       (hard bins, or soft-vote entries)
 //   k_int_reduce      Eq. 5 (pass 1)    per-tile row, column and total bin counts
 //   k_int_scan        Eq. 5 (pass 2)    carries: row counts left of each tile, column
 //                                       counts above it, counts above-left of it
 //   k_int_emit        Eq. 4 + Eq. 5     one-hot in registers, write the planes
+//                                       (uint32, or uint16 / uint8 mod 2^bits)
+//   k_soft_segtot,    Eq. 5, soft votes segment vote totals, their row prefix, and
+//   k_soft_rowscan,                     the weighted planes written once
+//   k_soft_emit
 //   k_cells           Eq. 6, Sec. 3.3   four-corner cell histograms, cached
-//   k_score           Sec. 3.1, Sec. 4  window features and inner products
+//   k_score           Sec. 3.1, Sec. 4  window features and inner products (vector units)
+//   k_score_prep,     Sec. 3.1, Sec. 4  the same on the matrix cores: one template per
+//   k_score_strip                       wave over strips of windows (K < 16)
+//   k_score_prep_wg*, Sec. 3.1, Sec. 4  windows x templates GEMM, 32 templates per
+//   k_score_wgemm                       workgroup (K >= 16)
 //   k_block_features  (optional output) normalised block vectors
 #include "hog.h"
 #include "hog_internal.h"

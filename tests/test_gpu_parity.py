@@ -221,3 +221,19 @@ def test_l2_many_templates_window_gemm(nb, k, w, h, ml):
     plan, out = run_gpu(desc, img, tmpl, bias)
     for l in range(plan.sizes.n_levels):
         _check_level(plan, out, img, l, tmpl=tmpl, bias=bias)
+
+
+@pytest.mark.parametrize("w,h,c,nb,norm", [
+    (32767, 130, 1, 8, hog.HOG_NORM_RAW),    # the widest level: 512 integral tiles across
+    (70, 32767, 3, 9, hog.HOG_NORM_L2),      # the tallest: 512 tiles down, 4080 windows
+    (32767, 1, 3, 8, hog.HOG_NORM_L2),       # one row: no interior, no cells, no windows
+    (1, 32767, 1, 4, hog.HOG_NORM_RAW),      # one column
+])
+def test_extreme_dimensions(w, h, c, nb, norm):
+    """Images at the maximum side length (32767) and one pixel thick: bins,
+    planes and cells bit for bit, every window's score within tolerance."""
+    desc = hog.make_desc(w, h, channels=c, n_bins=nb, norm=norm)
+    img = inputs.synth_image(w, h, c, 7300 + nb)
+    tmpl, bias = templates_for(desc, 7301 + nb)
+    plan, out = run_gpu(desc, img, tmpl, bias, block_feat=False)
+    _check_level(plan, out, img, 0, tmpl=tmpl, bias=bias)
