@@ -191,17 +191,23 @@ hog_plan_desc desc_for(const hog_server_config &c, int w, int h)
     return d;
 }
 
-// Cached batch plan for the given sizes (in order); nullptr on failure.
+// Cached batch plan for the given sizes (in order); nullptr on failure. A
+// new plan's tables go to the server's device; the calling thread's current
+// device is left as it was.
 hog_plan *plan_for(hog_server *s, const std::vector<std::pair<int, int>> &key)
 {
     std::lock_guard<std::mutex> lk(s->plan_mu);
-    (void)hipSetDevice(s->device);
     auto it = s->plans.find(key);
     if (it != s->plans.end()) return it->second;
     std::vector<hog_plan_desc> descs;
     for (auto &wh : key) descs.push_back(desc_for(s->cfg, wh.first, wh.second));
+    int prev = -1;
+    const bool switched = hipGetDevice(&prev) == hipSuccess && prev != s->device &&
+                          hipSetDevice(s->device) == hipSuccess;
     hog_plan *p = nullptr;
-    if (hog_plan_create_batch(descs.data(), (int)descs.size(), &p) != HOG_OK) return nullptr;
+    const hog_status st = hog_plan_create_batch(descs.data(), (int)descs.size(), &p);
+    if (switched) (void)hipSetDevice(prev);
+    if (st != HOG_OK) return nullptr;
     s->plans[key] = p;
     return p;
 }
