@@ -213,3 +213,42 @@ def test_full_batch64_in_the_benchmarked_launch():
                                                                  idx // li.windows_x)
                 check_scores(hog.level_scores(plan, scores, l)[wys, wxs, :], ref, absterm)
     g.destroy()
+
+
+@pytest.mark.parametrize("variant", [dict(plane_bits=8), dict(plane_bits=16), dict(votes=1)])
+def test_variants_in_batch_plans_graphs_and_autotune(variant):
+    """Narrow planes and soft votes through a batch plan, the autotuner and a
+    captured graph: the graph's replays equal an eager hog_run bit for bit,
+    and each image's scores equal its single-image plan's."""
+    import torch
+    sizes = [(320, 240), (257, 301), (96, 160)]
+    descs = [hog.make_desc(w, h, channels=3, n_bins=8, max_levels=0, scale=1.2, n_templates=2,
+                           norm=hog.HOG_NORM_L2, **variant) for w, h in sizes]
+    plan = hog.Plan(descs, batch=True)
+    lut = hog.hog_lut_build(8)
+    imgs = [inputs.synth_image(w, h, 3, 4900 + j) for j, (w, h) in enumerate(sizes)]
+    packed = torch.from_numpy(hog.pack_images(plan, imgs)).cuda()
+    tmpl, bias = inputs.synth_templates(2, plan.sizes.feature_dim, 4999)
+    tt, bt = torch.from_numpy(tmpl.reshape(-1)).cuda(), torch.from_numpy(bias).cuda()
+    ref = hog.Buffers(plan)
+    hog.autotune(plan, lut, packed, tt, bt, ref)
+    hog.hog_run(plan, lut, packed, tt, bt, ref)
+    torch.cuda.synchronize()
+    want = _snap(plan, ref)
+    buf = hog.Buffers(plan)
+    g = hog.Graph(plan, lut, packed, tt, bt, buf)
+    for rep in range(2):
+        g.launch()
+        torch.cuda.synchronize()
+        for x, y in zip(want, _snap(plan, buf)):
+            assert np.array_equal(x, y), f"replay {rep}"
+        buf.scores.zero_()
+    g.destroy()
+    scores = ref.scores.cpu().numpy()
+    for i, img in enumerate(imgs):
+        info = plan.images[i]
+        p1, o1 = run_gpu(descs[i], img, tmpl, bias, cell_hist=False, block_feat=False)
+        for k in range(info.n_levels):
+            a = hog.level_scores(plan, scores, info.first_level + k)
+            b = hog.level_scores(p1, o1["scores"], k)
+            assert np.array_equal(a.view(np.uint32), b.view(np.uint32)), f"image {i} level {k}"
