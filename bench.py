@@ -267,6 +267,38 @@ def main():
             kern_us[k] = round(tot / n * 1e3, 2)
     hog.hog_timing_enable(False)
 
+    # Beside the device-resident rate: the same steps with the input first
+    # copied from pinned host memory on the same stream (the PCIe-inclusive
+    # rate; never `value`, the boundary takes device pointers).
+    host_in = torch.empty(img_t.numel(), dtype=torch.uint8).pin_memory()
+    host_in.copy_(img_t.cpu())
+    n_h = min(args.steps, 50)
+    for _ in range(3):
+        img_t.copy_(host_in, non_blocking=True)
+        step()
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(n_h):
+        img_t.copy_(host_in, non_blocking=True)
+        step()
+    b.record(stream)
+    torch.cuda.synchronize()
+    h2d_ms = a.elapsed_time(b) / n_h
+    with_h2d = dict(ms_per_step=round(h2d_ms, 5), mpixel_per_s=round(sz.total_pixels / (h2d_ms * 1e3), 1),
+                    input_bytes=int(img_t.numel()))
+
+    # The input's bin statistics (level 0 of the first image): every bin
+    # populated and a visible no-bin share mean a non-degenerate workload.
+    li0 = plan.levels[0]
+    b0 = hog.level_bins(plan, buf.bins.cpu().numpy(), 0)
+    b0 = b0[0] if isinstance(b0, tuple) else b0
+    counts = np.bincount(b0.reshape(-1), minlength=256)
+    bin_stats = dict(level0=f"{li0.width}x{li0.height}",
+                     no_bin_fraction=round(float(counts[255]) / b0.size, 4),
+                     histogram=[int(c) for c in counts[:wl["n_bins"]]])
+
     # Roofline of the dominant kernel: the integral-image writer moves, per
     # processed pixel, N_b plane elements of ii_elem_bytes (4 for uint32
     # planes) written and 1 byte of bins read.
@@ -367,6 +399,8 @@ def main():
         "p99_ms": round(float(np.percentile(lat, 99)), 4),
         "wall_ms_timed": round(wall_ms, 2),
         "kernel_us": kern_us,
+        "with_h2d": with_h2d,
+        "bins": bin_stats,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
