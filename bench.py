@@ -219,7 +219,7 @@ def main():
             graph.launch(stream)
     else:
         def step():
-            hog.run_path(plan, lut, img_t, tmpl_t, bias_t, buf, stream)
+            hog.hog_run(plan, lut, img_t, tmpl_t, bias_t, buf, stream)
 
     for _ in range(args.warmup):
         step()
@@ -253,7 +253,9 @@ def main():
     lat = np.array(lat)
 
     # Per-kernel times: HIP event pairs recorded by the library around each
-    # launch, on the launch stream.
+    # launch, on the launch stream. Taken on the three calls, which launch
+    # each kernel once over all levels whatever the level groups, so every
+    # kernel is timed alone at the plan's full size.
     hog.hog_timing_enable(True)
     hog.hog_timing_reset()
     n_k = min(args.steps, 50)
@@ -391,7 +393,8 @@ def main():
             "plane_bits": 8 * sz.ii_elem_bytes,
             "votes": "soft (1/32)" if soft else "hard",
             "launch": "captured HIP graph of the batch plan" if batch else "three calls per step",
-            "tiles": {"bin_chunk": tiles.bin_chunk, "score_rows": tiles.score_rows, "how": "autotuned"},
+            "tiles": {"bin_chunk": tiles.bin_chunk, "score_rows": tiles.score_rows,
+                      "level_groups": tiles.level_groups, "how": "autotuned"},
         },
         "base_mpixel_per_s": round(sum(w * h for w, h in sizes) / (ms_per_step * 1e3), 2) if batch
         else round(wl["width"] * wl["height"] / (ms_per_step * 1e3), 2),

@@ -288,10 +288,18 @@ hog_status hog_scan_windows(const hog_plan *plan, const void *ii, const float *t
 /* ------------------------------------------------------------------------ */
 /* Tile shapes.                                                             */
 /* ------------------------------------------------------------------------ */
+#define HOG_MAX_LEVEL_GROUPS 4
 typedef struct {
-    int32_t bin_chunk;  /* bins per integral wave, 1..6 (a last, shorter chunk takes the rest) */
-    int32_t score_rows; /* window rows per strip of the one-template matrix-core scorer
-                           (L2, 8-cell-wide windows, K < 16, n_bins <= 20); 0 otherwise */
+    int32_t bin_chunk;    /* bins per integral wave, 1..6 (a last, shorter chunk takes the rest) */
+    int32_t score_rows;   /* window rows per strip of the one-template matrix-core scorer
+                             (L2, 8-cell-wide windows, K < 16, n_bins <= 20); 0 otherwise */
+    int32_t level_groups; /* hog_run and hog_graph_create only: the levels (of every image)
+                             split into up to this many contiguous ranges of about equal
+                             pixel counts, run on concurrent streams, each range starting
+                             once the previous one starts writing its planes. 0 or 1: one
+                             launch per kernel for all levels; at most HOG_MAX_LEVEL_GROUPS.
+                             get_tiles reports the number of ranges in use. Results are the
+                             same for every value. */
 } hog_tiles;
 
 hog_status hog_plan_get_tiles(const hog_plan *plan, hog_tiles *out);
@@ -302,8 +310,8 @@ hog_status hog_plan_set_tiles(hog_plan *plan, const hog_tiles *tiles);
 
 /* Autotuner: times the whole path (hog_run, reps runs per candidate) on the
  * caller's buffers for each candidate tile shape -- bins per integral wave,
- * then window rows per strip -- and installs the fastest; *chosen (nullable)
- * receives it. Synchronises the stream; the buffers' contents after the call
+ * then window rows per strip, then 1..HOG_MAX_LEVEL_GROUPS level groups --
+ * and installs the fastest; *chosen (nullable) receives it. Synchronises the stream; the buffers' contents after the call
  * are those of a hog_run. */
 hog_status hog_plan_autotune(hog_plan *plan, const hog_lut *lut, const uint8_t *img,
                              int64_t img_pitch, uint8_t *bins, void *ii, const float *tmpl,
@@ -317,7 +325,11 @@ hog_status hog_plan_autotune(hog_plan *plan, const hog_lut *lut, const uint8_t *
 /* hog_bin_map, hog_integral and hog_scan_windows (scores only; cells from the
  * cache for 8-pixel cells, else from ii) in one call, on the same buffers and
  * with the same layouts. Arguments are all checked before anything is
- * enqueued. */
+ * enqueued. With level groups (hog_tiles) the groups run on the plan's own
+ * streams (created on the plan's device by the first such call, freed by
+ * hog_plan_destroy), forked from and joined back into `stream`, so the work
+ * is ordered on `stream` as without groups; concurrent grouped calls on one
+ * plan take turns enqueueing and share those streams. */
 hog_status hog_run(const hog_plan *plan, const hog_lut *lut, const uint8_t *img, int64_t img_pitch,
                    uint8_t *bins, void *ii, const float *tmpl, const float *bias, float *scores,
                    void *workspace, void *stream);

@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -174,17 +175,36 @@ struct hog_lut {
     uint16_t *dev_soft; // soft-vote table, 511 * 511 entries b0 | w1 << 8
 };
 
+// Streams and events of a grouped run (level groups on concurrent streams):
+// group g > 0 runs on s[g - 1]; mid[g] is recorded when group g's planes
+// start, join[g - 1] when group g's scores are done.
+struct GroupStreams {
+    hipStream_t s[HOG_MAX_LEVEL_GROUPS - 1];
+    hipEvent_t mid[HOG_MAX_LEVEL_GROUPS];
+    hipEvent_t join[HOG_MAX_LEVEL_GROUPS - 1];
+};
+
 struct hog_plan {
     hog_plan_desc desc;  // image 0's (shared fields are equal across images)
     bool batch;          // images packed in one buffer; hog_bin_map takes img_pitch 0
+    int device;          // the device holding dev_mem
     std::vector<hog_image_info> images;
     std::vector<Level> levels;
     std::vector<hog_level_info> info;
     std::vector<int32_t> first;  // host copy of the per-kernel prefix tables
     size_t first_off;            // their offset in dev_mem
+    size_t gfirst_off;           // offset in dev_mem of the level groups' prefix tables
     hog_plan_sizes sizes;
     PlanDev dev;
     void *dev_mem;
+    // Level groups (hog_tiles.level_groups): views of dev over contiguous
+    // level ranges, each with its own prefix tables; empty for one group.
+    std::vector<PlanDev> groups;
+    // The plan's own streams for grouped hog_run calls (created on first
+    // use), and the lock that keeps one grouped enqueue at a time on them.
+    bool have_gs = false;
+    GroupStreams gs;
+    std::mutex gs_mu;
 };
 
 namespace hogk {
@@ -445,6 +465,7 @@ static hog_status create_plan(const hog_plan_desc *descs, int n_img, bool batch,
     if (!p) return fail(HOG_E_NOMEM, "host allocation failed");
     p->desc = d0;
     p->batch = batch;
+    p->device = 0;
     p->dev_mem = nullptr;
     std::vector<int32_t> mapx, mapy;
 
@@ -649,7 +670,11 @@ static hog_status create_plan(const hog_plan_desc *descs, int n_img, bool batch,
     const size_t mx_bytes = sizeof(int32_t) * mapx.size();
     const size_t my_bytes = sizeof(int32_t) * mapy.size();
     const size_t o_first = round_up(lv_bytes, 256);
-    const size_t o_mx = o_first + round_up(first_bytes, 256);
+    // The level groups' prefix tables: at most L + HOG_MAX_LEVEL_GROUPS
+    // entries per kernel over all groups.
+    const size_t gfirst_bytes = sizeof(int32_t) * hogk::KB_COUNT * (L + HOG_MAX_LEVEL_GROUPS);
+    const size_t o_gfirst = o_first + round_up(first_bytes, 256);
+    const size_t o_mx = o_gfirst + round_up(gfirst_bytes, 256);
     const size_t o_my = o_mx + round_up(mx_bytes, 256);
     const size_t total_bytes = o_my + round_up(my_bytes, 256) + 256;
     std::vector<uint8_t> blob(total_bytes, 0);
@@ -657,6 +682,7 @@ static hog_status create_plan(const hog_plan_desc *descs, int n_img, bool batch,
     std::memcpy(blob.data() + o_first, first.data(), first_bytes);
     p->first = first;
     p->first_off = o_first;
+    p->gfirst_off = o_gfirst;
     std::memcpy(blob.data() + o_mx, mapx.data(), mx_bytes);
     std::memcpy(blob.data() + o_my, mapy.data(), my_bytes);
     hipError_t e = hipMalloc(&p->dev_mem, total_bytes);
@@ -702,9 +728,9 @@ static hog_status create_plan(const hog_plan_desc *descs, int n_img, bool batch,
     pd.n_chunks = (nb + chunk_final - 1) / chunk_final;
     for (int k = 0; k < hogk::KB_COUNT; ++k) pd.total[k] = totals[k];
     {
-        int dev = 0, ncu = 0;
-        if (hipGetDevice(&dev) != hipSuccess ||
-            hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        int ncu = 0;
+        if (hipGetDevice(&p->device) != hipSuccess) p->device = 0;
+        if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, p->device) != hipSuccess ||
             ncu < 1)
             ncu = 256;
         pd.n_cu = ncu;
@@ -750,9 +776,43 @@ extern "C" hog_status hog_plan_get_image(const hog_plan *plan, int image, hog_im
     return HOG_OK;
 }
 
+static void destroy_group_streams(GroupStreams &g)
+{
+    for (int i = 0; i < HOG_MAX_LEVEL_GROUPS - 1; ++i) {
+        if (g.s[i]) (void)hipStreamDestroy(g.s[i]);
+        if (g.join[i]) (void)hipEventDestroy(g.join[i]);
+    }
+    for (int i = 0; i < HOG_MAX_LEVEL_GROUPS; ++i)
+        if (g.mid[i]) (void)hipEventDestroy(g.mid[i]);
+    std::memset(&g, 0, sizeof g);
+}
+
+// Streams (default priority, non-blocking) and timing-free events for a
+// grouped run, created on the current device.
+static hipError_t create_group_streams(GroupStreams &g)
+{
+    std::memset(&g, 0, sizeof g);
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < HOG_MAX_LEVEL_GROUPS - 1 && e == hipSuccess; ++i) {
+        e = hipStreamCreateWithFlags(&g.s[i], hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&g.join[i], hipEventDisableTiming);
+    }
+    for (int i = 0; i < HOG_MAX_LEVEL_GROUPS && e == hipSuccess; ++i)
+        e = hipEventCreateWithFlags(&g.mid[i], hipEventDisableTiming);
+    if (e != hipSuccess) destroy_group_streams(g);
+    return e;
+}
+
 extern "C" void hog_plan_destroy(hog_plan *plan)
 {
     if (!plan) return;
+    if (plan->have_gs) {
+        int cur = 0;
+        const bool got = hipGetDevice(&cur) == hipSuccess;
+        if (got && cur != plan->device) (void)hipSetDevice(plan->device);
+        destroy_group_streams(plan->gs);
+        if (got && cur != plan->device) (void)hipSetDevice(cur);
+    }
     if (plan->dev_mem) (void)hipFree(plan->dev_mem);
     delete plan;
 }
@@ -874,10 +934,64 @@ extern "C" hog_status hog_scan_windows(const hog_plan *plan, const void *ii, con
 // Bins per integral wave: the cap c split evenly (chunks of ceil(nb / ceil(nb / c))).
 static int chunk_for(int nb, int c) { return (nb + (nb + c - 1) / c - 1) / ((nb + c - 1) / c); }
 
-// Installs bins per integral wave and (strip scorer) window rows per strip,
-// updating the level table and the scorer's prefix table on the device.
-static hog_status apply_tiles(hog_plan *p, int chunk, int rows)
+// Level groups: up to G contiguous level ranges of about equal pixel counts
+// (one level may make up a range on its own), each a view of the plan's
+// tables whose prefix tables start at 0 for its first level. Fewer than two
+// ranges leave the plan ungrouped.
+static hog_status build_groups(hog_plan *p, int G)
 {
+    p->groups.clear();
+    const int L = p->dev.n_levels;
+    if (G < 2 || L < 2) return HOG_OK;
+    int64_t tot = 0;
+    for (const Level &v : p->levels) tot += (int64_t)v.w * v.h;
+    std::vector<int> start(1, 0);
+    int64_t acc = 0;
+    for (int l = 0; l + 1 < L; ++l) {
+        acc += (int64_t)p->levels[l].w * p->levels[l].h;
+        const int64_t k = (int64_t)start.size();  // ranges begun so far
+        if (k < G && acc * G >= tot * k) start.push_back(l + 1);
+    }
+    start.push_back(L);
+    const int ng = (int)start.size() - 1;
+    if (ng < 2) return HOG_OK;
+    std::vector<int32_t> gf;
+    std::vector<size_t> goff;
+    for (int g = 0; g < ng; ++g) {
+        goff.push_back(gf.size());
+        for (int k = 0; k < hogk::KB_COUNT; ++k) {
+            const int32_t *f = p->first.data() + (size_t)k * (L + 1);
+            for (int l = start[g]; l <= start[g + 1]; ++l) gf.push_back(f[l] - f[start[g]]);
+        }
+    }
+    // sum over ranges of KB_COUNT * (levels + 1) = KB_COUNT * (L + ng)
+    if (gf.size() > (size_t)hogk::KB_COUNT * (L + HOG_MAX_LEVEL_GROUPS))
+        return fail(HOG_E_INVALID, "level group tables overflow");
+    int32_t *dgf = (int32_t *)((uint8_t *)p->dev_mem + p->gfirst_off);
+    hipError_t e = hipMemcpy(dgf, gf.data(), sizeof(int32_t) * gf.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return device_fail(e, "hipMemcpy(level group tables)");
+    for (int g = 0; g < ng; ++g) {
+        PlanDev v = p->dev;
+        v.levels = p->dev.levels + start[g];
+        v.first = dgf + goff[g];
+        v.n_levels = start[g + 1] - start[g];
+        for (int k = 0; k < hogk::KB_COUNT; ++k) {
+            const int32_t *f = p->first.data() + (size_t)k * (L + 1);
+            v.total[k] = f[start[g + 1]] - f[start[g]];
+        }
+        p->groups.push_back(v);
+    }
+    return HOG_OK;
+}
+
+// Installs bins per integral wave, (strip scorer) window rows per strip and
+// the level groups, updating the level table and the prefix tables on the
+// device.
+static hog_status apply_tiles(hog_plan *p, int chunk, int rows, int groups)
+{
+    if (groups == 0) groups = 1;
+    if (groups < 1 || groups > HOG_MAX_LEVEL_GROUPS)
+        return fail(HOG_E_INVALID, "level_groups must be in [0, %d]", HOG_MAX_LEVEL_GROUPS);
     PlanDev &pd = p->dev;
     const int L = pd.n_levels, K = pd.n_templates;
     int64_t max_plane = 0;
@@ -907,27 +1021,31 @@ static hog_status apply_tiles(hog_plan *p, int chunk, int rows)
                           hipMemcpyHostToDevice);
         if (e != hipSuccess) return device_fail(e, "hipMemcpy(plan tables)");
     }
-    return HOG_OK;
+    return build_groups(p, groups);
 }
+
+static int level_groups_of(const hog_plan *p) { return p->groups.empty() ? 1 : (int)p->groups.size(); }
 
 extern "C" hog_status hog_plan_get_tiles(const hog_plan *plan, hog_tiles *out)
 {
     if (!plan || !out) return fail(HOG_E_INVALID, "plan or out is NULL");
     out->bin_chunk = plan->dev.bin_chunk;
     out->score_rows = plan->dev.scorer == 1 ? plan->dev.st_th : 0;
+    out->level_groups = level_groups_of(plan);
     return HOG_OK;
 }
 
 extern "C" hog_status hog_plan_set_tiles(hog_plan *plan, const hog_tiles *tiles)
 {
     if (!plan || !tiles) return fail(HOG_E_INVALID, "plan or tiles is NULL");
-    return apply_tiles(plan, tiles->bin_chunk, plan->dev.scorer == 1 ? tiles->score_rows : plan->dev.st_th);
+    return apply_tiles(plan, tiles->bin_chunk, plan->dev.scorer == 1 ? tiles->score_rows : plan->dev.st_th,
+                       tiles->level_groups);
 }
 
 static hog_status check_run_args(const hog_plan *plan, const hog_lut *lut, const uint8_t *img,
                                  int64_t img_pitch, uint8_t *bins, void *ii, const float *tmpl,
                                  const float *bias, float *scores, void *workspace);
-static hog_status run_path(const hog_plan *plan, const hog_lut *lut, const uint8_t *img, int64_t img_pitch,
+static hog_status run_plan(const hog_plan *plan, const hog_lut *lut, const uint8_t *img, int64_t img_pitch,
                            uint8_t *bins, void *ii, const float *tmpl, const float *bias, float *scores,
                            void *workspace, void *stream);
 
@@ -948,14 +1066,14 @@ extern "C" hog_status hog_plan_autotune(hog_plan *plan, const hog_lut *lut, cons
         return device_fail(e, "hipEventCreate");
     }
     // Mean time of reps whole runs (after one untimed run) with these tiles.
-    auto time_with = [&](int chunk, int rows, float *ms) -> hog_status {
-        hog_status r = apply_tiles(plan, chunk, rows);
+    auto time_with = [&](int chunk, int rows, int groups, float *ms) -> hog_status {
+        hog_status r = apply_tiles(plan, chunk, rows, groups);
         if (r != HOG_OK) return r;
-        r = run_path(plan, lut, img, img_pitch, bins, ii, tmpl, bias, scores, workspace, stream);
+        r = run_plan(plan, lut, img, img_pitch, bins, ii, tmpl, bias, scores, workspace, stream);
         if (r != HOG_OK) return r;
         hipError_t he = hipEventRecord(e0, s);
         for (int i = 0; i < reps && r == HOG_OK; ++i)
-            r = run_path(plan, lut, img, img_pitch, bins, ii, tmpl, bias, scores, workspace, stream);
+            r = run_plan(plan, lut, img, img_pitch, bins, ii, tmpl, bias, scores, workspace, stream);
         if (r != HOG_OK) return r;
         if (he == hipSuccess) he = hipEventRecord(e1, s);
         if (he == hipSuccess) he = hipEventSynchronize(e1);
@@ -963,16 +1081,17 @@ extern "C" hog_status hog_plan_autotune(hog_plan *plan, const hog_lut *lut, cons
         return he == hipSuccess ? HOG_OK : device_fail(he, "autotune timing");
     };
     const int nb = plan->dev.n_bins;
-    int best_chunk = plan->dev.bin_chunk, best_rows = plan->dev.st_th;
+    int best_chunk = plan->dev.bin_chunk, best_rows = plan->dev.st_th, best_groups = 1;
     float best = 1e30f;
-    // Bins per integral wave, then window rows per strip (strip scorer).
+    // Bins per integral wave, then window rows per strip (strip scorer), both
+    // with the levels in one group; then the number of level groups.
     int64_t max_plane = 0;
     for (const Level &v : plan->levels) max_plane = std::max(max_plane, v.ii_plane);
     for (int c = 2; c <= hogk::kMaxBinChunk && st == HOG_OK; ++c) {
         const int chunk = chunk_for(nb, c);
         if (chunk != c || (int64_t)chunk * max_plane * plan->dev.plane_bytes > ((int64_t)1 << 31) - 1) continue;
         float ms = 0.f;
-        st = time_with(chunk, best_rows, &ms);
+        st = time_with(chunk, best_rows, 1, &ms);
         if (st == HOG_OK && ms < best) {
             best = ms;
             best_chunk = chunk;
@@ -982,7 +1101,7 @@ extern "C" hog_status hog_plan_autotune(hog_plan *plan, const hog_lut *lut, cons
         const int cand[] = {8, 12, 16, 24, 32};
         for (int rows : cand) {
             float ms = 0.f;
-            st = time_with(best_chunk, rows, &ms);
+            st = time_with(best_chunk, rows, 1, &ms);
             if (st != HOG_OK) break;
             if (ms < best) {
                 best = ms;
@@ -990,10 +1109,18 @@ extern "C" hog_status hog_plan_autotune(hog_plan *plan, const hog_lut *lut, cons
             }
         }
     }
+    for (int g = 2; g <= HOG_MAX_LEVEL_GROUPS && st == HOG_OK && g <= plan->dev.n_levels; ++g) {
+        float ms = 0.f;
+        st = time_with(best_chunk, best_rows, g, &ms);
+        if (st == HOG_OK && ms < best) {
+            best = ms;
+            best_groups = g;
+        }
+    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (st != HOG_OK) return st;
-    st = apply_tiles(plan, best_chunk, best_rows);
+    st = apply_tiles(plan, best_chunk, best_rows, best_groups);
     if (st == HOG_OK && chosen) st = hog_plan_get_tiles(plan, chosen);
     return st;
 }
@@ -1029,13 +1156,118 @@ static hog_status run_path(const hog_plan *plan, const hog_lut *lut, const uint8
                             workspace, stream);
 }
 
+// The path with level groups. The matrix-core scorer's template weights are
+// prepared once, on the caller's stream. Group 0 then runs on that stream and
+// group g > 0 on gs.s[g - 1], which waits until group g - 1 has its carries
+// and starts writing planes: one group's bin map, reduce and scan run while
+// the previous group's plane writer holds HBM. Every group's end is joined
+// back into the caller's stream, so the call is ordered on it like run_path.
+static hog_status run_groups(const hog_plan *plan, const GroupStreams &gs, const hog_lut *lut,
+                             const uint8_t *img, int64_t img_pitch, uint8_t *bins, void *ii,
+                             const float *tmpl, const float *bias, float *scores, void *workspace,
+                             void *stream)
+{
+    hipStream_t s = (hipStream_t)stream;
+    uint8_t *ws = (uint8_t *)workspace;
+    const bool soft = plan->dev.votes == HOG_VOTES_SOFT;
+    const bool need_scores = plan->sizes.score_elems > 0;
+    const bool from_planes = plan->desc.scan.cell != 8 && !soft;
+    const char *what = "score_prep launch";
+    hipError_t e = hipSuccess;
+    if (need_scores)
+        e = timed_launch("score_prep", s, [&] { return hogk::launch_score_prep(plan->dev, ws, tmpl, s); });
+    const int ng = (int)plan->groups.size();
+    int forked = 0;  // groups g > 0 whose stream has joined this call's work
+    for (int g = 0; g < ng && e == hipSuccess; ++g) {
+        const PlanDev &v = plan->groups[g];
+        hipStream_t sg = g == 0 ? s : gs.s[g - 1];
+        if (g > 0) {
+            what = "hipStreamWaitEvent";
+            e = hipStreamWaitEvent(sg, gs.mid[g - 1], 0);
+            if (e != hipSuccess) break;
+            forked = g;
+        }
+        what = "bin_map launch";
+        e = timed_launch("bin_map", sg, [&] {
+            return soft ? hogk::launch_bin_map_soft(v, lut->dev_soft, img, img_pitch, bins, sg)
+                        : hogk::launch_bin_map(v, lut->dev_half, img, img_pitch, bins, sg);
+        });
+        if (e != hipSuccess) break;
+        if (soft) {
+            what = "hipEventRecord";
+            e = hipEventRecord(gs.mid[g], sg);
+            if (e != hipSuccess) break;
+            what = "integral_soft launch";
+            e = timed_launch("integral_soft", sg, [&] {
+                return hogk::launch_soft_integral(v, bins, ws, (uint32_t *)ii, sg);
+            });
+            if (e != hipSuccess) break;
+            what = "cells launch";
+            e = timed_launch("cells", sg, [&] { return hogk::launch_cells(v, ii, ws, nullptr, sg); });
+        } else {
+            what = "integral_reduce launch";
+            e = timed_launch("integral_reduce", sg, [&] { return hogk::launch_int_reduce(v, bins, ws, sg); });
+            if (e != hipSuccess) break;
+            what = "integral_scan launch";
+            e = timed_launch("integral_scan", sg, [&] { return hogk::launch_int_scan(v, ws, sg); });
+            if (e != hipSuccess) break;
+            what = "hipEventRecord";
+            e = hipEventRecord(gs.mid[g], sg);
+            if (e != hipSuccess) break;
+            what = "integral_emit launch";
+            e = timed_launch("integral_emit", sg, [&] { return hogk::launch_int_emit(v, bins, ws, ii, sg); });
+            if (e == hipSuccess && from_planes) {
+                what = "cells launch";
+                e = timed_launch("cells", sg, [&] { return hogk::launch_cells(v, ii, ws, nullptr, sg); });
+            }
+        }
+        if (e != hipSuccess) break;
+        if (need_scores) {
+            what = "score launch";
+            e = timed_launch("score", sg, [&] { return hogk::launch_score(v, ws, tmpl, bias, scores, sg, false); });
+        }
+    }
+    // Join every forked stream back, also after a failure.
+    for (int g = 1; g <= forked; ++g) {
+        hipError_t je = hipEventRecord(gs.join[g - 1], gs.s[g - 1]);
+        if (je == hipSuccess) je = hipStreamWaitEvent(s, gs.join[g - 1], 0);
+        if (je != hipSuccess && e == hipSuccess) {
+            e = je;
+            what = "joining level-group streams";
+        }
+    }
+    return e == hipSuccess ? HOG_OK : device_fail(e, what);
+}
+
+// run_path, or run_groups on the plan's own streams (created on first use,
+// on the plan's device) under the plan's lock.
+static hog_status run_plan(const hog_plan *plan, const hog_lut *lut, const uint8_t *img, int64_t img_pitch,
+                           uint8_t *bins, void *ii, const float *tmpl, const float *bias, float *scores,
+                           void *workspace, void *stream)
+{
+    if (plan->groups.empty())
+        return run_path(plan, lut, img, img_pitch, bins, ii, tmpl, bias, scores, workspace, stream);
+    hog_plan *mp = const_cast<hog_plan *>(plan);
+    std::lock_guard<std::mutex> lock(mp->gs_mu);
+    if (!mp->have_gs) {
+        int cur = 0;
+        hipError_t e = hipGetDevice(&cur);
+        if (e == hipSuccess && cur != mp->device) e = hipSetDevice(mp->device);
+        if (e == hipSuccess) e = create_group_streams(mp->gs);
+        if (cur != mp->device) (void)hipSetDevice(cur);
+        if (e != hipSuccess) return device_fail(e, "creating level-group streams");
+        mp->have_gs = true;
+    }
+    return run_groups(plan, mp->gs, lut, img, img_pitch, bins, ii, tmpl, bias, scores, workspace, stream);
+}
+
 extern "C" hog_status hog_run(const hog_plan *plan, const hog_lut *lut, const uint8_t *img, int64_t img_pitch,
                               uint8_t *bins, void *ii, const float *tmpl, const float *bias,
                               float *scores, void *workspace, void *stream)
 {
     hog_status st = check_run_args(plan, lut, img, img_pitch, bins, ii, tmpl, bias, scores, workspace);
     if (st != HOG_OK) return st;
-    return run_path(plan, lut, img, img_pitch, bins, ii, tmpl, bias, scores, workspace, stream);
+    return run_plan(plan, lut, img, img_pitch, bins, ii, tmpl, bias, scores, workspace, stream);
 }
 
 struct hog_graph {
@@ -1059,11 +1291,28 @@ extern "C" hog_status hog_graph_create(const hog_plan *plan, const hog_lut *lut,
         (void)hipStreamDestroy(cs);
         return device_fail(e, "hipStreamBeginCapture");
     }
+    // Level groups are captured on streams of this capture's own: their fork
+    // and join events become the graph's edges.
+    GroupStreams gs;
+    std::memset(&gs, 0, sizeof gs);
+    if (!plan->groups.empty()) {
+        e = create_group_streams(gs);
+        if (e != hipSuccess) {
+            hipGraph_t dead = nullptr;
+            (void)hipStreamEndCapture(cs, &dead);
+            if (dead) (void)hipGraphDestroy(dead);
+            (void)hipStreamDestroy(cs);
+            return device_fail(e, "creating level-group streams");
+        }
+    }
     g_capturing = true;
-    st = run_path(plan, lut, img, img_pitch, bins, ii, tmpl, bias, scores, workspace, cs);
+    st = plan->groups.empty()
+             ? run_path(plan, lut, img, img_pitch, bins, ii, tmpl, bias, scores, workspace, cs)
+             : run_groups(plan, gs, lut, img, img_pitch, bins, ii, tmpl, bias, scores, workspace, cs);
     g_capturing = false;
     hipGraph_t graph = nullptr;
     e = hipStreamEndCapture(cs, &graph);
+    if (!plan->groups.empty()) destroy_group_streams(gs);
     (void)hipStreamDestroy(cs);
     if (st != HOG_OK || e != hipSuccess) {
         if (graph) (void)hipGraphDestroy(graph);

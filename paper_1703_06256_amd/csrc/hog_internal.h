@@ -137,8 +137,13 @@ hipError_t launch_cells(const PlanDev &p, const void *ii, uint8_t *ws, uint32_t 
                         hipStream_t stream);
 hipError_t launch_cache_export(const PlanDev &p, const uint8_t *ws, uint32_t *cell_hist,
                                hipStream_t stream);
+// The matrix-core scorers' prepared template weights (rewritten in the
+// workspace; the vector scorer has none).
+hipError_t launch_score_prep(const PlanDev &p, uint8_t *ws, const float *tmpl, hipStream_t stream);
+// Window scores; prep = false when launch_score_prep has already run on this
+// workspace for these templates.
 hipError_t launch_score(const PlanDev &p, const uint8_t *ws, const float *tmpl, const float *bias,
-                        float *scores, hipStream_t stream);
+                        float *scores, hipStream_t stream, bool prep = true);
 hipError_t launch_block_features(const PlanDev &p, const uint8_t *ws, float *block_feat,
                                  hipStream_t stream);
 

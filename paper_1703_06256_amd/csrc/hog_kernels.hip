@@ -1830,69 +1830,94 @@ hipError_t launch_cache_export(const PlanDev &p, const uint8_t *ws, uint32_t *ce
     return hipGetLastError();
 }
 
-hipError_t launch_score(const PlanDev &p, const uint8_t *ws, const float *tmpl, const float *bias,
-                        float *scores, hipStream_t stream)
+static WgArgs wg_args(const PlanDev &p)
 {
-    const int64_t n = p.total[KB_STILE];
-    if (n == 0) return hipSuccess;
-    const dim3 grid((unsigned)n), block(256);
-    const int32_t *f = first_of(p, KB_STILE);
+    WgArgs m;
+    m.nb = p.n_bins;
+    m.nby = p.win_cells_y - 1;
+    m.k = p.n_templates;
+    m.dim = p.feat_dim;
+    m.tprep_off = p.tprep_off;
+    m.tprep_stride = p.tprep_stride;
+    m.eps = p.eps_counts;  // the matrix-core scorers work on cell counts
+    return m;
+}
+
+static StripArgs strip_args(const PlanDev &p)
+{
+    StripArgs m;
+    m.nb = p.n_bins;
+    m.nby = p.win_cells_y - 1;
+    m.k = p.n_templates;
+    m.th = p.st_th;
+    m.dim = p.feat_dim;
+    m.lds_wave = p.st_lds_bytes / 4;
+    m.tprep_off = p.tprep_off;
+    m.tprep_stride = p.tprep_stride;
+    m.eps = p.eps_counts;  // the matrix-core scorers work on cell counts
+    return m;
+}
+
+hipError_t launch_score_prep(const PlanDev &p, uint8_t *ws, const float *tmpl, hipStream_t stream)
+{
+    if (p.total[KB_STILE] == 0) return hipSuccess;
     if (p.scorer == 2) {
-        WgArgs m;
-        m.nb = p.n_bins;
-        m.nby = p.win_cells_y - 1;
-        m.k = p.n_templates;
-        m.dim = p.feat_dim;
-        m.tprep_off = p.tprep_off;
-        m.tprep_stride = p.tprep_stride;
-        m.eps = p.eps_counts;  // the matrix-core scorers work on cell counts
+        const WgArgs m = wg_args(p);
         const unsigned ktiles = (unsigned)((m.k + 31) / 32);
-        uint8_t *wsw = const_cast<uint8_t *>(ws);
         // Fragments per tile: [by][bx][step][hi|lo][lane].
         const int64_t n_frag = (int64_t)m.nby * kStripMaxBX * (p.mfma_ks / 4) * 2 * 64;
         const dim3 fgrid(blocks_for(n_frag, 256), ktiles);
-        hipLaunchKernelGGL(k_score_prep_wg_scale, dim3(32 * ktiles), dim3(64), 0, stream, m, tmpl, wsw, n_frag * 16);
+        hipLaunchKernelGGL(k_score_prep_wg_scale, dim3(32 * ktiles), dim3(64), 0, stream, m, tmpl, ws, n_frag * 16);
         switch (p.mfma_ks) {
-        case 8:
-            hipLaunchKernelGGL(k_score_prep_wg<8>, fgrid, dim3(256), 0, stream, m, tmpl, wsw);
-            hipLaunchKernelGGL(k_score_wgemm<8>, grid, block, 0, stream, p.levels, f, p.n_levels, m, ws, bias, scores);
-            break;
-        case 16:
-            hipLaunchKernelGGL(k_score_prep_wg<16>, fgrid, dim3(256), 0, stream, m, tmpl, wsw);
-            hipLaunchKernelGGL(k_score_wgemm<16>, grid, block, 0, stream, p.levels, f, p.n_levels, m, ws, bias, scores);
-            break;
+        case 8: hipLaunchKernelGGL(k_score_prep_wg<8>, fgrid, dim3(256), 0, stream, m, tmpl, ws); break;
+        case 16: hipLaunchKernelGGL(k_score_prep_wg<16>, fgrid, dim3(256), 0, stream, m, tmpl, ws); break;
         default: return hipErrorInvalidValue;
         }
         return hipGetLastError();
     }
     if (p.scorer == 1) {
-        StripArgs m;
-        m.nb = p.n_bins;
-        m.nby = p.win_cells_y - 1;
-        m.k = p.n_templates;
-        m.th = p.st_th;
-        m.dim = p.feat_dim;
-        m.lds_wave = p.st_lds_bytes / 4;
-        m.tprep_off = p.tprep_off;
-        m.tprep_stride = p.tprep_stride;
-        m.eps = p.eps_counts;  // the matrix-core scorers work on cell counts
-        const dim3 pgrid((unsigned)m.k), pblock(64 * kStripMaxBX), sgrid(blocks_for(n, 4));
-        // The prepared weights are rewritten in the workspace by every call.
-        uint8_t *wsw = const_cast<uint8_t *>(ws);
+        const StripArgs m = strip_args(p);
+        const dim3 pgrid((unsigned)m.k), pblock(64 * kStripMaxBX);
+        switch (p.mfma_ks) {
+        case 8: hipLaunchKernelGGL(k_score_prep<8>, pgrid, pblock, 0, stream, m, tmpl, ws); break;
+        case 16: hipLaunchKernelGGL(k_score_prep<16>, pgrid, pblock, 0, stream, m, tmpl, ws); break;
+        case 20: hipLaunchKernelGGL(k_score_prep<20>, pgrid, pblock, 0, stream, m, tmpl, ws); break;
+        default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
+    return hipSuccess;  // the vector scorer reads the templates as given
+}
+
+hipError_t launch_score(const PlanDev &p, const uint8_t *ws, const float *tmpl, const float *bias,
+                        float *scores, hipStream_t stream, bool prep)
+{
+    const int64_t n = p.total[KB_STILE];
+    if (n == 0) return hipSuccess;
+    const dim3 grid((unsigned)n), block(256);
+    const int32_t *f = first_of(p, KB_STILE);
+    if (prep) {
+        // The prepared weights are rewritten in the workspace by every such call.
+        hipError_t e = launch_score_prep(p, const_cast<uint8_t *>(ws), tmpl, stream);
+        if (e != hipSuccess) return e;
+    }
+    if (p.scorer == 2) {
+        const WgArgs m = wg_args(p);
+        switch (p.mfma_ks) {
+        case 8: hipLaunchKernelGGL(k_score_wgemm<8>, grid, block, 0, stream, p.levels, f, p.n_levels, m, ws, bias, scores); break;
+        case 16: hipLaunchKernelGGL(k_score_wgemm<16>, grid, block, 0, stream, p.levels, f, p.n_levels, m, ws, bias, scores); break;
+        default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
+    if (p.scorer == 1) {
+        const StripArgs m = strip_args(p);
+        const dim3 sgrid(blocks_for(n, 4));
         const size_t lds = (size_t)p.st_lds_bytes;
         switch (p.mfma_ks) {
-        case 8:
-            hipLaunchKernelGGL(k_score_prep<8>, pgrid, pblock, 0, stream, m, tmpl, wsw);
-            hipLaunchKernelGGL(k_score_strip<8>, sgrid, block, lds, stream, p.levels, f, p.n_levels, m, ws, bias, scores);
-            break;
-        case 16:
-            hipLaunchKernelGGL(k_score_prep<16>, pgrid, pblock, 0, stream, m, tmpl, wsw);
-            hipLaunchKernelGGL(k_score_strip<16>, sgrid, block, lds, stream, p.levels, f, p.n_levels, m, ws, bias, scores);
-            break;
-        case 20:
-            hipLaunchKernelGGL(k_score_prep<20>, pgrid, pblock, 0, stream, m, tmpl, wsw);
-            hipLaunchKernelGGL(k_score_strip<20>, sgrid, block, lds, stream, p.levels, f, p.n_levels, m, ws, bias, scores);
-            break;
+        case 8: hipLaunchKernelGGL(k_score_strip<8>, sgrid, block, lds, stream, p.levels, f, p.n_levels, m, ws, bias, scores); break;
+        case 16: hipLaunchKernelGGL(k_score_strip<16>, sgrid, block, lds, stream, p.levels, f, p.n_levels, m, ws, bias, scores); break;
+        case 20: hipLaunchKernelGGL(k_score_strip<20>, sgrid, block, lds, stream, p.levels, f, p.n_levels, m, ws, bias, scores); break;
         default: return hipErrorInvalidValue;
         }
         return hipGetLastError();

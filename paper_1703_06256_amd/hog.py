@@ -21,6 +21,7 @@ HOG_NORM_RAW, HOG_NORM_L2 = 0, 1
 HOG_ORIENT_SIGNED, HOG_ORIENT_UNSIGNED = 0, 1
 HOG_VOTES_HARD, HOG_VOTES_SOFT = 0, 1
 HOG_SOFT_QUANTUM = 32
+HOG_MAX_LEVEL_GROUPS = 4
 LUT_SIDE = 511
 
 # Every symbol include/hog.h declares.
@@ -76,7 +77,8 @@ class ImageInfo(ctypes.Structure):
 
 
 class Tiles(ctypes.Structure):
-    _fields_ = [("bin_chunk", ctypes.c_int32), ("score_rows", ctypes.c_int32)]
+    _fields_ = [("bin_chunk", ctypes.c_int32), ("score_rows", ctypes.c_int32),
+                ("level_groups", ctypes.c_int32)]
 
 
 class ServerConfig(ctypes.Structure):
@@ -433,8 +435,8 @@ def plan_tiles(plan: Plan) -> Tiles:
     return t
 
 
-def set_plan_tiles(plan: Plan, bin_chunk: int, score_rows: int = 0):
-    t = Tiles(bin_chunk, score_rows)
+def set_plan_tiles(plan: Plan, bin_chunk: int, score_rows: int = 0, level_groups: int = 1):
+    t = Tiles(bin_chunk, score_rows, level_groups)
     _check(load_library().hog_plan_set_tiles(plan.handle, ctypes.byref(t)))
 
 
