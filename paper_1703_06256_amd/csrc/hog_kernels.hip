@@ -589,7 +589,6 @@ __global__ __launch_bounds__(256) void k_int_emit(const Level *__restrict__ lv,
 
     auto do_row = [&](int bin, int y) {
         const int rel = bin - b0;
-        const int r = y + 1;
         const int rr = y - y0;
 #pragma unroll
         for (int j = 0; j < NBC; ++j) {
