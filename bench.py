@@ -392,7 +392,7 @@ def main():
             "templates": K,
             "plane_bits": 8 * sz.ii_elem_bytes,
             "votes": "soft (1/32)" if soft else "hard",
-            "launch": "captured HIP graph of the batch plan" if batch else "three calls per step",
+            "launch": "captured HIP graph of the batch plan" if batch else "hog_run per step",
             "tiles": {"bin_chunk": tiles.bin_chunk, "score_rows": tiles.score_rows,
                       "level_groups": tiles.level_groups, "how": "autotuned"},
         },
