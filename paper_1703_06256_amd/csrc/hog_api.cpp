@@ -563,9 +563,13 @@ static hog_status create_plan(const hog_plan_desc *descs, int n_img, bool batch,
         v.ws_cache = ws_off;
         ws_off = round_up(ws_off + (int64_t)nb * v.cby * v.cbx * 64 * 2, 256);
         v.ws_stot = 0;
-        if (soft) {  // segment vote totals, uint32 [nb][h][tiles_x]
+        v.ws_scol = 0;
+        if (soft) {  // tile vote totals per row and per column, uint32
+            const int64_t hp = (int64_t)hogk::kTile * v.tiles_y, wp = (int64_t)hogk::kTile * v.tiles_x;
             v.ws_stot = ws_off;
-            ws_off = round_up(ws_off + (int64_t)nb * v.h * v.tiles_x * 4, 256);
+            ws_off = round_up(ws_off + (int64_t)nb * v.tiles_x * hp * 4, 256);
+            v.ws_scol = ws_off;
+            ws_off = round_up(ws_off + (int64_t)nb * v.tiles_y * wp * 4, 256);
         }
 
         info.width = lw;
@@ -647,9 +651,9 @@ static hog_status create_plan(const hog_plan_desc *descs, int n_img, bool batch,
         items[hogk::KB_BLOCK] = (sp.norm == HOG_NORM_L2 && v.cells_x >= 2 && v.cells_y >= 2)
                                     ? (int64_t)(v.cells_x - 1) * (v.cells_y - 1)
                                     : 0;
-        items[hogk::KB_SSEG] = soft ? (int64_t)v.h * v.tiles_x : 0;
-        items[hogk::KB_SSCAN] = soft ? (int64_t)nb * v.h : 0;
-        items[hogk::KB_SEMIT] = soft ? (int64_t)nb * v.tiles_x : 0;
+        items[hogk::KB_SSEG] = soft ? (int64_t)v.tiles_x * v.tiles_y : 0;
+        items[hogk::KB_SSCAN] = soft ? (int64_t)nb * v.h + (int64_t)nb * hogk::kTile * v.tiles_x : 0;
+        items[hogk::KB_SEMIT] = soft ? (int64_t)v.tiles_x * v.tiles_y * ((nb + 1) / 2) : 0;
         for (int k = 0; k < hogk::KB_COUNT; ++k) {
             first[(size_t)k * (L + 1) + l] = (int32_t)totals[k];
             totals[k] += items[k];
@@ -864,13 +868,17 @@ extern "C" hog_status hog_integral(const hog_plan *plan, const uint8_t *bins, vo
     hipStream_t s = (hipStream_t)stream;
     uint8_t *ws = (uint8_t *)workspace;
     if (plan->dev.votes == HOG_VOTES_SOFT) {
-        // Weighted planes (row pass, column pass), then every cell cached.
+        // Weighted planes; every cell cached, by the plane writer for 8-pixel
+        // cells, else from the planes.
+        const bool fused = plan->desc.scan.cell == 8;
         hipError_t e = timed_launch("integral_soft", s, [&] {
-            return hogk::launch_soft_integral(plan->dev, bins, ws, (uint32_t *)ii, s);
+            return hogk::launch_soft_integral(plan->dev, bins, ws, (uint32_t *)ii, fused, s);
         });
         if (e != hipSuccess) return device_fail(e, "integral_soft launch");
-        e = timed_launch("cells", s, [&] { return hogk::launch_cells(plan->dev, ii, ws, nullptr, s); });
-        if (e != hipSuccess) return device_fail(e, "cells launch");
+        if (!fused) {
+            e = timed_launch("cells", s, [&] { return hogk::launch_cells(plan->dev, ii, ws, nullptr, s); });
+            if (e != hipSuccess) return device_fail(e, "cells launch");
+        }
         return HOG_OK;
     }
     hipError_t e = timed_launch("integral_reduce", s, [&] {
@@ -1198,12 +1206,15 @@ static hog_status run_groups(const hog_plan *plan, const GroupStreams &gs, const
             e = hipEventRecord(gs.mid[g], sg);
             if (e != hipSuccess) break;
             what = "integral_soft launch";
+            const bool fused = plan->desc.scan.cell == 8;
             e = timed_launch("integral_soft", sg, [&] {
-                return hogk::launch_soft_integral(v, bins, ws, (uint32_t *)ii, sg);
+                return hogk::launch_soft_integral(v, bins, ws, (uint32_t *)ii, fused, sg);
             });
             if (e != hipSuccess) break;
-            what = "cells launch";
-            e = timed_launch("cells", sg, [&] { return hogk::launch_cells(v, ii, ws, nullptr, sg); });
+            if (!fused) {
+                what = "cells launch";
+                e = timed_launch("cells", sg, [&] { return hogk::launch_cells(v, ii, ws, nullptr, sg); });
+            }
         } else {
             what = "integral_reduce launch";
             e = timed_launch("integral_reduce", sg, [&] { return hogk::launch_int_reduce(v, bins, ws, sg); });

@@ -52,9 +52,9 @@ enum {
     KB_CELL,        // threads of the cell kernel: cells
     KB_STILE,       // workgroups of the scorer: window tiles
     KB_BLOCK,       // threads of the block-feature kernel: blocks
-    KB_SSEG,        // soft votes: waves of the segment totals, one per (row, 64-column segment)
-    KB_SSCAN,       // soft votes: threads of the row prefix, one per (bin, row)
-    KB_SEMIT,       // soft votes: waves of the plane writer, one per (bin, 64-column segment)
+    KB_SSEG,        // soft votes: waves of the tile reduce, one per integral tile
+    KB_SSCAN,       // soft votes: threads of the prefixes, one per (bin, row) then per (bin, column)
+    KB_SEMIT,       // soft votes: waves of the plane writer, one per (integral tile, pair of bins)
     KB_COUNT
 };
 
@@ -83,7 +83,8 @@ struct Level {
     int64_t ws_cs;      // uint16 [tiles_y][nb][wp]   column x's count above tile row ty
     int64_t ws_p;       // uint32 [tiles_y][tiles_x][nb]  count above and left of the tile
     int64_t ws_cache;   // uint16 [nb][cby][cbx][8][8] cell histogram cache
-    int64_t ws_stot;    // soft votes: uint32 [nb][h][tiles_x] segment vote totals, then their row prefix
+    int64_t ws_stot;    // soft votes: uint32 [nb][tiles_x][hp] votes of each tile in row y, then left of it
+    int64_t ws_scol;    // soft votes: uint32 [nb][tiles_y][wp] votes of each tile in column x, then above it
 };
 
 struct PlanDev {
@@ -128,8 +129,9 @@ hipError_t launch_int_reduce(const PlanDev &p, const uint8_t *bins, uint8_t *ws,
 // images (segment totals, their row prefix, one top-down writer per segment).
 hipError_t launch_bin_map_soft(const PlanDev &p, const uint16_t *soft_lut, const uint8_t *img,
                                int64_t img_pitch, uint8_t *bins, hipStream_t stream);
+// With cells, the writer also fills the cell cache (8-pixel cells only).
 hipError_t launch_soft_integral(const PlanDev &p, const uint8_t *bins, uint8_t *ws, uint32_t *ii,
-                                hipStream_t stream);
+                                bool cells, hipStream_t stream);
 hipError_t launch_int_scan(const PlanDev &p, uint8_t *ws, hipStream_t stream);
 hipError_t launch_int_emit(const PlanDev &p, const uint8_t *bins, uint8_t *ws, void *ii,
                            hipStream_t stream);

@@ -12,9 +12,9 @@
 //                                       counts above it, counts above-left of it
 //   k_int_emit        Eq. 4 + Eq. 5     one-hot in registers, write the planes
 //                                       (uint32, or uint16 / uint8 mod 2^bits)
-//   k_soft_segtot,    Eq. 5, soft votes segment vote totals, their row prefix, and
-//   k_soft_rowscan,                     the weighted planes written once
-//   k_soft_emit
+//   k_soft_reduce,    Eq. 5, soft votes per-tile row and column vote totals, their
+//   k_soft_scan,                        prefixes, and the weighted planes written
+//   k_soft_emit                         once (with the cell cache for 8-pixel cells)
 //   k_cells           Eq. 6, Sec. 3.3   four-corner cell histograms, cached
 //   k_score           Sec. 3.1, Sec. 4  window features and inner products (vector units)
 //   k_score_prep,     Sec. 3.1, Sec. 4  the same on the matrix cores: one template per
@@ -246,8 +246,7 @@ __device__ __forceinline__ void stage_bin_tile(uint8_t *tb, __amdgpu_buffer_rsrc
     for (int m = 0; m < 4; ++m) {
         const int k = lane + 64 * m;
         const int row = k >> 2, seg = k & 3;
-        const u32x4 d = __builtin_amdgcn_raw_buffer_load_b128(bsrc, tx * kTile + 16 * seg,
-                                                              (y0 + row) * bpitch, 0);
+        const u32x4 d = __builtin_amdgcn_raw_buffer_load_b128(bsrc, (y0 + row) * bpitch + tx * kTile + 16 * seg, 0, 0);
         *reinterpret_cast<u32x4 *>(tb + row * kTile + 16 * seg) = d;
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -300,8 +299,8 @@ __global__ __launch_bounds__(64) void k_int_reduce(const Level *__restrict__ lv,
         for (int m = 0; m < 4; ++m) {
             const int k = lane + 64 * m;
             const int row = k >> 2, seg = k & 3;
-            const u32x4 d = __builtin_amdgcn_raw_buffer_load_b128(bsrc, tx * kTile + 16 * seg,
-                                                                  (ty * kTile + row) * bpitch, 0);
+            const u32x4 d = __builtin_amdgcn_raw_buffer_load_b128(
+                bsrc, (ty * kTile + row) * bpitch + tx * kTile + 16 * seg, 0, 0);
             uint32_t *dst = reinterpret_cast<uint32_t *>(tb + row * kRedStride + 16 * seg);
             dst[0] = d[0];
             dst[1] = d[1];
@@ -700,132 +699,296 @@ __global__ __launch_bounds__(256) void k_cells(const Level *__restrict__ lv,
 
 // ---------------------------------------------------------------------------
 // Soft votes (Sec. 2's two-bin split, quantised to 1/HOG_SOFT_QUANTUM):
-// weighted integral images in three passes, the hard path's structure with
-// vote weights in place of unit counts. A pixel with soft entry b0 | w1 << 8
-// gives Q - w1 to bin b0 and w1 to bin b0 + 1 mod nb (both to bin 0 when
-// nb = 1).
-//   1. k_soft_segtot: per 64-column segment s of row y, each bin's vote total
-//      (an LDS histogram per wave), into the workspace [n][y][s];
-//   2. k_soft_rowscan: per (bin, row), those totals become their exclusive
-//      prefix along the row: the votes left of each segment;
-//   3. k_soft_emit: per (bin, segment), one wave walks the rows top down;
-//      lane = column. Row y's prefix inside the segment is a wave scan of the
-//      votes, plus the votes left of the segment; adding it to the lane's
-//      running column sum gives ii(x, y), written once.
+// weighted integral images in the hard path's three passes over 64 x 64
+// tiles, with vote weights in place of unit counts. A pixel with soft entry
+// b0 | w1 << 8 gives Q - w1 to bin b0 and w1 to bin b0 + 1 mod nb (both to
+// bin 0 when nb = 1).
+//   1. k_soft_reduce: per tile, each bin's vote total in each of its rows,
+//      into [n][tx][y] (row totals), and in each of its columns, into
+//      [n][ty][x] (column totals);
+//   2. k_soft_scan: the row totals become their exclusive prefix over tile
+//      columns (the votes left of the tile in each row), the column totals
+//      their exclusive prefix over tile rows (the votes above it in each
+//      column);
+//   3. k_soft_emit: per (tile, pair of bins), one wave seeds each column with
+//      its plane value just above the tile -- the votes left of the tile in
+//      the rows above, plus the prefix along the tile's columns of the votes
+//      above -- then walks the tile's rows: each row's prefix inside the tile
+//      is a wave scan of the votes, plus the votes left of the tile, and
+//      ii(x, y) is written once. The two bins' votes share one scan as the
+//      16-bit halves of a dword: a tile row holds at most 64 Q = 2048 votes
+//      per bin, so the halves never carry into each other. With 8-pixel cells
+//      the writer also caches every cell (Eq. 6) at each 8th row, as
+//      k_int_emit does.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ uint32_t soft_vote_for(uint32_t e, int n, int nb)
+
+// Inclusive prefix sum over the 64 lanes of a full wave, by DPP: shifts of
+// 1, 2, 4 and 8 lanes inside each row of 16 (zero fill), then the last lane
+// of row 0 (row 2) added to row 1 (row 3), then the last lane of row 1 added
+// to rows 2 and 3. Every lane must be active.
+__device__ __forceinline__ uint32_t wave_incl_scan_dpp(uint32_t v)
 {
-    constexpr uint32_t Q = HOG_SOFT_QUANTUM;
-    const uint32_t b0 = e & 255u, w1 = e >> 8;
-    if (b0 == (uint32_t)kNoBin) return 0u;
-    const uint32_t b1 = b0 + 1 == (uint32_t)nb ? 0u : b0 + 1;
-    return (b0 == (uint32_t)n ? Q - w1 : 0u) + (b1 == (uint32_t)n ? w1 : 0u);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xF, 0xF, true);   // row_shr:1
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xF, 0xF, true);   // row_shr:2
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xF, 0xF, true);   // row_shr:4
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xF, 0xF, true);   // row_shr:8
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xA, 0xF, false);  // row_bcast:15
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xC, 0xF, false);  // row_bcast:31
+    return v;
 }
 
-__global__ __launch_bounds__(256) void k_soft_segtot(const Level *__restrict__ lv,
-                                                     const int32_t *__restrict__ first, int n_levels,
-                                                     int nb, const uint8_t *__restrict__ bins,
-                                                     uint8_t *__restrict__ ws)
+__global__ __launch_bounds__(64) void k_soft_reduce(const Level *__restrict__ lv,
+                                                    const int32_t *__restrict__ first, int n_levels,
+                                                    int nb, const uint8_t *__restrict__ bins,
+                                                    uint8_t *__restrict__ ws)
 {
+    // One wave per tile, every bin at once. LDS: the tile's soft entries
+    // (row stride kStride bytes, 33 dwords, so lane-per-row reads hit
+    // distinct banks), then per-lane histograms colh and rowh: each lane only
+    // ever adds to its own slots. A total never exceeds 64 Q = 2048, so two
+    // bins share a dword, 16 bits each (bin n: dword n / 2, half n % 2).
     constexpr uint32_t Q = HOG_SOFT_QUANTUM;
-    __shared__ uint32_t hist[4][64];
-    const int wid = wave_id_in_block(), lane = threadIdx.x & 63;
-    const int gw = (int)blockIdx.x * 4 + wid;
-    if (gw >= first[n_levels]) return;  // whole wave; no workgroup barrier below
-    const int l = find_level(first, n_levels, gw);
+    constexpr int kStride = 2 * kTile + 4;
+    extern __shared__ __attribute__((aligned(16))) uint32_t sred_smem[];
+    const int tile = (int)blockIdx.x;
+    const int lane = (int)threadIdx.x;
+    if (tile >= first[n_levels]) return;
+    const int l = find_level(first, n_levels, tile);
     const Level &v = lv[l];
-    const int rel = gw - first[l];
-    const int sg = rel % v.tiles_x, y = rel / v.tiles_x;
-    uint32_t *h = hist[wid];
-    h[lane] = 0u;
-    lds_order();
-    const int x = sg * kTile + lane;
-    const uint16_t *row = reinterpret_cast<const uint16_t *>(bins + v.bins_off + (int64_t)y * v.bins_pitch);
-    const uint32_t e = x < v.w ? (uint32_t)row[x] : (uint32_t)kNoBin;
-    const uint32_t b0 = e & 255u, w1 = e >> 8;
-    if (b0 != (uint32_t)kNoBin) {
-        const uint32_t b1 = b0 + 1 == (uint32_t)nb ? 0u : b0 + 1;
-        if (w1 < Q) atomicAdd(&h[b0], Q - w1);
-        if (w1 > 0) atomicAdd(&h[b1], w1);
+    const int t = tile - first[l];
+    const int tx = t % v.tiles_x, ty = t / v.tiles_x;
+    uint8_t *tb = reinterpret_cast<uint8_t *>(sred_smem);
+    const int nw = (nb + 1) >> 1;  // dwords per lane and histogram
+    uint32_t *colh = sred_smem + kTile * kStride / 4;
+    uint32_t *rowh = colh + nw * 64;
+    for (int k = 0; k < nw; ++k) {
+        colh[k * 64 + lane] = 0u;
+        rowh[k * 64 + lane] = 0u;
     }
-    lds_order();
-    uint32_t *tot = reinterpret_cast<uint32_t *>(ws + v.ws_stot);
-    if (lane < nb) tot[((int64_t)lane * v.h + y) * v.tiles_x + sg] = h[lane];
+    auto slot = [](uint32_t b) { return (int)(b >> 1) * 64; };
+    auto shift = [](uint32_t b) { return 16u * (b & 1u); };
+    // Adds the votes of entry e to the histogram slots of lane ln.
+    auto vote = [&](uint32_t *h, uint32_t e, int ln) {
+        const uint32_t b0 = e & 255u, w1 = e >> 8;
+        if (b0 < (uint32_t)nb) {
+            const uint32_t b1 = b0 + 1 == (uint32_t)nb ? 0u : b0 + 1;
+            atomicAdd(&h[slot(b0) + ln], (Q - w1) << shift(b0));
+            atomicAdd(&h[slot(b1) + ln], w1 << shift(b1));
+        }
+    };
+    {
+        typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+        // Rows past the level's height read as 0 (outside the buffer range);
+        // the tile's 128 bytes of a row lie inside the row pitch.
+        const __amdgpu_buffer_rsrc_t bsrc = buffer_rsrc(bins + v.bins_off, (uint32_t)(v.bins_pitch * v.h));
+        const int bpitch = (int)v.bins_pitch;
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+            const int k = lane + 64 * m;
+            const int row = k >> 3, seg = k & 7;
+            const u32x4 d = __builtin_amdgcn_raw_buffer_load_b128(
+                bsrc, (ty * kTile + row) * bpitch + tx * 2 * kTile + 16 * seg, 0, 0);
+            uint32_t *dst = reinterpret_cast<uint32_t *>(tb + row * kStride + 16 * seg);
+            dst[0] = d[0];
+            dst[1] = d[1];
+            dst[2] = d[2];
+            dst[3] = d[3];
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    const int y0 = ty * kTile, nrows = min(kTile, v.h - y0);
+    const int ncols = min(kTile, v.w - tx * kTile);
+    // Column totals: lane = column; 16 rows read before their adds.
+    if (lane < ncols) {
+        const uint16_t *cp = reinterpret_cast<const uint16_t *>(tb) + lane;
+        for (int r0 = 0; r0 < nrows; r0 += 16) {
+            uint32_t e[16];
+#pragma unroll
+            for (int j = 0; j < 16; ++j) e[j] = cp[(r0 + j) * (kStride / 2)];
+#pragma unroll
+            for (int j = 0; j < 16; ++j)
+                if (r0 + j < nrows) vote(colh, e[j], lane);
+        }
+    }
+    // Row totals: lane = row; two entries per dword.
+    if (lane < nrows) {
+        const uint32_t *rp = reinterpret_cast<const uint32_t *>(tb + lane * kStride);
+        for (int k0 = 0; k0 < kTile / 2; k0 += 8) {
+            uint32_t d[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) d[j] = rp[k0 + j];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int c = 2 * (k0 + j);
+                if (c < ncols) vote(rowh, d[j] & 0xFFFFu, lane);
+                if (c + 1 < ncols) vote(rowh, d[j] >> 16, lane);
+            }
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    // Row totals [n][tx][hp] (lane = row), column totals [n][ty][wp] (lane =
+    // column; 0 right of the level).
+    const int64_t hp = (int64_t)kTile * v.tiles_y, wp = (int64_t)kTile * v.tiles_x;
+    uint32_t *rowtot = reinterpret_cast<uint32_t *>(ws + v.ws_stot) + (int64_t)tx * hp + y0 + lane;
+    uint32_t *coltot = reinterpret_cast<uint32_t *>(ws + v.ws_scol) + (int64_t)ty * wp + tx * kTile + lane;
+    for (int n = 0; n < nb; ++n) {
+        const uint32_t b = (uint32_t)n;
+        if (lane < nrows) rowtot[(int64_t)n * v.tiles_x * hp] = (rowh[slot(b) + lane] >> shift(b)) & 0xFFFFu;
+        coltot[(int64_t)n * v.tiles_y * wp] = (colh[slot(b) + lane] >> shift(b)) & 0xFFFFu;
+    }
 }
 
-__global__ __launch_bounds__(256) void k_soft_rowscan(const Level *__restrict__ lv,
-                                                      const int32_t *__restrict__ first, int n_levels,
-                                                      uint8_t *__restrict__ ws)
+// Pass 2: one thread per (bin, row) -- exclusive prefix of the row totals
+// over tile columns -- then one per (bin, column) -- exclusive prefix of the
+// column totals over tile rows.
+__global__ __launch_bounds__(256) void k_soft_scan(const Level *__restrict__ lv,
+                                                   const int32_t *__restrict__ first, int n_levels,
+                                                   int nb, uint8_t *__restrict__ ws)
 {
     const int g = (int)(blockIdx.x * 256 + threadIdx.x);
     if (g >= first[n_levels]) return;
     const int l = find_level(first, n_levels, g);
     const Level &v = lv[l];
-    const int rel = g - first[l];  // = n * h + y
-    uint32_t *t = reinterpret_cast<uint32_t *>(ws + v.ws_stot) + (int64_t)rel * v.tiles_x;
+    int rel = g - first[l];
+    const int64_t hp = (int64_t)kTile * v.tiles_y, wp = (int64_t)kTile * v.tiles_x;
+    uint32_t *t;
+    int64_t stride;
+    int count;
+    if (rel < nb * v.h) {  // row job: rel = n * h + y
+        const int n = rel / v.h, y = rel % v.h;
+        t = reinterpret_cast<uint32_t *>(ws + v.ws_stot) + (int64_t)n * v.tiles_x * hp + y;
+        stride = hp;
+        count = v.tiles_x;
+    } else {  // column job: rel = n * wp + x
+        rel -= nb * v.h;
+        const int n = rel / (int)wp, x = rel % (int)wp;
+        t = reinterpret_cast<uint32_t *>(ws + v.ws_scol) + (int64_t)n * v.tiles_y * wp + x;
+        stride = wp;
+        count = v.tiles_y;
+    }
     uint32_t acc = 0;
-    int sg = 0;
-    for (; sg + 8 <= v.tiles_x; sg += 8) {
+    int k = 0;
+    for (; k + 8 <= count; k += 8) {
         uint32_t c[8];
 #pragma unroll
-        for (int i = 0; i < 8; ++i) c[i] = t[sg + i];
+        for (int i = 0; i < 8; ++i) c[i] = t[(k + i) * stride];
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
-            t[sg + i] = acc;
+            t[(k + i) * stride] = acc;
             acc += c[i];
         }
     }
-    for (; sg < v.tiles_x; ++sg) {
-        const uint32_t c = t[sg];
-        t[sg] = acc;
+    for (; k < count; ++k) {
+        const uint32_t c = t[k * stride];
+        t[k * stride] = acc;
         acc += c;
     }
 }
 
+template <bool CELLS>
 __global__ __launch_bounds__(256) void k_soft_emit(const Level *__restrict__ lv,
                                                    const int32_t *__restrict__ first, int n_levels,
                                                    int nb, const uint8_t *__restrict__ bins,
-                                                   const uint8_t *__restrict__ ws,
-                                                   uint32_t *__restrict__ ii)
+                                                   uint8_t *__restrict__ ws, uint32_t *__restrict__ ii)
 {
+    constexpr uint32_t Q = HOG_SOFT_QUANTUM;
     constexpr int kRows = 16;  // bin rows loaded ahead
     const int gw = (int)blockIdx.x * 4 + wave_id_in_block();
-    if (gw >= first[n_levels]) return;
+    if (gw >= first[n_levels]) return;  // whole wave: the scans below need every lane
     const int lane = threadIdx.x & 63;
     const int l = find_level(first, n_levels, gw);
     const Level &v = lv[l];
+    const int pairs = (nb + 1) >> 1;
     const int rel = gw - first[l];
-    const int n = rel / v.tiles_x, sg = rel % v.tiles_x;
-    const int x = sg * kTile + lane;
+    const int tile = rel / pairs, n0 = 2 * (rel % pairs);
+    const int tx = tile % v.tiles_x, ty = tile / v.tiles_x;
+    const bool two = n0 + 1 < nb;  // wave-uniform: the pair's second bin exists
+    // Bin n takes Q - w1 from pixels with b0 == n and w1 from those with
+    // b0 == n - 1 (mod nb); a pixel without a bin (b0 = 255) matches neither.
+    const uint32_t m0 = (uint32_t)n0, p0 = (uint32_t)(n0 == 0 ? nb - 1 : n0 - 1);
+    const uint32_t m1 = (uint32_t)n0 + 1, p1 = (uint32_t)n0;
+    const int x = tx * kTile + lane;
     const bool xin = x < v.w, store = x < v.ii_pitch;
     const int xc = min(x, v.w - 1);
-    const uint32_t *tot = reinterpret_cast<const uint32_t *>(ws + v.ws_stot) + (int64_t)n * v.h * v.tiles_x + sg;
-    const uint8_t *brow = bins + v.bins_off + 2 * (int64_t)xc;
-    uint32_t *out = ii + v.ii_off + (int64_t)n * v.ii_plane + x;
-    uint32_t acc = 0;
-    for (int y0 = 0; y0 < v.h; y0 += kTile) {
-        // Lane i holds the votes left of the segment in row y0 + i.
-        const uint32_t cv = y0 + lane < v.h ? tot[(int64_t)(y0 + lane) * v.tiles_x] : 0u;
-        const int y1 = min(y0 + kTile, v.h);
-        int y = y0;
-        for (; y + kRows <= y1; y += kRows) {
-            uint32_t e[kRows];
-#pragma unroll
-            for (int i = 0; i < kRows; ++i) e[i] = *reinterpret_cast<const uint16_t *>(brow + (int64_t)(y + i) * v.bins_pitch);
-#pragma unroll
-            for (int i = 0; i < kRows; ++i) {
-                const uint32_t vote = xin ? soft_vote_for(e[i], n, nb) : 0u;
-                acc += wave_incl_scan(vote, lane) + (uint32_t)__builtin_amdgcn_readlane((int)cv, y + i - y0);
-                if (store) out[(int64_t)(y + i) * v.ii_pitch] = acc;
-            }
-        }
-        for (; y < y1; ++y) {
-            const uint32_t e = *reinterpret_cast<const uint16_t *>(brow + (int64_t)y * v.bins_pitch);
-            const uint32_t vote = xin ? soft_vote_for(e, n, nb) : 0u;
-            acc += wave_incl_scan(vote, lane) + (uint32_t)__builtin_amdgcn_readlane((int)cv, y - y0);
-            if (store) out[(int64_t)y * v.ii_pitch] = acc;
-        }
+    const int y0 = ty * kTile, y1 = min(y0 + kTile, v.h);
+    const int64_t hp = (int64_t)kTile * v.tiles_y, wp = (int64_t)kTile * v.tiles_x;
+    // Votes left of the tile, per row, of both bins; votes above it, per column.
+    const uint32_t *left0p = reinterpret_cast<const uint32_t *>(ws + v.ws_stot) + ((int64_t)n0 * v.tiles_x + tx) * hp;
+    const uint32_t *left1p = left0p + v.tiles_x * hp;
+    const uint32_t *above0p = reinterpret_cast<const uint32_t *>(ws + v.ws_scol) + ((int64_t)n0 * v.tiles_y + ty) * wp + x;
+    const uint32_t *above1p = above0p + v.tiles_y * wp;
+    // left*: the plane value at column 64 tx - 1 (the votes left of the tile
+    // summed down the rows), here at row y0 - 1.
+    uint32_t s0 = 0, s1 = 0;
+    for (int yb = 0; yb < y0; yb += kTile) {
+        s0 += left0p[yb + lane];
+        if (two) s1 += left1p[yb + lane];
     }
+    uint32_t left0 = (uint32_t)__builtin_amdgcn_readlane((int)wave_incl_scan_dpp(s0), 63);
+    uint32_t left1 = (uint32_t)__builtin_amdgcn_readlane((int)wave_incl_scan_dpp(s1), 63);
+    // ii(x, y0 - 1): the votes left of the tile above it, plus those above
+    // the tile in its columns up to x.
+    uint32_t acc0 = left0 + wave_incl_scan_dpp(above0p[0]);
+    uint32_t acc1 = left1 + wave_incl_scan_dpp(two ? above1p[0] : 0u);
+    const uint8_t *brow = bins + v.bins_off + 2 * (int64_t)xc;
+    uint32_t *out0 = ii + v.ii_off + (int64_t)n0 * v.ii_plane + x;
+    uint32_t *out1 = out0 + v.ii_plane;
+    // Cells: lanes 8c + 7 hold column x1 = 8 cx + 7 of cell cx; prev* is
+    // ii(x1) - ii(x1 - 8) at the previous corner row (row y0 - 1 to start).
+    uint16_t *cache = reinterpret_cast<uint16_t *>(ws + v.ws_cache);
+    const int cx = x >> 3;
+    const bool cell_lane = CELLS && (lane & 7) == 7 && cx < v.cells_x;
+    auto corner_diff = [&](uint32_t a, uint32_t left) {
+        const uint32_t w = __shfl_up(a, 8u);
+        return a - (lane < 8 ? left : w);
+    };
+    uint32_t prev0 = 0, prev1 = 0;
+    if (CELLS) {
+        prev0 = corner_diff(acc0, left0);
+        prev1 = corner_diff(acc1, left1);
+    }
+    auto corner = [&](int y) {  // y = 8 cy + 7, cy < cells_y
+        const int cy = y >> 3;
+        const uint32_t d0 = corner_diff(acc0, left0), d1 = corner_diff(acc1, left1);
+        if (cell_lane) {
+            cache[cache_index(v, n0, cy, cx)] = (uint16_t)(d0 - prev0);
+            if (two) cache[cache_index(v, n0 + 1, cy, cx)] = (uint16_t)(d1 - prev1);
+        }
+        prev0 = d0;
+        prev1 = d1;
+    };
+    // Lane i holds the votes left of the tile in row y0 + i.
+    const bool rin = y0 + lane < v.h;
+    const uint32_t cv0 = rin ? left0p[y0 + lane] : 0u;
+    const uint32_t cv1 = rin && two ? left1p[y0 + lane] : 0u;
+    auto row = [&](uint32_t e, int i) {
+        const int y = y0 + i;
+        e = xin ? e : (uint32_t)kNoBin;
+        const uint32_t b0 = e & 255u, w1 = e >> 8, qw = Q - w1;
+        const uint32_t v0 = (b0 == m0 ? qw : 0u) + (b0 == p0 ? w1 : 0u);
+        const uint32_t v1 = two ? (b0 == m1 ? qw : 0u) + (b0 == p1 ? w1 : 0u) : 0u;
+        const uint32_t sc = wave_incl_scan_dpp(v0 | v1 << 16);
+        const uint32_t c0 = (uint32_t)__builtin_amdgcn_readlane((int)cv0, i);
+        const uint32_t c1 = (uint32_t)__builtin_amdgcn_readlane((int)cv1, i);
+        acc0 += (sc & 0xFFFFu) + c0;
+        acc1 += (sc >> 16) + c1;
+        left0 += c0;
+        left1 += c1;
+        if (store) {
+            out0[(int64_t)y * v.ii_pitch] = acc0;
+            if (two) out1[(int64_t)y * v.ii_pitch] = acc1;
+        }
+        if (CELLS && (y & 7) == 7 && (y >> 3) < v.cells_y) corner(y);
+    };
+    int y = y0;
+    for (; y + kRows <= y1; y += kRows) {  // y - y0 is a multiple of 16
+        uint32_t e[kRows];
+#pragma unroll
+        for (int i = 0; i < kRows; ++i) e[i] = *reinterpret_cast<const uint16_t *>(brow + (int64_t)(y + i) * v.bins_pitch);
+#pragma unroll
+        for (int i = 0; i < kRows; ++i) row(e[i], y + i - y0);
+    }
+    for (; y < y1; ++y) row(*reinterpret_cast<const uint16_t *>(brow + (int64_t)y * v.bins_pitch), y - y0);
 }
 
 // Cell histograms cached by k_int_emit, exported as uint32 [cy][cx][n].
@@ -1713,19 +1876,25 @@ hipError_t launch_bin_map_soft(const PlanDev &p, const uint16_t *soft_lut, const
 }
 
 hipError_t launch_soft_integral(const PlanDev &p, const uint8_t *bins, uint8_t *ws, uint32_t *ii,
-                                hipStream_t stream)
+                                bool cells, hipStream_t stream)
 {
     if (p.total[KB_SSEG] == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_soft_segtot, dim3(blocks_for(p.total[KB_SSEG], 4)), dim3(256), 0, stream, p.levels,
+    const size_t lds = (size_t)kTile * (2 * kTile + 4) + (size_t)((p.n_bins + 1) / 2) * 64 * 4 * 2;
+    hipLaunchKernelGGL(k_soft_reduce, dim3((unsigned)p.total[KB_SSEG]), dim3(64), lds, stream, p.levels,
                        first_of(p, KB_SSEG), p.n_levels, p.n_bins, bins, ws);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_soft_rowscan, dim3(blocks_for(p.total[KB_SSCAN], 256)), dim3(256), 0, stream, p.levels,
-                       first_of(p, KB_SSCAN), p.n_levels, ws);
+    hipLaunchKernelGGL(k_soft_scan, dim3(blocks_for(p.total[KB_SSCAN], 256)), dim3(256), 0, stream, p.levels,
+                       first_of(p, KB_SSCAN), p.n_levels, p.n_bins, ws);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_soft_emit, dim3(blocks_for(p.total[KB_SEMIT], 4)), dim3(256), 0, stream, p.levels,
-                       first_of(p, KB_SEMIT), p.n_levels, p.n_bins, bins, ws, ii);
+    const dim3 grid(blocks_for(p.total[KB_SEMIT], 4));
+    if (cells)
+        hipLaunchKernelGGL(k_soft_emit<true>, grid, dim3(256), 0, stream, p.levels, first_of(p, KB_SEMIT),
+                           p.n_levels, p.n_bins, bins, ws, ii);
+    else
+        hipLaunchKernelGGL(k_soft_emit<false>, grid, dim3(256), 0, stream, p.levels, first_of(p, KB_SEMIT),
+                           p.n_levels, p.n_bins, bins, ws, ii);
     return hipGetLastError();
 }
 

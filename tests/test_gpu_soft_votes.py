@@ -23,6 +23,7 @@ CASES = [
     dict(width=300, height=260, channels=3, n_bins=9, cell=12, win_cells_x=5, win_cells_y=8,
          norm=hog.HOG_NORM_L2),
     dict(width=200, height=170, channels=1, n_bins=1),
+    dict(width=150, height=140, channels=3, n_bins=2),  # one pair of bins, each the other's neighbour
 ]
 
 
