@@ -908,8 +908,7 @@ __global__ __launch_bounds__(256) void k_soft_emit(const Level *__restrict__ lv,
     const uint32_t m0 = (uint32_t)n0, p0 = (uint32_t)(n0 == 0 ? nb - 1 : n0 - 1);
     const uint32_t m1 = (uint32_t)n0 + 1, p1 = (uint32_t)n0;
     const int x = tx * kTile + lane;
-    const bool xin = x < v.w, store = x < v.ii_pitch;
-    const int xc = min(x, v.w - 1);
+    const bool xin = x < v.w;
     const int y0 = ty * kTile, y1 = min(y0 + kTile, v.h);
     const int64_t hp = (int64_t)kTile * v.tiles_y, wp = (int64_t)kTile * v.tiles_x;
     // Votes left of the tile, per row, of both bins; votes above it, per column.
@@ -918,9 +917,20 @@ __global__ __launch_bounds__(256) void k_soft_emit(const Level *__restrict__ lv,
     const uint32_t *above0p = reinterpret_cast<const uint32_t *>(ws + v.ws_scol) + ((int64_t)n0 * v.tiles_y + ty) * wp + x;
     const uint32_t *above1p = above0p + v.tiles_y * wp;
     // left*: the plane value at column 64 tx - 1 (the votes left of the tile
-    // summed down the rows), here at row y0 - 1.
+    // summed down the rows), here at row y0 - 1; four tile rows per step.
     uint32_t s0 = 0, s1 = 0;
-    for (int yb = 0; yb < y0; yb += kTile) {
+    int yb = 0;
+    for (; yb + 4 * kTile <= y0; yb += 4 * kTile) {
+        uint32_t a[4], b[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            a[k] = left0p[yb + k * kTile + lane];
+            b[k] = two ? left1p[yb + k * kTile + lane] : 0u;
+        }
+        s0 += (a[0] + a[1]) + (a[2] + a[3]);
+        s1 += (b[0] + b[1]) + (b[2] + b[3]);
+    }
+    for (; yb < y0; yb += kTile) {
         s0 += left0p[yb + lane];
         if (two) s1 += left1p[yb + lane];
     }
@@ -930,9 +940,6 @@ __global__ __launch_bounds__(256) void k_soft_emit(const Level *__restrict__ lv,
     // the tile in its columns up to x.
     uint32_t acc0 = left0 + wave_incl_scan_dpp(above0p[0]);
     uint32_t acc1 = left1 + wave_incl_scan_dpp(two ? above1p[0] : 0u);
-    const uint8_t *brow = bins + v.bins_off + 2 * (int64_t)xc;
-    uint32_t *out0 = ii + v.ii_off + (int64_t)n0 * v.ii_plane + x;
-    uint32_t *out1 = out0 + v.ii_plane;
     // Cells: lanes 8c + 7 hold column x1 = 8 cx + 7 of cell cx; prev* is
     // ii(x1) - ii(x1 - 8) at the previous corner row (row y0 - 1 to start).
     uint16_t *cache = reinterpret_cast<uint16_t *>(ws + v.ws_cache);
@@ -961,6 +968,38 @@ __global__ __launch_bounds__(256) void k_soft_emit(const Level *__restrict__ lv,
     const bool rin = y0 + lane < v.h;
     const uint32_t cv0 = rin ? left0p[y0 + lane] : 0u;
     const uint32_t cv1 = rin && two ? left1p[y0 + lane] : 0u;
+    // The tile's soft entries (64 rows of 128 bytes) staged in LDS: with these
+    // every global load happens before the first plane store (on gfx9 one
+    // counter tracks loads and stores, so a load waited for between stores
+    // would also wait for every store before it). Rows past the level's
+    // height read as 0 and are never used; columns right of it are masked.
+    __shared__ __attribute__((aligned(16))) uint8_t stiles[4][2 * kTile * kTile];
+    uint8_t *tb = stiles[wave_id_in_block()];
+    {
+        typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+        const __amdgpu_buffer_rsrc_t bsrc = buffer_rsrc(bins + v.bins_off, (uint32_t)(v.bins_pitch * v.h));
+        const int bpitch = (int)v.bins_pitch;
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+            const int k = lane + 64 * m;
+            const int r = k >> 3, seg = k & 7;
+            const u32x4 d = __builtin_amdgcn_raw_buffer_load_b128(
+                bsrc, (y0 + r) * bpitch + tx * 2 * kTile + 16 * seg, 0, 0);
+            *reinterpret_cast<u32x4 *>(tb + r * 2 * kTile + 16 * seg) = d;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    }
+    const uint16_t *te = reinterpret_cast<const uint16_t *>(tb) + lane;
+    // The pair's planes as one buffer (2 planes * 4 bytes < 2^31: the plan
+    // keeps w * h * Q below 2^32). Lanes right of the row pitch store at its
+    // last element: right of the level every lane holds the value of column
+    // w - 1, so those duplicate stores write the same value.
+    const int planeb = (int)(v.ii_plane * 4), pitchb = (int)(v.ii_pitch * 4);
+    // (The size is made wave-uniform explicitly: a descriptor the compiler
+    // takes for divergent costs a loop around every store.)
+    const uint32_t isize = (uint32_t)__builtin_amdgcn_readfirstlane((two ? 2 : 1) * planeb);
+    const __amdgpu_buffer_rsrc_t isrc = buffer_rsrc(ii + v.ii_off + (int64_t)n0 * v.ii_plane, isize);
+    const int colb = min(x, (int)v.ii_pitch - 1) * 4;
     auto row = [&](uint32_t e, int i) {
         const int y = y0 + i;
         e = xin ? e : (uint32_t)kNoBin;
@@ -974,21 +1013,16 @@ __global__ __launch_bounds__(256) void k_soft_emit(const Level *__restrict__ lv,
         acc1 += (sc >> 16) + c1;
         left0 += c0;
         left1 += c1;
-        if (store) {
-            out0[(int64_t)y * v.ii_pitch] = acc0;
-            if (two) out1[(int64_t)y * v.ii_pitch] = acc1;
-        }
+        __builtin_amdgcn_raw_buffer_store_b32(acc0, isrc, colb, y * pitchb, 0);
+        if (two) __builtin_amdgcn_raw_buffer_store_b32(acc1, isrc, colb, planeb + y * pitchb, 0);
         if (CELLS && (y & 7) == 7 && (y >> 3) < v.cells_y) corner(y);
     };
     int y = y0;
     for (; y + kRows <= y1; y += kRows) {  // y - y0 is a multiple of 16
-        uint32_t e[kRows];
 #pragma unroll
-        for (int i = 0; i < kRows; ++i) e[i] = *reinterpret_cast<const uint16_t *>(brow + (int64_t)(y + i) * v.bins_pitch);
-#pragma unroll
-        for (int i = 0; i < kRows; ++i) row(e[i], y + i - y0);
+        for (int i = 0; i < kRows; ++i) row(te[(y + i - y0) * kTile], y + i - y0);
     }
-    for (; y < y1; ++y) row(*reinterpret_cast<const uint16_t *>(brow + (int64_t)y * v.bins_pitch), y - y0);
+    for (; y < y1; ++y) row(te[(y - y0) * kTile], y - y0);
 }
 
 // Cell histograms cached by k_int_emit, exported as uint32 [cy][cx][n].
