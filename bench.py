@@ -2,10 +2,10 @@
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
 
-A step is one pass of the whole path over one synthetic image:
-hog_bin_map (every pyramid level), hog_integral (one integral image per bin
-per level) and hog_scan_windows (cells, blocks, window scores), through the
-C ABI, with the image, templates and all buffers resident in HBM. With
+A step is one pass of the whole path over one synthetic image: one hog_run
+(bin map of every pyramid level, one integral image per bin per level, cells,
+blocks and window scores) through the C ABI, with the image, templates and
+all buffers resident in HBM. With
 --workload batch64 a step is one pass over a batch of 64 images (one batch
 plan, replayed as a captured HIP graph); the line then also gives the same
 images run through 64 single-image plans, one after another. With
@@ -16,8 +16,10 @@ server's throughput at that offered load, with its latency percentiles.
 
 Prints one JSON line: processed Mpixel/s (pixels summed over pyramid
 levels), per-step latency percentiles, per-kernel times, the roofline of the
-dominant kernel (the integral-image writer) measured live with HIP events,
-and the CPU oracle timed on this host over one full step.
+dominant kernel (the integral-image writer) measured live with HIP events
+(beside this GPU's own 1 GiB copy and fill rates), the rate with the image
+copied from pinned host memory each step, the input's bin statistics, and
+the CPU oracle timed on this host over one full step.
 """
 from __future__ import annotations
 
@@ -343,12 +345,37 @@ def main():
             extra[name] = dict(ms=round(t, 4), mpixel_per_s=round(sz.total_pixels / (t * 1e3), 1))
         extra["speedup_vs_per_image"] = round(extra["per_image"]["ms"] / ms_per_step, 3)
         del singles
+    # This GPU's plain 1 GiB copy (read + write) and fill (write only) rates,
+    # timed the same way on the same stream: what a bandwidth-bound kernel
+    # reaches in practice, beside the 8 TB/s peak.
+    src = torch.ones(1 << 28, dtype=torch.int32, device="cuda")
+    dst = torch.empty_like(src)
+
+    def rate(fn, nbytes, reps=5):
+        fn()
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(reps):
+            fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        return nbytes * reps / (a.elapsed_time(b) * 1e-3) / 1e9
+
+    copy_gbs = rate(lambda: dst.copy_(src), 2 * 4 * src.numel())
+    fill_gbs = rate(lambda: dst.fill_(7), 4 * dst.numel())
+    del src, dst
+
     emit_us = kern_us.get(emit_kernel, float("nan"))
     achieved = emit_bytes / (emit_us * 1e-6) / 1e9
+    traffic = None if soft else measured_traffic(args.workload, tiles.bin_chunk)
     roofline = dict(bound="hbm", kernel=emit_kernel, achieved=round(achieved, 1),
                     peak=HBM_PEAK_GBS, unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4),
-                    traffic=None if soft else measured_traffic(args.workload, tiles.bin_chunk),
-                    algorithmic_bytes_per_launch=emit_bytes)
+                    traffic=traffic, algorithmic_bytes_per_launch=emit_bytes,
+                    measured=None if traffic is None else round(traffic / (emit_us * 1e-6) / 1e9, 1),
+                    copy_GBps=round(copy_gbs, 1), fill_GBps=round(fill_gbs, 1),
+                    frac_of_fill=round(achieved / fill_gbs, 4))
 
     if args.copy_calibration:
         # A plain copy of known size: its FETCH_SIZE / WRITE_SIZE counters give
