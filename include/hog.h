@@ -432,8 +432,10 @@ hog_status hog_wait_any(hog_server *server, uint64_t *tickets, int cap, int64_t 
 /* bracketed by a pair of HIP events recorded on the launch stream; totals  */
 /* accumulate per kernel name until hog_timing_reset. Not thread-safe.      */
 /* Names: "bin_map", "integral_reduce", "integral_scan", "integral_emit",   */
-/* "integral_soft" (soft votes),                                             */
-/* "cells", "score", "block_features".                                       */
+/* "integral_soft" (soft votes: tile reduce, prefixes and plane writer, the */
+/* writer also caching 8-pixel cells), "cells", "score", "block_features",  */
+/* and, for hog_run with level groups, "score_prep" (the template weights,  */
+/* prepared once); there each kernel is timed per level group.              */
 /* ------------------------------------------------------------------------ */
 hog_status hog_timing_enable(int on);
 hog_status hog_timing_reset(void);
