@@ -376,13 +376,18 @@ __device__ __forceinline__ void lds_order()
     asm volatile("" ::: "memory");
 }
 
-__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v, int lane)
+// Inclusive prefix sum over the 64 lanes of a full wave, by DPP: shifts of
+// 1, 2, 4 and 8 lanes inside each row of 16 (zero fill), then the last lane
+// of row 0 (row 2) added to row 1 (row 3), then the last lane of row 1 added
+// to rows 2 and 3. Every lane must be active.
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v)
 {
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const uint32_t o = __shfl_up(v, (unsigned)d);
-        if (lane >= d) v += o;
-    }
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xF, 0xF, true);   // row_shr:1
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xF, 0xF, true);   // row_shr:2
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xF, 0xF, true);   // row_shr:4
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xF, 0xF, true);   // row_shr:8
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xA, 0xF, false);  // row_bcast:15
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xC, 0xF, false);  // row_bcast:31
     return v;
 }
 
@@ -482,7 +487,7 @@ __global__ __launch_bounds__(256) void k_int_scan(const Level *__restrict__ lv,
                 for (int i = 0; i < kRows; ++i) {
                     if (ty0 + i < v.tiles_y) {  // wave-uniform
                         if (on) P[((int64_t)(ty0 + i) * v.tiles_x + tx) * nb] = above[c];
-                        const uint32_t incl = wave_incl_scan(t[i], lane);
+                        const uint32_t incl = wave_incl_scan(t[i]);
                         above[c] += carry[i] + incl - t[i];  // plus this row's tiles left of tx
                         carry[i] += (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
                     }
@@ -558,7 +563,7 @@ __global__ __launch_bounds__(256) void k_int_emit(const Level *__restrict__ lv,
 #pragma unroll
     for (int j = 0; j < NBC; ++j) {
         const uint32_t pj = j < nbc ? Pb[j] : 0u;
-        run[j] = pj + wave_incl_scan(j < nbc ? (uint32_t)CSb[(int64_t)j * wp + x] : 0u, lane);
+        run[j] = pj + wave_incl_scan(j < nbc ? (uint32_t)CSb[(int64_t)j * wp + x] : 0u);
         top[j] = run[j];
         lrun[j] = pj;
         ltop[j] = pj;
@@ -721,22 +726,6 @@ __global__ __launch_bounds__(256) void k_cells(const Level *__restrict__ lv,
 //      the writer also caches every cell (Eq. 6) at each 8th row, as
 //      k_int_emit does.
 // ---------------------------------------------------------------------------
-
-// Inclusive prefix sum over the 64 lanes of a full wave, by DPP: shifts of
-// 1, 2, 4 and 8 lanes inside each row of 16 (zero fill), then the last lane
-// of row 0 (row 2) added to row 1 (row 3), then the last lane of row 1 added
-// to rows 2 and 3. Every lane must be active.
-__device__ __forceinline__ uint32_t wave_incl_scan_dpp(uint32_t v)
-{
-    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xF, 0xF, true);   // row_shr:1
-    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xF, 0xF, true);   // row_shr:2
-    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xF, 0xF, true);   // row_shr:4
-    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xF, 0xF, true);   // row_shr:8
-    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xA, 0xF, false);  // row_bcast:15
-    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xC, 0xF, false);  // row_bcast:31
-    return v;
-}
-
 __global__ __launch_bounds__(64) void k_soft_reduce(const Level *__restrict__ lv,
                                                     const int32_t *__restrict__ first, int n_levels,
                                                     int nb, const uint8_t *__restrict__ bins,
@@ -934,12 +923,12 @@ __global__ __launch_bounds__(256) void k_soft_emit(const Level *__restrict__ lv,
         s0 += left0p[yb + lane];
         if (two) s1 += left1p[yb + lane];
     }
-    uint32_t left0 = (uint32_t)__builtin_amdgcn_readlane((int)wave_incl_scan_dpp(s0), 63);
-    uint32_t left1 = (uint32_t)__builtin_amdgcn_readlane((int)wave_incl_scan_dpp(s1), 63);
+    uint32_t left0 = (uint32_t)__builtin_amdgcn_readlane((int)wave_incl_scan(s0), 63);
+    uint32_t left1 = (uint32_t)__builtin_amdgcn_readlane((int)wave_incl_scan(s1), 63);
     // ii(x, y0 - 1): the votes left of the tile above it, plus those above
     // the tile in its columns up to x.
-    uint32_t acc0 = left0 + wave_incl_scan_dpp(above0p[0]);
-    uint32_t acc1 = left1 + wave_incl_scan_dpp(two ? above1p[0] : 0u);
+    uint32_t acc0 = left0 + wave_incl_scan(above0p[0]);
+    uint32_t acc1 = left1 + wave_incl_scan(two ? above1p[0] : 0u);
     // Cells: lanes 8c + 7 hold column x1 = 8 cx + 7 of cell cx; prev* is
     // ii(x1) - ii(x1 - 8) at the previous corner row (row y0 - 1 to start).
     uint16_t *cache = reinterpret_cast<uint16_t *>(ws + v.ws_cache);
@@ -1006,7 +995,7 @@ __global__ __launch_bounds__(256) void k_soft_emit(const Level *__restrict__ lv,
         const uint32_t b0 = e & 255u, w1 = e >> 8, qw = Q - w1;
         const uint32_t v0 = (b0 == m0 ? qw : 0u) + (b0 == p0 ? w1 : 0u);
         const uint32_t v1 = two ? (b0 == m1 ? qw : 0u) + (b0 == p1 ? w1 : 0u) : 0u;
-        const uint32_t sc = wave_incl_scan_dpp(v0 | v1 << 16);
+        const uint32_t sc = wave_incl_scan(v0 | v1 << 16);
         const uint32_t c0 = (uint32_t)__builtin_amdgcn_readlane((int)cv0, i);
         const uint32_t c1 = (uint32_t)__builtin_amdgcn_readlane((int)cv1, i);
         acc0 += (sc & 0xFFFFu) + c0;
