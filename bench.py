@@ -63,7 +63,7 @@ WORKLOADS = {
     "pyramid_1920x1080_u8": dict(width=1920, height=1080, channels=3, n_bins=18, max_levels=0,
                                  scale=1.05, norm=1, seed=1002, tseed=9002, plane_bits=8),
     # The pyramid workload with two-bin soft votes (quantised to 1/32 pixel):
-    # weighted uint32 planes from a row pass and a column pass.
+    # weighted uint32 planes, each written once (tile reduce, prefixes, writer).
     "pyramid_1920x1080_soft": dict(width=1920, height=1080, channels=3, n_bins=18, max_levels=0,
                                    scale=1.05, norm=1, seed=1002, tseed=9002, votes=1),
 }
