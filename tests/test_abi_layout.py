@@ -54,8 +54,29 @@ def test_ctypes_structs_match_the_header(tmp_path):
             assert size == ctypes.sizeof(t), f"{cname}.{f} size"
 
 
-def test_header_constants_match_the_binding():
-    text = open(os.path.join(ROOT, "include", "hog.h")).read()
-    for name in ("HOG_SOFT_QUANTUM", "HOG_MAX_LEVEL_GROUPS", "HOG_NO_BIN"):
-        line = next(ln for ln in text.splitlines() if ln.startswith(f"#define {name} "))
-        assert int(line.split()[2]) == getattr(hog, name), name
+CONSTANTS = {  # header name -> binding name
+    **{n: n for n in ("HOG_OK", "HOG_E_INVALID", "HOG_E_NOMEM", "HOG_E_DEVICE", "HOG_E_BUSY",
+                      "HOG_E_NOT_READY", "HOG_NO_BIN", "HOG_NORM_RAW", "HOG_NORM_L2",
+                      "HOG_ORIENT_SIGNED", "HOG_ORIENT_UNSIGNED", "HOG_VOTES_HARD", "HOG_VOTES_SOFT",
+                      "HOG_SOFT_QUANTUM", "HOG_MAX_LEVEL_GROUPS")},
+    "HOG_LUT_SIDE": "LUT_SIDE",
+}
+
+
+@pytest.mark.skipif(shutil.which("gcc") is None, reason="needs gcc")
+def test_header_constants_match_the_binding(tmp_path):
+    """Every enum value and #define the binding mirrors, as the C compiler
+    sees it through the header."""
+    lines = ['#include <stdio.h>', '#include "hog.h"', "int main(void) {"]
+    lines += [f'    printf("{c} %d\\n", (int)({c}));' for c in CONSTANTS]
+    lines += ["    return 0;", "}"]
+    src = tmp_path / "consts.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "consts"
+    r = subprocess.run(["gcc", "-std=c99", "-Wall", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                       capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout
+    got = dict((k, int(v)) for k, v in (ln.split() for ln in out.splitlines()))
+    for c, py in CONSTANTS.items():
+        assert got[c] == getattr(hog, py), c
