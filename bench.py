@@ -420,7 +420,10 @@ def main():
                     traffic=traffic, algorithmic_bytes_per_launch=emit_bytes,
                     measured=None if traffic is None else round(traffic / (emit_us * 1e-6) / 1e9, 1),
                     copy_GBps=round(copy_gbs, 1), fill_GBps=round(fill_gbs, 1),
-                    frac_of_fill=round(achieved / fill_gbs, 4))
+                    frac_of_fill=round(achieved / fill_gbs, 4), frac_of_copy=round(achieved / copy_gbs, 4))
+    if traffic is not None:
+        roofline["measured_frac"] = round(roofline["measured"] / HBM_PEAK_GBS, 4)
+        roofline["measured_frac_of_copy"] = round(roofline["measured"] / copy_gbs, 4)
 
     if args.copy_calibration:
         # A plain copy of known size: its FETCH_SIZE / WRITE_SIZE counters give
