@@ -100,6 +100,28 @@ def batch_sizes(wl):
     return [(int(rng.integers(320, 1921)), int(rng.integers(240, 1081))) for _ in range(wl["batch"])]
 
 
+def workload_inputs(wl):
+    """A workload's plan, its host images, the flat host input the step reads
+    (the image, or the batch packed as the plan says) and its templates and
+    biases, all seeded."""
+    import numpy as np
+    from paper_1703_06256_amd import hog, inputs
+    kw = dict(channels=wl["channels"], n_bins=wl["n_bins"], max_levels=wl["max_levels"], scale=wl["scale"],
+              norm=wl["norm"], n_templates=wl.get("templates", 1), plane_bits=wl.get("plane_bits", 32),
+              votes=wl.get("votes", 0))
+    if "batch" in wl:
+        sizes = batch_sizes(wl)
+        plan = hog.Plan([hog.make_desc(w, h, **kw) for w, h in sizes], batch=True)
+        imgs = [inputs.synth_image(w, h, wl["channels"], wl["seed"] + j) for j, (w, h) in enumerate(sizes)]
+        host = hog.pack_images(plan, imgs)
+    else:
+        plan = hog.Plan(hog.make_desc(wl["width"], wl["height"], **kw))
+        imgs = [inputs.synth_image(wl["width"], wl["height"], wl["channels"], wl["seed"])]
+        host = np.ascontiguousarray(imgs[0].reshape(-1))
+    tmpl, bias = inputs.synth_templates(kw["n_templates"], plan.sizes.feature_dim, wl["tseed"])
+    return plan, imgs, host, tmpl, bias
+
+
 def oracle_image(img, wl, w, h, tmpl, bias):
     """The oracle over one image's whole pyramid; returns processed pixels."""
     import oracle
@@ -188,25 +210,10 @@ def main():
     wl = WORKLOADS[args.workload]
     batch = "batch" in wl
     K = wl.get("templates", 1)
-    if batch:
-        sizes = batch_sizes(wl)
-        descs = [hog.make_desc(w, h, channels=wl["channels"], n_bins=wl["n_bins"],
-                               max_levels=wl["max_levels"], scale=wl["scale"], norm=wl["norm"],
-                               n_templates=K, plane_bits=wl.get("plane_bits", 32),
-                               votes=wl.get("votes", 0)) for w, h in sizes]
-        plan = hog.Plan(descs, batch=True)
-        imgs = [inputs.synth_image(w, h, wl["channels"], wl["seed"] + j) for j, (w, h) in enumerate(sizes)]
-        img_t = torch.from_numpy(hog.pack_images(plan, imgs)).cuda()
-    else:
-        desc = hog.make_desc(wl["width"], wl["height"], channels=wl["channels"], n_bins=wl["n_bins"],
-                             max_levels=wl["max_levels"], scale=wl["scale"], norm=wl["norm"],
-                             n_templates=K, plane_bits=wl.get("plane_bits", 32), votes=wl.get("votes", 0))
-        plan = hog.Plan(desc)
-        img = inputs.synth_image(wl["width"], wl["height"], wl["channels"], wl["seed"])
-        img_t = torch.from_numpy(img.reshape(-1)).cuda()
+    plan, imgs, host_img, tmpl, bias = workload_inputs(wl)
+    img_t = torch.from_numpy(host_img).cuda()
     sz = plan.sizes
     lut = hog.hog_lut_build(wl["n_bins"])
-    tmpl, bias = inputs.synth_templates(K, sz.feature_dim, wl["tseed"])
     tmpl_t = torch.from_numpy(tmpl.reshape(-1)).cuda()
     bias_t = torch.from_numpy(bias).cuda()
     buf = hog.Buffers(plan)
@@ -362,8 +369,8 @@ def main():
         # The same images through 64 single-image plans, launched one image
         # after another (eager), and the batch plan launched eagerly.
         singles = []
-        for j, (w, h) in enumerate(sizes):
-            p1 = hog.Plan(descs[j])
+        for j in range(len(imgs)):
+            p1 = hog.Plan(plan.descs[j])
             b1 = hog.Buffers(p1)
             singles.append((p1, torch.from_numpy(imgs[j].reshape(-1)).cuda(), b1))
 
@@ -471,7 +478,7 @@ def main():
             "tiles": {"bin_chunk": tiles.bin_chunk, "score_rows": tiles.score_rows,
                       "level_groups": tiles.level_groups, "how": "autotuned"},
         },
-        "base_mpixel_per_s": round(sum(w * h for w, h in sizes) / (ms_per_step * 1e3), 2) if batch
+        "base_mpixel_per_s": round(sum(d.width * d.height for d in plan.descs) / (ms_per_step * 1e3), 2) if batch
         else round(wl["width"] * wl["height"] / (ms_per_step * 1e3), 2),
         "p50_ms": round(float(np.percentile(lat, 50)), 4),
         "p99_ms": round(float(np.percentile(lat, 99)), 4),

@@ -174,14 +174,10 @@ def test_full_batch64_in_the_benchmarked_launch():
     sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
     import bench
     wl = bench.WORKLOADS["batch64"]
-    sizes = bench.batch_sizes(wl)
-    descs = [hog.make_desc(w, h, channels=3, n_bins=8, max_levels=0, scale=1.1, n_templates=32,
-                           norm=hog.HOG_NORM_L2) for w, h in sizes]
-    plan = hog.Plan(descs, batch=True)
-    assert plan.sizes.n_levels == 1088
-    imgs = [inputs.synth_image(w, h, 3, wl["seed"] + j) for j, (w, h) in enumerate(sizes)]
-    packed = torch.from_numpy(hog.pack_images(plan, imgs)).cuda()
-    tmpl, bias = inputs.synth_templates(32, plan.sizes.feature_dim, wl["tseed"])
+    plan, imgs, host, tmpl, bias = bench.workload_inputs(wl)
+    descs = plan.descs
+    assert plan.sizes.n_levels == 1088 and tmpl.shape[0] == 32
+    packed = torch.from_numpy(host).cuda()
     tt, bt = torch.from_numpy(tmpl.reshape(-1)).cuda(), torch.from_numpy(bias).cuda()
     lut = hog.hog_lut_build(8)
     buf = hog.Buffers(plan, cell_hist=False, block_feat=False)
