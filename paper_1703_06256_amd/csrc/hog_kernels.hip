@@ -1768,26 +1768,51 @@ __global__ __launch_bounds__(256, NBP == 8 ? 2 : 1) void k_score_wgemm(const Lev
                         &ring[(wy0 + by + rho + w) % kWgSlots][(32 * mu + n + bx) * NBP + kf % (2 * NBP)]);
                 }
             }
+            float iv[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) iv[q] = invb[wave + 4 * (q >> 1)][32 * (q & 1) + n + bx];
             float16v_t d[4];
 #pragma unroll
             for (int q = 0; q < 4; ++q)
 #pragma unroll
                 for (int r = 0; r < 16; ++r) d[q][r] = 0.f;
+            // Left alone, the compiler issues all 16 products and then the 64
+            // scalings. The scheduling barriers make it issue the products
+            // of q = 0, 1 first, then alternate those of q = 2, 3 with the
+            // scalings of q = 0, 1 (group masks: 0x008 matrix instructions,
+            // 0x002 other vector ALU), so both units work at once. Each
+            // S[q][r] still takes its terms in bx order.
 #pragma unroll
             for (int s2 = 0; s2 < KS; ++s2)
 #pragma unroll
-                for (int q = 0; q < 4; ++q) d[q] = __builtin_amdgcn_mfma_f32_32x32x16_f16(bh[s2], wf[q][s2], d[q], 0, 0, 0);
+                for (int q = 0; q < 2; ++q) d[q] = __builtin_amdgcn_mfma_f32_32x32x16_f16(bh[s2], wf[q][s2], d[q], 0, 0, 0);
 #pragma unroll
             for (int s2 = 0; s2 < KS; ++s2)
 #pragma unroll
-                for (int q = 0; q < 4; ++q) d[q] = __builtin_amdgcn_mfma_f32_32x32x16_f16(bl[s2], wf[q][s2], d[q], 0, 0, 0);
+                for (int q = 0; q < 2; ++q) d[q] = __builtin_amdgcn_mfma_f32_32x32x16_f16(bl[s2], wf[q][s2], d[q], 0, 0, 0);
+            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int rho = wave + 4 * (q >> 1), mu = q & 1;
-                const float iv = invb[rho][32 * mu + n + bx];
+            for (int s2 = 0; s2 < KS; ++s2)
 #pragma unroll
-                for (int r = 0; r < 16; ++r) S[q][r] = fmaf(d[q][r], iv, S[q][r]);
+                for (int q = 2; q < 4; ++q) d[q] = __builtin_amdgcn_mfma_f32_32x32x16_f16(bh[s2], wf[q][s2], d[q], 0, 0, 0);
+#pragma unroll
+            for (int s2 = 0; s2 < KS; ++s2)
+#pragma unroll
+                for (int q = 2; q < 4; ++q) d[q] = __builtin_amdgcn_mfma_f32_32x32x16_f16(bl[s2], wf[q][s2], d[q], 0, 0, 0);
+#pragma unroll
+            for (int q = 0; q < 2; ++q)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) S[q][r] = fmaf(d[q][r], iv[q], S[q][r]);
+#pragma unroll
+            for (int i = 0; i < 4 * KS; ++i) {
+                __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+                __builtin_amdgcn_sched_group_barrier(0x002, 32 / (4 * KS), 0);
             }
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int q = 2; q < 4; ++q)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) S[q][r] = fmaf(d[q][r], iv[q], S[q][r]);
         }
         __syncthreads();  // done with this by's ring slot, fragments and norms
         if (by + 1 < nby) {
