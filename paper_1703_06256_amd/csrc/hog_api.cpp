@@ -509,8 +509,10 @@ static hog_status create_plan(const hog_plan_desc *descs, int n_img, bool batch,
         v.tiles_y = (lh + hogk::kTile - 1) / hogk::kTile;
         v.bm_gx = (lw + hogk::kBinCols - 1) / hogk::kBinCols;
         v.bm_gy = (lh + hogk::kBinRows - 1) / hogk::kBinRows;
-        v.st_x = v.win_x ? (v.win_x + best_tw - 1) / best_tw : 0;
-        v.st_y = v.win_y ? (v.win_y + best_th - 1) / best_th : 0;
+        const bool narrow = scorer == 2 && hogk::wgemm_narrow(v.win_x);  // as k_score_wgemm tiles it
+        const int tw = narrow ? hogk::kWgW / 2 : best_tw, th = narrow ? 2 * hogk::kWgTH : best_th;
+        v.st_x = v.win_x ? (v.win_x + tw - 1) / tw : 0;
+        v.st_y = v.win_y ? (v.win_y + th - 1) / th : 0;
         v.src_w = d.width;
         v.src_h = d.height;
         v.src_off = ii_info.img_offset;

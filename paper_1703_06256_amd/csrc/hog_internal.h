@@ -33,6 +33,9 @@ constexpr int kStripMaxBX = 7;
 // 32 templates.
 constexpr int kWgW = 64;
 constexpr int kWgTH = 8;
+// Levels at most kWgW / 2 windows wide take tiles of kWgW / 2 x 2 kWgTH
+// windows instead, so that they do not leave half of each tile empty.
+constexpr bool wgemm_narrow(int win_x) { return win_x <= kWgW / 2; }
 
 // Workspace bytes of one template's prepared weights for nbp bin slots per
 // cell: fragments [bx][step][hi|lo][lane] of 16 bytes (one step per 32 or, at

@@ -1545,15 +1545,30 @@ __global__ __launch_bounds__(256, 2) void k_score_strip(const Level *__restrict_
 // fp16; k_score_prep_wg scales each template by a power of two (its max |T|
 // into [2^14, 2^15)) and splits it into fp16 hi + lo.
 //
-// A workgroup covers kWgW window columns x kWgTH window rows for one tile of
-// 32 templates; wave w owns rows w and w + 4, each as two 32-window halves.
-// It walks by = 0 .. nby - 1: cell rows wy0 + by .. + kWgTH sit in an LDS
-// ring (one new row per by), the norms of the kWgTH block rows are
-// recomputed, and the template fragments of the positions (by, 0 .. 6) are in
-// LDS, double-buffered and fetched one by ahead.
+// A workgroup covers one tile of windows for one tile of 32 templates, in
+// one of two shapes (WgShape): kWgW window columns x kWgTH rows, where wave w
+// owns rows w and w + 4, each as two 32-window halves; or, on levels at most
+// kWgW / 2 windows wide, 32 columns x 2 kWgTH rows, where wave w owns rows
+// w, w + 4, w + 8 and w + 12. Narrow levels would leave half of a wide tile
+// empty. The workgroup walks by = 0 .. nby - 1: the tile's cell rows wy0 + by
+// .. + TH sit in an LDS ring (one new row per by), the norms of its TH block
+// rows are recomputed, and the template fragments of the positions (by, 0 ..
+// 6) are in LDS, double-buffered and fetched one by ahead.
 // ---------------------------------------------------------------------------
-constexpr int kWgCells = kWgW + 8;     // cell columns staged per row
-constexpr int kWgSlots = kWgTH + 1;    // cell-row ring
+template <bool NARROW>
+struct WgShape {
+    static constexpr int W = NARROW ? kWgW / 2 : kWgW;     // window columns
+    static constexpr int TH = NARROW ? 2 * kWgTH : kWgTH;  // window rows
+    static constexpr int CELLS = W + 8;                    // cell columns staged per row
+    static constexpr int SLOTS = TH + 1;                   // cell-row ring
+};
+// The LDS arrays hold either shape.
+constexpr int kWgRingCells = WgShape<false>::SLOTS * WgShape<false>::CELLS > WgShape<true>::SLOTS * WgShape<true>::CELLS
+                                 ? WgShape<false>::SLOTS * WgShape<false>::CELLS
+                                 : WgShape<true>::SLOTS * WgShape<true>::CELLS;
+constexpr int kWgInvCells = WgShape<false>::TH * WgShape<false>::CELLS > WgShape<true>::TH * WgShape<true>::CELLS
+                                ? WgShape<false>::TH * WgShape<false>::CELLS
+                                : WgShape<true>::TH * WgShape<true>::CELLS;
 
 struct WgArgs {
     int nb, nby, k, dim;
@@ -1637,40 +1652,44 @@ __global__ __launch_bounds__(256) void k_score_prep_wg(WgArgs a, const float *__
 }
 
 template <int NBP>
-__global__ __launch_bounds__(256, NBP == 8 ? 2 : 1) void k_score_wgemm(const Level *__restrict__ lv,
-                                                                      const int32_t *__restrict__ first,
-                                                                      int n_levels, WgArgs a,
-                                                                      const uint8_t *__restrict__ ws,
-                                                                      const float *__restrict__ bias,
-                                                                      float *__restrict__ scores)
+struct WgLds {
+    static constexpr int NFRAG = kStripMaxBX * (NBP / 4) * 2;  // fragments per block row offset: [bx][s][hi|lo]
+    typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+    u32x4 bst[2][NFRAG * 64];
+    __attribute__((aligned(16))) _Float16 ring[kWgRingCells * NBP];
+    float sqr[kWgRingCells];
+    float invb[kWgInvCells];
+};
+
+template <int NBP, bool NARROW>
+__device__ __forceinline__ void wgemm_tile(WgLds<NBP> &L, const Level &v, int rel, const WgArgs &a,
+                                           const uint8_t *__restrict__ ws, const float *__restrict__ bias,
+                                           float *__restrict__ scores)
 {
+    using Sh = WgShape<NARROW>;
     constexpr int KS = NBP / 4;                  // 16-feature steps per block
-    constexpr int NFRAG = kStripMaxBX * KS * 2;  // fragments per block row offset: [bx][s][hi|lo]
-    constexpr int ROWH = kWgCells * NBP;         // halves per staged cell row
-    constexpr int NSEG = kWgCells / 8;           // 8-cell segments of the blocked cache
+    constexpr int NFRAG = WgLds<NBP>::NFRAG;
+    constexpr int CELLS = Sh::CELLS, SLOTS = Sh::SLOTS, TH = Sh::TH;
+    constexpr int ROWH = CELLS * NBP;            // halves per staged cell row
+    constexpr int NSEG = CELLS / 8;              // 8-cell segments of the blocked cache
     constexpr int PF = NFRAG * 64 / 256;         // 16-byte fragment loads per thread and by
     typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
-    __shared__ u32x4 bst[2][NFRAG * 64];
-    __shared__ __attribute__((aligned(16))) _Float16 ring[kWgSlots][ROWH];
-    __shared__ float sqr[kWgSlots][kWgCells];
-    __shared__ float invb[kWgTH][kWgCells];
+    auto &bst = L.bst;
+    _Float16 (*ring)[ROWH] = reinterpret_cast<_Float16 (*)[ROWH]>(L.ring);
+    float (*sqr)[CELLS] = reinterpret_cast<float (*)[CELLS]>(L.sqr);
+    float (*invb)[CELLS] = reinterpret_cast<float (*)[CELLS]>(L.invb);
 
-    const int wg = (int)blockIdx.x;
-    if (wg >= first[n_levels]) return;  // whole workgroup
-    const int l = find_level(first, n_levels, wg);
-    const Level &v = lv[l];
-    int rel = wg - first[l];
     const int tx = rel % v.st_x;
     rel /= v.st_x;
     const int ty = rel % v.st_y, kt = rel / v.st_y;
-    const int wx0 = tx * kWgW, wy0 = ty * kWgTH, kk0 = 32 * kt;
+    const int wx0 = tx * Sh::W, wy0 = ty * TH, kk0 = 32 * kt;
     const int tid = (int)threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int n = lane & 31, h = lane >> 5;
     const int nb = a.nb, nby = a.nby;
     const uint8_t *tp = ws + a.tprep_off + (int64_t)kt * a.tprep_stride;
     const u32x4 *tfrag = reinterpret_cast<const u32x4 *>(tp);
 
-    for (int i = tid; i < kWgSlots * ROWH / 8; i += 256)
+    for (int i = tid; i < SLOTS * ROWH / 8; i += 256)
         reinterpret_cast<u32x4 *>(&ring[0][0])[i] = u32x4{0u, 0u, 0u, 0u};
 
     // Cell row cy: thread t < nb * NSEG loads bin t / NSEG of cells
@@ -1687,14 +1706,14 @@ __global__ __launch_bounds__(256, NBP == 8 ? 2 : 1) void k_score_wgemm(const Lev
     };
     auto store_row = [&](int cy, const u16x8_t &val) {
         if (tid < nb * NSEG) {
-            _Float16 *rp = &ring[cy % kWgSlots][8 * f_seg * NBP + f_bin];
+            _Float16 *rp = &ring[cy % SLOTS][8 * f_seg * NBP + f_bin];
 #pragma unroll
             for (int e = 0; e < 8; ++e) rp[e * NBP] = (_Float16)val[e];
         }
     };
-    auto row_sq = [&](int cy) {  // threads < kWgCells
-        if (tid < kWgCells) {
-            const _Float16 *cp = &ring[cy % kWgSlots][tid * NBP];
+    auto row_sq = [&](int cy) {  // threads < CELLS
+        if (tid < CELLS) {
+            const _Float16 *cp = &ring[cy % SLOTS][tid * NBP];
             typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
             float s = 0.f;
 #pragma unroll
@@ -1702,7 +1721,7 @@ __global__ __launch_bounds__(256, NBP == 8 ? 2 : 1) void k_score_wgemm(const Lev
                 const half2_t hv = {cp[2 * j], cp[2 * j + 1]};
                 s = __builtin_amdgcn_fdot2(hv, hv, s, false);
             }
-            sqr[cy % kWgSlots][tid] = s;
+            sqr[cy % SLOTS][tid] = s;
         }
     };
     auto fetch_frags = [&](int by, u32x4 (&pf)[PF]) {
@@ -1714,22 +1733,22 @@ __global__ __launch_bounds__(256, NBP == 8 ? 2 : 1) void k_score_wgemm(const Lev
         for (int i = 0; i < PF; ++i) bst[buf][tid + 256 * i] = pf[i];
     };
 
-    // Prologue: cell rows wy0 .. wy0 + kWgTH, fragments of by = 0, and the
+    // Prologue: cell rows wy0 .. wy0 + TH, fragments of by = 0, and the
     // next row and fragments in flight.
     u32x4 pf[PF];
     fetch_frags(0, pf);
     {
-        u16x8_t rows[kWgTH + 1];
+        u16x8_t rows[TH + 1];
 #pragma unroll
-        for (int i = 0; i <= kWgTH; ++i) rows[i] = fetch_row(wy0 + i);
+        for (int i = 0; i <= TH; ++i) rows[i] = fetch_row(wy0 + i);
         __syncthreads();  // ring zeroed
 #pragma unroll
-        for (int i = 0; i <= kWgTH; ++i) store_row(wy0 + i, rows[i]);
+        for (int i = 0; i <= TH; ++i) store_row(wy0 + i, rows[i]);
     }
     store_frags(0, pf);
     __syncthreads();
-    for (int i = 0; i <= kWgTH; ++i) row_sq(wy0 + i);
-    u16x8_t cpre = fetch_row(wy0 + kWgTH + 1);
+    for (int i = 0; i <= TH; ++i) row_sq(wy0 + i);
+    u16x8_t cpre = fetch_row(wy0 + TH + 1);
     if (nby > 1) fetch_frags(1, pf);
 
     // Window rows of this wave: rho = wave, wave + 4; halves mu = 0, 1.
@@ -1741,9 +1760,9 @@ __global__ __launch_bounds__(256, NBP == 8 ? 2 : 1) void k_score_wgemm(const Lev
 
     for (int by = 0; by < nby; ++by) {
         __syncthreads();  // rows and their sums of squares are in place
-        for (int i = tid; i < kWgTH * (kWgCells - 1); i += 256) {
-            const int rho = i / (kWgCells - 1), c = i - rho * (kWgCells - 1);
-            const int s0 = (wy0 + by + rho) % kWgSlots, s1 = (wy0 + by + rho + 1) % kWgSlots;
+        for (int i = tid; i < TH * (CELLS - 1); i += 256) {
+            const int rho = i / (CELLS - 1), c = i - rho * (CELLS - 1);
+            const int s0 = (wy0 + by + rho) % SLOTS, s1 = (wy0 + by + rho + 1) % SLOTS;
             invb[rho][c] = inv_block_norm((sqr[s0][c] + sqr[s0][c + 1]) + (sqr[s1][c] + sqr[s1][c + 1]), a.eps);
         }
         __syncthreads();
@@ -1759,18 +1778,19 @@ __global__ __launch_bounds__(256, NBP == 8 ? 2 : 1) void k_score_wgemm(const Lev
             half8_t wf[4][KS];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const int rho = wave + 4 * (q >> 1), mu = q & 1;
+                const int rho = NARROW ? wave + 4 * q : wave + 4 * (q >> 1), mu = NARROW ? 0 : q & 1;
 #pragma unroll
                 for (int s2 = 0; s2 < KS; ++s2) {
                     const int kf = 16 * s2 + 8 * h;
                     const int w = kf / (2 * NBP);
                     wf[q][s2] = *reinterpret_cast<const half8_t *>(
-                        &ring[(wy0 + by + rho + w) % kWgSlots][(32 * mu + n + bx) * NBP + kf % (2 * NBP)]);
+                        &ring[(wy0 + by + rho + w) % SLOTS][(32 * mu + n + bx) * NBP + kf % (2 * NBP)]);
                 }
             }
             float iv[4];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) iv[q] = invb[wave + 4 * (q >> 1)][32 * (q & 1) + n + bx];
+            for (int q = 0; q < 4; ++q)
+                iv[q] = NARROW ? invb[wave + 4 * q][n + bx] : invb[wave + 4 * (q >> 1)][32 * (q & 1) + n + bx];
             float16v_t d[4];
 #pragma unroll
             for (int q = 0; q < 4; ++q)
@@ -1817,10 +1837,10 @@ __global__ __launch_bounds__(256, NBP == 8 ? 2 : 1) void k_score_wgemm(const Lev
         __syncthreads();  // done with this by's ring slot, fragments and norms
         if (by + 1 < nby) {
             store_frags((by + 1) & 1, pf);
-            store_row(wy0 + by + kWgTH + 1, cpre);
+            store_row(wy0 + by + TH + 1, cpre);
             __syncthreads();
-            row_sq(wy0 + by + kWgTH + 1);
-            cpre = fetch_row(wy0 + by + kWgTH + 2);
+            row_sq(wy0 + by + TH + 1);
+            cpre = fetch_row(wy0 + by + TH + 2);
             if (by + 2 < nby) fetch_frags(by + 2, pf);
         }
     }
@@ -1829,7 +1849,7 @@ __global__ __launch_bounds__(256, NBP == 8 ? 2 : 1) void k_score_wgemm(const Lev
     const float *cs = reinterpret_cast<const float *>(tp + (int64_t)nby * NFRAG * 64 * 16);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-        const int rho = wave + 4 * (q >> 1), mu = q & 1;
+        const int rho = NARROW ? wave + 4 * q : wave + 4 * (q >> 1), mu = NARROW ? 0 : q & 1;
         const int wx = wx0 + 32 * mu + n, wy = wy0 + rho;
         if (wx < v.win_x && wy < v.win_y) {
             float *out = scores + v.score_off + ((int64_t)wy * v.win_x + wx) * a.k;
@@ -1841,6 +1861,26 @@ __global__ __launch_bounds__(256, NBP == 8 ? 2 : 1) void k_score_wgemm(const Lev
             }
         }
     }
+}
+
+template <int NBP>
+__global__ __launch_bounds__(256, NBP == 8 ? 2 : 1) void k_score_wgemm(const Level *__restrict__ lv,
+                                                                      const int32_t *__restrict__ first,
+                                                                      int n_levels, WgArgs a,
+                                                                      const uint8_t *__restrict__ ws,
+                                                                      const float *__restrict__ bias,
+                                                                      float *__restrict__ scores)
+{
+    __shared__ WgLds<NBP> lds;
+    const int wg = (int)blockIdx.x;
+    if (wg >= first[n_levels]) return;  // whole workgroup
+    const int l = find_level(first, n_levels, wg);
+    const Level &v = lv[l];
+    // The plan tiles a level the same way (wgemm_narrow).
+    if (wgemm_narrow(v.win_x))
+        wgemm_tile<NBP, true>(lds, v, wg - first[l], a, ws, bias, scores);
+    else
+        wgemm_tile<NBP, false>(lds, v, wg - first[l], a, ws, bias, scores);
 }
 
 // Optional output: every normalised 2x2 block, f = h / sqrt(|v|^2 + eps^2).
