@@ -1551,9 +1551,9 @@ __global__ __launch_bounds__(256, 2) void k_score_strip(const Level *__restrict_
 // kWgW / 2 windows wide, 32 columns x 2 kWgTH rows, where wave w owns rows
 // w, w + 4, w + 8 and w + 12. Narrow levels would leave half of a wide tile
 // empty. The workgroup walks by = 0 .. nby - 1: the tile's cell rows wy0 + by
-// .. + TH sit in an LDS ring (one new row per by), the norms of its TH block
-// rows are recomputed, and the template fragments of the positions (by, 0 ..
-// 6) are in LDS, double-buffered and fetched one by ahead.
+// .. + TH sit in an LDS ring (one new row per by), so do the norms of the TH
+// block rows in use (one new row per by), and the template fragments of the
+// positions (by, 0 .. 6) are in LDS, double-buffered and fetched one by ahead.
 // ---------------------------------------------------------------------------
 template <bool NARROW>
 struct WgShape {
@@ -1760,10 +1760,15 @@ __device__ __forceinline__ void wgemm_tile(WgLds<NBP> &L, const Level &v, int re
 
     for (int by = 0; by < nby; ++by) {
         __syncthreads();  // rows and their sums of squares are in place
-        for (int i = tid; i < TH * (CELLS - 1); i += 256) {
-            const int rho = i / (CELLS - 1), c = i - rho * (CELLS - 1);
-            const int s0 = (wy0 + by + rho) % SLOTS, s1 = (wy0 + by + rho + 1) % SLOTS;
-            invb[rho][c] = inv_block_norm((sqr[s0][c] + sqr[s0][c + 1]) + (sqr[s1][c] + sqr[s1][c + 1]), a.eps);
+        // Norms of the block rows new to the tile's window rows: all TH at
+        // by = 0, then one per by. Block row wy0 + Y sits in invb[Y % TH]
+        // while it is in use (by <= Y < by + TH).
+        const int r0 = by == 0 ? 0 : TH - 1;
+        for (int i = tid; i < (TH - r0) * (CELLS - 1); i += 256) {
+            const int rho = r0 + i / (CELLS - 1), c = i - (rho - r0) * (CELLS - 1);
+            const int Y = by + rho;
+            const int s0 = (wy0 + Y) % SLOTS, s1 = (wy0 + Y + 1) % SLOTS;
+            invb[Y % TH][c] = inv_block_norm((sqr[s0][c] + sqr[s0][c + 1]) + (sqr[s1][c] + sqr[s1][c + 1]), a.eps);
         }
         __syncthreads();
         const half8_t *bf = reinterpret_cast<const half8_t *>(bst[by & 1]);
@@ -1790,7 +1795,8 @@ __device__ __forceinline__ void wgemm_tile(WgLds<NBP> &L, const Level &v, int re
             float iv[4];
 #pragma unroll
             for (int q = 0; q < 4; ++q)
-                iv[q] = NARROW ? invb[wave + 4 * q][n + bx] : invb[wave + 4 * (q >> 1)][32 * (q & 1) + n + bx];
+                iv[q] = NARROW ? invb[(by + wave + 4 * q) % TH][n + bx]
+                               : invb[(by + wave + 4 * (q >> 1)) % TH][32 * (q & 1) + n + bx];
             float16v_t d[4];
 #pragma unroll
             for (int q = 0; q < 4; ++q)
