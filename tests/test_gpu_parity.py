@@ -223,6 +223,28 @@ def test_l2_many_templates_window_gemm(nb, k, w, h, ml):
         _check_level(plan, out, img, l, tmpl=tmpl, bias=bias)
 
 
+@pytest.mark.parametrize("nb,k,w,h", [
+    (8, 32, 319, 263),    # 32 windows across: the last level width with 32 x 16 tiles
+    (8, 32, 320, 263),    # 33 windows across: 64 x 8 tiles, the second one almost empty
+    (16, 16, 575, 136),   # 64 windows across, 2 rows: one full 64 x 8 tile row
+    (8, 48, 576, 151),    # 65 across, 3 rows, K = 48: a partial template tile
+    (8, 32, 70, 32767),   # 1 window across, 4080 down: 255 tiles of 32 x 16
+    (16, 32, 32767, 130), # 4088 across, 1 down: 64 x 8 tiles, 7 of 8 rows empty
+])
+def test_window_gemm_tile_shapes(nb, k, w, h):
+    """The window GEMM tiles levels at most 32 windows wide with 32 x 16
+    windows and wider ones with 64 x 8: both sides of that boundary, full
+    and partial tiles of either shape, and both at the maximum side length.
+    Bins, planes and cells bit for bit; scores of sampled windows (all of
+    them on the small images) within tolerance."""
+    desc = hog.make_desc(w, h, channels=3, n_bins=nb, n_templates=k, norm=hog.HOG_NORM_L2)
+    img = inputs.synth_image(w, h, 3, 7500 + w % 97 + k)
+    tmpl, bias = templates_for(desc, 7501 + nb + k)
+    plan, out = run_gpu(desc, img, tmpl, bias, block_feat=False)
+    big = w * h > 1_000_000
+    _check_level(plan, out, img, 0, check_all_scores=not big, sample=200, seed=7502, tmpl=tmpl, bias=bias)
+
+
 @pytest.mark.parametrize("w,h,c,nb,norm", [
     (32767, 130, 1, 8, hog.HOG_NORM_RAW),    # the widest level: 512 integral tiles across
     (70, 32767, 3, 9, hog.HOG_NORM_L2),      # the tallest: 512 tiles down, 4080 windows
