@@ -507,9 +507,9 @@ __global__ __launch_bounds__(256) void k_int_scan(const Level *__restrict__ lv,
 //
 // Every 8th padded row is a row of cell corners: the lanes on every 8th
 // padded column hold P(r, c); P(r, c-8) comes from the lane 8 to the left
-// (or, for the tile's first cell, the plane column 64 tx, kept as a scalar:
-// its value at row 64 ty plus the row carries E), P(r-8, .) from the
-// previous corner row. Their four-corner sum (Eq. 6) is the cell's
+// (or, for the tile's first cell, the plane column 64 tx: its value at row
+// 64 ty plus the row carries E of the tile's rows so far, a wave scan of E
+// read at each corner row), P(r-8, .) from the previous corner row. Their four-corner sum (Eq. 6) is the cell's
 // histogram entry, cached here once per cell (uint16 [n][cy][cx]).
 //
 // The planes hold ii(x, y) at [y * pitch + x] (Eq. 5, one value per pixel),
@@ -570,6 +570,9 @@ __global__ __launch_bounds__(256) void k_int_emit(const Level *__restrict__ lv,
         ecar[j] = (j < nbc && er < H) ? (uint32_t)Eb[(int64_t)j * hp + er] : 0u;
         cellacc[j] = 0u;
     }
+    uint32_t ecum[NBC];  // lane r: P + the row carries of the tile's rows up to y0 + r
+#pragma unroll
+    for (int j = 0; j < NBC; ++j) ecum[j] = (CELLS && j < nbc) ? lrun[j] + wave_incl_scan(ecar[j]) : 0u;
     // All global loads of the tile happen here, before the first plane store:
     // on gfx9 one counter tracks loads and stores, so a load waited for later
     // would also wait for every store issued before it.
@@ -591,18 +594,20 @@ __global__ __launch_bounds__(256) void k_int_emit(const Level *__restrict__ lv,
             __builtin_amdgcn_raw_buffer_store_b8((uint8_t)val, isrc, (int)colb, j * planeb + y * pitchb, 0);
     };
 
-    auto do_row = [&](int bin, int y) {
+    // FULL: the chunk has all NBC bins (every chunk but possibly the last),
+    // so the per-bin test is compiled out.
+    auto do_row = [&](auto full_c, int bin, int y) {
+        constexpr bool FULL = decltype(full_c)::value;
         const int rel = bin - b0;
         const int rr = y - y0;
 #pragma unroll
         for (int j = 0; j < NBC; ++j) {
-            if (j >= nbc) break;  // wave-uniform
+            if (!FULL && j >= nbc) break;  // wave-uniform
             const bool hit = rel == j;
             const uint64_t m = __ballot(hit);
             const uint32_t e = (uint32_t)__builtin_amdgcn_readlane((int)ecar[j], rr);
             run[j] += e + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
                                                     __builtin_amdgcn_mbcnt_lo((uint32_t)m, hit ? 1u : 0u));
-            lrun[j] += e;
             store_row(j, y, run[j]);
         }
     };
@@ -610,13 +615,17 @@ __global__ __launch_bounds__(256) void k_int_emit(const Level *__restrict__ lv,
     // 8k + 7 computes the cell (k, q) of the tile (q = its cell row); the value
     // moves to lane 8q + k, so after the tile's 8 corner rows each lane holds
     // one cell of the tile's 8 x 8 block.
-    auto do_corners = [&](int y) {
+    auto do_corners = [&](auto full_c, int y) {
+        constexpr bool FULL = decltype(full_c)::value;
         if constexpr (CELLS) {
             const int q = ((y + 1) >> 3) - 1 - 8 * ty;
             const int src = 8 * (lane & 7) + 7;
 #pragma unroll
             for (int j = 0; j < NBC; ++j) {
-                if (j >= nbc) break;  // wave-uniform
+                if (!FULL && j >= nbc) break;  // wave-uniform
+                // The plane value left of the tile in row y: P plus the row
+                // carries of the tile's rows up to y.
+                lrun[j] = (uint32_t)__builtin_amdgcn_readlane((int)ecum[j], y - y0);
                 const uint32_t rl = __shfl_up(run[j], 8u);
                 const uint32_t tl = __shfl_up(top[j], 8u);
                 const uint32_t left = (lane == 7) ? lrun[j] : rl;
@@ -634,21 +643,27 @@ __global__ __launch_bounds__(256) void k_int_emit(const Level *__restrict__ lv,
         return xin ? raw : kNoBin;
     };
 
-    int yb = y0;
-    for (; yb + kRowBatch <= y1; yb += kRowBatch) {  // yb is a multiple of 16
-        int bb[kRowBatch];
+    auto rows = [&](auto full_c) {
+        int yb = y0;
+        for (; yb + kRowBatch <= y1; yb += kRowBatch) {  // yb is a multiple of 16
+            int bb[kRowBatch];
 #pragma unroll
-        for (int i = 0; i < kRowBatch; ++i) bb[i] = load_bin(yb + i);
+            for (int i = 0; i < kRowBatch; ++i) bb[i] = load_bin(yb + i);
 #pragma unroll
-        for (int i = 0; i < kRowBatch; ++i) {
-            do_row(bb[i], yb + i);
-            if ((i & 7) == 7) do_corners(yb + i);
+            for (int i = 0; i < kRowBatch; ++i) {
+                do_row(full_c, bb[i], yb + i);
+                if ((i & 7) == 7) do_corners(full_c, yb + i);
+            }
         }
-    }
-    for (; yb < y1; ++yb) {
-        do_row(load_bin(yb), yb);
-        if (((yb + 1) & 7) == 0) do_corners(yb);
-    }
+        for (; yb < y1; ++yb) {
+            do_row(full_c, load_bin(yb), yb);
+            if (((yb + 1) & 7) == 0) do_corners(full_c, yb);
+        }
+    };
+    if (nbc == NBC)
+        rows(std::true_type{});
+    else
+        rows(std::false_type{});
     if constexpr (CELLS) {
         // One whole 128-byte line per bin: the tile's 8 x 8 cells.
         if (tx < v.cbx && ty < v.cby) {
