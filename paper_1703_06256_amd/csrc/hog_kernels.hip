@@ -938,8 +938,8 @@ __global__ __launch_bounds__(256) void k_soft_emit(const Level *__restrict__ lv,
         s0 += left0p[yb + lane];
         if (two) s1 += left1p[yb + lane];
     }
-    uint32_t left0 = (uint32_t)__builtin_amdgcn_readlane((int)wave_incl_scan(s0), 63);
-    uint32_t left1 = (uint32_t)__builtin_amdgcn_readlane((int)wave_incl_scan(s1), 63);
+    const uint32_t left0 = (uint32_t)__builtin_amdgcn_readlane((int)wave_incl_scan(s0), 63);
+    const uint32_t left1 = (uint32_t)__builtin_amdgcn_readlane((int)wave_incl_scan(s1), 63);
     // ii(x, y0 - 1): the votes left of the tile above it, plus those above
     // the tile in its columns up to x.
     uint32_t acc0 = left0 + wave_incl_scan(above0p[0]);
@@ -958,20 +958,27 @@ __global__ __launch_bounds__(256) void k_soft_emit(const Level *__restrict__ lv,
         prev0 = corner_diff(acc0, left0);
         prev1 = corner_diff(acc1, left1);
     }
-    auto corner = [&](int y) {  // y = 8 cy + 7, cy < cells_y
-        const int cy = y >> 3;
-        const uint32_t d0 = corner_diff(acc0, left0), d1 = corner_diff(acc1, left1);
+    // Lane i holds the votes left of the tile in row y0 + i; cum0 / cum1
+    // their sums over the tile's rows up to y0 + i.
+    const bool rin = y0 + lane < v.h;
+    const uint32_t cv0 = rin ? left0p[y0 + lane] : 0u;
+    const uint32_t cv1 = rin && two ? left1p[y0 + lane] : 0u;
+    const uint32_t cum0 = wave_incl_scan(cv0), cum1 = wave_incl_scan(cv1);
+    // Row y = y0 + i = 8 cy + 7, cy < cells_y. The plane value left of the
+    // tile in that row is the votes above the tile's rows plus cum at i.
+    auto corner = [&](auto two_c, int i) {
+        constexpr bool TWO = decltype(two_c)::value;
+        const int cy = (y0 + i) >> 3;
+        const uint32_t l0 = left0 + (uint32_t)__builtin_amdgcn_readlane((int)cum0, i);
+        const uint32_t l1 = left1 + (uint32_t)__builtin_amdgcn_readlane((int)cum1, i);
+        const uint32_t d0 = corner_diff(acc0, l0), d1 = corner_diff(acc1, l1);
         if (cell_lane) {
             cache[cache_index(v, n0, cy, cx)] = (uint16_t)(d0 - prev0);
-            if (two) cache[cache_index(v, n0 + 1, cy, cx)] = (uint16_t)(d1 - prev1);
+            if (TWO) cache[cache_index(v, n0 + 1, cy, cx)] = (uint16_t)(d1 - prev1);
         }
         prev0 = d0;
         prev1 = d1;
     };
-    // Lane i holds the votes left of the tile in row y0 + i.
-    const bool rin = y0 + lane < v.h;
-    const uint32_t cv0 = rin ? left0p[y0 + lane] : 0u;
-    const uint32_t cv1 = rin && two ? left1p[y0 + lane] : 0u;
     // The tile's soft entries (64 rows of 128 bytes) staged in LDS: with these
     // every global load happens before the first plane store (on gfx9 one
     // counter tracks loads and stores, so a load waited for between stores
@@ -1004,29 +1011,36 @@ __global__ __launch_bounds__(256) void k_soft_emit(const Level *__restrict__ lv,
     const uint32_t isize = (uint32_t)__builtin_amdgcn_readfirstlane((two ? 2 : 1) * planeb);
     const __amdgpu_buffer_rsrc_t isrc = buffer_rsrc(ii + v.ii_off + (int64_t)n0 * v.ii_plane, isize);
     const int colb = min(x, (int)v.ii_pitch - 1) * 4;
-    auto row = [&](uint32_t e, int i) {
+    // TWO: the pair's second bin exists (every pair but possibly the last),
+    // so its per-row tests are compiled out.
+    auto row = [&](auto two_c, uint32_t e, int i) {
+        constexpr bool TWO = decltype(two_c)::value;
         const int y = y0 + i;
         e = xin ? e : (uint32_t)kNoBin;
         const uint32_t b0 = e & 255u, w1 = e >> 8, qw = Q - w1;
         const uint32_t v0 = (b0 == m0 ? qw : 0u) + (b0 == p0 ? w1 : 0u);
-        const uint32_t v1 = two ? (b0 == m1 ? qw : 0u) + (b0 == p1 ? w1 : 0u) : 0u;
+        const uint32_t v1 = TWO ? (b0 == m1 ? qw : 0u) + (b0 == p1 ? w1 : 0u) : 0u;
         const uint32_t sc = wave_incl_scan(v0 | v1 << 16);
         const uint32_t c0 = (uint32_t)__builtin_amdgcn_readlane((int)cv0, i);
         const uint32_t c1 = (uint32_t)__builtin_amdgcn_readlane((int)cv1, i);
         acc0 += (sc & 0xFFFFu) + c0;
         acc1 += (sc >> 16) + c1;
-        left0 += c0;
-        left1 += c1;
         __builtin_amdgcn_raw_buffer_store_b32(acc0, isrc, colb, y * pitchb, 0);
-        if (two) __builtin_amdgcn_raw_buffer_store_b32(acc1, isrc, colb, planeb + y * pitchb, 0);
-        if (CELLS && (y & 7) == 7 && (y >> 3) < v.cells_y) corner(y);
+        if (TWO) __builtin_amdgcn_raw_buffer_store_b32(acc1, isrc, colb, planeb + y * pitchb, 0);
+        if (CELLS && (i & 7) == 7 && (y >> 3) < v.cells_y) corner(two_c, i);  // y0 is a multiple of 64
     };
-    int y = y0;
-    for (; y + kRows <= y1; y += kRows) {  // y - y0 is a multiple of 16
+    auto rows = [&](auto two_c) {
+        int y = y0;
+        for (; y + kRows <= y1; y += kRows) {  // y - y0 is a multiple of 16
 #pragma unroll
-        for (int i = 0; i < kRows; ++i) row(te[(y + i - y0) * kTile], y + i - y0);
-    }
-    for (; y < y1; ++y) row(te[(y - y0) * kTile], y - y0);
+            for (int i = 0; i < kRows; ++i) row(two_c, te[(y + i - y0) * kTile], y + i - y0);
+        }
+        for (; y < y1; ++y) row(two_c, te[(y - y0) * kTile], y - y0);
+    };
+    if (two)
+        rows(std::true_type{});
+    else
+        rows(std::false_type{});
 }
 
 // Cell histograms cached by k_int_emit, exported as uint32 [cy][cx][n].
