@@ -313,23 +313,33 @@ __global__ __launch_bounds__(64) void k_int_reduce(const Level *__restrict__ lv,
     const int x = tx * kTile + lane;
     const bool xin = x < v.w;
     const int ncols = min(kTile, v.w - tx * kTile);
-    // Column counts: lane = column.
+    // Column counts: lane = column. Each batch of 16 bins is read before
+    // its adds: the compiler keeps LDS reads and atomics in program order,
+    // so a read after an add would wait for the add's round trip.
     if (xin) {
-        for (int r = 0; r < nrows; ++r) {
-            const int b = tb[r * kRedStride + lane];
-            if (b < nb) atomicAdd(&colh[slot(b) + lane], one(b));
+        for (int r0 = 0; r0 < nrows; r0 += 16) {
+            int bb[16];
+#pragma unroll
+            for (int i = 0; i < 16; ++i) bb[i] = r0 + i < nrows ? tb[(r0 + i) * kRedStride + lane] : kNoBin;
+#pragma unroll
+            for (int i = 0; i < 16; ++i)
+                if (bb[i] < nb) atomicAdd(&colh[slot(bb[i]) + lane], one(bb[i]));
         }
     }
-    // Row counts: lane = row.
+    // Row counts: lane = row; its 64 bins are read first, 16 at a time.
     if (lane < nrows) {
         const uint32_t *rp = reinterpret_cast<const uint32_t *>(tb + lane * kRedStride);
-        for (int k = 0; k < kTile / 4; ++k) {
-            const uint32_t d = rp[k];
+        for (int k0 = 0; k0 < kTile / 4; k0 += 4) {
+            uint32_t d[4];
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int b = (int)((d >> (8 * e)) & 255u);
-                if (4 * k + e < ncols && b < nb) atomicAdd(&rowh[slot(b) + lane], one(b));
-            }
+            for (int k = 0; k < 4; ++k) d[k] = rp[k0 + k];
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int b = (int)((d[k] >> (8 * e)) & 255u);
+                    if (4 * (k0 + k) + e < ncols && b < nb) atomicAdd(&rowh[slot(b) + lane], one(b));
+                }
         }
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
