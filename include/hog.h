@@ -119,6 +119,21 @@ int hog_lut_bins(const hog_lut *lut);
  * valid until hog_lut_free. */
 const uint8_t *hog_lut_host(const hog_lut *lut);
 
+/* The device copies a hog_lut holds (Sec. 2's table as the kernels read it):
+ *   HOG_LUT_DEVICE_FULL  uint8 [511][511], layout as hog_lut_fill_host_ex;
+ *   HOG_LUT_DEVICE_HALF  uint8 [256][511], the dy >= 0 rows that hog_bin_map
+ *                        stages in LDS: entry (dx, dy) = bin(dx, dy) | f << 6
+ *                        (255 for no bin), where bin(dx, -dy) =
+ *                        n_bins - 1 - bin(dx, dy) + f;
+ *   HOG_LUT_DEVICE_SOFT  uint16 [511][511], layout as hog_lut_fill_soft_host. */
+enum { HOG_LUT_DEVICE_FULL = 0, HOG_LUT_DEVICE_HALF = 1, HOG_LUT_DEVICE_SOFT = 2 };
+/* Copy device table `table` of lut into host memory dst (caller-owned,
+ * `bytes` must equal that table's size: 261121, 130816 or 522242), reading it
+ * back from the device (synchronous; for tests and tools). HOG_E_INVALID for
+ * a NULL argument, an unknown table or a wrong size; HOG_E_DEVICE if the
+ * copy fails. */
+hog_status hog_lut_read_device(const hog_lut *lut, int table, void *dst, int64_t bytes);
+
 /* ------------------------------------------------------------------------ */
 /* Plan: level geometry and buffer layout for one image shape.              */
 /* ------------------------------------------------------------------------ */

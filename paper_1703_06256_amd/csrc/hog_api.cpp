@@ -330,6 +330,24 @@ int hog_lut_bins(const hog_lut *lut) { return lut ? lut->n_bins : 0; }
 
 const uint8_t *hog_lut_host(const hog_lut *lut) { return lut ? lut->host.data() : nullptr; }
 
+hog_status hog_lut_read_device(const hog_lut *lut, int table, void *dst, int64_t bytes)
+{
+    if (!lut || !dst) return fail(HOG_E_INVALID, "lut or dst is NULL");
+    const void *src = nullptr;
+    int64_t size = 0;
+    switch (table) {
+    case HOG_LUT_DEVICE_FULL: src = lut->dev; size = (int64_t)HOG_LUT_SIDE * HOG_LUT_SIDE; break;
+    case HOG_LUT_DEVICE_HALF: src = lut->dev_half; size = hogk::kLutHalfBytes; break;
+    case HOG_LUT_DEVICE_SOFT: src = lut->dev_soft; size = (int64_t)HOG_LUT_SIDE * HOG_LUT_SIDE * 2; break;
+    default: return fail(HOG_E_INVALID, "unknown table %d", table);
+    }
+    if (bytes != size) return fail(HOG_E_INVALID, "table %d has %lld bytes, not %lld", table, (long long)size,
+                                   (long long)bytes);
+    const hipError_t e = hipMemcpy(dst, src, (size_t)size, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return device_fail(e, "hipMemcpy(lut table)");
+    return HOG_OK;
+}
+
 // ---------------------------------------------------------------------------
 // Planning.
 // ---------------------------------------------------------------------------
@@ -614,7 +632,7 @@ static hog_status create_plan(const hog_plan_desc *descs, int n_img, bool batch,
         // per tile of 32 templates: fragments [by][bx][step][hi|lo][lane] of
         // 16 bytes, then 32 scales (float), then their exponents (int)
         const int64_t frags = (int64_t)(sp.win_cells_y - 1) * hogk::kStripMaxBX * (mfma_ks / 4) * 2 * 64;
-        tprep_stride = round_up(frags * 16 + 32 * 8, 256);
+        tprep_stride = round_up(frags * 16 + 32 * 12, 256);  // fragments, scales, exponents, flags
         tprep_off = round_up(ws_off, 256);
         ws_off = tprep_off + tprep_stride * ((K + 31) / 32);
     }

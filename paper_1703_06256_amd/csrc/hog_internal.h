@@ -38,11 +38,12 @@ constexpr int kWgTH = 8;
 constexpr bool wgemm_narrow(int win_x) { return win_x <= kWgW / 2; }
 
 // Workspace bytes of one template's prepared weights for nbp bin slots per
-// cell: fragments [bx][step][hi|lo][lane] of 16 bytes (one step per 32 or, at
-// the end, 16 features of the 4 nbp), then the column scales [lane] (float).
+// cell: fragments [bx][slot][lane] of 16 bytes (nbp / 4 slots: the fp16 hi and
+// lo halves of the products' steps, or the FP32 weights in exact mode), then
+// the column scales [lane] (float), then the template's mode (int, padded).
 constexpr int64_t strip_prep_bytes(int nbp)
 {
-    return (int64_t)kStripMaxBX * ((4 * nbp) / 32 + ((4 * nbp) % 32) / 16) * 2 * 64 * 16 + 64 * 4;
+    return (int64_t)kStripMaxBX * (nbp / 4) * 64 * 16 + 64 * 4 + 256;
 }
 
 // Kernel indices into the per-kernel prefix tables.

@@ -1251,8 +1251,10 @@ __global__ __launch_bounds__(256) void k_score(const Level *__restrict__ lv,
 //
 // The counts are exact in fp16. k_score_prep scales each weight column n
 // by a power of two (its max |T| over all bx into [2^14, 2^15)) and splits it
-// into fp16 hi + lo (~22 bits of each weight); both products are added into
-// the block's FP32 accumulator. A block's 4 NBP features are its cells (u, w) in the
+// into fp16 hi + lo (each weight to 2^-22 relative); both products go into
+// the block's FP32 accumulator. A template whose column weights span more
+// than about 2^17 (where the lo halves would be fp16 subnormals) is scored in
+// exact mode: the same walk with FP32 weights and FP32 16x16x4 products. A block's 4 NBP features are its cells (u, w) in the
 // order w, u with NBP bin slots each (padding zero); the feature axis is
 // covered by 16x16x32 steps, plus one 16x16x16 step when 4 NBP = 80.
 // Cells sit in LDS as fp16 [cell][NBP] in a ring of four cell rows; each row
@@ -1262,6 +1264,16 @@ __global__ __launch_bounds__(256) void k_score(const Level *__restrict__ lv,
 // once the compiler keeps them in order (lds_order).
 // ---------------------------------------------------------------------------
 constexpr int kStripCells = kStripW + 8;    // cell columns staged per row
+
+template <int V>
+struct IntTag {
+    static constexpr int value = V;
+};
+// Matrix-core scorer modes, per template (strips) or per tile of 32
+// templates (window GEMM): fp16 hi + lo weights (the strips), the same with
+// the lo halves scaled by 2^11 and the counts they multiply by 2^-11 (the
+// window GEMM), or FP32 weights (either).
+enum { kModeSplit = 0, kModeExact = 1, kModeWide = 2 };
 
 struct StripArgs {
     int nb, nby, k, th, dim, lds_wave;
@@ -1302,18 +1314,34 @@ __device__ __forceinline__ int strip_weight_index(int k, int nbp, int nb, int nb
 }
 
 // One workgroup per template, wave bx (kStripMaxBX waves): the B fragments of
-// every step for that bx, hi and lo, in the layout the strip kernel loads.
-// Column n (block row offset) gets one power-of-two scale for all its bx.
+// every step for that bx, in the layout the strip kernel loads: slots
+// [bx][i][lane] of 16 bytes (i < NBP / 4), then the column scales [lane]
+// (float), then the template's mode (int).
+// kModeSplit: column n (block row offset) gets one power of two for all its
+// bx, bringing its max |T| into [2^14, 2^15), and each scaled weight sv is
+// split into fp16 hi = sv rounded and lo = (sv - hi) rounded; slot 2 j holds
+// the hi and slot 2 j + 1 the lo halves of 16x16x32 step j, and the 16x16x16
+// step (if any) is slot 2 K32, hi in its low and lo in its high 8 bytes.
+// hi + lo holds sv to 2^-22 relative when |sv| >= 2^-3; below that lo is an
+// fp16 subnormal and loses bits. So if any nonzero weight of the template
+// scales below 2^-3 (its column also holds weights about 2^17 times larger),
+// the template takes kModeExact instead: its FP32 weights unscaled, slot i
+// holding the weights of bins 4 i .. 4 i + 3 of cell q = lane / 16 of the
+// block (the 16x16x4 FP32 products' layout), and scale 1.
 template <int NBP>
 __global__ __launch_bounds__(64 * kStripMaxBX) void k_score_prep(StripArgs a, const float *__restrict__ tmpl,
                                                                  uint8_t *__restrict__ ws)
 {
     using Sh = StripShape<NBP>;
+    constexpr int NI = NBP / 4;  // 16-byte slots per (bx, lane)
+    typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
     __shared__ float colmax[kStripMaxBX][64];
+    __shared__ int need_exact;
     const int lane = threadIdx.x & 63, bx = wave_id_in_block();
     const int kk = (int)blockIdx.x;
     const int n = lane & 15, q = lane >> 4;
     const float *tk = tmpl + (int64_t)kk * a.dim;
+    if (threadIdx.x == 0) need_exact = 0;
     float vals[Sh::S][8];
     float mx = 0.f;
 #pragma unroll
@@ -1339,20 +1367,53 @@ __global__ __launch_bounds__(64 * kStripMaxBX) void k_score_prep(StripArgs a, co
     int ex = 0;
     if (mx > 0.f) (void)frexpf(mx, &ex);  // mx = f 2^ex, f in [0.5, 1)
     const int e = mx > 0.f ? 15 - ex : 0;
+    float svmin = INFINITY;  // smallest nonzero scaled weight
+#pragma unroll
+    for (int j = 0; j < Sh::S; ++j)
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+            if (vals[j][i] != 0.f) svmin = fminf(svmin, fabsf(ldexpf(vals[j][i], e)));
+    if (svmin < 0x1p-3f) need_exact = 1;
+    __syncthreads();
+    const int mode = need_exact ? kModeExact : kModeSplit;
+    const bool exact = mode == kModeExact;
     uint8_t *tp = ws + a.tprep_off + (int64_t)kk * a.tprep_stride;
+    u32x4 *frag = reinterpret_cast<u32x4 *>(tp) + (int64_t)bx * NI * 64 + lane;
+    if (exact) {
 #pragma unroll
-    for (int j = 0; j < Sh::S; ++j) {
-        half8_t h, lo;
+        for (int i = 0; i < NI; ++i) {
+            float4_t f;
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            const float sv = ldexpf(vals[j][i], e);
-            h[i] = (_Float16)sv;
-            lo[i] = (_Float16)(sv - (float)h[i]);
+            for (int c = 0; c < 4; ++c) {
+                const int idx = strip_weight_index(q * NBP + 4 * i + c, NBP, a.nb, a.nby, n, bx);
+                f[c] = idx >= 0 ? tk[idx] : 0.f;
+            }
+            frag[(int64_t)i * 64] = __builtin_bit_cast(u32x4, f);
         }
-        *reinterpret_cast<half8_t *>(tp + (((int64_t)(bx * Sh::S + j) * 2 + 0) * 64 + lane) * 16) = h;
-        *reinterpret_cast<half8_t *>(tp + (((int64_t)(bx * Sh::S + j) * 2 + 1) * 64 + lane) * 16) = lo;
+    } else {
+#pragma unroll
+        for (int j = 0; j < Sh::S; ++j) {
+            half8_t h, lo;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const float sv = ldexpf(vals[j][i], e);
+                h[i] = (_Float16)sv;
+                lo[i] = (_Float16)(sv - (float)h[i]);
+            }
+            if (j < Sh::K32) {
+                frag[(int64_t)(2 * j) * 64] = __builtin_bit_cast(u32x4, h);
+                frag[(int64_t)(2 * j + 1) * 64] = __builtin_bit_cast(u32x4, lo);
+            } else {  // the 16x16x16 step: four features per lane
+                frag[(int64_t)(2 * j) * 64] =
+                    __builtin_bit_cast(u32x4, __builtin_shufflevector(h, lo, 0, 1, 2, 3, 8, 9, 10, 11));
+            }
+        }
     }
-    if (bx == 0) reinterpret_cast<float *>(tp + (int64_t)kStripMaxBX * Sh::S * 2 * 64 * 16)[lane] = ldexpf(1.f, -e);
+    if (bx == 0) {
+        float *cs = reinterpret_cast<float *>(tp + (int64_t)kStripMaxBX * NI * 64 * 16);
+        cs[lane] = exact ? 1.f : ldexpf(1.f, -e);
+        if (lane == 0) reinterpret_cast<int *>(cs + 64)[0] = mode;
+    }
 }
 
 template <int NBP>
@@ -1434,31 +1495,25 @@ __global__ __launch_bounds__(256, 2) void k_score_strip(const Level *__restrict_
     u16x8_t pre0 = fetch(wy_lo), pre1 = fetch(wy_lo + 1);
     u16x8_t pre2 = fetch(wy_lo + 2), pre3 = fetch(wy_lo + 3);
 
-    // Prepared B fragments (k_score_prep) and column scales.
+    // Prepared B fragments (k_score_prep), column scales and mode.
+    constexpr int NI = NBP / 4;
+    typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
     const uint8_t *tp = ws + a.tprep_off + (int64_t)kk * a.tprep_stride;
-    half8_t bh[kStripMaxBX][Sh::K32], bl[kStripMaxBX][Sh::K32];
-    half4_t bh16[kStripMaxBX], bl16[kStripMaxBX];
+    const u32x4 *frag = reinterpret_cast<const u32x4 *>(tp) + lane;
+    u32x4 braw[kStripMaxBX][NI];
 #pragma unroll
-    for (int bx = 0; bx < kStripMaxBX; ++bx) {
+    for (int bx = 0; bx < kStripMaxBX; ++bx)
 #pragma unroll
-        for (int j = 0; j < Sh::K32; ++j) {
-            bh[bx][j] = *reinterpret_cast<const half8_t *>(tp + (((int64_t)(bx * Sh::S + j) * 2 + 0) * 64 + lane) * 16);
-            bl[bx][j] = *reinterpret_cast<const half8_t *>(tp + (((int64_t)(bx * Sh::S + j) * 2 + 1) * 64 + lane) * 16);
-        }
-        if constexpr (Sh::K16 > 0) {
-            bh16[bx] = *reinterpret_cast<const half4_t *>(tp + (((int64_t)(bx * Sh::S + Sh::K32) * 2 + 0) * 64 + lane) * 16);
-            bl16[bx] = *reinterpret_cast<const half4_t *>(tp + (((int64_t)(bx * Sh::S + Sh::K32) * 2 + 1) * 64 + lane) * 16);
-        }
-    }
-    float cs = reinterpret_cast<const float *>(tp + (int64_t)kStripMaxBX * Sh::S * 2 * 64 * 16)[lane];
+        for (int i = 0; i < NI; ++i) braw[bx][i] = frag[(int64_t)(bx * NI + i) * 64];
+    const float *csp = reinterpret_cast<const float *>(tp + (int64_t)kStripMaxBX * NI * 64 * 16);
+    const float cs = csp[lane];
+    const int mode = __builtin_amdgcn_readfirstlane(reinterpret_cast<const int *>(csp + 64)[0]);
     // Keep the fragments in registers for the whole strip: without this the
     // compiler may reload them from memory inside the row loop.
 #pragma unroll
-    for (int bx = 0; bx < kStripMaxBX; ++bx) {
+    for (int bx = 0; bx < kStripMaxBX; ++bx)
 #pragma unroll
-        for (int j = 0; j < Sh::K32; ++j) asm volatile("" : "+v"(bh[bx][j]), "+v"(bl[bx][j]));
-        if constexpr (Sh::K16 > 0) asm volatile("" : "+v"(bh16[bx]), "+v"(bl16[bx]));
-    }
+        for (int i = 0; i < NI; ++i) asm volatile("" : "+v"(braw[bx][i]));
 
     // A fragments: window column m = lane % 16; lane group q = lane / 16 takes
     // features k0 .. k0 + 7 (16x16x32) or k0 .. k0 + 3 (16x16x16) of each block:
@@ -1497,74 +1552,133 @@ __global__ __launch_bounds__(256, 2) void k_score_strip(const Level *__restrict_
 
     // Cell rows Y and Y + 1 are in the ring; rows Y + 2 and Y + 3 are in
     // flight in pre2 and pre3 (fetched two block rows ahead).
-    for (int Y = wy_lo; Y <= y_last; ++Y) {
-        const bool more = Y + 2 <= y_last + 1;
-        lds_order();
-        // iv[t] = inv of block 4 q + t of this row (t = r + bx <= 9).
-        float iv[10];
-        {
-            const float *ib = invb + (Y & 1) * 32 + 4 * q;
-            const float4_t f0 = *reinterpret_cast<const float4_t *>(ib);
-            const float4_t f1 = *reinterpret_cast<const float4_t *>(ib + 4);
-            const float2 f2 = *reinterpret_cast<const float2 *>(ib + 8);
-            iv[0] = f0[0]; iv[1] = f0[1]; iv[2] = f0[2]; iv[3] = f0[3];
-            iv[4] = f1[0]; iv[5] = f1[1]; iv[6] = f1[2]; iv[7] = f1[3];
-            iv[8] = f2.x; iv[9] = f2.y;
-        }
-        // One FP32 accumulator per bx; the hi and lo products of a step are
-        // issued bx-interleaved so consecutive instructions are independent.
-        float4_t d[kStripMaxBX];
-#pragma unroll
-        for (int bx = 0; bx < kStripMaxBX; ++bx) d[bx] = float4_t{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int j = 0; j < Sh::K32; ++j) {
-            const _Float16 *ap = ring + ((Y + a_row[j]) & 3) * ROWH + a_off[j];
-            half8_t av[kStripMaxBX];
-#pragma unroll
-            for (int bx = 0; bx < kStripMaxBX; ++bx) av[bx] = load_a8(ap + bx * NBP);
-#pragma unroll
-            for (int bx = 0; bx < kStripMaxBX; ++bx)
-                d[bx] = __builtin_amdgcn_mfma_f32_16x16x32_f16(av[bx], bh[bx][j], d[bx], 0, 0, 0);
-#pragma unroll
-            for (int bx = 0; bx < kStripMaxBX; ++bx)
-                d[bx] = __builtin_amdgcn_mfma_f32_16x16x32_f16(av[bx], bl[bx][j], d[bx], 0, 0, 0);
-        }
-        if constexpr (Sh::K16 > 0) {
-            const _Float16 *ap = ring + ((Y + a_row[Sh::K32]) & 3) * ROWH + a_off[Sh::K32];
-            half4_t av[kStripMaxBX];
-#pragma unroll
-            for (int bx = 0; bx < kStripMaxBX; ++bx) av[bx] = *reinterpret_cast<const half4_t *>(ap + bx * NBP);
-#pragma unroll
-            for (int bx = 0; bx < kStripMaxBX; ++bx)
-                d[bx] = __builtin_amdgcn_mfma_f32_16x16x16f16(av[bx], bh16[bx], d[bx], 0, 0, 0);
-#pragma unroll
-            for (int bx = 0; bx < kStripMaxBX; ++bx)
-                d[bx] = __builtin_amdgcn_mfma_f32_16x16x16f16(av[bx], bl16[bx], d[bx], 0, 0, 0);
-        }
-        float acc32[4] = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int bx = 0; bx < kStripMaxBX; ++bx)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) acc32[r] = fmaf(d[bx][r], iv[r + bx], acc32[r]);
-        const int wy_done = Y - (a.nby - 1);
-        const bool done = m == a.nby - 1 && wy_done >= wy_lo && wy_done < wy_hi;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            acc[r] += (double)(acc32[r] * cs);
-            if (done) outb[(wy_done - wy_lo) * kStripW + 4 * q + r] = (float)(bk + acc[r]);
-            acc[r] = shift_row_right(acc[r]);
-        }
-        if (more) {
-            store_row((Y + 2) & 3, pre2);
+    // The row loop once per mode (a uniform branch outside it, so that each
+    // loop gets its own register allocation).
+    auto rows = [&](auto mtag) {
+        constexpr int M = decltype(mtag)::value;
+        for (int Y = wy_lo; Y <= y_last; ++Y) {
+            const bool more = Y + 2 <= y_last + 1;
             lds_order();
-            // Next block row's norms, one row ahead of their use.
-            const float sq2 = row_sq((Y + 2) & 3);
-            block_norms(Y + 1, sq1, sq2);
-            sq1 = sq2;
+            // iv[t] = inv of block 4 q + t of this row (t = r + bx <= 9).
+            float iv[10];
+            {
+                const float *ib = invb + (Y & 1) * 32 + 4 * q;
+                const float4_t f0 = *reinterpret_cast<const float4_t *>(ib);
+                const float4_t f1 = *reinterpret_cast<const float4_t *>(ib + 4);
+                const float2 f2 = *reinterpret_cast<const float2 *>(ib + 8);
+                iv[0] = f0[0]; iv[1] = f0[1]; iv[2] = f0[2]; iv[3] = f0[3];
+                iv[4] = f1[0]; iv[5] = f1[1]; iv[6] = f1[2]; iv[7] = f1[3];
+                iv[8] = f2.x; iv[9] = f2.y;
+            }
+            // One FP32 accumulator per bx; the hi and lo products of a step are
+            // issued bx-interleaved so consecutive instructions are independent.
+            float4_t d[kStripMaxBX];
+            auto zero_d = [&] {
+#pragma unroll
+                for (int bx = 0; bx < kStripMaxBX; ++bx) d[bx] = float4_t{0.f, 0.f, 0.f, 0.f};
+            };
+            // The fp16 products of every step, hi and lo halves.
+            auto f16_products = [&] {
+#pragma unroll
+                for (int j = 0; j < Sh::K32; ++j) {
+                    const _Float16 *ap = ring + ((Y + a_row[j]) & 3) * ROWH + a_off[j];
+                    half8_t av[kStripMaxBX];
+#pragma unroll
+                    for (int bx = 0; bx < kStripMaxBX; ++bx) av[bx] = load_a8(ap + bx * NBP);
+#pragma unroll
+                    for (int bx = 0; bx < kStripMaxBX; ++bx)
+                        d[bx] = __builtin_amdgcn_mfma_f32_16x16x32_f16(
+                            av[bx], __builtin_bit_cast(half8_t, braw[bx][2 * j]), d[bx], 0, 0, 0);
+#pragma unroll
+                    for (int bx = 0; bx < kStripMaxBX; ++bx)
+                        d[bx] = __builtin_amdgcn_mfma_f32_16x16x32_f16(
+                            av[bx], __builtin_bit_cast(half8_t, braw[bx][2 * j + 1]), d[bx], 0, 0, 0);
+                }
+                if constexpr (Sh::K16 > 0) {
+                    // The 16x16x16 products take the 16x16x32 products' results
+                    // as their accumulator input. Left alone the compiler may
+                    // issue one right behind the 16x16x32 product it reads, with
+                    // no wait states, and that read has been seen to miss the
+                    // chain's last two products (the last bx lost its second
+                    // step). No matrix instruction crosses this barrier (LDS
+                    // reads, vector and scalar ALU may: mask 0x106), so each
+                    // bx's last 16x16x32 product is followed by those of later
+                    // bx and the 16x16x16 ones of earlier bx before its own
+                    // 16x16x16 product reads it (at least five other products).
+                    __builtin_amdgcn_sched_barrier(0x106);
+                    const _Float16 *ap = ring + ((Y + a_row[Sh::K32]) & 3) * ROWH + a_off[Sh::K32];
+                    half4_t av[kStripMaxBX];
+#pragma unroll
+                    for (int bx = 0; bx < kStripMaxBX; ++bx) av[bx] = *reinterpret_cast<const half4_t *>(ap + bx * NBP);
+#pragma unroll
+                    for (int bx = 0; bx < kStripMaxBX; ++bx) {
+                        const half8_t hl = __builtin_bit_cast(half8_t, braw[bx][2 * Sh::K32]);
+                        d[bx] = __builtin_amdgcn_mfma_f32_16x16x16f16(
+                            av[bx], __builtin_shufflevector(hl, hl, 0, 1, 2, 3), d[bx], 0, 0, 0);
+                    }
+#pragma unroll
+                    for (int bx = 0; bx < kStripMaxBX; ++bx) {
+                        const half8_t hl = __builtin_bit_cast(half8_t, braw[bx][2 * Sh::K32]);
+                        d[bx] = __builtin_amdgcn_mfma_f32_16x16x16f16(
+                            av[bx], __builtin_shufflevector(hl, hl, 4, 5, 6, 7), d[bx], 0, 0, 0);
+                    }
+                }
+            };
+            // acc32[r] (+)= sum_bx inv(Y, 4 q + r + bx) d[bx][r].
+            float acc32[4] = {0.f, 0.f, 0.f, 0.f};
+            auto fold = [&](float (&t)[4]) {
+#pragma unroll
+                for (int bx = 0; bx < kStripMaxBX; ++bx)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) t[r] = fmaf(d[bx][r], iv[r + bx], t[r]);
+            };
+            zero_d();
+            if constexpr (M == kModeSplit) {
+                f16_products();
+                fold(acc32);
+            } else {
+                // Exact mode: FP32 products, 4 features per step. Lane group q
+                // takes cell q of each block -- cell row Y + q / 2, column
+                // m + bx + q % 2 of the staged row -- bins 4 i .. 4 i + 3 at slot i.
+                const _Float16 *cp = ring + ((Y + (q >> 1)) & 3) * ROWH + (m + (q & 1)) * NBP;
+#pragma unroll
+                for (int i = 0; i < NI; ++i) {
+                    half4_t av[kStripMaxBX];
+#pragma unroll
+                    for (int bx = 0; bx < kStripMaxBX; ++bx) av[bx] = *reinterpret_cast<const half4_t *>(cp + bx * NBP + 4 * i);
+#pragma unroll
+                    for (int c = 0; c < 4; ++c)
+#pragma unroll
+                        for (int bx = 0; bx < kStripMaxBX; ++bx)
+                            d[bx] = __builtin_amdgcn_mfma_f32_16x16x4f32((float)av[bx][c],
+                                                                        __uint_as_float(braw[bx][i][c]), d[bx], 0, 0, 0);
+                }
+                fold(acc32);
+            }
+            const int wy_done = Y - (a.nby - 1);
+            const bool done = m == a.nby - 1 && wy_done >= wy_lo && wy_done < wy_hi;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                acc[r] += (double)(acc32[r] * cs);
+                if (done) outb[(wy_done - wy_lo) * kStripW + 4 * q + r] = (float)(bk + acc[r]);
+                acc[r] = shift_row_right(acc[r]);
+            }
+            if (more) {
+                store_row((Y + 2) & 3, pre2);
+                lds_order();
+                // Next block row's norms, one row ahead of their use.
+                const float sq2 = row_sq((Y + 2) & 3);
+                block_norms(Y + 1, sq1, sq2);
+                sq1 = sq2;
+            }
+            pre2 = pre3;
+            if (Y + 4 <= y_last + 1) pre3 = fetch(Y + 4);
         }
-        pre2 = pre3;
-        if (Y + 4 <= y_last + 1) pre3 = fetch(Y + 4);
-    }
+    };
+    if (mode == kModeExact)
+        rows(IntTag<kModeExact>{});
+    else
+        rows(IntTag<kModeSplit>{});
     lds_order();
     const int n_out = (wy_hi - wy_lo) * kStripW;
     for (int i = lane; i < n_out; i += 64) {
@@ -1582,7 +1696,14 @@ __global__ __launch_bounds__(256, 2) void k_score_strip(const Level *__restrict_
 // holds one window and the block's 1/sqrt(|v|^2 + eps^2) is one scale per
 // lane: S[k][m] += inv(B(m, p)) * D_p[k][m] (FP32). The counts are exact in
 // fp16; k_score_prep_wg scales each template by a power of two (its max |T|
-// into [2^14, 2^15)) and splits it into fp16 hi + lo.
+// into [2^14, 2^15)) and splits it into fp16 hi + lo, lo stored times 2^11
+// and multiplying the counts times 2^-11 (exact in fp16), so that each weight
+// within about 2^28 of its template's largest keeps 2^-22 relative (an
+// unscaled lo half would be an fp16 subnormal from about 2^17 down: with 32
+// templates per tile that range is common). A tile holding a template
+// that neither split carries to 2^-22 relative (a nonzero weight more than
+// about 2^28 below the template's largest) is scored in exact mode: FP32
+// weights and FP32 32x32x2 products on the same tiles.
 //
 // A workgroup covers one tile of windows for one tile of 32 templates, in
 // one of two shapes (WgShape): kWgW window columns x kWgTH rows, where wave w
@@ -1617,21 +1738,21 @@ struct WgArgs {
 
 typedef float float16v_t __attribute__((ext_vector_type(16)));
 
-// One workgroup (1024 threads) per tile of 32 templates: per-template scales,
-// then the A fragments [p][s][hi|lo][lane] (lane: template kk0 + lane % 32,
-// features 16 s + 8 (lane / 32) .. + 7 of the block at position p).
 // Per template: the power of two that brings its max |T| into [2^14, 2^15)
-// -- exponent e (int) and scale 2^-e (float), stored after its tile's
-// fragments. One wave per template slot of every tile (0 past the last
-// template), 8 loads in flight per lane.
+// -- scale 2^-e (float [32]) and exponent e (int [32]), stored after its
+// tile's fragments -- and the template's mode (int [32] after those):
+// kModeExact if some nonzero weight scales below 2^-14 (where hi is an fp16
+// subnormal), else kModeWide. A tile with an exact template is scored in
+// exact mode. One wave per template slot of every
+// tile (0 past the last template), 8 loads in flight per lane.
 __global__ __launch_bounds__(64) void k_score_prep_wg_scale(WgArgs a, const float *__restrict__ tmpl,
                                                             uint8_t *__restrict__ ws, int64_t frag_bytes)
 {
     const int kk = (int)blockIdx.x, kt = kk >> 5, tk = kk & 31;
     const int lane = threadIdx.x;
+    const float *t = tmpl + (int64_t)kk * a.dim;
     float mx = 0.f;
     if (kk < a.k) {
-        const float *t = tmpl + (int64_t)kk * a.dim;
         int i = lane;
         for (; i + 7 * 64 < a.dim; i += 8 * 64) {
             float r[8];
@@ -1647,17 +1768,32 @@ __global__ __launch_bounds__(64) void k_score_prep_wg_scale(WgArgs a, const floa
     int ex = 0;
     if (mx > 0.f) (void)frexpf(mx, &ex);  // mx = f 2^ex, f in [0.5, 1)
     const int e = mx > 0.f ? 15 - ex : 0;
+    float svmin = INFINITY;  // smallest nonzero scaled weight
+    if (kk < a.k)
+        for (int i = lane; i < a.dim; i += 64) {
+            const float w = t[i];
+            if (w != 0.f) svmin = fminf(svmin, fabsf(ldexpf(w, e)));
+        }
+    const bool any_exact = __any(svmin < 0x1p-14f);
     uint8_t *tp = ws + a.tprep_off + (int64_t)kt * a.tprep_stride + frag_bytes;
     if (lane == 0) {
         reinterpret_cast<float *>(tp)[tk] = ldexpf(1.f, -e);
         reinterpret_cast<int *>(tp + 32 * 4)[tk] = e;
+        reinterpret_cast<int *>(tp + 32 * 8)[tk] = any_exact ? kModeExact : kModeWide;
     }
 }
 
-// The A fragments [p][s][hi|lo][lane] of a tile (lane: template kk0 + lane %
-// 32, features 16 s + 8 (lane / 32) .. + 7 of the block at position p),
-// scaled by 2^e and split into fp16 hi + lo: one fragment per thread, over
-// as many workgroups as the tile has fragments / 256.
+// The A fragments of a tile, 16 bytes per thread, over as many workgroups as
+// the tile has fragments / 256. Split mode: [p][s][hi|lo][lane] (lane:
+// template kk0 + lane % 32, features 16 s + 8 (lane / 32) .. + 7 of the block
+// at position p), the weights sv scaled by 2^e and split into fp16 hi = sv
+// rounded and lo = (sv - hi) 2^11 rounded (the scorer multiplies lo by the
+// counts times 2^-11, which is exact in fp16).
+// Exact mode (a template of the tile flagged by k_score_prep_wg_scale): the
+// FP32 weights [p][t][lane] for the 32x32x2 FP32 products, t < 2 NBP: lane
+// (template kk0 + lane % 32, h = lane / 32) holds feature h 2 NBP + t of the
+// block (cell row h, cell t / NBP, bin t % NBP). Both take 512 NBP bytes per
+// block position.
 template <int NBP>
 __global__ __launch_bounds__(256) void k_score_prep_wg(WgArgs a, const float *__restrict__ tmpl,
                                                        uint8_t *__restrict__ ws)
@@ -1669,9 +1805,29 @@ __global__ __launch_bounds__(256) void k_score_prep_wg(WgArgs a, const float *__
     const int f = (int)(blockIdx.x * 256 + threadIdx.x);
     if (f >= n_frag) return;
     const int *ex = reinterpret_cast<const int *>(tp + (int64_t)n_frag * 16 + 32 * 4);
+    const int *tmode = ex + 32;
+    bool exact = false;
+    for (int i = 0; i < 32; ++i) exact |= tmode[i] == kModeExact;
     const int lane = f & 63, rest = f >> 6;
-    const int hl = rest & 1, s = (rest >> 1) % KS, pos = (rest >> 1) / KS;
+    const int pos = (rest >> 1) / KS;
     const int by = pos / kStripMaxBX, bx = pos % kStripMaxBX;
+    const float *tpos = tmpl + (int64_t)(by * kStripMaxBX + bx) * 4 * a.nb;
+    if (exact) {
+        // Floats 4 fl .. 4 fl + 3 of position pos, fl = the thread's 16-byte
+        // slot within it; float j sits at [t = j / 64][lane' = j % 64].
+        const int fl = f - pos * KS * 2 * 64;
+        float4_t out;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int j = 4 * fl + c, t = j >> 6, ln = j & 63;
+            const int kk = kk0 + (ln & 31), h = ln >> 5;
+            const int u = t / NBP, bin = t % NBP;
+            out[c] = kk < a.k && bin < a.nb ? tpos[(int64_t)kk * a.dim + (h * 2 + u) * a.nb + bin] : 0.f;
+        }
+        *reinterpret_cast<float4_t *>(tp + (int64_t)f * 16) = out;
+        return;
+    }
+    const int hl = rest & 1, s = (rest >> 1) % KS;
     const int kk = kk0 + (lane & 31), h = lane >> 5;
     const int e = ex[lane & 31];
     half8_t out;
@@ -1681,11 +1837,10 @@ __global__ __launch_bounds__(256) void k_score_prep_wg(WgArgs a, const float *__
         const int w = kf / (2 * NBP), rem = kf % (2 * NBP);
         const int u = rem / NBP, bin = rem % NBP;
         float val = 0.f;
-        if (kk < a.k && bin < a.nb)
-            val = tmpl[(int64_t)kk * a.dim + ((by * kStripMaxBX + bx) * 4 + w * 2 + u) * a.nb + bin];
+        if (kk < a.k && bin < a.nb) val = tpos[(int64_t)kk * a.dim + (w * 2 + u) * a.nb + bin];
         const float sv = ldexpf(val, e);
         const _Float16 hi = (_Float16)sv;
-        out[i] = hl == 0 ? hi : (_Float16)(sv - (float)hi);
+        out[i] = hl == 0 ? hi : (_Float16)((sv - (float)hi) * 2048.f);
     }
     *reinterpret_cast<half8_t *>(tp + (int64_t)f * 16) = out;
 }
@@ -1727,6 +1882,9 @@ __device__ __forceinline__ void wgemm_tile(WgLds<NBP> &L, const Level &v, int re
     const int nb = a.nb, nby = a.nby;
     const uint8_t *tp = ws + a.tprep_off + (int64_t)kt * a.tprep_stride;
     const u32x4 *tfrag = reinterpret_cast<const u32x4 *>(tp);
+    // The tile's mode: the strongest among its templates' (k_score_prep_wg_scale).
+    const int tmode = reinterpret_cast<const int *>(tp + (int64_t)nby * NFRAG * 64 * 16 + 32 * 8)[lane & 31];
+    const bool exact = __any(tmode == kModeExact);
 
     for (int i = tid; i < SLOTS * ROWH / 8; i += 256)
         reinterpret_cast<u32x4 *>(&ring[0][0])[i] = u32x4{0u, 0u, 0u, 0u};
@@ -1797,100 +1955,135 @@ __device__ __forceinline__ void wgemm_tile(WgLds<NBP> &L, const Level &v, int re
 #pragma unroll
         for (int r = 0; r < 16; ++r) S[q][r] = 0.f;
 
-    for (int by = 0; by < nby; ++by) {
-        __syncthreads();  // rows and their sums of squares are in place
-        // Norms of the block rows new to the tile's window rows: all TH at
-        // by = 0, then one per by. Block row wy0 + Y sits in invb[Y % TH]
-        // while it is in use (by <= Y < by + TH).
-        const int r0 = by == 0 ? 0 : TH - 1;
-        for (int i = tid; i < (TH - r0) * (CELLS - 1); i += 256) {
-            const int rho = r0 + i / (CELLS - 1), c = i - (rho - r0) * (CELLS - 1);
-            const int Y = by + rho;
-            const int s0 = (wy0 + Y) % SLOTS, s1 = (wy0 + Y + 1) % SLOTS;
-            invb[Y % TH][c] = inv_block_norm((sqr[s0][c] + sqr[s0][c + 1]) + (sqr[s1][c] + sqr[s1][c + 1]), a.eps);
-        }
-        __syncthreads();
-        const half8_t *bf = reinterpret_cast<const half8_t *>(bst[by & 1]);
-#pragma unroll 1
-        for (int bx = 0; bx < kStripMaxBX; ++bx) {
-            half8_t bh[KS], bl[KS];
-#pragma unroll
-            for (int s2 = 0; s2 < KS; ++s2) {
-                bh[s2] = bf[((bx * KS + s2) * 2 + 0) * 64 + lane];
-                bl[s2] = bf[((bx * KS + s2) * 2 + 1) * 64 + lane];
+    // The block-row walk once per mode (a uniform branch outside it, so that
+    // each walk gets its own register allocation).
+    auto walk = [&](auto mtag) {
+        constexpr int M = decltype(mtag)::value;
+        for (int by = 0; by < nby; ++by) {
+            __syncthreads();  // rows and their sums of squares are in place
+            // Norms of the block rows new to the tile's window rows: all TH at
+            // by = 0, then one per by. Block row wy0 + Y sits in invb[Y % TH]
+            // while it is in use (by <= Y < by + TH).
+            const int r0 = by == 0 ? 0 : TH - 1;
+            for (int i = tid; i < (TH - r0) * (CELLS - 1); i += 256) {
+                const int rho = r0 + i / (CELLS - 1), c = i - (rho - r0) * (CELLS - 1);
+                const int Y = by + rho;
+                const int s0 = (wy0 + Y) % SLOTS, s1 = (wy0 + Y + 1) % SLOTS;
+                invb[Y % TH][c] = inv_block_norm((sqr[s0][c] + sqr[s0][c + 1]) + (sqr[s1][c] + sqr[s1][c + 1]), a.eps);
             }
-            half8_t wf[4][KS];
+            __syncthreads();
+            if constexpr (M == kModeExact) {
+                // Exact mode: FP32 products, 2 features per step; at step t lane
+                // (template or window n, h) takes feature h 2 NBP + t of the block:
+                // cell row h, cell t / NBP, bin t % NBP.
+                const float *af = reinterpret_cast<const float *>(bst[by & 1]);
+#pragma unroll 1
+                for (int bx = 0; bx < kStripMaxBX; ++bx) {
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int rho = NARROW ? wave + 4 * q : wave + 4 * (q >> 1), mu = NARROW ? 0 : q & 1;
+                    for (int q = 0; q < 4; ++q) {
+                        const int rho = NARROW ? wave + 4 * q : wave + 4 * (q >> 1), mu = NARROW ? 0 : q & 1;
+                        const float ivq = invb[(by + rho) % TH][32 * mu + n + bx];
+                        const int wi = ((wy0 + by + rho + h) % SLOTS) * ROWH + (32 * mu + n + bx) * NBP;
+                        float16v_t d;
+#pragma unroll
+                        for (int r = 0; r < 16; ++r) d[r] = 0.f;
+#pragma unroll 2
+                        for (int t = 0; t < 2 * NBP; ++t)
+                            d = __builtin_amdgcn_mfma_f32_32x32x2f32(af[(bx * 2 * NBP + t) * 64 + lane],
+                                                                    (float)L.ring[wi + t], d, 0, 0, 0);
+#pragma unroll
+                        for (int r = 0; r < 16; ++r) S[q][r] = fmaf(d[r], ivq, S[q][r]);
+                    }
+                }
+            } else {
+            const half8_t *bf = reinterpret_cast<const half8_t *>(bst[by & 1]);
+#pragma unroll 1
+            for (int bx = 0; bx < kStripMaxBX; ++bx) {
+                half8_t bh[KS], bl[KS];
 #pragma unroll
                 for (int s2 = 0; s2 < KS; ++s2) {
-                    const int kf = 16 * s2 + 8 * h;
-                    const int w = kf / (2 * NBP);
-                    wf[q][s2] = *reinterpret_cast<const half8_t *>(
-                        &ring[(wy0 + by + rho + w) % SLOTS][(32 * mu + n + bx) * NBP + kf % (2 * NBP)]);
+                    bh[s2] = bf[((bx * KS + s2) * 2 + 0) * 64 + lane];
+                    bl[s2] = bf[((bx * KS + s2) * 2 + 1) * 64 + lane];
                 }
+                half8_t wf[4][KS];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int rho = NARROW ? wave + 4 * q : wave + 4 * (q >> 1), mu = NARROW ? 0 : q & 1;
+#pragma unroll
+                    for (int s2 = 0; s2 < KS; ++s2) {
+                        const int kf = 16 * s2 + 8 * h;
+                        const int w = kf / (2 * NBP);
+                        wf[q][s2] = *reinterpret_cast<const half8_t *>(
+                            &ring[(wy0 + by + rho + w) % SLOTS][(32 * mu + n + bx) * NBP + kf % (2 * NBP)]);
+                    }
+                }
+                float iv[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    iv[q] = NARROW ? invb[(by + wave + 4 * q) % TH][n + bx]
+                                   : invb[(by + wave + 4 * (q >> 1)) % TH][32 * (q & 1) + n + bx];
+                float16v_t d[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) d[q][r] = 0.f;
+                // Left alone, the compiler issues all 16 products and then the 64
+                // scalings. The scheduling barriers make it issue the products
+                // of q = 0, 1 first, then alternate those of q = 2, 3 with the
+                // scalings of q = 0, 1 (group masks: 0x008 matrix instructions,
+                // 0x002 other vector ALU), so both units work at once. Each
+                // S[q][r] still takes its terms in bx order.
+#pragma unroll
+                for (int s2 = 0; s2 < KS; ++s2)
+#pragma unroll
+                    for (int q = 0; q < 2; ++q) d[q] = __builtin_amdgcn_mfma_f32_32x32x16_f16(bh[s2], wf[q][s2], d[q], 0, 0, 0);
+#pragma unroll
+                for (int s2 = 0; s2 < KS; ++s2)
+#pragma unroll
+                    for (int q = 0; q < 2; ++q) d[q] = __builtin_amdgcn_mfma_f32_32x32x16_f16(bl[s2], wf[q][s2] * (_Float16)0x1p-11f, d[q], 0, 0, 0);
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int s2 = 0; s2 < KS; ++s2)
+#pragma unroll
+                    for (int q = 2; q < 4; ++q) d[q] = __builtin_amdgcn_mfma_f32_32x32x16_f16(bh[s2], wf[q][s2], d[q], 0, 0, 0);
+#pragma unroll
+                for (int s2 = 0; s2 < KS; ++s2)
+#pragma unroll
+                    for (int q = 2; q < 4; ++q) d[q] = __builtin_amdgcn_mfma_f32_32x32x16_f16(bl[s2], wf[q][s2] * (_Float16)0x1p-11f, d[q], 0, 0, 0);
+#pragma unroll
+                for (int q = 0; q < 2; ++q)
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) S[q][r] = fmaf(d[q][r], iv[q], S[q][r]);
+#pragma unroll
+                for (int i = 0; i < 4 * KS; ++i) {
+                    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+                    __builtin_amdgcn_sched_group_barrier(0x002, 32 / (4 * KS), 0);
+                }
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int q = 2; q < 4; ++q)
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) S[q][r] = fmaf(d[q][r], iv[q], S[q][r]);
             }
-            float iv[4];
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-                iv[q] = NARROW ? invb[(by + wave + 4 * q) % TH][n + bx]
-                               : invb[(by + wave + 4 * (q >> 1)) % TH][32 * (q & 1) + n + bx];
-            float16v_t d[4];
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-#pragma unroll
-                for (int r = 0; r < 16; ++r) d[q][r] = 0.f;
-            // Left alone, the compiler issues all 16 products and then the 64
-            // scalings. The scheduling barriers make it issue the products
-            // of q = 0, 1 first, then alternate those of q = 2, 3 with the
-            // scalings of q = 0, 1 (group masks: 0x008 matrix instructions,
-            // 0x002 other vector ALU), so both units work at once. Each
-            // S[q][r] still takes its terms in bx order.
-#pragma unroll
-            for (int s2 = 0; s2 < KS; ++s2)
-#pragma unroll
-                for (int q = 0; q < 2; ++q) d[q] = __builtin_amdgcn_mfma_f32_32x32x16_f16(bh[s2], wf[q][s2], d[q], 0, 0, 0);
-#pragma unroll
-            for (int s2 = 0; s2 < KS; ++s2)
-#pragma unroll
-                for (int q = 0; q < 2; ++q) d[q] = __builtin_amdgcn_mfma_f32_32x32x16_f16(bl[s2], wf[q][s2], d[q], 0, 0, 0);
-            __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-            for (int s2 = 0; s2 < KS; ++s2)
-#pragma unroll
-                for (int q = 2; q < 4; ++q) d[q] = __builtin_amdgcn_mfma_f32_32x32x16_f16(bh[s2], wf[q][s2], d[q], 0, 0, 0);
-#pragma unroll
-            for (int s2 = 0; s2 < KS; ++s2)
-#pragma unroll
-                for (int q = 2; q < 4; ++q) d[q] = __builtin_amdgcn_mfma_f32_32x32x16_f16(bl[s2], wf[q][s2], d[q], 0, 0, 0);
-#pragma unroll
-            for (int q = 0; q < 2; ++q)
-#pragma unroll
-                for (int r = 0; r < 16; ++r) S[q][r] = fmaf(d[q][r], iv[q], S[q][r]);
-#pragma unroll
-            for (int i = 0; i < 4 * KS; ++i) {
-                __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-                __builtin_amdgcn_sched_group_barrier(0x002, 32 / (4 * KS), 0);
             }
-            __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-            for (int q = 2; q < 4; ++q)
-#pragma unroll
-                for (int r = 0; r < 16; ++r) S[q][r] = fmaf(d[q][r], iv[q], S[q][r]);
+            __syncthreads();  // done with this by's ring slot, fragments and norms
+            if (by + 1 < nby) {
+                store_frags((by + 1) & 1, pf);
+                store_row(wy0 + by + TH + 1, cpre);
+                __syncthreads();
+                row_sq(wy0 + by + TH + 1);
+                cpre = fetch_row(wy0 + by + TH + 2);
+                if (by + 2 < nby) fetch_frags(by + 2, pf);
+            }
         }
-        __syncthreads();  // done with this by's ring slot, fragments and norms
-        if (by + 1 < nby) {
-            store_frags((by + 1) & 1, pf);
-            store_row(wy0 + by + TH + 1, cpre);
-            __syncthreads();
-            row_sq(wy0 + by + TH + 1);
-            cpre = fetch_row(wy0 + by + TH + 2);
-            if (by + 2 < nby) fetch_frags(by + 2, pf);
-        }
-    }
+    };
+    if (exact)
+        walk(IntTag<kModeExact>{});
+    else
+        walk(IntTag<kModeWide>{});
 
-    // scores[(wy * win_x + wx) * K + k] = bias_k + cs_k * S[k][window].
+    // scores[(wy * win_x + wx) * K + k] = bias_k + cs_k * S[k][window] (cs_k = 1
+    // in exact mode).
     const float *cs = reinterpret_cast<const float *>(tp + (int64_t)nby * NFRAG * 64 * 16);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -1902,7 +2095,7 @@ __device__ __forceinline__ void wgemm_tile(WgLds<NBP> &L, const Level &v, int re
             for (int r = 0; r < 16; ++r) {
                 const int kr = 8 * (r >> 2) + 4 * h + (r & 3);
                 if (kk0 + kr < a.k)
-                    out[kk0 + kr] = (float)((double)bias[kk0 + kr] + (double)(cs[kr] * S[q][r]));
+                    out[kk0 + kr] = (float)((double)bias[kk0 + kr] + (double)((exact ? 1.f : cs[kr]) * S[q][r]));
             }
         }
     }

@@ -22,12 +22,13 @@ HOG_ORIENT_SIGNED, HOG_ORIENT_UNSIGNED = 0, 1
 HOG_VOTES_HARD, HOG_VOTES_SOFT = 0, 1
 HOG_SOFT_QUANTUM = 32
 HOG_MAX_LEVEL_GROUPS = 4
+HOG_LUT_DEVICE_FULL, HOG_LUT_DEVICE_HALF, HOG_LUT_DEVICE_SOFT = 0, 1, 2
 LUT_SIDE = 511
 
 # Every symbol include/hog.h declares.
 EXPORTS = (
     "hog_last_error", "hog_lut_fill_host", "hog_lut_build", "hog_lut_free", "hog_lut_bins",
-    "hog_lut_host", "hog_lut_fill_host_ex", "hog_lut_build_ex", "hog_lut_orientation",
+    "hog_lut_host", "hog_lut_read_device", "hog_lut_fill_host_ex", "hog_lut_build_ex", "hog_lut_orientation",
     "hog_lut_fill_soft_host", "hog_plan_create", "hog_plan_create_batch", "hog_plan_images",
     "hog_plan_get_image", "hog_plan_destroy", "hog_plan_get_sizes",
     "hog_plan_get_level", "hog_bin_map", "hog_integral", "hog_scan_windows", "hog_run",
@@ -137,6 +138,7 @@ def load_library():
         "hog_lut_free": ([vp], None),
         "hog_lut_bins": ([vp], i32),
         "hog_lut_host": ([vp], vp),
+        "hog_lut_read_device": ([vp, i32, vp, i64], i32),
         "hog_plan_create": ([ctypes.POINTER(PlanDesc), ctypes.POINTER(vp)], i32),
         "hog_plan_create_batch": ([ctypes.POINTER(PlanDesc), i32, ctypes.POINTER(vp)], i32),
         "hog_plan_images": ([vp], i32),
@@ -230,6 +232,17 @@ class Lut:
         p = load_library().hog_lut_host(self.handle)
         buf = (ctypes.c_uint8 * (LUT_SIDE * LUT_SIDE)).from_address(p)
         return np.frombuffer(buf, dtype=np.uint8).reshape(LUT_SIDE, LUT_SIDE).copy()
+
+    def device_table(self, table: int) -> np.ndarray:
+        """A device copy read back: HOG_LUT_DEVICE_FULL uint8[511][511],
+        HOG_LUT_DEVICE_HALF uint8[256][511], HOG_LUT_DEVICE_SOFT uint16[511][511]."""
+        shape, dt = {HOG_LUT_DEVICE_FULL: ((LUT_SIDE, LUT_SIDE), np.uint8),
+                     HOG_LUT_DEVICE_HALF: ((256, LUT_SIDE), np.uint8),
+                     HOG_LUT_DEVICE_SOFT: ((LUT_SIDE, LUT_SIDE), np.uint16)}[table]
+        out = np.empty(shape, dt)
+        _check(load_library().hog_lut_read_device(self.handle, int(table), out.ctypes.data_as(ctypes.c_void_p),
+                                                  out.nbytes))
+        return out
 
     def free(self):
         if self.handle:

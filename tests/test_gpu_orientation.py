@@ -1,5 +1,5 @@
 """Unsigned orientation (the table variant of Fig. 4's 9-bin, 0..180 degree
-example): the device table, and the whole path run with it, against the
+example): the host table, and the whole path run with it, against the
 oracle's unsigned bins -- bins, planes and cells bit for bit, scores within
 tolerance. The kernels are those of the signed path; only the table differs."""
 import numpy as np
@@ -16,7 +16,9 @@ pytestmark = pytest.mark.gpu
 U = hog.HOG_ORIENT_UNSIGNED
 
 
-def test_unsigned_device_table_matches_oracle():
+def test_unsigned_host_table_matches_oracle():
+    """The host copy of a built unsigned table; the device copies are read
+    back in test_gpu_lut_pairs."""
     for nb in (4, 9, 18, 64):
         lut = hog.hog_lut_build(nb, U)
         assert hog.load_library().hog_lut_orientation(lut.handle) == U

@@ -156,7 +156,9 @@ def test_repeat_is_bitwise_identical():
         assert np.array_equal(outs[0][key], outs[1][key]), key
 
 
-def test_lut_device_copy_matches_oracle():
+def test_lut_host_copy_matches_oracle():
+    """The host copy a built table keeps (hog_lut_host); the device copies are
+    read back in test_gpu_lut_pairs."""
     for nb in (8, 18, 20):
         lut = hog.hog_lut_build(nb)
         assert np.array_equal(lut.host_table(), oracle.bin_table(nb))
