@@ -349,6 +349,25 @@ hog_status hog_run(const hog_plan *plan, const hog_lut *lut, const uint8_t *img,
                    uint8_t *bins, void *ii, const float *tmpl, const float *bias, float *scores,
                    void *workspace, void *stream);
 
+/* hog_run without a workspace argument and without any allocation, for
+ * callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc). The workspace is a
+ * library-owned static device array of HOG_STATIC_SCRATCH_BYTES, one per GPU,
+ * held from library load until the process ends; its address is looked up
+ * once per device on the first call there. Same buffers, layouts and results
+ * as hog_run with one difference: the levels run as one group (the plan's
+ * level_groups are not used, since their streams are created on first use),
+ * and no kernel timing is recorded. The plan's device must be the current
+ * device. HOG_E_INVALID, with nothing enqueued, if the plan's workspace_bytes
+ * exceeds HOG_STATIC_SCRATCH_BYTES or an argument is invalid. Every call on a
+ * GPU shares that GPU's array, and its contents on entry are ignored: calls
+ * whose work overlaps on one GPU (different streams, or threads) race on it
+ * and must be ordered by the caller. */
+#define HOG_STATIC_SCRATCH_BYTES (64ll << 20)
+hog_status hog_run_static(const hog_plan *plan, const hog_lut *lut, const uint8_t *img, int64_t img_pitch,
+                          uint8_t *bins, void *ii, const float *tmpl, const float *bias, float *scores,
+                          void *stream);
+
 /* hog_run captured once into a HIP graph for these exact buffers, replayed by
  * hog_graph_launch with one launch: for callers that run the same plan on the
  * same buffers again and again (a batch refilled in place, video frames).

@@ -49,6 +49,7 @@ struct PendingTiming {
 };
 bool g_timing_on = false;
 thread_local bool g_capturing = false;  // inside hog_graph_create: no timing events
+thread_local bool g_no_alloc = false;   // inside hog_run_static: no timing events either
 std::vector<PendingTiming> g_pending;
 std::vector<hipEvent_t> g_event_pool;
 std::map<std::string, std::pair<int64_t, double>> g_timing_totals;
@@ -66,7 +67,7 @@ hipError_t take_event(hipEvent_t *ev)
 template <class F>
 hipError_t timed_launch(const char *name, hipStream_t stream, F &&launch)
 {
-    if (!g_timing_on || g_capturing) return launch();
+    if (!g_timing_on || g_capturing || g_no_alloc) return launch();
     hipEvent_t a = nullptr, b = nullptr;
     hipError_t e = take_event(&a);
     if (e == hipSuccess) e = take_event(&b);
@@ -1299,6 +1300,55 @@ extern "C" hog_status hog_run(const hog_plan *plan, const hog_lut *lut, const ui
     hog_status st = check_run_args(plan, lut, img, img_pitch, bins, ii, tmpl, bias, scores, workspace);
     if (st != HOG_OK) return st;
     return run_plan(plan, lut, img, img_pitch, bins, ii, tmpl, bias, scores, workspace, stream);
+}
+
+// The workspace of hog_run_static: one static device array per GPU (each
+// device that loads the library holds its own copy). Host code never uses
+// the symbol itself, only the address hipGetSymbolAddress gives for the
+// current device, looked up once per device and kept.
+static __device__ __align__(256) uint8_t scratch[HOG_STATIC_SCRATCH_BYTES];
+static std::mutex g_scratch_mu;
+static std::map<int, void *> g_scratch_ptr;
+
+static hog_status static_scratch(int device, void **out)
+{
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    auto it = g_scratch_ptr.find(device);
+    if (it != g_scratch_ptr.end()) {
+        *out = it->second;
+        return HOG_OK;
+    }
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) return device_fail(e != hipSuccess ? e : hipErrorInvalidSymbol,
+                                                    "hipGetSymbolAddress(scratch)");
+    g_scratch_ptr[device] = ptr;
+    *out = ptr;
+    return HOG_OK;
+}
+
+extern "C" hog_status hog_run_static(const hog_plan *plan, const hog_lut *lut, const uint8_t *img,
+                                     int64_t img_pitch, uint8_t *bins, void *ii, const float *tmpl,
+                                     const float *bias, float *scores, void *stream)
+{
+    uint8_t placeholder = 0;  // the workspace is checked below, not passed in
+    hog_status st = check_run_args(plan, lut, img, img_pitch, bins, ii, tmpl, bias, scores, &placeholder);
+    if (st != HOG_OK) return st;
+    if (plan->sizes.workspace_bytes > HOG_STATIC_SCRATCH_BYTES)
+        return fail(HOG_E_INVALID, "the plan needs %lld workspace bytes; the static scratch holds %lld",
+                    (long long)plan->sizes.workspace_bytes, (long long)HOG_STATIC_SCRATCH_BYTES);
+    int cur = 0;
+    const hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return device_fail(e, "hipGetDevice");
+    if (cur != plan->device)
+        return fail(HOG_E_INVALID, "the plan is on device %d, the current device is %d", plan->device, cur);
+    void *ws = nullptr;
+    st = static_scratch(cur, &ws);
+    if (st != HOG_OK) return st;
+    g_no_alloc = true;
+    st = run_path(plan, lut, img, img_pitch, bins, ii, tmpl, bias, scores, ws, stream);
+    g_no_alloc = false;
+    return st;
 }
 
 struct hog_graph {

@@ -23,6 +23,7 @@ HOG_VOTES_HARD, HOG_VOTES_SOFT = 0, 1
 HOG_SOFT_QUANTUM = 32
 HOG_MAX_LEVEL_GROUPS = 4
 HOG_LUT_DEVICE_FULL, HOG_LUT_DEVICE_HALF, HOG_LUT_DEVICE_SOFT = 0, 1, 2
+HOG_STATIC_SCRATCH_BYTES = 64 << 20
 LUT_SIDE = 511
 
 # Every symbol include/hog.h declares.
@@ -31,7 +32,7 @@ EXPORTS = (
     "hog_lut_host", "hog_lut_read_device", "hog_lut_fill_host_ex", "hog_lut_build_ex", "hog_lut_orientation",
     "hog_lut_fill_soft_host", "hog_plan_create", "hog_plan_create_batch", "hog_plan_images",
     "hog_plan_get_image", "hog_plan_destroy", "hog_plan_get_sizes",
-    "hog_plan_get_level", "hog_bin_map", "hog_integral", "hog_scan_windows", "hog_run",
+    "hog_plan_get_level", "hog_bin_map", "hog_integral", "hog_scan_windows", "hog_run", "hog_run_static",
     "hog_graph_create", "hog_graph_launch", "hog_graph_destroy", "hog_plan_get_tiles",
     "hog_plan_set_tiles", "hog_plan_autotune", "hog_server_create", "hog_server_destroy",
     "hog_server_warm", "hog_submit", "hog_poll", "hog_wait_any",
@@ -150,6 +151,7 @@ def load_library():
         "hog_integral": ([vp, vp, vp, vp, vp], i32),
         "hog_scan_windows": ([vp, vp, vp, vp, vp, vp, vp, vp, vp], i32),
         "hog_run": ([vp, vp, vp, i64, vp, vp, vp, vp, vp, vp, vp], i32),
+        "hog_run_static": ([vp, vp, vp, i64, vp, vp, vp, vp, vp, vp], i32),
         "hog_graph_create": ([vp, vp, vp, i64, vp, vp, vp, vp, vp, vp, ctypes.POINTER(vp)], i32),
         "hog_graph_launch": ([vp, vp], i32),
         "hog_graph_destroy": ([vp], None),
@@ -417,7 +419,7 @@ def run_path(plan: Plan, lut: Lut, img, tmpl, bias, buf: Buffers, stream=None,
                      buf.workspace, buf.cell_hist, buf.block_feat, stream)
 
 
-def _run_args(plan: Plan, lut: Lut, img, tmpl, bias, buf: "Buffers", img_pitch=None):
+def _run_args(plan: Plan, lut: Lut, img, tmpl, bias, buf: "Buffers", img_pitch=None, with_workspace=True):
     import torch
     d = plan.desc
     if plan.batch:
@@ -428,18 +430,27 @@ def _run_args(plan: Plan, lut: Lut, img, tmpl, bias, buf: "Buffers", img_pitch=N
         pitch = d.width * d.channels if img_pitch is None else int(img_pitch)
         need = (d.height - 1) * pitch + d.width * d.channels
     k = d.n_templates
-    return (plan.handle, lut.handle, _dptr(img, torch.uint8, need, "img"), pitch,
+    args = (plan.handle, lut.handle, _dptr(img, torch.uint8, need, "img"), pitch,
             _dptr(buf.bins, torch.uint8, plan.sizes.bins_bytes, "bins"),
             _dptr(buf.ii, ii_dtype(plan), plan.sizes.ii_elems, "ii"),
             _dptr(tmpl, torch.float32, k * plan.sizes.feature_dim, "tmpl"),
             _dptr(bias, torch.float32, k, "bias"),
-            _dptr(buf.scores, torch.float32, plan.sizes.score_elems, "scores"),
-            _dptr(buf.workspace, torch.uint8, plan.sizes.workspace_bytes, "workspace"))
+            _dptr(buf.scores, torch.float32, plan.sizes.score_elems, "scores"))
+    if with_workspace:
+        args += (_dptr(buf.workspace, torch.uint8, plan.sizes.workspace_bytes, "workspace"),)
+    return args
 
 
 def hog_run(plan: Plan, lut: Lut, img, tmpl, bias, buf: "Buffers", stream=None, img_pitch=None):
     """The whole path in one C call (hog_run)."""
     _check(load_library().hog_run(*_run_args(plan, lut, img, tmpl, bias, buf, img_pitch), _stream(stream)))
+
+
+def hog_run_static(plan: Plan, lut: Lut, img, tmpl, bias, buf: "Buffers", stream=None, img_pitch=None):
+    """hog_run on the library's static scratch (no workspace; buf.workspace is
+    not used and may be None)."""
+    args = _run_args(plan, lut, img, tmpl, bias, buf, img_pitch, with_workspace=False)
+    _check(load_library().hog_run_static(*args, _stream(stream)))
 
 
 def plan_tiles(plan: Plan) -> Tiles:

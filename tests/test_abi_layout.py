@@ -59,7 +59,7 @@ CONSTANTS = {  # header name -> binding name
                       "HOG_E_NOT_READY", "HOG_NO_BIN", "HOG_NORM_RAW", "HOG_NORM_L2",
                       "HOG_ORIENT_SIGNED", "HOG_ORIENT_UNSIGNED", "HOG_VOTES_HARD", "HOG_VOTES_SOFT",
                       "HOG_SOFT_QUANTUM", "HOG_MAX_LEVEL_GROUPS", "HOG_LUT_DEVICE_FULL",
-                      "HOG_LUT_DEVICE_HALF", "HOG_LUT_DEVICE_SOFT")},
+                      "HOG_LUT_DEVICE_HALF", "HOG_LUT_DEVICE_SOFT", "HOG_STATIC_SCRATCH_BYTES")},
     "HOG_LUT_SIDE": "LUT_SIDE",
 }
 
