@@ -15,11 +15,17 @@ hog_poll) and, for comparison, through the per-image path; the value is the
 server's throughput at that offered load, with its latency percentiles.
 
 Prints one JSON line: processed Mpixel/s (pixels summed over pyramid
-levels), per-step latency percentiles, per-kernel times, the roofline of the
-dominant kernel (the integral-image writer) measured live with HIP events
-(beside this GPU's own 1 GiB copy and fill rates), the rate with the image
-copied from pinned host memory each step, the input's bin statistics, and
-the CPU oracle timed on this host over one full step.
+levels), per-step latency percentiles (at least 200 single-step samples),
+per-kernel times, the roofline of the dominant kernel (the integral-image
+writer) measured live with HIP events (beside this GPU's own 1 GiB copy and
+fill rates) and of the whole path (its algorithmic bytes per step over the
+step time), the rate with the image copied from pinned host memory each
+step, the input's bin statistics, and the CPU oracle timed on this host
+over one full step, single-threaded and split by level across the host's
+cores. Steps cycle through distinct buffer sets totalling at least
+--ring-bytes (1 GiB), so that a small workload is timed from HBM and not
+from the last-level cache; the two small workloads also report their
+batched form (one batch plan of many such images, one graph launch).
 """
 from __future__ import annotations
 
@@ -45,10 +51,10 @@ WORKLOADS = {
                               scale=1.05, norm=1, seed=1002, tseed=9002),
     # 800x600 RGB, N_b = 8, single level, L2 blocks (3360-dim), one template.
     "rgb_800x600": dict(width=800, height=600, channels=3, n_bins=8, max_levels=1, scale=1.0,
-                        norm=1, seed=1001, tseed=9001),
+                        norm=1, seed=1001, tseed=9001, batched_form=64, oracle_images=16),
     # 320x240 grey, N_b = 8, single level, raw 8x16x8 cell features.
     "gray_320x240": dict(width=320, height=240, channels=1, n_bins=8, max_levels=1, scale=1.0,
-                         norm=0, seed=1000, tseed=9000),
+                         norm=0, seed=1000, tseed=9000, batched_form=400, oracle_images=192),
     # Batched: 64 RGB images, sizes uniform in 320..1920 x 240..1080 (seeded),
     # each with a 1.1 pyramid, N_b = 8, L2 blocks (3360-dim), 32 templates; one
     # batch plan replayed as a captured HIP graph, beside the same 64 images
@@ -94,6 +100,17 @@ def measured_traffic(workload, bin_chunk):
     return int(t.group(1))
 
 
+def path_bytes_per_pixel(wl, templates):
+    """Algorithmic HBM bytes per processed pixel of one pass of the path: the
+    image (C), the bin map written and read (2), the integral images written
+    (4 N_b) and read at the cell corners (4 N_b / 64), the cell histograms
+    (4 N_b / 64) and the scores (4 K / 64), per 8 x 8 cell of every level.
+    Narrow planes scale the plane terms by their element size."""
+    eb = wl.get("plane_bits", 32) // 8
+    nb = wl["n_bins"]
+    return wl["channels"] + 2 + eb * nb * (1 + 1 / 64) + 4 * nb / 64 + 4 * templates / 64
+
+
 def batch_sizes(wl):
     import numpy as np
     rng = np.random.default_rng(wl["size_seed"])
@@ -122,46 +139,98 @@ def workload_inputs(wl):
     return plan, imgs, host, tmpl, bias
 
 
-def oracle_image(img, wl, w, h, tmpl, bias):
-    """The oracle over one image's whole pyramid; returns processed pixels."""
+def oracle_units(wl):
+    """The independent units of one step's oracle sample: (image index, level)
+    pairs -- every level of the image, or of the first images of a batch."""
+    if "batch" in wl:
+        sizes = batch_sizes(wl)[:2]
+    else:  # one image, or several distinct ones for a small workload
+        sizes = [(wl["width"], wl["height"])] * wl.get("oracle_images", 1)
     import oracle
+    units = []
+    for j, (w, h) in enumerate(sizes):
+        n = len(oracle.pyramid(w, h, wl["scale"], 64, 128, wl["max_levels"])) if wl["max_levels"] != 1 else 1
+        units += [(j, w, h, l) for l in range(n)]
+    return units
+
+
+def oracle_unit(args):
+    """The oracle over one level of one image: bins (FP64 angle), Eq. 5
+    integral images, brute-force window scores; returns processed pixels.
+    Runs in the bench process or in a worker process."""
+    import oracle
+    from paper_1703_06256_amd import inputs
+    name, j, w, h, l = args
+    wl = WORKLOADS[name]
+    img = inputs.synth_image(w, h, wl["channels"], wl["seed"] + j)
+    tmpl, bias = inputs.synth_templates(wl.get("templates", 1), oracle_dim(wl), wl["tseed"])
     p = oracle.ScanParams(norm=wl["norm"])
     nb = wl["n_bins"]
-    levels = oracle.pyramid(w, h, wl["scale"], 64, 128, wl["max_levels"]) \
-        if wl["max_levels"] != 1 else [(w, h, 1.0)]
-    px = 0
-    for l, (lw, lh, s) in enumerate(levels):
-        lvl = img if l == 0 else oracle.resize_nn(img, s, lw, lh)
-        bins = oracle.bin_map(lvl, nb)
-        oracle.integral(bins, nb)
-        nwx, nwy = oracle.window_grid(lw, lh, p)
-        if nwx:
-            oracle.score_windows(bins, nb, p, tmpl, bias)
-        px += lw * lh
-    return px, len(levels)
-
-
-def cpu_baseline(wl, tmpl, bias):
-    """The oracle (single thread) over one full step of the same workload, or
-    (batches) over the first images of the batch."""
-    from paper_1703_06256_amd import inputs
-    t0 = time.perf_counter()
-    if "batch" in wl:
-        px = n_lv = 0
-        n_img = 2
-        for j, (w, h) in enumerate(batch_sizes(wl)[:n_img]):
-            img = inputs.synth_image(w, h, wl["channels"], wl["seed"] + j)
-            a, b = oracle_image(img, wl, w, h, tmpl, bias)
-            px += a
-            n_lv += b
-        what = f"the first {n_img} images of the batch ({n_lv} levels, {px} processed pixels"
+    if l == 0:
+        lw, lh, lvl = w, h, img
     else:
-        img = inputs.synth_image(wl["width"], wl["height"], wl["channels"], wl["seed"])
-        px, n_lv = oracle_image(img, wl, wl["width"], wl["height"], tmpl, bias)
-        what = f"one full step ({n_lv} levels, {px} processed pixels"
-    dt = time.perf_counter() - t0
-    return dict(value=px / dt / 1e6, unit="Mpixel/s", cores=1, kind="oracle",
-                sample=f"{what}: FP64 bins, Eq.5 integrals, brute-force window scores) in {dt:.2f} s")
+        lw, lh, s = oracle.pyramid(w, h, wl["scale"], 64, 128, wl["max_levels"])[l]
+        lvl = oracle.resize_nn(img, s, lw, lh)
+    bins = oracle.bin_map(lvl, nb)
+    oracle.integral(bins, nb)
+    nwx, _ = oracle.window_grid(lw, lh, p)
+    if nwx:
+        oracle.score_windows(bins, nb, p, tmpl, bias)
+    return lw * lh
+
+
+def oracle_dim(wl):
+    import oracle
+    return oracle.ScanParams(norm=wl["norm"]).dim(wl["n_bins"])
+
+
+def host_cpu():
+    """(threads this process may run on, capped at the machine's CPU share, and the
+    CPU model)."""
+    n = len(os.sched_getaffinity(0))
+    cap = os.environ.get("OMP_NUM_THREADS")
+    if cap and cap.isdigit():
+        n = min(n, int(cap))
+    model = "unknown"
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                model = ln.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return n, model
+
+
+def cpu_baseline(name):
+    """The oracle over one full step of the workload (batches: its first two
+    images), timed single-threaded, then split by level across worker
+    processes on the host cores. Run before the GPU is touched."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    wl = WORKLOADS[name]
+    units = [(name,) + u for u in oracle_units(wl)]
+    t0 = time.perf_counter()
+    px = sum(oracle_unit(u) for u in units)
+    dt1 = time.perf_counter() - t0
+    n, model = host_cpu()
+    workers = max(1, min(n, len(units)))
+    # Largest levels first so that the pool ends together.
+    order = sorted(units, key=lambda u: -(u[2] * u[3]) / wl["scale"] ** (2 * u[4]))
+    with cf.ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn")) as ex:
+        list(ex.map(oracle_unit, [units[-1]] * workers))  # start the workers
+        t0 = time.perf_counter()
+        px_all = sum(ex.map(oracle_unit, order))
+        dtn = time.perf_counter() - t0
+    n_img = len({u[1] for u in units})
+    what = (f"the first 2 images of the batch ({len(units)} levels, {px} processed pixels)" if "batch" in wl else
+            f"one full step ({len(units)} levels, {px} processed pixels)" if n_img == 1 else
+            f"{n_img} distinct images of the workload ({px} processed pixels)")
+    return dict(value=round(px_all / dtn / 1e6, 3), unit="Mpixel/s", cores=workers, kind="oracle",
+                sample=f"{what}: FP64 bins, Eq. 5 integrals, brute-force window scores; levels split "
+                       f"across {workers} worker processes, {dtn:.2f} s",
+                single_thread=dict(value=round(px / dt1 / 1e6, 3), cores=1, seconds=round(dt1, 2)),
+                host=dict(cpu_model=model, threads_available=len(os.sched_getaffinity(0))))
 
 
 def main():
@@ -172,7 +241,10 @@ def main():
     ap.add_argument("--workload", default="pyramid_1920x1080", choices=sorted(WORKLOADS) + ["serve"])
     ap.add_argument("--rate", type=float, default=2000.0,
                     help="serve: offered load in requests per second (Poisson)")
-    ap.add_argument("--requests", type=int, default=400, help="serve: requests in the stream")
+    ap.add_argument("--requests", type=int, default=4000, help="serve: requests in the stream")
+    ap.add_argument("--ring-bytes", type=float, default=float(1 << 30),
+                    help="distinct buffer sets cycled through by the timed steps, at least this many "
+                         "bytes in all (so that small workloads are timed from HBM, not the last-level cache)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 1 GiB device-to-device copy (for counter calibration)")
@@ -184,6 +256,13 @@ def main():
         sys.exit(2)
 
     import numpy as np
+
+    # The oracle on the host cores, before anything touches the GPU (its
+    # worker processes are started from a process that has not used HIP).
+    cpu = None
+    if not args.no_cpu_baseline and args.workload != "serve":
+        cpu = cpu_baseline(args.workload)
+
     import torch
     from paper_1703_06256_amd import hog, inputs
 
@@ -221,14 +300,29 @@ def main():
 
     # Tile shapes picked by timing candidates on these buffers.
     tiles = hog.autotune(plan, lut, img_t, tmpl_t, bias_t, buf, stream, reps=3)
+
+    # A ring of distinct buffer sets (input, bins, planes, scores, workspace)
+    # of at least --ring-bytes in all: consecutive steps never find their
+    # data in the last-level cache, whatever the workload's size.
+    set_bytes = (img_t.numel() + sz.bins_bytes + sz.ii_elems * sz.ii_elem_bytes + 4 * sz.score_elems
+                 + sz.workspace_bytes)
+    n_sets = max(1, min(1024, -(-int(args.ring_bytes) // set_bytes)))
+    sets = [(img_t, buf)]
+    for _ in range(n_sets - 1):
+        sets.append((img_t.clone(), hog.Buffers(plan)))
+    ring = [0]
     if batch:
-        graph = hog.Graph(plan, lut, img_t, tmpl_t, bias_t, buf)
+        graphs = [hog.Graph(plan, lut, im, tmpl_t, bias_t, b) for im, b in sets]
+        graph = graphs[0]
 
         def step():
-            graph.launch(stream)
+            graphs[ring[0] % n_sets].launch(stream)
+            ring[0] += 1
     else:
         def step():
-            hog.hog_run(plan, lut, img_t, tmpl_t, bias_t, buf, stream)
+            im, b = sets[ring[0] % n_sets]
+            hog.hog_run(plan, lut, im, tmpl_t, bias_t, b, stream)
+            ring[0] += 1
 
     for _ in range(args.warmup):
         step()
@@ -250,7 +344,7 @@ def main():
 
     # Per-step latency (each step alone between two events).
     lat = []
-    n_lat = min(args.steps, 200)
+    n_lat = max(200, min(args.steps, 2000))
     for _ in range(n_lat):
         a = torch.cuda.Event(enable_timing=True)
         b = torch.cuda.Event(enable_timing=True)
@@ -267,9 +361,10 @@ def main():
     # kernel is timed alone at the plan's full size.
     hog.hog_timing_enable(True)
     hog.hog_timing_reset()
-    n_k = min(args.steps, 50)
-    for _ in range(n_k):
-        hog.run_path(plan, lut, img_t, tmpl_t, bias_t, buf, stream)  # eager: a graph records no events
+    n_k = max(min(args.steps, 200), min(50, 4 * n_sets))
+    for i in range(n_k):
+        im, b = sets[i % n_sets]
+        hog.run_path(plan, lut, im, tmpl_t, bias_t, b, stream)  # eager: a graph records no events
     torch.cuda.synchronize()
     kern_us = {}
     for k in KERNELS:
@@ -397,6 +492,46 @@ def main():
             extra[name] = dict(ms=round(t, 4), mpixel_per_s=round(sz.total_pixels / (t * 1e3), 1))
         extra["speedup_vs_per_image"] = round(extra["per_image"]["ms"] / ms_per_step, 3)
         del singles
+    if "batched_form" in wl:
+        # The same image size as one batch plan of many distinct images,
+        # replayed as one captured graph: the batched form beside the
+        # per-image launches above.
+        nb_img = wl["batched_form"]
+        kw = dict(channels=wl["channels"], n_bins=wl["n_bins"], max_levels=wl["max_levels"],
+                  scale=wl["scale"], norm=wl["norm"], n_templates=K)
+        bplan = hog.Plan([hog.make_desc(wl["width"], wl["height"], **kw)] * nb_img, batch=True)
+        bimgs = [inputs.synth_image(wl["width"], wl["height"], wl["channels"], wl["seed"] + 10000 + j)
+                 for j in range(nb_img)]
+        bimg_t = torch.from_numpy(hog.pack_images(bplan, bimgs)).cuda()
+        bbuf = hog.Buffers(bplan)
+        btiles = hog.autotune(bplan, lut, bimg_t, tmpl_t, bias_t, bbuf, stream, reps=3)
+        bgraph = hog.Graph(bplan, lut, bimg_t, tmpl_t, bias_t, bbuf)
+        for _ in range(5):
+            bgraph.launch(stream)
+        torch.cuda.synchronize()
+        blat = []
+        for _ in range(200):
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            bgraph.launch(stream)
+            b.record(stream)
+            b.synchronize()
+            blat.append(a.elapsed_time(b))
+        bms = float(np.mean(blat))
+        bpx = bplan.sizes.total_pixels
+        bbytes = path_bytes_per_pixel(wl, K) * bpx
+        extra["batched_form"] = dict(
+            images=nb_img, launch="one captured HIP graph of a batch plan", ms_per_batch=round(bms, 4),
+            mpixel_per_s=round(bpx / (bms * 1e3), 1),
+            speedup_vs_per_image=round(bpx / (bms * 1e3) / value, 3),
+            p50_ms=round(float(np.percentile(blat, 50)), 4), p99_ms=round(float(np.percentile(blat, 99)), 4),
+            path_frac=round(bbytes / (bms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            tiles={"bin_chunk": btiles.bin_chunk, "score_rows": btiles.score_rows,
+                   "level_groups": btiles.level_groups})
+        bgraph.destroy()
+        del bbuf, bimg_t
+
     # This GPU's plain 1 GiB copy (read + write) and fill (write only) rates,
     # timed the same way on the same stream: what a bandwidth-bound kernel
     # reaches in practice, beside the 8 TB/s peak.
@@ -431,6 +566,11 @@ def main():
     if traffic is not None:
         roofline["measured_frac"] = round(roofline["measured"] / HBM_PEAK_GBS, 4)
         roofline["measured_frac_of_copy"] = round(roofline["measured"] / copy_gbs, 4)
+    # The whole path: its algorithmic bytes per step over the step time.
+    path_bytes = path_bytes_per_pixel(wl, K) * sz.total_pixels
+    roofline["path_bytes_per_step"] = int(path_bytes)
+    roofline["path_GBps"] = round(path_bytes / (ms_per_step * 1e-3) / 1e9, 1)
+    roofline["path_frac"] = round(path_bytes / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
 
     if args.copy_calibration:
         # A plain copy of known size: its FETCH_SIZE / WRITE_SIZE counters give
@@ -441,10 +581,6 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-
-    cpu = None
-    if not args.no_cpu_baseline:
-        cpu = cpu_baseline(wl, tmpl, bias)
 
     out = {
         "metric": METRIC,
@@ -475,6 +611,7 @@ def main():
             "plane_bits": 8 * sz.ii_elem_bytes,
             "votes": "soft (1/32)" if soft else "hard",
             "launch": "captured HIP graph of the batch plan" if batch else "hog_run per step",
+            "buffer_sets": n_sets,
             "tiles": {"bin_chunk": tiles.bin_chunk, "score_rows": tiles.score_rows,
                       "level_groups": tiles.level_groups, "how": "autotuned"},
         },

@@ -52,3 +52,27 @@ def test_traffic_lookup_matches_the_committed_summary():
         assert t is not None and algorithmic <= t < 1.2 * algorithmic, (c, t)
     assert bench.measured_traffic("pyramid_1920x1080", 1) is None  # not a candidate the autotuner runs
     assert bench.measured_traffic("no_such_workload", 6) is None
+
+
+def test_path_bytes_per_pixel_follow_the_cost_model():
+    """C + 2 + 4 N_b (1 + 1/64) + 4 N_b / 64 + 4 K / 64 bytes per processed pixel."""
+    assert abs(bench.path_bytes_per_pixel(bench.WORKLOADS["pyramid_1920x1080"], 1) - 79.3125) < 1e-9
+    assert abs(bench.path_bytes_per_pixel(bench.WORKLOADS["gray_320x240"], 1) - 36.0625) < 1e-9
+    assert abs(bench.path_bytes_per_pixel(bench.WORKLOADS["rgb_800x600"], 1) - 38.0625) < 1e-9
+    u16 = bench.path_bytes_per_pixel(bench.WORKLOADS["pyramid_1920x1080_u16"], 1)
+    assert abs(u16 - (5 + 2 * 18 * (1 + 1 / 64) + 72 / 64 + 4 / 64)) < 1e-9
+
+
+def test_oracle_units_cover_every_level():
+    units = bench.oracle_units(bench.WORKLOADS["pyramid_1920x1080"])
+    assert len(units) == 44 and [u[3] for u in units] == list(range(44))
+    small = bench.oracle_units(bench.WORKLOADS["gray_320x240"])
+    assert small == [(j, 320, 240, 0) for j in range(192)]  # distinct seeded images
+    assert len({u[0] for u in bench.oracle_units(bench.WORKLOADS["batch64"])}) == 2
+
+
+def test_cpu_baseline_reports_both_modes_and_the_host():
+    r = bench.cpu_baseline("gray_320x240")
+    assert r["kind"] == "oracle" and r["unit"] == "Mpixel/s" and r["value"] > 0
+    assert r["cores"] >= 1 and r["single_thread"]["cores"] == 1 and r["single_thread"]["value"] > 0
+    assert r["host"]["cpu_model"] and r["host"]["threads_available"] >= 1
