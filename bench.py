@@ -246,6 +246,9 @@ def main():
                     help="distinct buffer sets cycled through by the timed steps, at least this many "
                          "bytes in all (so that small workloads are timed from HBM, not the last-level cache)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--lut", choices=("auto", "lds", "l2"), default="auto",
+                    help="where the bin map reads the lookup table: as the autotuner picks, the LDS "
+                         "half table, or the full table through L2")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 1 GiB device-to-device copy (for counter calibration)")
     args = ap.parse_args()
@@ -300,6 +303,10 @@ def main():
 
     # Tile shapes picked by timing candidates on these buffers.
     tiles = hog.autotune(plan, lut, img_t, tmpl_t, bias_t, buf, stream, reps=3)
+    if args.lut != "auto":
+        hog.set_plan_tiles(plan, tiles.bin_chunk, tiles.score_rows, tiles.level_groups,
+                           lut_global=1 if args.lut == "l2" else 0)
+        tiles = hog.plan_tiles(plan)
 
     # A ring of distinct buffer sets (input, bins, planes, scores, workspace)
     # of at least --ring-bytes in all: consecutive steps never find their
@@ -613,7 +620,9 @@ def main():
             "launch": "captured HIP graph of the batch plan" if batch else "hog_run per step",
             "buffer_sets": n_sets,
             "tiles": {"bin_chunk": tiles.bin_chunk, "score_rows": tiles.score_rows,
-                      "level_groups": tiles.level_groups, "how": "autotuned"},
+                      "level_groups": tiles.level_groups,
+                      "lut": "full table through L2" if tiles.lut_global else "half table in LDS",
+                      "how": "autotuned" if args.lut == "auto" else f"autotuned, table forced to {args.lut}"},
         },
         "base_mpixel_per_s": round(sum(d.width * d.height for d in plan.descs) / (ms_per_step * 1e3), 2) if batch
         else round(wl["width"] * wl["height"] / (ms_per_step * 1e3), 2),

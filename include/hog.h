@@ -315,6 +315,10 @@ typedef struct {
                              launch per kernel for all levels; at most HOG_MAX_LEVEL_GROUPS.
                              get_tiles reports the number of ranges in use. Results are the
                              same for every value. */
+    int32_t lut_global;   /* where hog_bin_map reads the Sec. 2 table (hard votes): 0, the
+                             dy >= 0 half staged in each workgroup's LDS; 1, the full
+                             511 x 511 table read through the L1/L2 caches. Results are the
+                             same for both. */
 } hog_tiles;
 
 hog_status hog_plan_get_tiles(const hog_plan *plan, hog_tiles *out);
@@ -325,7 +329,8 @@ hog_status hog_plan_set_tiles(hog_plan *plan, const hog_tiles *tiles);
 
 /* Autotuner: times the whole path (hog_run, reps runs per candidate) on the
  * caller's buffers for each candidate tile shape -- bins per integral wave,
- * then window rows per strip, then 1..HOG_MAX_LEVEL_GROUPS level groups --
+ * then window rows per strip, then the table in LDS or through L2, then
+ * 1..HOG_MAX_LEVEL_GROUPS level groups --
  * and installs the fastest; *chosen (nullable) receives it. Synchronises the stream; the buffers' contents after the call
  * are those of a hog_run. */
 hog_status hog_plan_autotune(hog_plan *plan, const hog_lut *lut, const uint8_t *img,

@@ -750,6 +750,7 @@ static hog_status create_plan(const hog_plan_desc *descs, int n_img, bool batch,
     pd.cell_stride = nbp;
     pd.plane_bytes = pb;
     pd.bin_chunk = chunk_final;  // bins per wave; a last, smaller chunk takes the rest
+    pd.lut_global = 0;           // the LDS half table until tiles say otherwise
     pd.n_chunks = (nb + chunk_final - 1) / chunk_final;
     for (int k = 0; k < hogk::KB_COUNT; ++k) pd.total[k] = totals[k];
     {
@@ -876,7 +877,7 @@ extern "C" hog_status hog_bin_map(const hog_plan *plan, const hog_lut *lut, cons
     hipError_t e = timed_launch("bin_map", s, [&] {
         return plan->dev.votes == HOG_VOTES_SOFT
                    ? hogk::launch_bin_map_soft(plan->dev, lut->dev_soft, img, img_pitch, bins, s)
-                   : hogk::launch_bin_map(plan->dev, lut->dev_half, img, img_pitch, bins, s);
+                   : hogk::launch_bin_map(plan->dev, lut->dev_half, lut->dev, img, img_pitch, bins, s);
     });
     if (e != hipSuccess) return device_fail(e, "bin_map launch");
     return HOG_OK;
@@ -1016,9 +1017,10 @@ static hog_status build_groups(hog_plan *p, int G)
 // Installs bins per integral wave, (strip scorer) window rows per strip and
 // the level groups, updating the level table and the prefix tables on the
 // device.
-static hog_status apply_tiles(hog_plan *p, int chunk, int rows, int groups)
+static hog_status apply_tiles(hog_plan *p, int chunk, int rows, int groups, int lut_global)
 {
     if (groups == 0) groups = 1;
+    if (lut_global != 0 && lut_global != 1) return fail(HOG_E_INVALID, "lut_global must be 0 or 1");
     if (groups < 1 || groups > HOG_MAX_LEVEL_GROUPS)
         return fail(HOG_E_INVALID, "level_groups must be in [0, %d]", HOG_MAX_LEVEL_GROUPS);
     PlanDev &pd = p->dev;
@@ -1029,6 +1031,7 @@ static hog_status apply_tiles(hog_plan *p, int chunk, int rows, int groups)
         return fail(HOG_E_INVALID, "bins per integral wave must be in [1, %d] and fit 2 GiB", hogk::kMaxBinChunk);
     pd.bin_chunk = chunk;
     pd.n_chunks = (pd.n_bins + chunk - 1) / chunk;
+    pd.lut_global = lut_global;
     if (pd.scorer == 1 && rows != pd.st_th) {
         if (rows < 1 || rows > 64) return fail(HOG_E_INVALID, "window rows per strip must be in [1, 64]");
         pd.st_th = rows;
@@ -1061,6 +1064,7 @@ extern "C" hog_status hog_plan_get_tiles(const hog_plan *plan, hog_tiles *out)
     out->bin_chunk = plan->dev.bin_chunk;
     out->score_rows = plan->dev.scorer == 1 ? plan->dev.st_th : 0;
     out->level_groups = level_groups_of(plan);
+    out->lut_global = plan->dev.lut_global;
     return HOG_OK;
 }
 
@@ -1068,7 +1072,7 @@ extern "C" hog_status hog_plan_set_tiles(hog_plan *plan, const hog_tiles *tiles)
 {
     if (!plan || !tiles) return fail(HOG_E_INVALID, "plan or tiles is NULL");
     return apply_tiles(plan, tiles->bin_chunk, plan->dev.scorer == 1 ? tiles->score_rows : plan->dev.st_th,
-                       tiles->level_groups);
+                       tiles->level_groups, tiles->lut_global);
 }
 
 static hog_status check_run_args(const hog_plan *plan, const hog_lut *lut, const uint8_t *img,
@@ -1095,8 +1099,9 @@ extern "C" hog_status hog_plan_autotune(hog_plan *plan, const hog_lut *lut, cons
         return device_fail(e, "hipEventCreate");
     }
     // Mean time of reps whole runs (after one untimed run) with these tiles.
+    int best_lut = plan->dev.lut_global;
     auto time_with = [&](int chunk, int rows, int groups, float *ms) -> hog_status {
-        hog_status r = apply_tiles(plan, chunk, rows, groups);
+        hog_status r = apply_tiles(plan, chunk, rows, groups, best_lut);
         if (r != HOG_OK) return r;
         r = run_plan(plan, lut, img, img_pitch, bins, ii, tmpl, bias, scores, workspace, stream);
         if (r != HOG_OK) return r;
@@ -1138,6 +1143,16 @@ extern "C" hog_status hog_plan_autotune(hog_plan *plan, const hog_lut *lut, cons
             }
         }
     }
+    if (st == HOG_OK && plan->dev.votes == HOG_VOTES_HARD) {
+        const int cur = best_lut;
+        best_lut = 1 - cur;
+        float ms = 0.f;
+        st = time_with(best_chunk, best_rows, 1, &ms);
+        if (st == HOG_OK && ms < best)
+            best = ms;
+        else
+            best_lut = cur;
+    }
     for (int g = 2; g <= HOG_MAX_LEVEL_GROUPS && st == HOG_OK && g <= plan->dev.n_levels; ++g) {
         float ms = 0.f;
         st = time_with(best_chunk, best_rows, g, &ms);
@@ -1149,7 +1164,7 @@ extern "C" hog_status hog_plan_autotune(hog_plan *plan, const hog_lut *lut, cons
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (st != HOG_OK) return st;
-    st = apply_tiles(plan, best_chunk, best_rows, best_groups);
+    st = apply_tiles(plan, best_chunk, best_rows, best_groups, best_lut);
     if (st == HOG_OK && chosen) st = hog_plan_get_tiles(plan, chosen);
     return st;
 }
@@ -1219,7 +1234,7 @@ static hog_status run_groups(const hog_plan *plan, const GroupStreams &gs, const
         what = "bin_map launch";
         e = timed_launch("bin_map", sg, [&] {
             return soft ? hogk::launch_bin_map_soft(v, lut->dev_soft, img, img_pitch, bins, sg)
-                        : hogk::launch_bin_map(v, lut->dev_half, img, img_pitch, bins, sg);
+                        : hogk::launch_bin_map(v, lut->dev_half, lut->dev, img, img_pitch, bins, sg);
         });
         if (e != hipSuccess) break;
         if (soft) {

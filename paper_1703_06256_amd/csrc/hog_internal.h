@@ -113,6 +113,7 @@ struct PlanDev {
     int32_t cell_stride;       // floats per staged cell in the scorer's LDS
     int32_t plane_bytes;       // bytes per integral-image element: 4, 2 or 1 (ii mod 2^(8 bytes))
     int32_t bin_chunk;         // bins per integral wave
+    int32_t lut_global;        // bin map: 0 the LDS half table, 1 the full table through L2
     int32_t n_chunks;
     int32_t n_cu;              // compute units of the device (persistent grids)
     int64_t tprep_off;         // workspace bytes: prepared template fragments (matrix-core scorer)
@@ -125,8 +126,8 @@ void set_last_error(const char *msg);
 
 // Launchers (hog_kernels.hip). Each enqueues one kernel on `stream` and
 // returns the launch status.
-hipError_t launch_bin_map(const PlanDev &p, const uint8_t *lut_half, const uint8_t *img,
-                          int64_t img_pitch, uint8_t *bins, hipStream_t stream);
+hipError_t launch_bin_map(const PlanDev &p, const uint8_t *lut_half, const uint8_t *lut_full,
+                          const uint8_t *img, int64_t img_pitch, uint8_t *bins, hipStream_t stream);
 hipError_t launch_int_reduce(const PlanDev &p, const uint8_t *bins, uint8_t *ws,
                              hipStream_t stream);
 // Soft votes: bin map from the uint16 soft table, and the weighted integral

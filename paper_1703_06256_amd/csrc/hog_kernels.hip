@@ -113,7 +113,12 @@ __device__ __forceinline__ uint32_t from_right_lane(uint32_t v)
 // Soft votes (SOFT): the same walk; the lookup is the uint16 soft-table
 // entry b0 | w1 << 8 (522 KB, read through L2; no LDS table), stored as two
 // bytes per pixel.
-template <int C, bool SOFT>
+//
+// GLUT: the hard-vote lookup reads the full 511 x 511 table (261 KB) through
+// the L1/L2 caches instead of the LDS half table (no staging and no LDS, so
+// smaller workgroups, several per CU); the plan picks one
+// (hog_tiles.lut_global).
+template <int C, bool SOFT, bool GLUT = false>
 __global__ __launch_bounds__(1024) void k_bin_map(const Level *__restrict__ lv,
                                                   const int32_t *__restrict__ first, int n_levels,
                                                   const int32_t *__restrict__ mapx,
@@ -125,7 +130,9 @@ __global__ __launch_bounds__(1024) void k_bin_map(const Level *__restrict__ lv,
                                                   uint8_t *__restrict__ bins)
 {
     const uint8_t *lut = nullptr;
-    if constexpr (!SOFT) {
+    if constexpr (GLUT) {
+        lut = lut_half;  // the full table here
+    } else if constexpr (!SOFT) {
         __shared__ __attribute__((aligned(16))) uint8_t lut_lds[kLutHalfBytes];
         typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
         const u32x4 *src = reinterpret_cast<const u32x4 *>(lut_half);
@@ -217,6 +224,9 @@ __global__ __launch_bounds__(1024) void k_bin_map(const Level *__restrict__ lv,
             if constexpr (SOFT) {
                 const uint16_t e = soft[ok ? (bdy + 255) * 511 + (bdx + 255) : 0];
                 b[i] = ok ? e : (uint16_t)kNoBin;
+            } else if constexpr (GLUT) {
+                const uint8_t e = lut[ok ? (bdy + 255) * 511 + (bdx + 255) : 0];
+                b[i] = ok ? e : (uint8_t)kNoBin;
             } else {
                 const int ady = bdy < 0 ? -bdy : bdy;
                 const uint32_t e = lut[ok ? ady * 511 + (bdx + 255) : 0];
@@ -2165,12 +2175,24 @@ inline const int32_t *first_of(const PlanDev &p, int k)
 
 }  // namespace
 
-hipError_t launch_bin_map(const PlanDev &p, const uint8_t *lut_half, const uint8_t *img,
-                          int64_t img_pitch, uint8_t *bins, hipStream_t stream)
+hipError_t launch_bin_map(const PlanDev &p, const uint8_t *lut_half, const uint8_t *lut_full,
+                          const uint8_t *img, int64_t img_pitch, uint8_t *bins, hipStream_t stream)
 {
     const int64_t items = p.total[KB_BINMAP];
     if (items == 0) return hipSuccess;
     const int64_t per_block = 16;  // waves of a 1024-thread workgroup
+    if (p.lut_global) {  // no LDS table: 4-wave workgroups, up to 7 per CU (the registers allow 7 waves per SIMD)
+        const unsigned grid = (unsigned)std::min<int64_t>((items + 3) / 4, 7 * (int64_t)p.n_cu);
+        if (p.channels == 1)
+            hipLaunchKernelGGL((k_bin_map<1, false, true>), dim3(grid), dim3(256), 0, stream, p.levels,
+                               first_of(p, KB_BINMAP), p.n_levels, p.mapx, p.mapy, img, img_pitch,
+                               p.n_bins, lut_full, nullptr, bins);
+        else
+            hipLaunchKernelGGL((k_bin_map<3, false, true>), dim3(grid), dim3(256), 0, stream, p.levels,
+                               first_of(p, KB_BINMAP), p.n_levels, p.mapx, p.mapy, img, img_pitch,
+                               p.n_bins, lut_full, nullptr, bins);
+        return hipGetLastError();
+    }
     const unsigned grid = (unsigned)std::min<int64_t>((items + per_block - 1) / per_block, p.n_cu);
     if (p.channels == 1)
         hipLaunchKernelGGL((k_bin_map<1, false>), dim3(grid), dim3(1024), 0, stream, p.levels,

@@ -80,7 +80,7 @@ class ImageInfo(ctypes.Structure):
 
 class Tiles(ctypes.Structure):
     _fields_ = [("bin_chunk", ctypes.c_int32), ("score_rows", ctypes.c_int32),
-                ("level_groups", ctypes.c_int32)]
+                ("level_groups", ctypes.c_int32), ("lut_global", ctypes.c_int32)]
 
 
 class ServerConfig(ctypes.Structure):
@@ -459,8 +459,9 @@ def plan_tiles(plan: Plan) -> Tiles:
     return t
 
 
-def set_plan_tiles(plan: Plan, bin_chunk: int, score_rows: int = 0, level_groups: int = 1):
-    t = Tiles(bin_chunk, score_rows, level_groups)
+def set_plan_tiles(plan: Plan, bin_chunk: int, score_rows: int = 0, level_groups: int = 1,
+                   lut_global: int = 0):
+    t = Tiles(bin_chunk, score_rows, level_groups, lut_global)
     _check(load_library().hog_plan_set_tiles(plan.handle, ctypes.byref(t)))
 
 

@@ -98,11 +98,15 @@ def test_device_tables_equal_oracle(nb, orientation):
     lut.free()
 
 
-def _bin_map_gpu(img, nb, orientation, votes):
+def _bin_map_gpu(img, nb, orientation, votes, lut_global=0):
     import torch
     c = img.shape[2]
     desc = hog.make_desc(SIDE, SIDE, channels=c, n_bins=nb, votes=votes)
     plan = hog.Plan(desc)
+    if lut_global:
+        t = hog.plan_tiles(plan)
+        hog.set_plan_tiles(plan, t.bin_chunk, t.score_rows, 1, lut_global=1)
+        assert hog.plan_tiles(plan).lut_global == 1
     lut = hog.hog_lut_build(nb, orientation)
     img_t = torch.from_numpy(np.ascontiguousarray(img).reshape(-1)).cuda()
     bins = torch.empty(plan.sizes.bins_bytes, dtype=torch.uint8, device="cuda")
@@ -115,13 +119,16 @@ def _bin_map_gpu(img, nb, orientation, votes):
 
 
 @pytest.mark.gpu
+@pytest.mark.parametrize("lut_global", [0, 1])
 @pytest.mark.parametrize("channels", [1, 3])
 @pytest.mark.parametrize("orientation", ORIENT)
 @pytest.mark.parametrize("nb", BINS)
-def test_bin_map_every_gradient_pair(nb, orientation, channels):
+def test_bin_map_every_gradient_pair(nb, orientation, channels, lut_global):
+    """Both table placements: the LDS half table with its mirror flags, and
+    the full table read through L2 (hog_tiles.lut_global)."""
     unsigned = orientation == hog.HOG_ORIENT_UNSIGNED
     img = pair_image(channels, 500 + nb + 7 * channels + orientation)
-    got = _bin_map_gpu(img, nb, orientation, hog.HOG_VOTES_HARD)
+    got = _bin_map_gpu(img, nb, orientation, hog.HOG_VOTES_HARD, lut_global)
     want = oracle.bin_map(img, nb, unsigned)
     assert np.array_equal(got, want)
     # Every table entry was looked up at some lattice pixel.
