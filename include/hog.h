@@ -419,7 +419,9 @@ typedef struct hog_server hog_server;
  * the same image size behind it, while slots and arena memory allow -- a
  * request's footprint is that of its plan's buffers (bins, N_b uint32
  * integral images per level, workspace, scores, image) -- and runs it as one
- * batch plan (hog_plan_create_batch, cached per size and count) on one of
+ * batch plan (hog_plan_create_batch, cached per size and count: at most
+ * 4 max_batch + 16 plans, the least recently used idle ones dropped beyond
+ * that; a batch that cannot be planned is retried with fewer requests) on one of
  * `streams` non-blocking streams: copy in from the pinned host arena
  * (host_budget bytes), hog_run, each request's scores out into its own
  * region of a pinned output arena (room for 2 * max_slots results of the

@@ -138,8 +138,17 @@ struct Slot {
     hipEvent_t done = nullptr;
     bool busy = false;
     std::vector<ReqPtr> reqs;
-    hog_plan *plan = nullptr;
+    hog_plan *plan = nullptr;  // pinned in the plan cache while the batch runs
+    std::vector<std::pair<int, int>> plan_key;
     int64_t off = 0, bytes = 0;
+};
+
+// A cached batch plan: pinned (pins > 0) while a caller or a running batch
+// uses it; unpinned plans are evicted least recently used first.
+struct CachedPlan {
+    hog_plan *plan = nullptr;
+    uint64_t last_use = 0;
+    int pins = 0;
 };
 
 }  // namespace
@@ -157,7 +166,9 @@ struct hog_server {
     Arena out_arena;
     hogk::CopyPool copies;
     std::vector<Slot> slots;
-    std::map<std::vector<std::pair<int, int>>, hog_plan *> plans;  // by batch composition
+    std::map<std::vector<std::pair<int, int>>, CachedPlan> plans;  // by batch composition
+    size_t plan_cap = 0;     // cached plans kept: 4 max_batch + 16
+    uint64_t plan_clock = 0;
     std::mutex mu;                                                 // guards the fields below
     std::condition_variable cv;       // wakes the worker
     std::condition_variable done_cv;  // wakes hog_wait_any
@@ -191,14 +202,21 @@ hog_plan_desc desc_for(const hog_server_config &c, int w, int h)
     return d;
 }
 
-// Cached batch plan for the given sizes (in order); nullptr on failure. A
-// new plan's tables go to the server's device; the calling thread's current
-// device is left as it was.
+// The cached batch plan for the given sizes (in order), pinned for the caller
+// (release it with plan_release); nullptr on failure. A new plan's tables go
+// to the server's device; the calling thread's current device is left as it
+// was. Beyond plan_cap cached plans, unpinned ones are destroyed least
+// recently used first, so that a stream of ever new image sizes does not
+// hold plan tables without bound.
 hog_plan *plan_for(hog_server *s, const std::vector<std::pair<int, int>> &key)
 {
     std::lock_guard<std::mutex> lk(s->plan_mu);
     auto it = s->plans.find(key);
-    if (it != s->plans.end()) return it->second;
+    if (it != s->plans.end()) {
+        it->second.last_use = ++s->plan_clock;
+        ++it->second.pins;
+        return it->second.plan;
+    }
     std::vector<hog_plan_desc> descs;
     for (auto &wh : key) descs.push_back(desc_for(s->cfg, wh.first, wh.second));
     int prev = -1;
@@ -208,8 +226,27 @@ hog_plan *plan_for(hog_server *s, const std::vector<std::pair<int, int>> &key)
     const hog_status st = hog_plan_create_batch(descs.data(), (int)descs.size(), &p);
     if (switched) (void)hipSetDevice(prev);
     if (st != HOG_OK) return nullptr;
-    s->plans[key] = p;
+    CachedPlan &cp = s->plans[key];
+    cp.plan = p;
+    cp.last_use = ++s->plan_clock;
+    cp.pins = 1;
+    while (s->plans.size() > s->plan_cap) {
+        auto victim = s->plans.end();
+        for (auto jt = s->plans.begin(); jt != s->plans.end(); ++jt)
+            if (jt->second.pins == 0 && (victim == s->plans.end() || jt->second.last_use < victim->second.last_use))
+                victim = jt;
+        if (victim == s->plans.end()) break;  // every cached plan is in use
+        hog_plan_destroy(victim->second.plan);
+        s->plans.erase(victim);
+    }
     return p;
+}
+
+void plan_release(hog_server *s, const std::vector<std::pair<int, int>> &key)
+{
+    std::lock_guard<std::mutex> lk(s->plan_mu);
+    auto it = s->plans.find(key);
+    if (it != s->plans.end() && it->second.pins > 0) --it->second.pins;
 }
 
 int64_t batch_bytes(hog_plan *p, int64_t img_bytes)
@@ -244,6 +281,8 @@ void finish(hog_server *s, Slot &sl, hipError_t err)
     sl.reqs.clear();
     sl.busy = false;
     ++s->events;
+    if (sl.plan) plan_release(s, sl.plan_key);
+    sl.plan = nullptr;
 }
 
 // Launches one batch into a free slot if requests and memory allow: the
@@ -271,7 +310,11 @@ bool admit(hog_server *s, Slot &sl)
             img_bytes += r->img_bytes;
         }
         hog_plan *p = plan_for(s, key);
-        if (!p) {  // cannot plan this batch: fail its oldest request
+        if (!p && take.size() > 1) {  // cannot plan this batch (e.g. out of memory): try a smaller one
+            take.pop_back();
+            continue;
+        }
+        if (!p) {  // cannot plan even this request alone: fail it
             std::lock_guard<std::mutex> lk(s->mu);
             ReqPtr r = take.front();
             r->status = HOG_E_INVALID;
@@ -319,6 +362,7 @@ bool admit(hog_server *s, Slot &sl)
             }
         }
         if (!ok) {
+            plan_release(s, key);
             take.pop_back();
             continue;
         }
@@ -344,6 +388,7 @@ bool admit(hog_server *s, Slot &sl)
         if (e == hipSuccess && st == HOG_OK) e = hipEventRecord(sl.done, sl.stream);
         sl.reqs = order;
         sl.plan = p;
+        sl.plan_key = key;
         sl.off = off;
         sl.bytes = bytes;
         sl.busy = true;
@@ -435,6 +480,7 @@ extern "C" hog_status hog_server_create(const hog_server_config *cfg, const floa
     hog_server *s = new (std::nothrow) hog_server;
     if (!s) return srv_fail(HOG_E_NOMEM, "host allocation failed");
     s->cfg = c;
+    s->plan_cap = 4 * (size_t)c.max_batch + 16;
     hipError_t e = hipGetDevice(&s->device);
     auto cleanup = [&](hog_status st, const char *what) {
         hog_server_destroy(s);
@@ -492,7 +538,7 @@ extern "C" void hog_server_destroy(hog_server *s)
     }
     if (s->host_base) (void)hipHostFree(s->host_base);
     if (s->out_base) (void)hipHostFree(s->out_base);
-    for (auto &kv : s->plans) hog_plan_destroy(kv.second);
+    for (auto &kv : s->plans) hog_plan_destroy(kv.second.plan);
     if (s->arena_base) (void)hipFree(s->arena_base);
     if (s->d_tmpl) (void)hipFree(s->d_tmpl);
     if (s->d_bias) (void)hipFree(s->d_bias);
@@ -516,6 +562,7 @@ extern "C" hog_status hog_submit(hog_server *s, const uint8_t *host_img, int w, 
             return srv_fail(HOG_E_INVALID, "cannot plan a %dx%d image: %s", w, h, why.c_str());
         }
         fp = batch_bytes(p, (int64_t)w * h * s->cfg.channels);
+        plan_release(s, key);
     }
     if (fp > s->cfg.memory_budget)
         return srv_fail(HOG_E_INVALID, "a %dx%d image needs %lld bytes, over the memory budget", w, h,
@@ -608,6 +655,7 @@ extern "C" hog_status hog_server_warm(hog_server *s, int w, int h)
             const std::string why = hog_last_error();
             return srv_fail(HOG_E_INVALID, "cannot plan %d images of %dx%d: %s", n, w, h, why.c_str());
         }
+        plan_release(s, key);
     }
     return HOG_OK;
 }

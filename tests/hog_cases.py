@@ -23,7 +23,7 @@ def run_gpu(desc: hog.PlanDesc, img: np.ndarray, tmpl: np.ndarray, bias: np.ndar
     lut = hog.hog_lut_build(desc.n_bins, orientation)
     if block_feat is None:
         block_feat = desc.scan.norm == hog.HOG_NORM_L2
-    buf = hog.Buffers(plan, cell_hist=cell_hist, block_feat=block_feat)
+    buf = GuardedBuffers(plan, cell_hist=cell_hist, block_feat=block_feat)
     img_t = torch.from_numpy(np.ascontiguousarray(img).reshape(-1)).to("cuda")
     tmpl_t = torch.from_numpy(np.ascontiguousarray(tmpl, np.float32).reshape(-1)).to("cuda")
     bias_t = torch.from_numpy(np.ascontiguousarray(bias, np.float32).reshape(-1)).to("cuda")
@@ -60,7 +60,7 @@ def run_gpu_batch(descs, imgs, tmpl: np.ndarray, bias: np.ndarray, cell_hist=Tru
     plan = hog.Plan(descs, batch=True)
     lut = hog.hog_lut_build(plan.desc.n_bins)
     l2 = plan.desc.scan.norm == hog.HOG_NORM_L2
-    buf = hog.Buffers(plan, cell_hist=cell_hist, block_feat=l2)
+    buf = GuardedBuffers(plan, cell_hist=cell_hist, block_feat=l2)
     packed = torch.from_numpy(hog.pack_images(plan, imgs)).to("cuda")
     tmpl_t = torch.from_numpy(np.ascontiguousarray(tmpl, np.float32).reshape(-1)).to("cuda")
     bias_t = torch.from_numpy(np.ascontiguousarray(bias, np.float32).reshape(-1)).to("cuda")
@@ -99,3 +99,57 @@ def check_features(got: np.ndarray, ref: np.ndarray):
 def templates_for(desc: hog.PlanDesc, seed: int):
     plan_dim = oracle_params(desc).dim(desc.n_bins)
     return inputs.synth_templates(desc.n_templates, plan_dim, seed)
+
+
+# Canaries: every output buffer of a GPU test sits inside a larger allocation
+# whose GUARD bytes before and after it hold a fixed pattern; after the test
+# the pattern must be intact, so no kernel wrote outside the caller's buffers
+# (the plane writer's duplicate stores into row padding and its buffer-range
+# drops past a level's last row included).
+GUARD = 64 * 1024
+GUARD_BYTE = 0xA5
+_guarded = []
+
+
+class GuardedBuffers:
+    """hog.Buffers with guard bands (same fields, same sizes)."""
+
+    def __init__(self, plan, device="cuda", cell_hist=False, block_feat=False):
+        import torch
+        self._regions = []
+        s = plan.sizes
+
+        def alloc(name, n, dtype):
+            esz = torch.empty(0, dtype=dtype).element_size()
+            g = GUARD // esz
+            base = torch.empty(n + 2 * g, dtype=dtype, device=device)
+            base.view(torch.uint8).fill_(GUARD_BYTE)
+            self._regions.append((name, base, g * esz, n * esz))
+            return base[g:g + n]
+
+        self.bins = alloc("bins", max(s.bins_bytes, 1), torch.uint8)
+        self.ii = alloc("ii", max(s.ii_elems, 1), hog.ii_dtype(plan))
+        self.scores = alloc("scores", max(s.score_elems, 1), torch.float32)
+        self.workspace = alloc("workspace", max(s.workspace_bytes, 1), torch.uint8)
+        self.cell_hist = alloc("cell_hist", max(s.cell_elems, 1), torch.int32) if cell_hist else None
+        self.block_feat = alloc("block_feat", max(s.block_elems, 1), torch.float32) if block_feat else None
+        _guarded.append(self)
+
+    def check_guards(self):
+        import torch
+        for name, base, g, n in self._regions:
+            b = base.view(torch.uint8)
+            for part, view in (("before", b[:g]), ("after", b[g + n:])):
+                bad = int((view != GUARD_BYTE).sum())
+                assert bad == 0, f"{bad} bytes written {part} the {name} buffer"
+
+
+def check_all_guards():
+    """Check and forget every GuardedBuffers made since the last call."""
+    import torch
+    torch.cuda.synchronize()
+    try:
+        for b in _guarded:
+            b.check_guards()
+    finally:
+        _guarded.clear()

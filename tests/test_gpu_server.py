@@ -269,3 +269,23 @@ def test_server_votes_and_plane_bits(votes, plane_bits):
             want = hog.level_scores(plan, out["scores"], 0).reshape(-1)
             assert np.array_equal(res[t][0].view(np.uint32), want.view(np.uint32)), (w, h, pb)
     torch.cuda.synchronize()
+
+
+def test_many_distinct_sizes_past_the_plan_cache_bound():
+    """More distinct image sizes than the server caches plans for (4 max_batch
+    + 16 = 24 with max_batch 2): plans are dropped and rebuilt as sizes
+    return, and every request still equals its image run alone."""
+    tmpl, bias = _templates()
+    srv = hog.Server(tmpl, bias, channels=3, n_bins=8, max_width=224, max_height=248,
+                     memory_budget=256 << 20, host_budget=64 << 20, max_slots=4, max_batch=2, streams=2)
+    sizes = [(64 + 4 * i, 128 + 3 * i) for i in range(40)]
+    order = sizes + sizes[::-3]  # some sizes come back after their plans were dropped
+    reqs = []
+    for j, (w, h) in enumerate(order):
+        img = inputs.synth_image(w, h, 3, 7700 + j)
+        reqs.append((srv.submit(img), img, w, h))
+    res = _wait(srv, [r[0] for r in reqs], [_cap(r[2], r[3]) for r in reqs])
+    for t, img, w, h in reqs:
+        want, _, _ = _alone(img, tmpl, bias)
+        assert np.array_equal(res[t][0].view(np.uint32), want.view(np.uint32)), f"{w}x{h}"
+    srv.close()
