@@ -460,6 +460,28 @@ static hog_status create_plan(const hog_plan_desc *descs, int n_img, bool batch,
         const int64_t rowh = (int64_t)(hogk::kStripW + 8) * mfma_ks;  // halves per staged cell row
         best_lds = 4 * round_up(4 * rowh * 2 + 64 * 4 + (int64_t)hogk::kStripW * best_th * 4, 16);
     }
+    int raw_waves = 0;
+    if (scorer == 0 && sp.norm == HOG_NORM_RAW) {
+        // Raw features: 64 windows per workgroup (tw x th = 64, one per lane),
+        // min(wcy, 16) waves splitting each window's cell rows; the shape
+        // staging the fewest cells per tile that fits 64 KB of LDS.
+        const int R = std::min(sp.win_cells_y, 16);
+        int64_t best_cells = INT64_MAX;
+        for (int tw = 64; tw >= 1; tw /= 2) {
+            const int th = 64 / tw;
+            const int64_t CW = tw + sp.win_cells_x - 1, CH = th + sp.win_cells_y - 1;
+            const int64_t lds = round_up(CH * CW * nbp, 2) * 4 + 2 * (int64_t)R * 64 * 8;
+            if (lds > 65536 || CH * CW >= best_cells) continue;
+            best_cells = CH * CW;
+            best_tw = tw;
+            best_th = th;
+            best_lds = lds;
+        }
+        if (best_tw > 0) {
+            scorer = 3;
+            raw_waves = R;
+        }
+    }
     if (scorer == 0) {
         double best_cost = 1e30;
         for (int tw = 1; tw <= 64; tw *= 2)
@@ -747,6 +769,7 @@ static hog_status create_plan(const hog_plan_desc *descs, int n_img, bool batch,
     pd.st_lds_bytes = (int32_t)best_lds;
     pd.mfma_ks = mfma_ks;
     pd.scorer = scorer;
+    pd.st_waves = raw_waves;
     pd.cell_stride = nbp;
     pd.plane_bytes = pb;
     pd.bin_chunk = chunk_final;  // bins per wave; a last, smaller chunk takes the rest

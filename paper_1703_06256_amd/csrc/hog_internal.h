@@ -107,7 +107,9 @@ struct PlanDev {
     int32_t votes;             // HOG_VOTES_HARD or HOG_VOTES_SOFT
     int32_t feat_dim;
     int32_t st_tw, st_th;      // scorer tile (windows)
-    int32_t scorer;            // 0: vector units; 1: strips (one template per wave); 2: window GEMM (K >= 16)
+    int32_t scorer;            // 0: vector units; 1: strips (one template per wave); 2: window GEMM (K >= 16);
+                               // 3: raw features on the vector units, 64 windows per workgroup
+    int32_t st_waves;          // raw scorer: waves per workgroup (they split the window's cell rows)
     int32_t mfma_ks;           // matrix-core scorers: bin slots per cell (8, 16 or 20)
     int32_t st_lds_bytes;      // scorer dynamic LDS
     int32_t cell_stride;       // floats per staged cell in the scorer's LDS

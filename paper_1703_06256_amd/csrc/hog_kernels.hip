@@ -1241,6 +1241,113 @@ __global__ __launch_bounds__(256) void k_score(const Level *__restrict__ lv,
 }
 
 // ---------------------------------------------------------------------------
+// Sec. 3.1 / Fig. 4 + Sec. 4 with raw features: a window's feature is its
+// wcx x wcy cell histograms in row-major order, so its score is the bias
+// plus one N_b-term inner product per cell. A workgroup takes a tile of
+// tw x th = 64 windows, one per lane, and stages the cells they use into LDS
+// as floats (up to kRawStage loads in flight per thread). Its R waves split
+// the window's cell rows (wave r takes rows r, r + R, ...), so each lane walks
+// about wcy / R rows instead of all of them, with the template weights of a
+// row wave-uniform (scalar loads). As in k_score, each cell's N_b products
+// form one FP32 partial and the partials are added in FP64: per wave, then
+// across the waves in LDS.
+// ---------------------------------------------------------------------------
+constexpr int kRawStage = 8;
+
+template <int NB, int WCX>
+__global__ __launch_bounds__(1024) void k_score_raw(const Level *__restrict__ lv,
+                                                    const int32_t *__restrict__ first, int n_levels,
+                                                    ScoreArgs a, const uint8_t *__restrict__ ws,
+                                                    const float *__restrict__ tmpl,
+                                                    const float *__restrict__ bias,
+                                                    float *__restrict__ scores)
+{
+    extern __shared__ float lds[];
+    const int wg = (int)blockIdx.x;
+    if (wg >= first[n_levels]) return;
+    const int l = find_level(first, n_levels, wg);
+    const Level &v = lv[l];
+    const int rel = wg - first[l];
+    const int stx = rel % v.st_x, sty = rel / v.st_x;
+    const int wx0 = stx * a.tw, wy0 = sty * a.th;
+    const int nb = NB > 0 ? NB : a.nb;
+    const int nbp = NB > 0 ? NB : a.nbp;  // staged floats per cell
+    const int wcx = WCX > 0 ? WCX : a.wcx;
+    const int CW = a.tw + wcx - 1, CH = a.th + a.wcy - 1;
+    const int nwaves = (int)(blockDim.x >> 6);
+    float *hc = lds;
+    double *red = reinterpret_cast<double *>(lds + ((CH * CW * nbp + 1) & ~1));  // [2][nwaves][64]
+
+    // Stage the tile's cells (zero outside the level's cell grid): element
+    // i = (n CH + r) CW + j, cell (wy0 + r, wx0 + j), bin n.
+    const uint16_t *cache = reinterpret_cast<const uint16_t *>(ws + v.ws_cache);
+    const int total = CH * CW * nb;
+    for (int base = (int)threadIdx.x; base < total; base += kRawStage * (int)blockDim.x) {
+        uint32_t val[kRawStage];
+        int dst[kRawStage];
+#pragma unroll
+        for (int u = 0; u < kRawStage; ++u) {
+            const int i = base + u * (int)blockDim.x;
+            val[u] = 0u;
+            dst[u] = -1;
+            if (i < total) {
+                const int j = i % CW, rest = i / CW;
+                const int r = rest % CH, n = rest / CH;
+                const int cy = wy0 + r, cx = wx0 + j;
+                if (cy < v.cells_y && cx < v.cells_x) val[u] = cache[cache_index(v, n, cy, cx)];
+                dst[u] = (r * CW + j) * nbp + n;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kRawStage; ++u)
+            if (dst[u] >= 0) hc[dst[u]] = (float)val[u] * a.vscale;  // exact: a power of two
+    }
+    __syncthreads();
+
+    const int lane = (int)threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+    const int tx = lane % a.tw, ty = lane / a.tw;
+    const int wx = wx0 + tx, wy = wy0 + ty;
+    const bool live = wx < v.win_x && wy < v.win_y;
+    float *sout = scores + v.score_off + ((int64_t)wy * v.win_x + wx) * a.k;
+
+    for (int k = 0; k < a.k; ++k) {
+        const float *T = tmpl + (int64_t)k * a.dim;
+        double s = 0.0;
+        for (int q = w; q < a.wcy; q += nwaves) {
+            const float *hrow = hc + ((ty + q) * CW + tx) * nbp;
+            const float *trow = T + (int64_t)q * wcx * nb;
+            if constexpr (NB > 0 && WCX > 0) {
+#pragma unroll
+                for (int qx = 0; qx < WCX; ++qx) {
+                    float h[NB];
+                    load_cell<NB>(hrow + qx * NB, h);
+                    s += (double)dot_acc<NB>(trow + qx * NB, h, 0.f);
+                }
+            } else {
+                for (int qx = 0; qx < wcx; ++qx) {
+                    const float *hp = hrow + qx * nbp;
+                    const float *wt = trow + qx * nb;
+                    float g = 0.f;
+                    for (int n = 0; n < nb; ++n) g = fmaf(wt[n], hp[n], g);
+                    s += (double)g;
+                }
+            }
+        }
+        double *rk = red + (k & 1) * nwaves * 64;
+        rk[w * 64 + lane] = s;
+        __syncthreads();
+        if (w == 0 && live) {
+            double t = (double)bias[k];
+            for (int r = 0; r < nwaves; ++r) t += rk[r * 64 + lane];
+            sout[k] = (float)t;
+        }
+        // The next template writes the other half of red; the one after it
+        // this half again, behind the barrier of the next iteration.
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Sec. 3.1 / Fig. 4 + Sec. 4 on the matrix cores (L2 blocks of 2 x 2 cells).
 //
 // score(wx, wy) = bias + sum over block positions (by, bx) of
@@ -2451,6 +2558,22 @@ hipError_t launch_score(const PlanDev &p, const uint8_t *ws, const float *tmpl, 
     a.eps = p.eps;
     a.vscale = p.vscale;
     const size_t lds = (size_t)p.st_lds_bytes;
+    if (p.scorer == 3) {
+        const dim3 rblock((unsigned)(64 * p.st_waves));
+        if (p.win_cells_x == 8 && p.n_bins == 8)
+            hipLaunchKernelGGL((k_score_raw<8, 8>), grid, rblock, lds, stream, p.levels, f, p.n_levels, a,
+                               ws, tmpl, bias, scores);
+        else if (p.win_cells_x == 8 && p.n_bins == 9)
+            hipLaunchKernelGGL((k_score_raw<9, 8>), grid, rblock, lds, stream, p.levels, f, p.n_levels, a,
+                               ws, tmpl, bias, scores);
+        else if (p.win_cells_x == 8 && p.n_bins == 18)
+            hipLaunchKernelGGL((k_score_raw<18, 8>), grid, rblock, lds, stream, p.levels, f, p.n_levels, a,
+                               ws, tmpl, bias, scores);
+        else
+            hipLaunchKernelGGL((k_score_raw<0, 0>), grid, rblock, lds, stream, p.levels, f, p.n_levels, a,
+                               ws, tmpl, bias, scores);
+        return hipGetLastError();
+    }
     const bool w8 = p.win_cells_x == 8 && p.norm == 1;
     if (w8 && p.n_bins == 8)
         hipLaunchKernelGGL((k_score<8, 8>), grid, block, lds, stream, p.levels, f, p.n_levels, a,
