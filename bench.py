@@ -402,50 +402,49 @@ def main():
     with_h2d = dict(ms_per_step=round(h2d_ms, 5), mpixel_per_s=round(sz.total_pixels / (h2d_ms * 1e3), 1),
                     input_bytes=int(img_t.numel()))
 
-    # The same with the copies overlapped: two input buffers; a copy stream
-    # fills one from pinned memory while the launch stream runs the step on
-    # the other (events order each buffer's copy before its step and after
-    # its previous step).
-    img_b = torch.empty_like(img_t)
-    ins = [img_t, img_b]
+    # The same with the copies overlapped: two streams, each with its own
+    # input and buffer set, take alternate steps; on each, a step's copy
+    # follows that stream's previous step, so one stream's copy runs while
+    # the other computes. No step waits on another stream: the two streams
+    # join the launch stream only at the ends of the timed region.
+    ov_streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    ov_sets = [sets[j] if j < n_sets else (img_t.clone(), hog.Buffers(plan)) for j in range(2)]
+    ov_ins = [torch.empty_like(img_t) for _ in range(2)]
     if batch:
-        graph_b = hog.Graph(plan, lut, img_b, tmpl_t, bias_t, buf)
-        steps = [lambda: graph.launch(stream), lambda: graph_b.launch(stream)]
-    else:
-        steps = [lambda: hog.hog_run(plan, lut, img_t, tmpl_t, bias_t, buf, stream),
-                 lambda: hog.hog_run(plan, lut, img_b, tmpl_t, bias_t, buf, stream)]
-    cs = torch.cuda.Stream()
-    copied = [torch.cuda.Event(), torch.cuda.Event()]
-    used = [torch.cuda.Event(), torch.cuda.Event()]
+        ov_graphs = [hog.Graph(plan, lut, ov_ins[j], tmpl_t, bias_t, ov_sets[j][1]) for j in range(2)]
 
     def overlapped(n):
-        with torch.cuda.stream(cs):
-            ins[0].copy_(host_in, non_blocking=True)
-            copied[0].record(cs)
         for i in range(n):
-            k = i & 1
-            if i + 1 < n:
-                with torch.cuda.stream(cs):
-                    if i >= 1:
-                        cs.wait_event(used[1 - k])  # that buffer's previous step is done
-                    ins[1 - k].copy_(host_in, non_blocking=True)
-                    copied[1 - k].record(cs)
-            stream.wait_event(copied[k])
-            steps[k]()
-            used[k].record(stream)
+            j = i & 1
+            with torch.cuda.stream(ov_streams[j]):
+                ov_ins[j].copy_(host_in, non_blocking=True)
+                if batch:
+                    ov_graphs[j].launch(ov_streams[j])
+                else:
+                    hog.hog_run(plan, lut, ov_ins[j], tmpl_t, bias_t, ov_sets[j][1], ov_streams[j])
 
-    overlapped(4)
+    def joined(n):
+        a.record(stream)
+        for st in ov_streams:
+            st.wait_event(a)
+        overlapped(n)
+        for st in ov_streams:
+            e = torch.cuda.Event()
+            e.record(st)
+            stream.wait_event(e)
+        b.record(stream)
+
+    joined(4)
     torch.cuda.synchronize()
-    a.record(stream)
-    overlapped(n_h)
-    b.record(stream)
+    joined(n_h)
     torch.cuda.synchronize()
     ov_ms = a.elapsed_time(b) / n_h
     with_h2d["overlapped"] = dict(ms_per_step=round(ov_ms, 5),
                                   mpixel_per_s=round(sz.total_pixels / (ov_ms * 1e3), 1))
     if batch:
-        graph_b.destroy()
-    del img_b, ins
+        for g in ov_graphs:
+            g.destroy()
+    del ov_ins, ov_sets
 
     # The input's bin statistics (level 0 of the first image): every bin
     # populated and a visible no-bin share mean a non-degenerate workload.

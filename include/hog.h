@@ -338,6 +338,23 @@ hog_status hog_plan_autotune(hog_plan *plan, const hog_lut *lut, const uint8_t *
                              const float *bias, float *scores, void *workspace, void *stream,
                              int reps, hog_tiles *chosen);
 
+/* Autotune cache. path names a text file of earlier hog_plan_autotune
+ * results, one line per (device architecture and compute-unit count, build of
+ * this library, plan shape: every level's size and the plan's bins, channels,
+ * templates, scan parameters, plane width and votes); NULL closes the cache.
+ * Opening reads the file (it need not exist yet) and resets the counters.
+ * While a cache is open, hog_plan_autotune installs a stored result without
+ * timing anything (a hit: it runs the path once, so the buffers end as after
+ * a tuned call) or times the candidates as usual and appends the result (a
+ * miss). Lines that do not parse, and stored tiles the plan rejects, are
+ * ignored (the latter are re-tuned). A file that cannot be written keeps the
+ * results in memory only. Process-wide and thread-safe; HOG_E_INVALID for an
+ * empty path. */
+hog_status hog_tune_cache_open(const char *path);
+/* Hits and misses of hog_plan_autotune since the cache was opened, and the
+ * results it holds (each pointer nullable). */
+hog_status hog_tune_cache_stats(int64_t *hits, int64_t *misses, int64_t *entries);
+
 /* ------------------------------------------------------------------------ */
 /* The whole path at once.                                                  */
 /* ------------------------------------------------------------------------ */

@@ -5,6 +5,7 @@
 #include "hog_internal.h"
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -1105,6 +1106,82 @@ static hog_status run_plan(const hog_plan *plan, const hog_lut *lut, const uint8
                            uint8_t *bins, void *ii, const float *tmpl, const float *bias, float *scores,
                            void *workspace, void *stream);
 
+// Autotune cache: earlier hog_plan_autotune results, keyed by device,
+// library build and plan shape, kept in memory and appended to a text file
+// ("hogtune <key> <bin_chunk> <score_rows> <level_groups> <lut_global>").
+namespace {
+std::mutex g_tune_mu;
+std::string g_tune_path;
+std::map<uint64_t, std::array<int32_t, 4>> g_tune;
+int64_t g_tune_hits = 0, g_tune_misses = 0;
+
+uint64_t fnv1a(uint64_t h, const void *p, size_t n)
+{
+    const unsigned char *b = static_cast<const unsigned char *>(p);
+    for (size_t i = 0; i < n; ++i) h = (h ^ b[i]) * 1099511628211ull;
+    return h;
+}
+
+// The device (architecture, compute units), this build of the library, and
+// what the tiles' timing depends on in the plan: every level's size and the
+// shared parameters.
+uint64_t tune_key(const hog_plan *p)
+{
+    uint64_t h = 1469598103934665603ull;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, p->device) == hipSuccess) {
+        h = fnv1a(h, prop.gcnArchName, strnlen(prop.gcnArchName, sizeof prop.gcnArchName));
+        h = fnv1a(h, &prop.multiProcessorCount, sizeof prop.multiProcessorCount);
+    }
+    static const char build[] = __DATE__ " " __TIME__;
+    h = fnv1a(h, build, sizeof build);
+    const hog_plan_desc &d = p->desc;
+    const int32_t f[] = {d.channels, d.n_bins, d.n_templates, d.scan.cell, d.scan.win_cells_x,
+                         d.scan.win_cells_y, d.scan.block, d.scan.norm, d.plane_bits, d.votes,
+                         (int32_t)p->batch, (int32_t)p->levels.size()};
+    h = fnv1a(h, f, sizeof f);
+    uint32_t eps_bits;
+    std::memcpy(&eps_bits, &d.scan.eps, sizeof eps_bits);
+    h = fnv1a(h, &eps_bits, sizeof eps_bits);
+    for (const Level &v : p->levels) {
+        h = fnv1a(h, &v.w, sizeof v.w);
+        h = fnv1a(h, &v.h, sizeof v.h);
+    }
+    return h;
+}
+}  // namespace
+
+extern "C" hog_status hog_tune_cache_open(const char *path)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune.clear();
+    g_tune_hits = g_tune_misses = 0;
+    g_tune_path = path ? path : "";
+    if (!path) return HOG_OK;
+    if (!*path) return fail(HOG_E_INVALID, "empty cache path");
+    FILE *fp = std::fopen(path, "r");
+    if (!fp) return HOG_OK;  // created at the first result
+    char line[256];
+    while (std::fgets(line, sizeof line, fp)) {
+        unsigned long long key = 0;
+        int t[4];
+        char tail = 0;
+        if (std::sscanf(line, "hogtune %llx %d %d %d %d %c", &key, &t[0], &t[1], &t[2], &t[3], &tail) == 5)
+            g_tune[(uint64_t)key] = {t[0], t[1], t[2], t[3]};
+    }
+    std::fclose(fp);
+    return HOG_OK;
+}
+
+extern "C" hog_status hog_tune_cache_stats(int64_t *hits, int64_t *misses, int64_t *entries)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    if (hits) *hits = g_tune_hits;
+    if (misses) *misses = g_tune_misses;
+    if (entries) *entries = (int64_t)g_tune.size();
+    return HOG_OK;
+}
+
 extern "C" hog_status hog_plan_autotune(hog_plan *plan, const hog_lut *lut, const uint8_t *img,
                                         int64_t img_pitch, uint8_t *bins, void *ii, const float *tmpl,
                                         const float *bias, float *scores, void *workspace, void *stream,
@@ -1114,6 +1191,38 @@ extern "C" hog_status hog_plan_autotune(hog_plan *plan, const hog_lut *lut, cons
     if (st != HOG_OK) return st;
     if (reps < 1 || reps > 1000) return fail(HOG_E_INVALID, "reps must be in [1, 1000]");
     hipStream_t s = (hipStream_t)stream;
+    bool cached = false;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        cached = !g_tune_path.empty();
+    }
+    uint64_t key = 0;
+    if (cached) {
+        key = tune_key(plan);
+        std::array<int32_t, 4> t{};
+        bool found = false;
+        {
+            std::lock_guard<std::mutex> lk(g_tune_mu);
+            auto it = g_tune.find(key);
+            if (it != g_tune.end()) {
+                found = true;
+                t = it->second;
+            }
+        }
+        // A stored result is installed as it is (one hog_run leaves the
+        // buffers as the tuned call would); one the plan rejects is re-tuned.
+        if (found && apply_tiles(plan, t[0], t[1], t[2], t[3]) == HOG_OK) {
+            st = run_plan(plan, lut, img, img_pitch, bins, ii, tmpl, bias, scores, workspace, stream);
+            if (st != HOG_OK) return st;
+            hipError_t he = hipStreamSynchronize(s);
+            if (he != hipSuccess) return device_fail(he, "hipStreamSynchronize");
+            {
+                std::lock_guard<std::mutex> lk(g_tune_mu);
+                ++g_tune_hits;
+            }
+            return chosen ? hog_plan_get_tiles(plan, chosen) : HOG_OK;
+        }
+    }
     hipEvent_t e0 = nullptr, e1 = nullptr;
     hipError_t e = hipEventCreate(&e0);
     if (e == hipSuccess) e = hipEventCreate(&e1);
@@ -1188,6 +1297,19 @@ extern "C" hog_status hog_plan_autotune(hog_plan *plan, const hog_lut *lut, cons
     (void)hipEventDestroy(e1);
     if (st != HOG_OK) return st;
     st = apply_tiles(plan, best_chunk, best_rows, best_groups, best_lut);
+    if (st == HOG_OK && cached) {
+        const std::array<int32_t, 4> t = {plan->dev.bin_chunk, plan->dev.st_th, best_groups, best_lut};
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        ++g_tune_misses;
+        if (!g_tune_path.empty()) {
+            g_tune[key] = t;
+            // A file that cannot be written keeps the result in memory only.
+            if (FILE *fp = std::fopen(g_tune_path.c_str(), "a")) {
+                std::fprintf(fp, "hogtune %016llx %d %d %d %d\n", (unsigned long long)key, t[0], t[1], t[2], t[3]);
+                std::fclose(fp);
+            }
+        }
+    }
     if (st == HOG_OK && chosen) st = hog_plan_get_tiles(plan, chosen);
     return st;
 }

@@ -34,7 +34,8 @@ EXPORTS = (
     "hog_plan_get_image", "hog_plan_destroy", "hog_plan_get_sizes",
     "hog_plan_get_level", "hog_bin_map", "hog_integral", "hog_scan_windows", "hog_run", "hog_run_static",
     "hog_graph_create", "hog_graph_launch", "hog_graph_destroy", "hog_plan_get_tiles",
-    "hog_plan_set_tiles", "hog_plan_autotune", "hog_server_create", "hog_server_destroy",
+    "hog_plan_set_tiles", "hog_plan_autotune", "hog_tune_cache_open", "hog_tune_cache_stats",
+    "hog_server_create", "hog_server_destroy",
     "hog_server_warm", "hog_submit", "hog_poll", "hog_wait_any",
     "hog_timing_enable", "hog_timing_reset", "hog_timing_get",
 )
@@ -166,6 +167,8 @@ def load_library():
         "hog_plan_set_tiles": ([vp, ctypes.POINTER(Tiles)], i32),
         "hog_plan_autotune": ([vp, vp, vp, i64, vp, vp, vp, vp, vp, vp, vp, i32,
                                ctypes.POINTER(Tiles)], i32),
+        "hog_tune_cache_open": ([ctypes.c_char_p], i32),
+        "hog_tune_cache_stats": ([ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64)], i32),
         "hog_timing_enable": ([i32], i32),
         "hog_timing_reset": ([], i32),
         "hog_timing_get": ([ctypes.c_char_p, ctypes.POINTER(i64),
@@ -471,6 +474,19 @@ def autotune(plan: Plan, lut: Lut, img, tmpl, bias, buf: "Buffers", stream=None,
     _check(load_library().hog_plan_autotune(*_run_args(plan, lut, img, tmpl, bias, buf, img_pitch),
                                             _stream(stream), int(reps), ctypes.byref(t)))
     return t
+
+
+def tune_cache_open(path) -> None:
+    """hog_tune_cache_open: keep autotune results in the text file at path
+    (None closes the cache)."""
+    _check(load_library().hog_tune_cache_open(None if path is None else os.fsencode(path)))
+
+
+def tune_cache_stats():
+    """(hits, misses, entries) of the autotune cache since it was opened."""
+    h, m, e = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    _check(load_library().hog_tune_cache_stats(ctypes.byref(h), ctypes.byref(m), ctypes.byref(e)))
+    return h.value, m.value, e.value
 
 
 class Server:
