@@ -239,7 +239,8 @@ hog_status hog_plan_get_level(const hog_plan *plan, int level, hog_level_info *o
 /* ------------------------------------------------------------------------ */
 
 /* Eq. 1 + Sec. 2. img: device, uint8, row-major, channels interleaved,
- * img_pitch bytes per row (>= width*channels; 0 for a batch plan, whose
+ * img_pitch bytes per row (>= width*channels, with (height - 1) * img_pitch +
+ * width * channels < 2^32, else HOG_E_INVALID; 0 for a batch plan, whose
  * images are packed as hog_plan_get_image says). For every level, writes the
  * bin map into bins (device, plan layout): for interior pixels, per channel
  * dx = P[x+1][y] - P[x-1][y], dy = P[x][y+1] - P[x][y-1] (on the level's

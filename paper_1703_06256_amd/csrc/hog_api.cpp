@@ -886,6 +886,15 @@ extern "C" hog_status hog_plan_get_level(const hog_plan *plan, int level, hog_le
 // ---------------------------------------------------------------------------
 // The hot path.
 // ---------------------------------------------------------------------------
+// The bin map reads the source image through one buffer descriptor: its
+// bytes, (height - 1) * pitch + width * channels, must fit 32 bits. (Packed
+// batch images always do: 32767 x 32767 x 3 bytes is below 2^32.)
+static bool image_extent_ok(const hog_plan *plan, int64_t img_pitch)
+{
+    const hog_plan_desc &d = plan->desc;
+    return (int64_t)(d.height - 1) * img_pitch + (int64_t)d.width * d.channels <= (int64_t)0xFFFFFFFF;
+}
+
 extern "C" hog_status hog_bin_map(const hog_plan *plan, const hog_lut *lut, const uint8_t *img,
                                   int64_t img_pitch, uint8_t *bins, void *stream)
 {
@@ -896,6 +905,8 @@ extern "C" hog_status hog_bin_map(const hog_plan *plan, const hog_lut *lut, cons
         if (img_pitch != 0) return fail(HOG_E_INVALID, "a batch plan takes img_pitch 0 (images are packed)");
     } else if (img_pitch < (int64_t)plan->desc.width * plan->desc.channels) {
         return fail(HOG_E_INVALID, "img_pitch %lld < width*channels", (long long)img_pitch);
+    } else if (!image_extent_ok(plan, img_pitch)) {
+        return fail(HOG_E_INVALID, "image of img_pitch %lld spans 4 GiB or more", (long long)img_pitch);
     }
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = timed_launch("bin_map", s, [&] {
@@ -1328,6 +1339,8 @@ static hog_status check_run_args(const hog_plan *plan, const hog_lut *lut, const
         return fail(HOG_E_INVALID, "lut has %d bins, plan has %d", lut->n_bins, plan->desc.n_bins);
     if (plan->batch ? img_pitch != 0 : img_pitch < (int64_t)plan->desc.width * plan->desc.channels)
         return fail(HOG_E_INVALID, "bad img_pitch %lld", (long long)img_pitch);
+    if (!plan->batch && !image_extent_ok(plan, img_pitch))
+        return fail(HOG_E_INVALID, "image of img_pitch %lld spans 4 GiB or more", (long long)img_pitch);
     return HOG_OK;
 }
 

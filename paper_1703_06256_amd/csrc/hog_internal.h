@@ -16,6 +16,7 @@ constexpr int kBinCols = 62;
 constexpr int kBinRows = 16;
 // dy >= 0 half of the 511 x 511 lookup table, as staged in LDS.
 constexpr int kLutHalfBytes = 256 * 511;
+constexpr int kLutEntries = 511 * 511;  // the full (dx, dy) table
 
 // Integral images: a tile is kTile x kTile pixels, one wave per tile and per
 // chunk of at most kMaxBinChunk bins; bins are read kRowBatch rows at a time.

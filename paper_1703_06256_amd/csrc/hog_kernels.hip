@@ -130,9 +130,12 @@ __global__ __launch_bounds__(1024) void k_bin_map(const Level *__restrict__ lv,
                                                   uint8_t *__restrict__ bins)
 {
     const uint8_t *lut = nullptr;
-    if constexpr (GLUT) {
-        lut = lut_half;  // the full table here
-    } else if constexpr (!SOFT) {
+    // The table read through the caches (GLUT: the full 511 x 511 bytes,
+    // passed as lut_half; SOFT: 511 x 511 uint16 entries) by buffer loads of
+    // the entry's offset. Unused with the LDS half table.
+    const __amdgpu_buffer_rsrc_t trsrc =
+        SOFT ? buffer_rsrc(soft, 2 * kLutEntries) : buffer_rsrc(lut_half, kLutEntries);
+    if constexpr (!SOFT && !GLUT) {
         __shared__ __attribute__((aligned(16))) uint8_t lut_lds[kLutHalfBytes];
         typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
         const u32x4 *src = reinterpret_cast<const u32x4 *>(lut_half);
@@ -182,20 +185,23 @@ __global__ __launch_bounds__(1024) void k_bin_map(const Level *__restrict__ lv,
             coff = last ? 3 * (int64_t)sx - 1 : 3 * (int64_t)sx;
             shift = last ? 8u : 0u;
         }
-        const uint8_t *colp = img + v.src_off + coff;
+        // The source image through one buffer descriptor (its byte extent,
+        // below 2^32, is checked on the host): the lane's column offset in
+        // the vector operand, the row's offset in the scalar one, so no
+        // per-lane 64-bit address arithmetic.
+        const __amdgpu_buffer_rsrc_t isrc =
+            buffer_rsrc(img + v.src_off, (uint32_t)((int64_t)(v.src_h - 1) * pitch + (int64_t)src_w * C));
+        const int coff32 = (int)(uint32_t)coff;
 
         uint32_t smp[kBinRows + 2];
 #pragma unroll
         for (int i = 0; i < kBinRows + 2; ++i) {
             const int r = min(max(y0 - 1 + i, 0), H - 1);
-            const uint8_t *p = colp + (int64_t)my[r] * pitch;
-            if constexpr (C == 1) {
-                smp[i] = *p;
-            } else {
-                uint32_t w4;
-                __builtin_memcpy(&w4, p, 4);
-                smp[i] = w4;
-            }
+            const int roff = (int)(uint32_t)((int64_t)my[r] * pitch);
+            if constexpr (C == 1)
+                smp[i] = __builtin_amdgcn_raw_buffer_load_b8(isrc, coff32, roff, 0);
+            else
+                smp[i] = __builtin_amdgcn_raw_buffer_load_b32(isrc, coff32, roff, 0);
         }
 #pragma unroll
         for (int i = 0; i < kBinRows + 2; ++i) {
@@ -222,10 +228,11 @@ __global__ __launch_bounds__(1024) void k_bin_map(const Level *__restrict__ lv,
             }
             const bool ok = col_interior && y >= 1 && y <= H - 2 && best > 0;
             if constexpr (SOFT) {
-                const uint16_t e = soft[ok ? (bdy + 255) * 511 + (bdx + 255) : 0];
+                const uint16_t e = __builtin_amdgcn_raw_buffer_load_b16(
+                    trsrc, ok ? 2 * ((bdy + 255) * 511 + (bdx + 255)) : 0, 0, 0);
                 b[i] = ok ? e : (uint16_t)kNoBin;
             } else if constexpr (GLUT) {
-                const uint8_t e = lut[ok ? (bdy + 255) * 511 + (bdx + 255) : 0];
+                const uint8_t e = __builtin_amdgcn_raw_buffer_load_b8(trsrc, ok ? (bdy + 255) * 511 + (bdx + 255) : 0, 0, 0);
                 b[i] = ok ? e : (uint8_t)kNoBin;
             } else {
                 const int ady = bdy < 0 ? -bdy : bdy;
@@ -236,11 +243,16 @@ __global__ __launch_bounds__(1024) void k_bin_map(const Level *__restrict__ lv,
             }
         }
         const bool writer = lane >= 1 && lane <= kBinCols && col_ok;
-        bin_t *out = reinterpret_cast<bin_t *>(bins + v.bins_off) + x;
-        const int64_t pitch_e = v.bins_pitch / (int64_t)sizeof(bin_t);
+        const __amdgpu_buffer_rsrc_t bsrc = buffer_rsrc(bins + v.bins_off, (uint32_t)(v.bins_pitch * H));
+        const int xb = x * (int)sizeof(bin_t);
 #pragma unroll
         for (int i = 0; i < kBinRows; ++i)
-            if (writer && y0 + i < H) out[(int64_t)(y0 + i) * pitch_e] = b[i];
+            if (writer && y0 + i < H) {
+                if constexpr (SOFT)
+                    __builtin_amdgcn_raw_buffer_store_b16(b[i], bsrc, xb, (y0 + i) * (int)v.bins_pitch, 0);
+                else
+                    __builtin_amdgcn_raw_buffer_store_b8(b[i], bsrc, xb, (y0 + i) * (int)v.bins_pitch, 0);
+            }
     }
 }
 
