@@ -1842,7 +1842,8 @@ __global__ __launch_bounds__(256, 2) void k_score_strip(const Level *__restrict_
 // empty. The workgroup walks by = 0 .. nby - 1: the tile's cell rows wy0 + by
 // .. + TH sit in an LDS ring (one new row per by), so do the norms of the TH
 // block rows in use (one new row per by), and the template fragments of the
-// positions (by, 0 .. 6) are in LDS, double-buffered and fetched one by ahead.
+// positions (by, 0 .. 6) are in LDS, fetched between the barriers that end the
+// previous block row.
 // ---------------------------------------------------------------------------
 template <bool NARROW>
 struct WgShape {
@@ -1978,7 +1979,7 @@ template <int NBP>
 struct WgLds {
     static constexpr int NFRAG = kStripMaxBX * (NBP / 4) * 2;  // fragments per block row offset: [bx][s][hi|lo]
     typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
-    u32x4 bst[2][NFRAG * 64];
+    u32x4 bst[1][NFRAG * 64];  // one block row offset's fragments (written between barriers)
     __attribute__((aligned(16))) _Float16 ring[kWgRingCells * NBP];
     float sqr[kWgRingCells];
     float invb[kWgInvCells];
@@ -2054,28 +2055,29 @@ __device__ __forceinline__ void wgemm_tile(WgLds<NBP> &L, const Level &v, int re
 #pragma unroll
         for (int i = 0; i < PF; ++i) pf[i] = tfrag[(int64_t)by * NFRAG * 64 + tid + 256 * i];
     };
-    auto store_frags = [&](int buf, const u32x4 (&pf)[PF]) {
+    auto store_frags = [&](const u32x4 (&pf)[PF]) {
 #pragma unroll
-        for (int i = 0; i < PF; ++i) bst[buf][tid + 256 * i] = pf[i];
+        for (int i = 0; i < PF; ++i) bst[0][tid + 256 * i] = pf[i];
     };
 
-    // Prologue: cell rows wy0 .. wy0 + TH, fragments of by = 0, and the
-    // next row and fragments in flight.
-    u32x4 pf[PF];
-    fetch_frags(0, pf);
+    // Prologue: cell rows wy0 .. wy0 + TH and the fragments of by = 0; the
+    // next row in flight. (Fragments are fetched between the barriers that
+    // end each block row: holding them in registers across the walk would
+    // cost the registers that let three workgroups share a CU.)
     {
+        u32x4 pf[PF];
+        fetch_frags(0, pf);
         u16x8_t rows[TH + 1];
 #pragma unroll
         for (int i = 0; i <= TH; ++i) rows[i] = fetch_row(wy0 + i);
         __syncthreads();  // ring zeroed
 #pragma unroll
         for (int i = 0; i <= TH; ++i) store_row(wy0 + i, rows[i]);
+        store_frags(pf);
     }
-    store_frags(0, pf);
     __syncthreads();
     for (int i = 0; i <= TH; ++i) row_sq(wy0 + i);
     u16x8_t cpre = fetch_row(wy0 + TH + 1);
-    if (nby > 1) fetch_frags(1, pf);
 
     // Window rows of this wave: rho = wave, wave + 4; halves mu = 0, 1.
     float16v_t S[4];
@@ -2105,7 +2107,7 @@ __device__ __forceinline__ void wgemm_tile(WgLds<NBP> &L, const Level &v, int re
                 // Exact mode: FP32 products, 2 features per step; at step t lane
                 // (template or window n, h) takes feature h 2 NBP + t of the block:
                 // cell row h, cell t / NBP, bin t % NBP.
-                const float *af = reinterpret_cast<const float *>(bst[by & 1]);
+                const float *af = reinterpret_cast<const float *>(bst[0]);
 #pragma unroll 1
                 for (int bx = 0; bx < kStripMaxBX; ++bx) {
 #pragma unroll
@@ -2125,7 +2127,7 @@ __device__ __forceinline__ void wgemm_tile(WgLds<NBP> &L, const Level &v, int re
                     }
                 }
             } else {
-            const half8_t *bf = reinterpret_cast<const half8_t *>(bst[by & 1]);
+            const half8_t *bf = reinterpret_cast<const half8_t *>(bst[0]);
 #pragma unroll 1
             for (int bx = 0; bx < kStripMaxBX; ++bx) {
                 half8_t bh[KS], bl[KS];
@@ -2134,75 +2136,59 @@ __device__ __forceinline__ void wgemm_tile(WgLds<NBP> &L, const Level &v, int re
                     bh[s2] = bf[((bx * KS + s2) * 2 + 0) * 64 + lane];
                     bl[s2] = bf[((bx * KS + s2) * 2 + 1) * 64 + lane];
                 }
-                half8_t wf[4][KS];
+                // The four window groups q in two rounds of two accumulators
+                // each (registers for three workgroups per CU); per q the
+                // products still go hi s2 = 0, 1, then lo, and S[q] takes its
+                // terms in bx order.
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int rho = NARROW ? wave + 4 * q : wave + 4 * (q >> 1), mu = NARROW ? 0 : q & 1;
+                for (int g = 0; g < 2; ++g) {
+                    half8_t wf[2][KS];
+                    float iv[2];
 #pragma unroll
-                    for (int s2 = 0; s2 < KS; ++s2) {
-                        const int kf = 16 * s2 + 8 * h;
-                        const int w = kf / (2 * NBP);
-                        wf[q][s2] = *reinterpret_cast<const half8_t *>(
-                            &ring[(wy0 + by + rho + w) % SLOTS][(32 * mu + n + bx) * NBP + kf % (2 * NBP)]);
+                    for (int h2 = 0; h2 < 2; ++h2) {
+                        const int q = 2 * g + h2;
+                        const int rho = NARROW ? wave + 4 * q : wave + 4 * (q >> 1), mu = NARROW ? 0 : q & 1;
+#pragma unroll
+                        for (int s2 = 0; s2 < KS; ++s2) {
+                            const int kf = 16 * s2 + 8 * h;
+                            const int w = kf / (2 * NBP);
+                            wf[h2][s2] = *reinterpret_cast<const half8_t *>(
+                                &ring[(wy0 + by + rho + w) % SLOTS][(32 * mu + n + bx) * NBP + kf % (2 * NBP)]);
+                        }
+                        iv[h2] = invb[(by + rho) % TH][32 * mu + n + bx];
                     }
+                    float16v_t d[2];
+#pragma unroll
+                    for (int h2 = 0; h2 < 2; ++h2)
+#pragma unroll
+                        for (int r = 0; r < 16; ++r) d[h2][r] = 0.f;
+#pragma unroll
+                    for (int s2 = 0; s2 < KS; ++s2)
+#pragma unroll
+                        for (int h2 = 0; h2 < 2; ++h2)
+                            d[h2] = __builtin_amdgcn_mfma_f32_32x32x16_f16(bh[s2], wf[h2][s2], d[h2], 0, 0, 0);
+#pragma unroll
+                    for (int s2 = 0; s2 < KS; ++s2)
+#pragma unroll
+                        for (int h2 = 0; h2 < 2; ++h2)
+                            d[h2] = __builtin_amdgcn_mfma_f32_32x32x16_f16(bl[s2], wf[h2][s2] * (_Float16)0x1p-11f,
+                                                                          d[h2], 0, 0, 0);
+#pragma unroll
+                    for (int h2 = 0; h2 < 2; ++h2)
+#pragma unroll
+                        for (int r = 0; r < 16; ++r) S[2 * g + h2][r] = fmaf(d[h2][r], iv[h2], S[2 * g + h2][r]);
                 }
-                float iv[4];
-#pragma unroll
-                for (int q = 0; q < 4; ++q)
-                    iv[q] = NARROW ? invb[(by + wave + 4 * q) % TH][n + bx]
-                                   : invb[(by + wave + 4 * (q >> 1)) % TH][32 * (q & 1) + n + bx];
-                float16v_t d[4];
-#pragma unroll
-                for (int q = 0; q < 4; ++q)
-#pragma unroll
-                    for (int r = 0; r < 16; ++r) d[q][r] = 0.f;
-                // Left alone, the compiler issues all 16 products and then the 64
-                // scalings. The scheduling barriers make it issue the products
-                // of q = 0, 1 first, then alternate those of q = 2, 3 with the
-                // scalings of q = 0, 1 (group masks: 0x008 matrix instructions,
-                // 0x002 other vector ALU), so both units work at once. Each
-                // S[q][r] still takes its terms in bx order.
-#pragma unroll
-                for (int s2 = 0; s2 < KS; ++s2)
-#pragma unroll
-                    for (int q = 0; q < 2; ++q) d[q] = __builtin_amdgcn_mfma_f32_32x32x16_f16(bh[s2], wf[q][s2], d[q], 0, 0, 0);
-#pragma unroll
-                for (int s2 = 0; s2 < KS; ++s2)
-#pragma unroll
-                    for (int q = 0; q < 2; ++q) d[q] = __builtin_amdgcn_mfma_f32_32x32x16_f16(bl[s2], wf[q][s2] * (_Float16)0x1p-11f, d[q], 0, 0, 0);
-                __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-                for (int s2 = 0; s2 < KS; ++s2)
-#pragma unroll
-                    for (int q = 2; q < 4; ++q) d[q] = __builtin_amdgcn_mfma_f32_32x32x16_f16(bh[s2], wf[q][s2], d[q], 0, 0, 0);
-#pragma unroll
-                for (int s2 = 0; s2 < KS; ++s2)
-#pragma unroll
-                    for (int q = 2; q < 4; ++q) d[q] = __builtin_amdgcn_mfma_f32_32x32x16_f16(bl[s2], wf[q][s2] * (_Float16)0x1p-11f, d[q], 0, 0, 0);
-#pragma unroll
-                for (int q = 0; q < 2; ++q)
-#pragma unroll
-                    for (int r = 0; r < 16; ++r) S[q][r] = fmaf(d[q][r], iv[q], S[q][r]);
-#pragma unroll
-                for (int i = 0; i < 4 * KS; ++i) {
-                    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-                    __builtin_amdgcn_sched_group_barrier(0x002, 32 / (4 * KS), 0);
-                }
-                __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-                for (int q = 2; q < 4; ++q)
-#pragma unroll
-                    for (int r = 0; r < 16; ++r) S[q][r] = fmaf(d[q][r], iv[q], S[q][r]);
             }
             }
             __syncthreads();  // done with this by's ring slot, fragments and norms
             if (by + 1 < nby) {
-                store_frags((by + 1) & 1, pf);
+                u32x4 pf[PF];
+                fetch_frags(by + 1, pf);
                 store_row(wy0 + by + TH + 1, cpre);
+                store_frags(pf);
                 __syncthreads();
                 row_sq(wy0 + by + TH + 1);
                 cpre = fetch_row(wy0 + by + TH + 2);
-                if (by + 2 < nby) fetch_frags(by + 2, pf);
             }
         }
     };
@@ -2231,7 +2217,7 @@ __device__ __forceinline__ void wgemm_tile(WgLds<NBP> &L, const Level &v, int re
 }
 
 template <int NBP>
-__global__ __launch_bounds__(256, NBP == 8 ? 2 : 1) void k_score_wgemm(const Level *__restrict__ lv,
+__global__ __launch_bounds__(256, NBP == 8 ? 3 : 1) void k_score_wgemm(const Level *__restrict__ lv,
                                                                       const int32_t *__restrict__ first,
                                                                       int n_levels, WgArgs a,
                                                                       const uint8_t *__restrict__ ws,
