@@ -304,13 +304,16 @@ __global__ __launch_bounds__(64) void k_int_reduce(const Level *__restrict__ lv,
     const int tx = t % v.tiles_x, ty = t / v.tiles_x;
     uint8_t *tb = reinterpret_cast<uint8_t *>(red_smem);
     const int nw = (nb + 3) >> 2;  // dwords per lane and histogram
+    // Each histogram has one more slot, never read: pixels with no bin, and
+    // rows or columns outside the level, add there, so that every add is
+    // unconditional (no branch around each atomic).
     uint32_t *colh = red_smem + kTile * kRedStride / 4;
-    uint32_t *rowh = colh + nw * 64;
+    uint32_t *rowh = colh + (nw + 1) * 64;
     for (int n = 0; n < nw; ++n) {
         colh[n * 64 + lane] = 0u;
         rowh[n * 64 + lane] = 0u;
     }
-    auto slot = [](int b) { return (b >> 2) * 64; };
+    auto slot = [nb, nw](int b) { return (b < nb ? (b >> 2) : nw) * 64; };
     auto one = [](int b) { return 1u << (8 * (b & 3)); };
     auto count = [&](const uint32_t *h, int b, int ln) { return (h[slot(b) + ln] >> (8 * (b & 3))) & 255u; };
     {
@@ -344,8 +347,7 @@ __global__ __launch_bounds__(64) void k_int_reduce(const Level *__restrict__ lv,
 #pragma unroll
             for (int i = 0; i < 16; ++i) bb[i] = r0 + i < nrows ? tb[(r0 + i) * kRedStride + lane] : kNoBin;
 #pragma unroll
-            for (int i = 0; i < 16; ++i)
-                if (bb[i] < nb) atomicAdd(&colh[slot(bb[i]) + lane], one(bb[i]));
+            for (int i = 0; i < 16; ++i) atomicAdd(&colh[slot(bb[i]) + lane], one(bb[i]));
         }
     }
     // Row counts: lane = row; its 64 bins are read first, 16 at a time.
@@ -359,8 +361,8 @@ __global__ __launch_bounds__(64) void k_int_reduce(const Level *__restrict__ lv,
             for (int k = 0; k < 4; ++k)
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
-                    const int b = (int)((d[k] >> (8 * e)) & 255u);
-                    if (4 * (k0 + k) + e < ncols && b < nb) atomicAdd(&rowh[slot(b) + lane], one(b));
+                    const int b = 4 * (k0 + k) + e < ncols ? (int)((d[k] >> (8 * e)) & 255u) : kNoBin;
+                    atomicAdd(&rowh[slot(b) + lane], one(b));
                 }
         }
     }
@@ -795,22 +797,24 @@ __global__ __launch_bounds__(64) void k_soft_reduce(const Level *__restrict__ lv
     const int tx = t % v.tiles_x, ty = t / v.tiles_x;
     uint8_t *tb = reinterpret_cast<uint8_t *>(sred_smem);
     const int nw = (nb + 1) >> 1;  // dwords per lane and histogram
+    // One more slot per histogram, never read, takes the votes of entries
+    // with no bin and of rows or columns outside the level, so every add is
+    // unconditional.
     uint32_t *colh = sred_smem + kTile * kStride / 4;
-    uint32_t *rowh = colh + nw * 64;
+    uint32_t *rowh = colh + (nw + 1) * 64;
     for (int k = 0; k < nw; ++k) {
         colh[k * 64 + lane] = 0u;
         rowh[k * 64 + lane] = 0u;
     }
-    auto slot = [](uint32_t b) { return (int)(b >> 1) * 64; };
+    auto slot = [nb, nw](uint32_t b) { return (b < (uint32_t)nb ? (int)(b >> 1) : nw) * 64; };
     auto shift = [](uint32_t b) { return 16u * (b & 1u); };
-    // Adds the votes of entry e to the histogram slots of lane ln.
+    // Adds the votes of entry e to the histogram slots of lane ln (an entry
+    // with no bin, b0 = 255, sends both to the spare slot).
     auto vote = [&](uint32_t *h, uint32_t e, int ln) {
         const uint32_t b0 = e & 255u, w1 = e >> 8;
-        if (b0 < (uint32_t)nb) {
-            const uint32_t b1 = b0 + 1 == (uint32_t)nb ? 0u : b0 + 1;
-            atomicAdd(&h[slot(b0) + ln], (Q - w1) << shift(b0));
-            atomicAdd(&h[slot(b1) + ln], w1 << shift(b1));
-        }
+        const uint32_t b1 = b0 + 1 == (uint32_t)nb ? 0u : b0 + 1;
+        atomicAdd(&h[slot(b0) + ln], (Q - w1) << shift(b0));
+        atomicAdd(&h[slot(b1) + ln], w1 << shift(b1));
     };
     {
         typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
@@ -842,8 +846,7 @@ __global__ __launch_bounds__(64) void k_soft_reduce(const Level *__restrict__ lv
 #pragma unroll
             for (int j = 0; j < 16; ++j) e[j] = cp[(r0 + j) * (kStride / 2)];
 #pragma unroll
-            for (int j = 0; j < 16; ++j)
-                if (r0 + j < nrows) vote(colh, e[j], lane);
+            for (int j = 0; j < 16; ++j) vote(colh, r0 + j < nrows ? e[j] : (uint32_t)kNoBin, lane);
         }
     }
     // Row totals: lane = row; two entries per dword.
@@ -856,8 +859,8 @@ __global__ __launch_bounds__(64) void k_soft_reduce(const Level *__restrict__ lv
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
                 const int c = 2 * (k0 + j);
-                if (c < ncols) vote(rowh, d[j] & 0xFFFFu, lane);
-                if (c + 1 < ncols) vote(rowh, d[j] >> 16, lane);
+                vote(rowh, c < ncols ? d[j] & 0xFFFFu : (uint32_t)kNoBin, lane);
+                vote(rowh, c + 1 < ncols ? d[j] >> 16 : (uint32_t)kNoBin, lane);
             }
         }
     }
@@ -2332,7 +2335,7 @@ hipError_t launch_soft_integral(const PlanDev &p, const uint8_t *bins, uint8_t *
                                 bool cells, hipStream_t stream)
 {
     if (p.total[KB_SSEG] == 0) return hipSuccess;
-    const size_t lds = (size_t)kTile * (2 * kTile + 4) + (size_t)((p.n_bins + 1) / 2) * 64 * 4 * 2;
+    const size_t lds = (size_t)kTile * (2 * kTile + 4) + (size_t)((p.n_bins + 1) / 2 + 1) * 64 * 4 * 2;  // + spare slots
     hipLaunchKernelGGL(k_soft_reduce, dim3((unsigned)p.total[KB_SSEG]), dim3(64), lds, stream, p.levels,
                        first_of(p, KB_SSEG), p.n_levels, p.n_bins, bins, ws);
     hipError_t e = hipGetLastError();
@@ -2355,7 +2358,7 @@ hipError_t launch_int_reduce(const PlanDev &p, const uint8_t *bins, uint8_t *ws,
 {
     const int64_t tiles = p.total[KB_ITILE];
     if (tiles == 0) return hipSuccess;
-    const size_t lds = (size_t)kTile * 68 + (size_t)((p.n_bins + 3) / 4) * 64 * 4 * 2;
+    const size_t lds = (size_t)kTile * 68 + (size_t)((p.n_bins + 3) / 4 + 1) * 64 * 4 * 2;  // + spare slots
     hipLaunchKernelGGL(k_int_reduce, dim3((unsigned)tiles), dim3(64), lds, stream, p.levels,
                        first_of(p, KB_ITILE), p.n_levels, p.n_bins, bins, ws);
     return hipGetLastError();
