@@ -1481,10 +1481,13 @@ __global__ __launch_bounds__(64 * kStripMaxBX) void k_score_prep(StripArgs a, co
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
             float val = 0.f;
-            if (j < Sh::K32 || i < 4) {
+            if (j < Sh::K32 || i < 4) {  // compile-time
                 const int k = j < Sh::K32 ? 32 * j + 8 * q + i : 32 * Sh::K32 + 4 * q + i;
                 const int idx = strip_weight_index(k, NBP, a.nb, a.nby, n, bx);
-                if (idx >= 0) val = tk[idx];
+                // Padding slots load weight 0 and drop it: no branch per load,
+                // so every load of the template is in flight at once.
+                const float w = tk[idx >= 0 ? idx : 0];
+                val = idx >= 0 ? w : 0.f;
             }
             vals[j][i] = val;
             mx = fmaxf(mx, fabsf(val));
@@ -1518,7 +1521,8 @@ __global__ __launch_bounds__(64 * kStripMaxBX) void k_score_prep(StripArgs a, co
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
                 const int idx = strip_weight_index(q * NBP + 4 * i + c, NBP, a.nb, a.nby, n, bx);
-                f[c] = idx >= 0 ? tk[idx] : 0.f;
+                const float w = tk[idx >= 0 ? idx : 0];
+                f[c] = idx >= 0 ? w : 0.f;
             }
             frag[(int64_t)i * 64] = __builtin_bit_cast(u32x4, f);
         }
