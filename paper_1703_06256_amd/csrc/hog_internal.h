@@ -52,7 +52,7 @@ enum {
     KB_BINMAP = 0,  // waves
     KB_ITILE,       // integral tiles
     KB_CSCAN,       // threads of the column-prefix scan: 64 tiles_x * n_bins
-    KB_ESCAN,       // threads of the row-carry scan: h * n_bins
+    KB_ESCAN,       // threads of the row-carry scan: 64 tiles_y * n_bins
     KB_PSCAN,       // waves of the tile-total prefix: n_bins
     KB_CELL,        // threads of the cell kernel: cells
     KB_STILE,       // workgroups of the scorer: window tiles

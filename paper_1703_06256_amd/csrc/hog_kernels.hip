@@ -432,66 +432,71 @@ __global__ __launch_bounds__(256) void k_int_scan(const Level *__restrict__ lv,
                                                   int nb, ScanRanges r, uint8_t *__restrict__ ws)
 {
     const int blk = (int)blockIdx.x;
+    const int lane = threadIdx.x & 63;
+    // Rows and columns: each (level, bin) holds a whole number of waves (its
+    // items are the tile-rounded rows hp, or columns wp, both multiples of
+    // 64), so a wave's level, bin and tile counts are uniform: found from its
+    // first item, with the loads and stores through buffer descriptors and
+    // the tile in the scalar offset. Rows past the level's height compute
+    // carries nobody reads.
     if (blk < r.rows_blocks) {
-        const int g = blk * 256 + (int)threadIdx.x;
-        if (g >= first_e[n_levels]) return;
-        const int l = find_level(first_e, n_levels, g);
+        const int g0 = __builtin_amdgcn_readfirstlane(blk * 256 + (int)(threadIdx.x & ~63u));
+        if (g0 >= first_e[n_levels]) return;
+        const int l = find_level(first_e, n_levels, g0);
         const Level &v = lv[l];
-        const int rel = g - first_e[l];
-        const int n = rel / v.h, y = rel - n * v.h;
-        const int64_t hp = (int64_t)kTile * v.tiles_y, stride = (int64_t)nb * hp;
-        const uint8_t *rt = ws + v.ws_rowtot + n * hp + y;
-        uint16_t *e = reinterpret_cast<uint16_t *>(ws + v.ws_e) + n * hp + y;
+        // Byte offsets as unsigned 32-bit values (a level's carries stay below 2^32 bytes).
+        const uint32_t hp = kTile * v.tiles_y, stride = (uint32_t)nb * hp;
+        const uint32_t vo = (uint32_t)(g0 - first_e[l] + lane);  // n * hp + y
+        const __amdgpu_buffer_rsrc_t rts = buffer_rsrc(ws + v.ws_rowtot, (uint32_t)v.tiles_x * stride);
+        const __amdgpu_buffer_rsrc_t es = buffer_rsrc(ws + v.ws_e, 2u * (uint32_t)v.tiles_x * stride);
         uint32_t acc = 0;
         int tx = 0;
         for (; tx + 8 <= v.tiles_x; tx += 8) {
             uint32_t c[8];
 #pragma unroll
-            for (int i = 0; i < 8; ++i) c[i] = rt[(tx + i) * stride];
+            for (int i = 0; i < 8; ++i) c[i] = __builtin_amdgcn_raw_buffer_load_b8(rts, (int)vo, (int)((uint32_t)(tx + i) * stride), 0);
 #pragma unroll
             for (int i = 0; i < 8; ++i) {
-                e[(tx + i) * stride] = (uint16_t)acc;
+                __builtin_amdgcn_raw_buffer_store_b16((uint16_t)acc, es, (int)(2u * vo), (int)(2u * (uint32_t)(tx + i) * stride), 0);
                 acc += c[i];
             }
         }
         for (; tx < v.tiles_x; ++tx) {
-            const uint32_t c = rt[tx * stride];
-            e[tx * stride] = (uint16_t)acc;
+            const uint32_t c = __builtin_amdgcn_raw_buffer_load_b8(rts, (int)vo, (int)((uint32_t)tx * stride), 0);
+            __builtin_amdgcn_raw_buffer_store_b16((uint16_t)acc, es, (int)(2u * vo), (int)(2u * (uint32_t)tx * stride), 0);
             acc += c;
         }
         return;
     }
     if (blk < r.rows_blocks + r.cols_blocks) {
-        const int g = (blk - r.rows_blocks) * 256 + (int)threadIdx.x;
-        if (g >= first_c[n_levels]) return;
-        const int l = find_level(first_c, n_levels, g);
+        const int g0 = __builtin_amdgcn_readfirstlane((blk - r.rows_blocks) * 256 + (int)(threadIdx.x & ~63u));
+        if (g0 >= first_c[n_levels]) return;
+        const int l = find_level(first_c, n_levels, g0);
         const Level &v = lv[l];
-        const int rel = g - first_c[l];
-        const int64_t wp = (int64_t)kTile * v.tiles_x, stride = (int64_t)nb * wp;
-        const int n = rel / (int)wp, x = rel - n * (int)wp;
-        const uint8_t *ct = ws + v.ws_coltot + n * wp + x;
-        uint16_t *cs = reinterpret_cast<uint16_t *>(ws + v.ws_cs) + n * wp + x;
+        const uint32_t wp = kTile * v.tiles_x, stride = (uint32_t)nb * wp;
+        const uint32_t vo = (uint32_t)(g0 - first_c[l] + lane);  // n * wp + x
+        const __amdgpu_buffer_rsrc_t cts = buffer_rsrc(ws + v.ws_coltot, (uint32_t)v.tiles_y * stride);
+        const __amdgpu_buffer_rsrc_t css = buffer_rsrc(ws + v.ws_cs, 2u * (uint32_t)v.tiles_y * stride);
         uint32_t acc = 0;
         int ty = 0;
         for (; ty + 8 <= v.tiles_y; ty += 8) {
             uint32_t c[8];
 #pragma unroll
-            for (int i = 0; i < 8; ++i) c[i] = ct[(ty + i) * stride];
+            for (int i = 0; i < 8; ++i) c[i] = __builtin_amdgcn_raw_buffer_load_b8(cts, (int)vo, (int)((uint32_t)(ty + i) * stride), 0);
 #pragma unroll
             for (int i = 0; i < 8; ++i) {
-                cs[(ty + i) * stride] = (uint16_t)acc;
+                __builtin_amdgcn_raw_buffer_store_b16((uint16_t)acc, css, (int)(2u * vo), (int)(2u * (uint32_t)(ty + i) * stride), 0);
                 acc += c[i];
             }
         }
         for (; ty < v.tiles_y; ++ty) {
-            const uint32_t c = ct[ty * stride];
-            cs[ty * stride] = (uint16_t)acc;
+            const uint32_t c = __builtin_amdgcn_raw_buffer_load_b8(cts, (int)vo, (int)((uint32_t)ty * stride), 0);
+            __builtin_amdgcn_raw_buffer_store_b16((uint16_t)acc, css, (int)(2u * vo), (int)(2u * (uint32_t)ty * stride), 0);
             acc += c;
         }
         return;
     }
     // Tiles: one wave per (level, n); lanes over tile columns in chunks of 64.
-    const int lane = threadIdx.x & 63;
     const int g = (blk - r.rows_blocks - r.cols_blocks) * 4 + wave_id_in_block();
     if (g >= first_p[n_levels]) return;
     const int l = find_level(first_p, n_levels, g);
