@@ -696,7 +696,7 @@ static hog_status create_plan(const hog_plan_desc *descs, int n_img, bool batch,
                                     ? (int64_t)(v.cells_x - 1) * (v.cells_y - 1)
                                     : 0;
         items[hogk::KB_SSEG] = soft ? (int64_t)v.tiles_x * v.tiles_y : 0;
-        items[hogk::KB_SSCAN] = soft ? (int64_t)nb * v.h + (int64_t)nb * hogk::kTile * v.tiles_x : 0;
+        items[hogk::KB_SSCAN] = soft ? (int64_t)nb * hogk::kTile * v.tiles_y + (int64_t)nb * hogk::kTile * v.tiles_x : 0;
         items[hogk::KB_SEMIT] = soft ? (int64_t)v.tiles_x * v.tiles_y * ((nb + 1) / 2) : 0;
         for (int k = 0; k < hogk::KB_COUNT; ++k) {
             first[(size_t)k * (L + 1) + l] = (int32_t)totals[k];

@@ -58,7 +58,7 @@ enum {
     KB_STILE,       // workgroups of the scorer: window tiles
     KB_BLOCK,       // threads of the block-feature kernel: blocks
     KB_SSEG,        // soft votes: waves of the tile reduce, one per integral tile
-    KB_SSCAN,       // soft votes: threads of the prefixes, one per (bin, row) then per (bin, column)
+    KB_SSCAN,       // soft votes: threads of the prefixes, one per (bin, tile-rounded row) then per (bin, column)
     KB_SEMIT,       // soft votes: waves of the plane writer, one per (integral tile, pair of bins)
     KB_COUNT
 };

@@ -889,42 +889,43 @@ __global__ __launch_bounds__(256) void k_soft_scan(const Level *__restrict__ lv,
                                                    const int32_t *__restrict__ first, int n_levels,
                                                    int nb, uint8_t *__restrict__ ws)
 {
-    const int g = (int)(blockIdx.x * 256 + threadIdx.x);
-    if (g >= first[n_levels]) return;
-    const int l = find_level(first, n_levels, g);
+    // Row jobs are the tile-rounded rows hp per bin and column jobs the
+    // columns wp per bin, both multiples of 64, so a wave's level, kind and
+    // bin are uniform: found from its first item. Each (kind, bin) array goes
+    // through one buffer descriptor (below 2^32 bytes), the lane's row or
+    // column in the vector offset and the tile in the scalar one. Rows past
+    // the level's height compute sums nobody reads.
+    const int g0 = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * 256 + (threadIdx.x & ~63u)));
+    if (g0 >= first[n_levels]) return;
+    const int lane = threadIdx.x & 63;
+    const int l = find_level(first, n_levels, g0);
     const Level &v = lv[l];
-    int rel = g - first[l];
-    const int64_t hp = (int64_t)kTile * v.tiles_y, wp = (int64_t)kTile * v.tiles_x;
-    uint32_t *t;
-    int64_t stride;
-    int count;
-    if (rel < nb * v.h) {  // row job: rel = n * h + y
-        const int n = rel / v.h, y = rel % v.h;
-        t = reinterpret_cast<uint32_t *>(ws + v.ws_stot) + (int64_t)n * v.tiles_x * hp + y;
-        stride = hp;
-        count = v.tiles_x;
-    } else {  // column job: rel = n * wp + x
-        rel -= nb * v.h;
-        const int n = rel / (int)wp, x = rel % (int)wp;
-        t = reinterpret_cast<uint32_t *>(ws + v.ws_scol) + (int64_t)n * v.tiles_y * wp + x;
-        stride = wp;
-        count = v.tiles_y;
-    }
+    const uint32_t hp = kTile * v.tiles_y, wp = kTile * v.tiles_x;
+    uint32_t rel0 = (uint32_t)(g0 - first[l]);
+    const bool rows = rel0 < (uint32_t)nb * hp;
+    if (!rows) rel0 -= (uint32_t)nb * hp;
+    const uint32_t span = rows ? hp : wp;                  // items per bin
+    const uint32_t n = rel0 / span;                        // the wave's bin
+    const uint32_t count = rows ? v.tiles_x : v.tiles_y;   // tiles along the job
+    const uint32_t plane = count * span * 4u;              // bytes per bin
+    const __amdgpu_buffer_rsrc_t t = buffer_rsrc(ws + (rows ? v.ws_stot : v.ws_scol) + (int64_t)n * plane, plane);
+    const int vo = (int)(4u * (rel0 - n * span + lane));
+    const uint32_t step = 4u * span;
     uint32_t acc = 0;
-    int k = 0;
+    uint32_t k = 0;
     for (; k + 8 <= count; k += 8) {
         uint32_t c[8];
 #pragma unroll
-        for (int i = 0; i < 8; ++i) c[i] = t[(k + i) * stride];
+        for (int i = 0; i < 8; ++i) c[i] = __builtin_amdgcn_raw_buffer_load_b32(t, vo, (int)((k + i) * step), 0);
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
-            t[(k + i) * stride] = acc;
+            __builtin_amdgcn_raw_buffer_store_b32(acc, t, vo, (int)((k + i) * step), 0);
             acc += c[i];
         }
     }
     for (; k < count; ++k) {
-        const uint32_t c = t[k * stride];
-        t[k * stride] = acc;
+        const uint32_t c = __builtin_amdgcn_raw_buffer_load_b32(t, vo, (int)(k * step), 0);
+        __builtin_amdgcn_raw_buffer_store_b32(acc, t, vo, (int)(k * step), 0);
         acc += c;
     }
 }
