@@ -502,8 +502,13 @@ __global__ __launch_bounds__(256) void k_int_scan(const Level *__restrict__ lv,
     const int l = find_level(first_p, n_levels, g);
     const Level &v = lv[l];
     const int n = g - first_p[l];
-    const uint32_t *tt = reinterpret_cast<const uint32_t *>(ws + v.ws_tiletot) + n;
-    uint32_t *P = reinterpret_cast<uint32_t *>(ws + v.ws_p) + n;
+    // Tile totals in and prefixes out through buffer descriptors: lanes past
+    // the level's tile columns take an offset beyond the array, so their
+    // loads read 0 and their stores are dropped (no branch per lane).
+    const uint32_t tbytes = (uint32_t)(v.tiles_x * v.tiles_y * nb) * 4u;
+    const __amdgpu_buffer_rsrc_t tts = buffer_rsrc(ws + v.ws_tiletot, tbytes);
+    const __amdgpu_buffer_rsrc_t ps = buffer_rsrc(ws + v.ws_p, tbytes);
+    const int row_bytes = v.tiles_x * nb * 4;
     constexpr int kMaxChunks = 512 / 64;  // tiles_x <= 512 (width <= 32767)
     constexpr int kRows = 8;              // tile rows whose totals are loaded together
     uint32_t above[kMaxChunks];           // P of the current tile row, lane's columns
@@ -517,15 +522,17 @@ __global__ __launch_bounds__(256) void k_int_scan(const Level *__restrict__ lv,
         for (int c = 0; c < kMaxChunks; ++c) {
             if (64 * c < v.tiles_x) {  // wave-uniform
                 const int tx = 64 * c + lane;
-                const bool on = tx < v.tiles_x;
+                const int vo = tx < v.tiles_x ? (tx * nb + n) * 4 : (int)0x80000000u;
                 uint32_t t[kRows];
 #pragma unroll
                 for (int i = 0; i < kRows; ++i)
-                    t[i] = (on && ty0 + i < v.tiles_y) ? tt[((int64_t)(ty0 + i) * v.tiles_x + tx) * nb] : 0u;
+                    t[i] = ty0 + i < v.tiles_y  // wave-uniform
+                               ? __builtin_amdgcn_raw_buffer_load_b32(tts, vo, (ty0 + i) * row_bytes, 0)
+                               : 0u;
 #pragma unroll
                 for (int i = 0; i < kRows; ++i) {
                     if (ty0 + i < v.tiles_y) {  // wave-uniform
-                        if (on) P[((int64_t)(ty0 + i) * v.tiles_x + tx) * nb] = above[c];
+                        __builtin_amdgcn_raw_buffer_store_b32(above[c], ps, vo, (ty0 + i) * row_bytes, 0);
                         const uint32_t incl = wave_incl_scan(t[i]);
                         above[c] += carry[i] + incl - t[i];  // plus this row's tiles left of tx
                         carry[i] += (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
