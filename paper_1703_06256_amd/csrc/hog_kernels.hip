@@ -229,14 +229,17 @@ __global__ __launch_bounds__(1024) void k_bin_map(const Level *__restrict__ lv,
             const bool ok = col_interior && y >= 1 && y <= H - 2 && best > 0;
             if constexpr (SOFT) {
                 const uint16_t e = __builtin_amdgcn_raw_buffer_load_b16(
-                    trsrc, ok ? 2 * ((bdy + 255) * 511 + (bdx + 255)) : 0, 0, 0);
+                    trsrc, (2 * ((bdy + 255) * 511 + (bdx + 255))) & -(int)ok, 0, 0);
                 b[i] = ok ? e : (uint16_t)kNoBin;
             } else if constexpr (GLUT) {
-                const uint8_t e = __builtin_amdgcn_raw_buffer_load_b8(trsrc, ok ? (bdy + 255) * 511 + (bdx + 255) : 0, 0, 0);
+                const uint8_t e = __builtin_amdgcn_raw_buffer_load_b8(trsrc, ((bdy + 255) * 511 + (bdx + 255)) & -(int)ok, 0, 0);
                 b[i] = ok ? e : (uint8_t)kNoBin;
             } else {
                 const int ady = bdy < 0 ? -bdy : bdy;
-                const uint32_t e = lut[ok ? ady * 511 + (bdx + 255) : 0];
+                // Index 0 for lanes with no bin, by a mask rather than a
+                // select the compiler turns into a branch per row (whose
+                // exec masks then spill).
+                const uint32_t e = lut[(ady * 511 + (bdx + 255)) & -(int)ok];
                 const uint32_t half_bin = e & 63u;
                 const uint32_t bin = bdy < 0 ? (uint32_t)(nb - 1) - half_bin + (e >> 6) : half_bin;
                 b[i] = ok ? (uint8_t)bin : (uint8_t)kNoBin;
@@ -244,15 +247,24 @@ __global__ __launch_bounds__(1024) void k_bin_map(const Level *__restrict__ lv,
         }
         const bool writer = lane >= 1 && lane <= kBinCols && col_ok;
         const __amdgpu_buffer_rsrc_t bsrc = buffer_rsrc(bins + v.bins_off, (uint32_t)(v.bins_pitch * H));
-        const int xb = x * (int)sizeof(bin_t);
+        // Lanes that store nothing take an offset beyond the buffer, so their
+        // stores are dropped without a branch; rows past the level are left
+        // out by a scalar test, only in the last item of a column.
+        const int xw = writer ? x * (int)sizeof(bin_t) : (int)0x80000000u;
+        auto store = [&](int i) {
+            if constexpr (SOFT)
+                __builtin_amdgcn_raw_buffer_store_b16(b[i], bsrc, xw, (y0 + i) * (int)v.bins_pitch, 0);
+            else
+                __builtin_amdgcn_raw_buffer_store_b8(b[i], bsrc, xw, (y0 + i) * (int)v.bins_pitch, 0);
+        };
+        if (y0 + kBinRows <= H) {
 #pragma unroll
-        for (int i = 0; i < kBinRows; ++i)
-            if (writer && y0 + i < H) {
-                if constexpr (SOFT)
-                    __builtin_amdgcn_raw_buffer_store_b16(b[i], bsrc, xb, (y0 + i) * (int)v.bins_pitch, 0);
-                else
-                    __builtin_amdgcn_raw_buffer_store_b8(b[i], bsrc, xb, (y0 + i) * (int)v.bins_pitch, 0);
-            }
+            for (int i = 0; i < kBinRows; ++i) store(i);
+        } else {
+#pragma unroll
+            for (int i = 0; i < kBinRows; ++i)
+                if (y0 + i < H) store(i);  // wave-uniform
+        }
     }
 }
 
