@@ -302,7 +302,7 @@ def main():
     stream = torch.cuda.current_stream()
 
     # Tile shapes picked by timing candidates on these buffers.
-    tiles = hog.autotune(plan, lut, img_t, tmpl_t, bias_t, buf, stream, reps=3)
+    tiles = hog.autotune(plan, lut, img_t, tmpl_t, bias_t, buf, stream, reps=10)
     if args.lut != "auto":
         hog.set_plan_tiles(plan, tiles.bin_chunk, tiles.score_rows, tiles.level_groups,
                            lut_global=1 if args.lut == "l2" else 0)
@@ -510,7 +510,7 @@ def main():
                  for j in range(nb_img)]
         bimg_t = torch.from_numpy(hog.pack_images(bplan, bimgs)).cuda()
         bbuf = hog.Buffers(bplan)
-        btiles = hog.autotune(bplan, lut, bimg_t, tmpl_t, bias_t, bbuf, stream, reps=3)
+        btiles = hog.autotune(bplan, lut, bimg_t, tmpl_t, bias_t, bbuf, stream, reps=10)
         bgraph = hog.Graph(bplan, lut, bimg_t, tmpl_t, bias_t, bbuf)
         for _ in range(5):
             bgraph.launch(stream)
