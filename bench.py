@@ -537,6 +537,30 @@ def main():
                    "level_groups": btiles.level_groups})
         bgraph.destroy()
         del bbuf, bimg_t
+    if not batch:
+        # The same steps with each buffer set's hog_run captured once into a
+        # HIP graph and replayed over the same ring: what a caller that can
+        # capture saves in launch overhead. `value` stays the plain per-call
+        # rate above.
+        pgraphs = [hog.Graph(plan, lut, im, tmpl_t, bias_t, b) for im, b in sets]
+        for i in range(max(args.warmup, 3)):
+            pgraphs[i % n_sets].launch(stream)
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for i in range(args.steps):
+            pgraphs[i % n_sets].launch(stream)
+        b.record(stream)
+        torch.cuda.synchronize()
+        gms = a.elapsed_time(b) / args.steps
+        extra["per_image_graph"] = dict(
+            launch="hog_run captured into one HIP graph per buffer set", ms_per_step=round(gms, 5),
+            mpixel_per_s=round(sz.total_pixels / (gms * 1e3), 1), buffer_sets=n_sets,
+            speedup_vs_calls=round(ms_per_step / gms, 3))
+        for g in pgraphs:
+            g.destroy()
+        del pgraphs
 
     # This GPU's plain 1 GiB copy (read + write) and fill (write only) rates,
     # timed the same way on the same stream: what a bandwidth-bound kernel
