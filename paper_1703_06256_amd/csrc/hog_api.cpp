@@ -918,10 +918,11 @@ extern "C" hog_status hog_bin_map(const hog_plan *plan, const hog_lut *lut, cons
     return HOG_OK;
 }
 
-extern "C" hog_status hog_integral(const hog_plan *plan, const uint8_t *bins, void *ii,
-                                   void *workspace, void *stream)
+// hog_integral's passes. With prep_tmpl (hard votes, the one-template strip
+// scorer), the carry scan also prepares that scorer's template weights.
+static hog_status integral_impl(const hog_plan *plan, const uint8_t *bins, void *ii, void *workspace,
+                                void *stream, const float *prep_tmpl)
 {
-    if (!plan || !bins || !ii || !workspace) return fail(HOG_E_INVALID, "NULL argument");
     hipStream_t s = (hipStream_t)stream;
     uint8_t *ws = (uint8_t *)workspace;
     if (plan->dev.votes == HOG_VOTES_SOFT) {
@@ -943,7 +944,7 @@ extern "C" hog_status hog_integral(const hog_plan *plan, const uint8_t *bins, vo
     });
     if (e != hipSuccess) return device_fail(e, "integral_reduce launch");
     e = timed_launch("integral_scan", s, [&] {
-        return hogk::launch_int_scan(plan->dev, ws, s);
+        return hogk::launch_int_scan(plan->dev, ws, s, prep_tmpl);
     });
     if (e != hipSuccess) return device_fail(e, "integral_scan launch");
     e = timed_launch("integral_emit", s, [&] {
@@ -953,9 +954,18 @@ extern "C" hog_status hog_integral(const hog_plan *plan, const uint8_t *bins, vo
     return HOG_OK;
 }
 
-extern "C" hog_status hog_scan_windows(const hog_plan *plan, const void *ii, const float *tmpl,
-                                       const float *bias, float *scores, uint32_t *cell_hist,
-                                       float *block_feat, void *workspace, void *stream)
+extern "C" hog_status hog_integral(const hog_plan *plan, const uint8_t *bins, void *ii,
+                                   void *workspace, void *stream)
+{
+    if (!plan || !bins || !ii || !workspace) return fail(HOG_E_INVALID, "NULL argument");
+    return integral_impl(plan, bins, ii, workspace, stream, nullptr);
+}
+
+// hog_scan_windows; prep = false when the template weights were prepared on
+// this workspace by the carry scan of the same call.
+static hog_status scan_windows_impl(const hog_plan *plan, const void *ii, const float *tmpl,
+                                    const float *bias, float *scores, uint32_t *cell_hist,
+                                    float *block_feat, void *workspace, void *stream, bool prep)
 {
     if (!plan || !workspace) return fail(HOG_E_INVALID, "NULL argument");
     const bool need_scores = plan->sizes.score_elems > 0;
@@ -985,11 +995,18 @@ extern "C" hog_status hog_scan_windows(const hog_plan *plan, const void *ii, con
     }
     if (need_scores) {
         e = timed_launch("score", s, [&] {
-            return hogk::launch_score(plan->dev, ws, tmpl, bias, scores, s);
+            return hogk::launch_score(plan->dev, ws, tmpl, bias, scores, s, prep);
         });
         if (e != hipSuccess) return device_fail(e, "score launch");
     }
     return HOG_OK;
+}
+
+extern "C" hog_status hog_scan_windows(const hog_plan *plan, const void *ii, const float *tmpl,
+                                       const float *bias, float *scores, uint32_t *cell_hist,
+                                       float *block_feat, void *workspace, void *stream)
+{
+    return scan_windows_impl(plan, ii, tmpl, bias, scores, cell_hist, block_feat, workspace, stream, true);
 }
 
 // ---------------------------------------------------------------------------
@@ -1358,12 +1375,16 @@ static hog_status run_path(const hog_plan *plan, const hog_lut *lut, const uint8
 {
     hog_status st = hog_bin_map(plan, lut, img, img_pitch, bins, stream);
     if (st != HOG_OK) return st;
-    st = hog_integral(plan, bins, ii, workspace, stream);
+    // The one-template strip scorer's template prep runs inside the carry
+    // scan's launch instead of as a launch of its own before the scores.
+    const bool soft = plan->dev.votes == HOG_VOTES_SOFT;
+    const bool fuse_prep = !soft && plan->sizes.score_elems > 0 && hogk::scan_runs_prep(plan->dev);
+    st = integral_impl(plan, bins, ii, workspace, stream, fuse_prep ? tmpl : nullptr);
     if (st != HOG_OK) return st;
-    // hog_integral caches 8-pixel cells (every cell size with soft votes).
-    const bool from_planes = plan->desc.scan.cell != 8 && plan->dev.votes != HOG_VOTES_SOFT;
-    return hog_scan_windows(plan, from_planes ? ii : nullptr, tmpl, bias, scores, nullptr, nullptr,
-                            workspace, stream);
+    // The integral caches 8-pixel cells (every cell size with soft votes).
+    const bool from_planes = plan->desc.scan.cell != 8 && !soft;
+    return scan_windows_impl(plan, from_planes ? ii : nullptr, tmpl, bias, scores, nullptr, nullptr,
+                             workspace, stream, !fuse_prep);
 }
 
 // The path with level groups. The matrix-core scorer's template weights are

@@ -140,7 +140,11 @@ hipError_t launch_bin_map_soft(const PlanDev &p, const uint16_t *soft_lut, const
 // With cells, the writer also fills the cell cache (8-pixel cells only).
 hipError_t launch_soft_integral(const PlanDev &p, const uint8_t *bins, uint8_t *ws, uint32_t *ii,
                                 bool cells, hipStream_t stream);
-hipError_t launch_int_scan(const PlanDev &p, uint8_t *ws, hipStream_t stream);
+// With tmpl (the one-template strip scorer's weights), the launch also runs
+// that scorer's template prep, so launch_score can then skip it.
+hipError_t launch_int_scan(const PlanDev &p, uint8_t *ws, hipStream_t stream, const float *tmpl = nullptr);
+// Whether launch_int_scan runs the template prep for this plan when given tmpl.
+bool scan_runs_prep(const PlanDev &p);
 hipError_t launch_int_emit(const PlanDev &p, const uint8_t *bins, uint8_t *ws, void *ii,
                            hipStream_t stream);
 hipError_t launch_cells(const PlanDev &p, const void *ii, uint8_t *ws, uint32_t *cell_hist,

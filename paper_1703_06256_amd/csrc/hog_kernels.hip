@@ -404,6 +404,207 @@ __global__ __launch_bounds__(64) void k_int_reduce(const Level *__restrict__ lv,
     }
 }
 
+// Compiler-only ordering point for wave-private LDS traffic.
+__device__ __forceinline__ void lds_order()
+{
+    __builtin_amdgcn_wave_barrier();
+    asm volatile("" ::: "memory");
+}
+
+// ---------------------------------------------------------------------------
+// Template weights for the matrix-core scorers (Sec. 4 inner product): their
+// modes and, for the strip scorer, the prep of each template into B
+// fragments (run by k_score_prep, or beside the carries by k_int_scan).
+// ---------------------------------------------------------------------------
+// Matrix-core scorer modes, per template (strips) or per tile of 32
+// templates (window GEMM): fp16 hi + lo weights (the strips), the same with
+// the lo halves scaled by 2^11 and the counts they multiply by 2^-11 (the
+// window GEMM), or FP32 weights (either).
+enum { kModeSplit = 0, kModeExact = 1, kModeWide = 2 };
+
+struct StripArgs {
+    int nb, nby, k, th, dim, lds_wave;
+    int64_t tprep_off, tprep_stride;
+    float eps;
+};
+
+typedef _Float16 half8_t __attribute__((ext_vector_type(8)));
+typedef _Float16 half4_t __attribute__((ext_vector_type(4)));
+typedef float float4_t __attribute__((ext_vector_type(4)));
+typedef uint16_t u16x8_t __attribute__((ext_vector_type(8)));
+
+template <int NBP>
+struct StripShape {
+    static constexpr int K32 = (4 * NBP) / 32;         // 16x16x32 steps per block
+    static constexpr int K16 = ((4 * NBP) % 32) / 16;  // 16x16x16 steps (0 or 1)
+    static constexpr int S = K32 + K16;                // prepared fragments per (bx, hi|lo)
+    static_assert(4 * NBP == 32 * K32 + 16 * K16, "bin padding must fill the steps");
+};
+
+// Feature k of a block (cell order w, u; NBP slots per cell) -> template
+// element of block position (n, bx), or -1 for a padding slot / n >= nby.
+__device__ __forceinline__ int strip_weight_index(int k, int nbp, int nb, int nby, int n, int bx)
+{
+    const int w = k / (2 * nbp), rem = k % (2 * nbp);
+    const int u = rem / nbp, bin = rem % nbp;
+    if (n >= nby || bin >= nb) return -1;
+    return ((n * kStripMaxBX + bx) * 4 + w * 2 + u) * nb + bin;
+}
+
+// Template prep, one workgroup per template: the B fragments of every step
+// and block column bx, in the layout the strip kernel loads: slots
+// [bx][i][lane] of 16 bytes (i < NBP / 4), then the column scales [lane]
+// (float), then the template's mode (int).
+// kModeSplit: column n (block row offset) gets one power of two for all its
+// bx, bringing its max |T| into [2^14, 2^15), and each scaled weight sv is
+// split into fp16 hi = sv rounded and lo = (sv - hi) rounded; slot 2 j holds
+// the hi and slot 2 j + 1 the lo halves of 16x16x32 step j, and the 16x16x16
+// step (if any) is slot 2 K32, hi in its low and lo in its high 8 bytes.
+// hi + lo holds sv to 2^-22 relative when |sv| >= 2^-3; below that lo is an
+// fp16 subnormal and loses bits. So if any nonzero weight of the template
+// scales below 2^-3 (its column also holds weights about 2^17 times larger),
+// the template takes kModeExact instead: its FP32 weights unscaled, slot i
+// holding the weights of bins 4 i .. 4 i + 3 of cell q = lane / 16 of the
+// block (the 16x16x4 FP32 products' layout), and scale 1.
+//
+// The prep of template kk by the W waves of a workgroup, wave w taking the
+// block columns bx = w, w + W, ... (k_score_prep: W = kStripMaxBX, one each;
+// the carry scan's prep workgroups: W = 4, up to two each). colmax,
+// need_exact and wbuf (W x kStripPrepRows x 4 NBP floats) are the
+// workgroup's LDS.
+constexpr int kStripPrepRows = 16;  // block row offsets n a template may have (lane & 15)
+
+template <int NBP, int W>
+__device__ __forceinline__ void strip_prep(const StripArgs &a, const float *__restrict__ tmpl,
+                                           uint8_t *__restrict__ ws, int kk, float (*colmax)[64],
+                                           int *need_exact, float *wbuf)
+{
+    using Sh = StripShape<NBP>;
+    constexpr int NI = NBP / 4;                          // 16-byte slots per (bx, lane)
+    constexpr int BXW = (kStripMaxBX + W - 1) / W;       // block columns per wave
+    constexpr int RS = 4 * NBP;                          // LDS floats per block row offset
+    constexpr int NL = (RS + 63) / 64;                   // loads per block row offset
+    typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+    const int lane = threadIdx.x & 63, w = wave_id_in_block();
+    const int n = lane & 15, q = lane >> 4;
+    const float *tk = tmpl + (int64_t)kk * a.dim;
+    float *wb = wbuf + w * kStripPrepRows * RS;
+    if (threadIdx.x == 0) *need_exact = 0;
+    float vals[BXW][Sh::S][8];
+#pragma unroll
+    for (int r = 0; r < BXW; ++r) {
+        const int bx = w + W * r;
+        float mx = 0.f;
+        if (bx < kStripMaxBX) {  // wave-uniform
+            // The weights of block column bx are one run of 4 N_b consecutive
+            // template elements per block row offset n (its four cells'
+            // bins): loaded whole, 64 lanes at a time, into this wave's LDS
+            // rows, then gathered into the fragment layout. (Gathered straight
+            // from the template, each load would touch 64 cache lines.)
+            const int run = 4 * a.nb;
+            float t[kStripPrepRows][NL];
+#pragma unroll
+            for (int m = 0; m < kStripPrepRows; ++m)
+#pragma unroll
+                for (int h = 0; h < NL; ++h) {
+                    const int e = 64 * h + lane;
+                    const bool ok = (m < a.nby) & (e < run);
+                    t[m][h] = tk[ok ? (m * kStripMaxBX + bx) * run + e : 0];
+                }
+            lds_order();  // the previous column's gather reads come first
+#pragma unroll
+            for (int m = 0; m < kStripPrepRows; ++m)
+#pragma unroll
+                for (int h = 0; h < NL; ++h)
+                    if (64 * h + lane < RS) wb[m * RS + 64 * h + lane] = t[m][h];
+            lds_order();
+        }
+#pragma unroll
+        for (int j = 0; j < Sh::S; ++j)
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                float val = 0.f;
+                if ((j < Sh::K32 || i < 4) && bx < kStripMaxBX) {  // compile-time; wave-uniform
+                    const int k = j < Sh::K32 ? 32 * j + 8 * q + i : 32 * Sh::K32 + 4 * q + i;
+                    // Feature k: cell c = 2 w + u of the block, bin slot b;
+                    // padding slots and rows past the template weigh 0.
+                    const int c = 2 * (k / (2 * NBP)) + (k % (2 * NBP)) / NBP, b = k % NBP;
+                    const bool ok = (n < a.nby) & (b < a.nb);
+                    const float wt = wb[n * RS + (ok ? c * a.nb + b : 0)];
+                    val = ok ? wt : 0.f;
+                }
+                vals[r][j][i] = val;
+                mx = fmaxf(mx, fabsf(val));
+            }
+        if (bx < kStripMaxBX) colmax[bx][lane] = mx;  // wave-uniform
+    }
+    __syncthreads();
+    float mx = 0.f;
+#pragma unroll
+    for (int b = 0; b < kStripMaxBX; ++b)
+#pragma unroll
+        for (int g = 0; g < 4; ++g) mx = fmaxf(mx, colmax[b][16 * g + n]);
+    int ex = 0;
+    if (mx > 0.f) (void)frexpf(mx, &ex);  // mx = f 2^ex, f in [0.5, 1)
+    const int e = mx > 0.f ? 15 - ex : 0;
+    float svmin = INFINITY;  // smallest nonzero scaled weight
+#pragma unroll
+    for (int r = 0; r < BXW; ++r)
+#pragma unroll
+        for (int j = 0; j < Sh::S; ++j)
+#pragma unroll
+            for (int i = 0; i < 8; ++i)
+                if (vals[r][j][i] != 0.f) svmin = fminf(svmin, fabsf(ldexpf(vals[r][j][i], e)));
+    if (svmin < 0x1p-3f) *need_exact = 1;
+    __syncthreads();
+    const int mode = *need_exact ? kModeExact : kModeSplit;
+    const bool exact = mode == kModeExact;
+    uint8_t *tp = ws + a.tprep_off + (int64_t)kk * a.tprep_stride;
+#pragma unroll
+    for (int r = 0; r < BXW; ++r) {
+        const int bx = w + W * r;
+        if (bx >= kStripMaxBX) break;  // wave-uniform
+        u32x4 *frag = reinterpret_cast<u32x4 *>(tp) + (int64_t)bx * NI * 64 + lane;
+        if (exact) {
+#pragma unroll
+            for (int i = 0; i < NI; ++i) {
+                float4_t f;
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    const int idx = strip_weight_index(q * NBP + 4 * i + c, NBP, a.nb, a.nby, n, bx);
+                    const float wt = tk[idx >= 0 ? idx : 0];
+                    f[c] = idx >= 0 ? wt : 0.f;
+                }
+                frag[(int64_t)i * 64] = __builtin_bit_cast(u32x4, f);
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < Sh::S; ++j) {
+                half8_t h, lo;
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    const float sv = ldexpf(vals[r][j][i], e);
+                    h[i] = (_Float16)sv;
+                    lo[i] = (_Float16)(sv - (float)h[i]);
+                }
+                if (j < Sh::K32) {
+                    frag[(int64_t)(2 * j) * 64] = __builtin_bit_cast(u32x4, h);
+                    frag[(int64_t)(2 * j + 1) * 64] = __builtin_bit_cast(u32x4, lo);
+                } else {  // the 16x16x16 step: four features per lane
+                    frag[(int64_t)(2 * j) * 64] =
+                        __builtin_bit_cast(u32x4, __builtin_shufflevector(h, lo, 0, 1, 2, 3, 8, 9, 10, 11));
+                }
+            }
+        }
+    }
+    if (w == 0) {
+        float *cs = reinterpret_cast<float *>(tp + (int64_t)kStripMaxBX * NI * 64 * 16);
+        cs[lane] = exact ? 1.f : ldexpf(1.f, -e);
+        if (lane == 0) reinterpret_cast<int *>(cs + 64)[0] = mode;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Pass 2 (k_int_scan), one launch with three kinds of work (block ranges):
 //   rows:  E[tx][n][y]  = sum over t < tx of rowtot[t][n][y]   (thread per (n, y))
 //   cols:  CS[ty][n][x] = sum over k < ty of coltot[k][n][x]   (thread per (n, x))
@@ -412,15 +613,9 @@ __global__ __launch_bounds__(64) void k_int_reduce(const Level *__restrict__ lv,
 // From these the plane value just above a tile row is P + a prefix over the
 // tile's columns of CS, and the row carry of a pixel row is E (k_int_emit).
 struct ScanRanges {
-    int rows_blocks, cols_blocks;  // blocks of the first two kinds; the rest are tiles
+    int prep_blocks;               // template prep workgroups first (one per template), if any
+    int rows_blocks, cols_blocks;  // then blocks of the first two kinds; the rest are tiles
 };
-
-// Compiler-only ordering point for wave-private LDS traffic.
-__device__ __forceinline__ void lds_order()
-{
-    __builtin_amdgcn_wave_barrier();
-    asm volatile("" ::: "memory");
-}
 
 // Inclusive prefix sum over the 64 lanes of a full wave, by DPP: shifts of
 // 1, 2, 4 and 8 lanes inside each row of 16 (zero fill), then the last lane
@@ -437,13 +632,29 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v)
     return v;
 }
 
+// NBP > 0: the launch also prepares the one-template strip scorer's weights
+// (strip_prep, four waves per template) in its first r.prep_blocks
+// workgroups, beside the carries rather than as a launch of its own on the
+// path (the two write disjoint parts of the workspace).
+template <int NBP>
 __global__ __launch_bounds__(256) void k_int_scan(const Level *__restrict__ lv,
                                                   const int32_t *__restrict__ first_e,
                                                   const int32_t *__restrict__ first_c,
                                                   const int32_t *__restrict__ first_p, int n_levels,
-                                                  int nb, ScanRanges r, uint8_t *__restrict__ ws)
+                                                  int nb, ScanRanges r, uint8_t *__restrict__ ws,
+                                                  StripArgs pa, const float *__restrict__ tmpl)
 {
-    const int blk = (int)blockIdx.x;
+    int blk = (int)blockIdx.x;
+    if constexpr (NBP > 0) {
+        if (blk < r.prep_blocks) {
+            __shared__ float colmax[kStripMaxBX][64];
+            __shared__ int need_exact;
+            __shared__ float wbuf[4 * kStripPrepRows * 4 * (NBP > 0 ? NBP : 1)];
+            strip_prep<NBP, 4>(pa, tmpl, ws, blk, colmax, &need_exact, wbuf);
+            return;
+        }
+        blk -= r.prep_blocks;
+    }
     const int lane = threadIdx.x & 63;
     // Rows and columns: each (level, bin) holds a whole number of waves (its
     // items are the tile-rounded rows hp, or columns wp, both multiples of
@@ -1426,31 +1637,6 @@ template <int V>
 struct IntTag {
     static constexpr int value = V;
 };
-// Matrix-core scorer modes, per template (strips) or per tile of 32
-// templates (window GEMM): fp16 hi + lo weights (the strips), the same with
-// the lo halves scaled by 2^11 and the counts they multiply by 2^-11 (the
-// window GEMM), or FP32 weights (either).
-enum { kModeSplit = 0, kModeExact = 1, kModeWide = 2 };
-
-struct StripArgs {
-    int nb, nby, k, th, dim, lds_wave;
-    int64_t tprep_off, tprep_stride;
-    float eps;
-};
-
-typedef _Float16 half8_t __attribute__((ext_vector_type(8)));
-typedef _Float16 half4_t __attribute__((ext_vector_type(4)));
-typedef float float4_t __attribute__((ext_vector_type(4)));
-typedef uint16_t u16x8_t __attribute__((ext_vector_type(8)));
-
-template <int NBP>
-struct StripShape {
-    static constexpr int K32 = (4 * NBP) / 32;         // 16x16x32 steps per block
-    static constexpr int K16 = ((4 * NBP) % 32) / 16;  // 16x16x16 steps (0 or 1)
-    static constexpr int S = K32 + K16;                // prepared fragments per (bx, hi|lo)
-    static_assert(4 * NBP == 32 * K32 + 16 * K16, "bin padding must fill the steps");
-};
-
 // Lane i of each 16-lane row takes lane i-1's value; lane 0 of a row takes 0.
 __device__ __forceinline__ double shift_row_right(double x)
 {
@@ -1460,121 +1646,14 @@ __device__ __forceinline__ double shift_row_right(double x)
     return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
 }
 
-// Feature k of a block (cell order w, u; NBP slots per cell) -> template
-// element of block position (n, bx), or -1 for a padding slot / n >= nby.
-__device__ __forceinline__ int strip_weight_index(int k, int nbp, int nb, int nby, int n, int bx)
-{
-    const int w = k / (2 * nbp), rem = k % (2 * nbp);
-    const int u = rem / nbp, bin = rem % nbp;
-    if (n >= nby || bin >= nb) return -1;
-    return ((n * kStripMaxBX + bx) * 4 + w * 2 + u) * nb + bin;
-}
-
-// One workgroup per template, wave bx (kStripMaxBX waves): the B fragments of
-// every step for that bx, in the layout the strip kernel loads: slots
-// [bx][i][lane] of 16 bytes (i < NBP / 4), then the column scales [lane]
-// (float), then the template's mode (int).
-// kModeSplit: column n (block row offset) gets one power of two for all its
-// bx, bringing its max |T| into [2^14, 2^15), and each scaled weight sv is
-// split into fp16 hi = sv rounded and lo = (sv - hi) rounded; slot 2 j holds
-// the hi and slot 2 j + 1 the lo halves of 16x16x32 step j, and the 16x16x16
-// step (if any) is slot 2 K32, hi in its low and lo in its high 8 bytes.
-// hi + lo holds sv to 2^-22 relative when |sv| >= 2^-3; below that lo is an
-// fp16 subnormal and loses bits. So if any nonzero weight of the template
-// scales below 2^-3 (its column also holds weights about 2^17 times larger),
-// the template takes kModeExact instead: its FP32 weights unscaled, slot i
-// holding the weights of bins 4 i .. 4 i + 3 of cell q = lane / 16 of the
-// block (the 16x16x4 FP32 products' layout), and scale 1.
 template <int NBP>
 __global__ __launch_bounds__(64 * kStripMaxBX) void k_score_prep(StripArgs a, const float *__restrict__ tmpl,
                                                                  uint8_t *__restrict__ ws)
 {
-    using Sh = StripShape<NBP>;
-    constexpr int NI = NBP / 4;  // 16-byte slots per (bx, lane)
-    typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
     __shared__ float colmax[kStripMaxBX][64];
     __shared__ int need_exact;
-    const int lane = threadIdx.x & 63, bx = wave_id_in_block();
-    const int kk = (int)blockIdx.x;
-    const int n = lane & 15, q = lane >> 4;
-    const float *tk = tmpl + (int64_t)kk * a.dim;
-    if (threadIdx.x == 0) need_exact = 0;
-    float vals[Sh::S][8];
-    float mx = 0.f;
-#pragma unroll
-    for (int j = 0; j < Sh::S; ++j)
-#pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            float val = 0.f;
-            if (j < Sh::K32 || i < 4) {  // compile-time
-                const int k = j < Sh::K32 ? 32 * j + 8 * q + i : 32 * Sh::K32 + 4 * q + i;
-                const int idx = strip_weight_index(k, NBP, a.nb, a.nby, n, bx);
-                // Padding slots load weight 0 and drop it: no branch per load,
-                // so every load of the template is in flight at once.
-                const float w = tk[idx >= 0 ? idx : 0];
-                val = idx >= 0 ? w : 0.f;
-            }
-            vals[j][i] = val;
-            mx = fmaxf(mx, fabsf(val));
-        }
-    colmax[bx][lane] = mx;
-    __syncthreads();
-    mx = 0.f;
-#pragma unroll
-    for (int b = 0; b < kStripMaxBX; ++b)
-#pragma unroll
-        for (int g = 0; g < 4; ++g) mx = fmaxf(mx, colmax[b][16 * g + n]);
-    int ex = 0;
-    if (mx > 0.f) (void)frexpf(mx, &ex);  // mx = f 2^ex, f in [0.5, 1)
-    const int e = mx > 0.f ? 15 - ex : 0;
-    float svmin = INFINITY;  // smallest nonzero scaled weight
-#pragma unroll
-    for (int j = 0; j < Sh::S; ++j)
-#pragma unroll
-        for (int i = 0; i < 8; ++i)
-            if (vals[j][i] != 0.f) svmin = fminf(svmin, fabsf(ldexpf(vals[j][i], e)));
-    if (svmin < 0x1p-3f) need_exact = 1;
-    __syncthreads();
-    const int mode = need_exact ? kModeExact : kModeSplit;
-    const bool exact = mode == kModeExact;
-    uint8_t *tp = ws + a.tprep_off + (int64_t)kk * a.tprep_stride;
-    u32x4 *frag = reinterpret_cast<u32x4 *>(tp) + (int64_t)bx * NI * 64 + lane;
-    if (exact) {
-#pragma unroll
-        for (int i = 0; i < NI; ++i) {
-            float4_t f;
-#pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                const int idx = strip_weight_index(q * NBP + 4 * i + c, NBP, a.nb, a.nby, n, bx);
-                const float w = tk[idx >= 0 ? idx : 0];
-                f[c] = idx >= 0 ? w : 0.f;
-            }
-            frag[(int64_t)i * 64] = __builtin_bit_cast(u32x4, f);
-        }
-    } else {
-#pragma unroll
-        for (int j = 0; j < Sh::S; ++j) {
-            half8_t h, lo;
-#pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                const float sv = ldexpf(vals[j][i], e);
-                h[i] = (_Float16)sv;
-                lo[i] = (_Float16)(sv - (float)h[i]);
-            }
-            if (j < Sh::K32) {
-                frag[(int64_t)(2 * j) * 64] = __builtin_bit_cast(u32x4, h);
-                frag[(int64_t)(2 * j + 1) * 64] = __builtin_bit_cast(u32x4, lo);
-            } else {  // the 16x16x16 step: four features per lane
-                frag[(int64_t)(2 * j) * 64] =
-                    __builtin_bit_cast(u32x4, __builtin_shufflevector(h, lo, 0, 1, 2, 3, 8, 9, 10, 11));
-            }
-        }
-    }
-    if (bx == 0) {
-        float *cs = reinterpret_cast<float *>(tp + (int64_t)kStripMaxBX * NI * 64 * 16);
-        cs[lane] = exact ? 1.f : ldexpf(1.f, -e);
-        if (lane == 0) reinterpret_cast<int *>(cs + 64)[0] = mode;
-    }
+    __shared__ float wbuf[kStripMaxBX * kStripPrepRows * 4 * NBP];
+    strip_prep<NBP, kStripMaxBX>(a, tmpl, ws, (int)blockIdx.x, colmax, &need_exact, wbuf);
 }
 
 template <int NBP>
@@ -2393,16 +2472,31 @@ hipError_t launch_int_reduce(const PlanDev &p, const uint8_t *bins, uint8_t *ws,
     return hipGetLastError();
 }
 
-hipError_t launch_int_scan(const PlanDev &p, uint8_t *ws, hipStream_t stream)
+static StripArgs strip_args(const PlanDev &p);
+
+bool scan_runs_prep(const PlanDev &p) { return p.scorer == 1 && p.total[KB_STILE] > 0; }
+
+hipError_t launch_int_scan(const PlanDev &p, uint8_t *ws, hipStream_t stream, const float *tmpl)
 {
     ScanRanges r;
+    // The strip scorer's template prep rides along when tmpl is given.
+    const bool prep = tmpl && scan_runs_prep(p);
+    const StripArgs pa = prep ? strip_args(p) : StripArgs{};
+    r.prep_blocks = prep ? pa.k : 0;
     r.rows_blocks = (int)blocks_for(p.total[KB_ESCAN], 256);
     r.cols_blocks = (int)blocks_for(p.total[KB_CSCAN], 256);
     const int tile_blocks = (int)blocks_for(p.total[KB_PSCAN], 4);
-    const int n = r.rows_blocks + r.cols_blocks + tile_blocks;
+    const int n = r.prep_blocks + r.rows_blocks + r.cols_blocks + tile_blocks;
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_int_scan, dim3((unsigned)n), dim3(256), 0, stream, p.levels, first_of(p, KB_ESCAN),
-                       first_of(p, KB_CSCAN), first_of(p, KB_PSCAN), p.n_levels, p.n_bins, r, ws);
+    const dim3 grid((unsigned)n), block(256);
+    const int32_t *fe = first_of(p, KB_ESCAN), *fc = first_of(p, KB_CSCAN), *fp = first_of(p, KB_PSCAN);
+    switch (prep ? p.mfma_ks : 0) {
+    case 0: hipLaunchKernelGGL(k_int_scan<0>, grid, block, 0, stream, p.levels, fe, fc, fp, p.n_levels, p.n_bins, r, ws, pa, tmpl); break;
+    case 8: hipLaunchKernelGGL(k_int_scan<8>, grid, block, 0, stream, p.levels, fe, fc, fp, p.n_levels, p.n_bins, r, ws, pa, tmpl); break;
+    case 16: hipLaunchKernelGGL(k_int_scan<16>, grid, block, 0, stream, p.levels, fe, fc, fp, p.n_levels, p.n_bins, r, ws, pa, tmpl); break;
+    case 20: hipLaunchKernelGGL(k_int_scan<20>, grid, block, 0, stream, p.levels, fe, fc, fp, p.n_levels, p.n_bins, r, ws, pa, tmpl); break;
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
