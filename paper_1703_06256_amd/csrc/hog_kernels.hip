@@ -148,7 +148,11 @@ __global__ __launch_bounds__(1024) void k_bin_map(const Level *__restrict__ lv,
     const int lane = threadIdx.x & 63;
     const int n_items = first[n_levels];
     const int waves_per_block = (int)(blockDim.x >> 6);
-    for (int item = (int)blockIdx.x * waves_per_block + wave_id_in_block(); item < n_items;
+    // Wave w of workgroup b starts at item w * grid + b: each round of
+    // grid x waves items spreads over every workgroup, so the last, partial
+    // round adds at most one item to each wave of every CU rather than a
+    // whole round to the first CUs.
+    for (int item = wave_id_in_block() * (int)gridDim.x + (int)blockIdx.x; item < n_items;
          item += (int)gridDim.x * waves_per_block) {
         const int l = find_level(first, n_levels, item);
         const Level &v = lv[l];
