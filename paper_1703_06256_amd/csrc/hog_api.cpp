@@ -686,8 +686,9 @@ static hog_status create_plan(const hog_plan_desc *descs, int n_img, bool batch,
         int64_t items[hogk::KB_COUNT];
         items[hogk::KB_BINMAP] = (int64_t)v.bm_gx * v.bm_gy;
         items[hogk::KB_ITILE] = (int64_t)v.tiles_x * v.tiles_y;
-        items[hogk::KB_CSCAN] = (int64_t)hogk::kTile * v.tiles_x * nb;
-        items[hogk::KB_ESCAN] = (int64_t)hogk::kTile * v.tiles_y * nb;  // whole tiles: waves stay in one (level, bin)
+        // Four rows (columns) per thread, padded to whole waves per bin: waves stay in one (level, bin).
+        items[hogk::KB_CSCAN] = (int64_t)16 * round_up(v.tiles_x, 4) * nb;
+        items[hogk::KB_ESCAN] = (int64_t)16 * round_up(v.tiles_y, 4) * nb;
         items[hogk::KB_PSCAN] = nb;
         items[hogk::KB_CELL] = (int64_t)v.cells_x * v.cells_y;
         items[hogk::KB_STILE] = (int64_t)v.st_x * v.st_y *

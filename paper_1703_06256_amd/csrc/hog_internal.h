@@ -51,8 +51,8 @@ constexpr int64_t strip_prep_bytes(int nbp)
 enum {
     KB_BINMAP = 0,  // waves
     KB_ITILE,       // integral tiles
-    KB_CSCAN,       // threads of the column-prefix scan: 64 tiles_x * n_bins
-    KB_ESCAN,       // threads of the row-carry scan: 64 tiles_y * n_bins
+    KB_CSCAN,       // threads of the column-prefix scan: 16 round_up(tiles_x, 4) * n_bins (4 columns each)
+    KB_ESCAN,       // threads of the row-carry scan: 16 round_up(tiles_y, 4) * n_bins (4 rows each)
     KB_PSCAN,       // waves of the tile-total prefix: n_bins
     KB_CELL,        // threads of the cell kernel: cells
     KB_STILE,       // workgroups of the scorer: window tiles

@@ -660,39 +660,52 @@ __global__ __launch_bounds__(256) void k_int_scan(const Level *__restrict__ lv,
         blk -= r.prep_blocks;
     }
     const int lane = threadIdx.x & 63;
-    // Rows and columns: each (level, bin) holds a whole number of waves (its
-    // items are the tile-rounded rows hp, or columns wp, both multiples of
-    // 64), so a wave's level, bin and tile counts are uniform: found from its
-    // first item, with the loads and stores through buffer descriptors and
-    // the tile in the scalar offset. Rows past the level's height compute
-    // carries nobody reads.
+    // Rows and columns: each thread carries four consecutive rows (columns)
+    // of one bin: per tile one dword of four u8 counts in, four u16 carries
+    // (8 bytes) out, kept as two pairs of 16-bit halves (a carry is at most
+    // the level's width or height, below 2^15, so the halves never carry into
+    // each other). Each (level, bin) holds a whole number of waves (its
+    // threads are padded to a multiple of 64), so a wave's level, bin and tile
+    // counts are uniform: found from its first thread, with the loads and
+    // stores through buffer descriptors and the tile in the scalar offset.
+    // Padding threads take offsets beyond the descriptors' ranges (their
+    // loads read 0, their stores are dropped); rows past the level's height
+    // get carries nobody reads.
+    typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+    auto walk4 = [](__amdgpu_buffer_rsrc_t src, __amdgpu_buffer_rsrc_t dst, int vs, int vd, uint32_t stride,
+                    int count) {
+        uint32_t lo = 0, hi = 0;  // carries of elements 0, 1 | 2, 3 in 16-bit halves
+        auto step = [&](uint32_t c, int t) {
+            __builtin_amdgcn_raw_buffer_store_b64(u32x2{lo, hi}, dst, vd, (int)(2u * (uint32_t)t * stride), 0);
+            lo += (c & 0xFFu) | ((c << 8) & 0xFF0000u);
+            hi += ((c >> 16) & 0xFFu) | ((c >> 8) & 0xFF0000u);
+        };
+        int t = 0;
+        for (; t + 8 <= count; t += 8) {
+            uint32_t c[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) c[i] = __builtin_amdgcn_raw_buffer_load_b32(src, vs, (int)((uint32_t)(t + i) * stride), 0);
+#pragma unroll
+            for (int i = 0; i < 8; ++i) step(c[i], t + i);
+        }
+        for (; t < count; ++t) step(__builtin_amdgcn_raw_buffer_load_b32(src, vs, (int)((uint32_t)t * stride), 0), t);
+    };
     if (blk < r.rows_blocks) {
         const int g0 = __builtin_amdgcn_readfirstlane(blk * 256 + (int)(threadIdx.x & ~63u));
         if (g0 >= first_e[n_levels]) return;
         const int l = find_level(first_e, n_levels, g0);
         const Level &v = lv[l];
-        // Byte offsets as unsigned 32-bit values (a level's carries stay below 2^32 bytes).
+        // Byte offsets as unsigned 32-bit values (a level's carries stay below 2^31 bytes).
         const uint32_t hp = kTile * v.tiles_y, stride = (uint32_t)nb * hp;
-        const uint32_t vo = (uint32_t)(g0 - first_e[l] + lane);  // n * hp + y
+        const uint32_t q = 16u * (uint32_t)((v.tiles_y + 3) & ~3);  // threads per bin: hp / 4, whole waves
+        const uint32_t rel0 = (uint32_t)(g0 - first_e[l]);
+        const uint32_t n = rel0 / q;                           // wave-uniform
+        const uint32_t y = 4u * (rel0 - n * q + (uint32_t)lane);  // first of the thread's rows
+        const bool ok = y < hp;
         const __amdgpu_buffer_rsrc_t rts = buffer_rsrc(ws + v.ws_rowtot, (uint32_t)v.tiles_x * stride);
         const __amdgpu_buffer_rsrc_t es = buffer_rsrc(ws + v.ws_e, 2u * (uint32_t)v.tiles_x * stride);
-        uint32_t acc = 0;
-        int tx = 0;
-        for (; tx + 8 <= v.tiles_x; tx += 8) {
-            uint32_t c[8];
-#pragma unroll
-            for (int i = 0; i < 8; ++i) c[i] = __builtin_amdgcn_raw_buffer_load_b8(rts, (int)vo, (int)((uint32_t)(tx + i) * stride), 0);
-#pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                __builtin_amdgcn_raw_buffer_store_b16((uint16_t)acc, es, (int)(2u * vo), (int)(2u * (uint32_t)(tx + i) * stride), 0);
-                acc += c[i];
-            }
-        }
-        for (; tx < v.tiles_x; ++tx) {
-            const uint32_t c = __builtin_amdgcn_raw_buffer_load_b8(rts, (int)vo, (int)((uint32_t)tx * stride), 0);
-            __builtin_amdgcn_raw_buffer_store_b16((uint16_t)acc, es, (int)(2u * vo), (int)(2u * (uint32_t)tx * stride), 0);
-            acc += c;
-        }
+        walk4(rts, es, ok ? (int)(n * hp + y) : (int)0x80000000u, ok ? (int)(2u * (n * hp + y)) : (int)0x80000000u,
+              stride, v.tiles_x);
         return;
     }
     if (blk < r.rows_blocks + r.cols_blocks) {
@@ -701,26 +714,15 @@ __global__ __launch_bounds__(256) void k_int_scan(const Level *__restrict__ lv,
         const int l = find_level(first_c, n_levels, g0);
         const Level &v = lv[l];
         const uint32_t wp = kTile * v.tiles_x, stride = (uint32_t)nb * wp;
-        const uint32_t vo = (uint32_t)(g0 - first_c[l] + lane);  // n * wp + x
+        const uint32_t q = 16u * (uint32_t)((v.tiles_x + 3) & ~3);  // threads per bin: wp / 4, whole waves
+        const uint32_t rel0 = (uint32_t)(g0 - first_c[l]);
+        const uint32_t n = rel0 / q;
+        const uint32_t x = 4u * (rel0 - n * q + (uint32_t)lane);
+        const bool ok = x < wp;
         const __amdgpu_buffer_rsrc_t cts = buffer_rsrc(ws + v.ws_coltot, (uint32_t)v.tiles_y * stride);
         const __amdgpu_buffer_rsrc_t css = buffer_rsrc(ws + v.ws_cs, 2u * (uint32_t)v.tiles_y * stride);
-        uint32_t acc = 0;
-        int ty = 0;
-        for (; ty + 8 <= v.tiles_y; ty += 8) {
-            uint32_t c[8];
-#pragma unroll
-            for (int i = 0; i < 8; ++i) c[i] = __builtin_amdgcn_raw_buffer_load_b8(cts, (int)vo, (int)((uint32_t)(ty + i) * stride), 0);
-#pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                __builtin_amdgcn_raw_buffer_store_b16((uint16_t)acc, css, (int)(2u * vo), (int)(2u * (uint32_t)(ty + i) * stride), 0);
-                acc += c[i];
-            }
-        }
-        for (; ty < v.tiles_y; ++ty) {
-            const uint32_t c = __builtin_amdgcn_raw_buffer_load_b8(cts, (int)vo, (int)((uint32_t)ty * stride), 0);
-            __builtin_amdgcn_raw_buffer_store_b16((uint16_t)acc, css, (int)(2u * vo), (int)(2u * (uint32_t)ty * stride), 0);
-            acc += c;
-        }
+        walk4(cts, css, ok ? (int)(n * wp + x) : (int)0x80000000u, ok ? (int)(2u * (n * wp + x)) : (int)0x80000000u,
+              stride, v.tiles_y);
         return;
     }
     // Tiles: one wave per (level, n); lanes over tile columns in chunks of 64.
