@@ -329,7 +329,8 @@ __global__ __launch_bounds__(64) void k_int_reduce(const Level *__restrict__ lv,
         colh[n * 64 + lane] = 0u;
         rowh[n * 64 + lane] = 0u;
     }
-    auto slot = [nb, nw](int b) { return (b < nb ? (b >> 2) : nw) * 64; };
+    // Bins below nb: dword b / 4; no bin (255): the spare slot nw.
+    auto slot = [nw](int b) { return min(b >> 2, nw) * 64; };
     auto one = [](int b) { return 1u << (8 * (b & 3)); };
     auto count = [&](const uint32_t *h, int b, int ln) { return (h[slot(b) + ln] >> (8 * (b & 3))) & 255u; };
     {
@@ -349,25 +350,36 @@ __global__ __launch_bounds__(64) void k_int_reduce(const Level *__restrict__ lv,
             dst[3] = d[3];
         }
     }
+    // Byte 64 of row 0 is stride padding, never staged: kNoBin there serves
+    // the pixels outside the level, read by address rather than through a
+    // select on the loaded value (which the compiler turns into a branch).
+    constexpr int kNoBinByte = kTile;
+    if (lane == 0) tb[kNoBinByte] = (uint8_t)kNoBin;
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     const int y0 = ty * kTile, nrows = min(kTile, v.h - y0);
     const int x = tx * kTile + lane;
     const bool xin = x < v.w;
     const int ncols = min(kTile, v.w - tx * kTile);
-    // Column counts: lane = column. Each batch of 16 bins is read before
-    // its adds: the compiler keeps LDS reads and atomics in program order,
-    // so a read after an add would wait for the add's round trip.
-    if (xin) {
-        for (int r0 = 0; r0 < nrows; r0 += 16) {
+    // FULL: the whole tile lies inside the level (most tiles), so no pixel
+    // needs a test.
+    auto counts = [&](auto full_c) {
+        constexpr bool FULL = decltype(full_c)::value;
+        // Column counts: lane = column. Each batch of 16 bins is read before
+        // its adds: the compiler keeps LDS reads and atomics in program
+        // order, so a read after an add would wait for the add's round trip.
+        for (int r0 = 0; r0 < (FULL ? kTile : nrows); r0 += 16) {
             int bb[16];
 #pragma unroll
-            for (int i = 0; i < 16; ++i) bb[i] = r0 + i < nrows ? tb[(r0 + i) * kRedStride + lane] : kNoBin;
+            for (int i = 0; i < 16; ++i) {
+                if constexpr (FULL)
+                    bb[i] = tb[(r0 + i) * kRedStride + lane];
+                else
+                    bb[i] = tb[xin & (r0 + i < nrows) ? (r0 + i) * kRedStride + lane : kNoBinByte];
+            }
 #pragma unroll
             for (int i = 0; i < 16; ++i) atomicAdd(&colh[slot(bb[i]) + lane], one(bb[i]));
         }
-    }
-    // Row counts: lane = row; its 64 bins are read first, 16 at a time.
-    if (lane < nrows) {
+        // Row counts: lane = row; its 64 bins are read first, 16 at a time.
         const uint32_t *rp = reinterpret_cast<const uint32_t *>(tb + lane * kRedStride);
         for (int k0 = 0; k0 < kTile / 4; k0 += 4) {
             uint32_t d[4];
@@ -377,11 +389,17 @@ __global__ __launch_bounds__(64) void k_int_reduce(const Level *__restrict__ lv,
             for (int k = 0; k < 4; ++k)
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
-                    const int b = 4 * (k0 + k) + e < ncols ? (int)((d[k] >> (8 * e)) & 255u) : kNoBin;
+                    const int c = 4 * (k0 + k) + e;
+                    const int raw = (int)((d[k] >> (8 * e)) & 255u);
+                    const int b = FULL ? raw : ((lane < nrows) & (c < ncols) ? raw : kNoBin);
                     atomicAdd(&rowh[slot(b) + lane], one(b));
                 }
         }
-    }
+    };
+    if (nrows == kTile && ncols == kTile)
+        counts(std::true_type{});
+    else
+        counts(std::false_type{});
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     // rowtot [tx][n][hp], lane = row; coltot [ty][n][wp], lane = column (0
     // right of the level); tiletot [ty][tx][n].
