@@ -364,7 +364,10 @@ hog_status hog_tune_cache_stats(int64_t *hits, int64_t *misses, int64_t *entries
 /* hog_bin_map, hog_integral and hog_scan_windows (scores only; cells from the
  * cache for 8-pixel cells, else from ii) in one call, on the same buffers and
  * with the same layouts. Arguments are all checked before anything is
- * enqueued. With level groups (hog_tiles) the groups run on the plan's own
+ * enqueued. The scores equal those of the three calls bit for bit; without
+ * level groups the one-template matrix-core scorer's weights are prepared in
+ * the carry scan's launch rather than a launch of their own. With level
+ * groups (hog_tiles) the groups run on the plan's own
  * streams (created on the plan's device by the first such call, freed by
  * hog_plan_destroy), forked from and joined back into `stream`, so the work
  * is ordered on `stream` as without groups; concurrent grouped calls on one
