@@ -1738,19 +1738,19 @@ __global__ __launch_bounds__(256, 2) void k_score_strip(const Level *__restrict_
             for (int e = 0; e < 8; ++e) rp[e * NBP] = (_Float16)val[e];
         }
     };
-    // Sum of squared counts of staged cell `lane` (exact in FP32).
+    // Sum of squared counts of staged cell `lane` (exact in FP32). Lanes
+    // past the staged cells repeat the last one (no branch); the blocks they
+    // reach (22 and 23) are never read.
     auto row_sq = [&](int slot) -> float {
         float s = 0.f;
-        if (lane < kStripCells) {
-            const _Float16 *cp = ring + slot * ROWH + lane * NBP;
-            typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
+        const _Float16 *cp = ring + slot * ROWH + min(lane, kStripCells - 1) * NBP;
+        typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
 #pragma unroll
-            for (int j = 0; j < NBP / 4; ++j) {
-                const half4_t h = *reinterpret_cast<const half4_t *>(cp + 4 * j);
-                const half2_t h0 = {h[0], h[1]}, h1 = {h[2], h[3]};
-                s = __builtin_amdgcn_fdot2(h0, h0, s, false);
-                s = __builtin_amdgcn_fdot2(h1, h1, s, false);
-            }
+        for (int j = 0; j < NBP / 4; ++j) {
+            const half4_t h = *reinterpret_cast<const half4_t *>(cp + 4 * j);
+            const half2_t h0 = {h[0], h[1]}, h1 = {h[2], h[3]};
+            s = __builtin_amdgcn_fdot2(h0, h0, s, false);
+            s = __builtin_amdgcn_fdot2(h1, h1, s, false);
         }
         return s;
     };
@@ -1804,7 +1804,9 @@ __global__ __launch_bounds__(256, 2) void k_score_strip(const Level *__restrict_
     auto block_norms = [&](int Y, float sq0, float sq1) {
         const float t = sq0 + sq1;
         const float t1 = __builtin_bit_cast(float, from_right_lane(__builtin_bit_cast(uint32_t, t)));
-        if (lane < kStripCells) invb[(Y & 1) * 32 + lane] = inv_block_norm(t + t1, a.eps);
+        // Lanes 24 and up write the unused slots 24..31 (the same one from
+        // lane 31 on): no branch.
+        invb[(Y & 1) * 32 + min(lane, 31)] = inv_block_norm(t + t1, a.eps);
     };
     store_row(wy_lo & 3, pre0);
     store_row((wy_lo + 1) & 3, pre1);
@@ -1921,12 +1923,14 @@ __global__ __launch_bounds__(256, 2) void k_score_strip(const Level *__restrict_
             }
             const int wy_done = Y - (a.nby - 1);
             const bool done = m == a.nby - 1 && wy_done >= wy_lo && wy_done < wy_hi;
+            float4_t o;
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 acc[r] += (double)(acc32[r] * cs);
-                if (done) outb[(wy_done - wy_lo) * kStripW + 4 * q + r] = (float)(bk + acc[r]);
+                o[r] = (float)(bk + acc[r]);
                 acc[r] = shift_row_right(acc[r]);
             }
+            if (done) *reinterpret_cast<float4_t *>(outb + (wy_done - wy_lo) * kStripW + 4 * q) = o;
             if (more) {
                 store_row((Y + 2) & 3, pre2);
                 lds_order();
