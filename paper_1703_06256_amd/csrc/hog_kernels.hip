@@ -177,8 +177,9 @@ __global__ __launch_bounds__(1024) void k_bin_map(const Level *__restrict__ lv,
             continue;
         }
         // Every lane and row loads from a clamped, valid position, so the
-        // loads carry no condition and are all in flight at once; samples
-        // outside the level are zeroed afterwards.
+        // loads carry no condition and are all in flight at once. Samples
+        // outside the level (clamped copies) reach only pixels off the
+        // level's interior, which take no bin whatever they hold.
         const int sx = mapx[v.mapx_off + min(max(x, 0), W - 1)];
         // Byte offset of the sample in a source row; for RGB a 4-byte read that
         // stays inside the row (it starts one byte early at the last column).
@@ -207,12 +208,9 @@ __global__ __launch_bounds__(1024) void k_bin_map(const Level *__restrict__ lv,
             else
                 smp[i] = __builtin_amdgcn_raw_buffer_load_b32(isrc, coff32, roff, 0);
         }
+        if constexpr (C == 3) {
 #pragma unroll
-        for (int i = 0; i < kBinRows + 2; ++i) {
-            const int r = y0 - 1 + i;
-            uint32_t val = smp[i];
-            if constexpr (C == 3) val = (val >> shift) & 0xFFFFFFu;
-            smp[i] = (col_ok && r >= 0 && r < H) ? val : 0u;
+            for (int i = 0; i < kBinRows + 2; ++i) smp[i] = (smp[i] >> shift) & 0xFFFFFFu;
         }
         const bool col_interior = x >= 1 && x <= W - 2;
         typedef typename std::conditional<SOFT, uint16_t, uint8_t>::type bin_t;
@@ -222,9 +220,13 @@ __global__ __launch_bounds__(1024) void k_bin_map(const Level *__restrict__ lv,
             const int y = y0 + i;
             const uint32_t up = smp[i], cur = smp[i + 1], down = smp[i + 2];
             const uint32_t left = from_left_lane(cur), right = from_right_lane(cur);
-            int best = 0, bdx = 0, bdy = 0;
+            // Channel 0 seeds the choice unconditionally (m = 0 only when
+            // dx = dy = 0, the same as no choice at all).
+            int bdx = (int)(right & 255u) - (int)(left & 255u);
+            int bdy = (int)(down & 255u) - (int)(up & 255u);
+            int best = bdx * bdx + bdy * bdy;
 #pragma unroll
-            for (int c = 0; c < C; ++c) {
+            for (int c = 1; c < C; ++c) {
                 const int dx = (int)((right >> (8 * c)) & 255u) - (int)((left >> (8 * c)) & 255u);
                 const int dy = (int)((down >> (8 * c)) & 255u) - (int)((up >> (8 * c)) & 255u);
                 const int m = dx * dx + dy * dy;
