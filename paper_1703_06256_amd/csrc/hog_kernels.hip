@@ -1900,9 +1900,24 @@ __global__ __launch_bounds__(256, 2) void k_score_strip(const Level *__restrict_
 #pragma unroll
                     for (int r = 0; r < 4; ++r) t[r] = fmaf(d[bx][r], iv[r + bx], t[r]);
             };
+            // The next rows' staging and norms do not depend on this row's
+            // products (they write ring slot Y + 2 and invb[(Y + 1) & 1],
+            // which this row does not read, its iv being loaded above), so
+            // they run while the products are in the matrix pipe.
+            auto next_rows = [&] {
+                if (more) {
+                    store_row((Y + 2) & 3, pre2);
+                    lds_order();
+                    // Next block row's norms, one row ahead of their use.
+                    const float sq2 = row_sq((Y + 2) & 3);
+                    block_norms(Y + 1, sq1, sq2);
+                    sq1 = sq2;
+                }
+            };
             zero_d();
             if constexpr (M == kModeSplit) {
                 f16_products();
+                next_rows();
                 fold(acc32);
             } else {
                 // Exact mode: FP32 products, 4 features per step. Lane group q
@@ -1921,6 +1936,7 @@ __global__ __launch_bounds__(256, 2) void k_score_strip(const Level *__restrict_
                             d[bx] = __builtin_amdgcn_mfma_f32_16x16x4f32((float)av[bx][c],
                                                                         __uint_as_float(braw[bx][i][c]), d[bx], 0, 0, 0);
                 }
+                next_rows();
                 fold(acc32);
             }
             const int wy_done = Y - (a.nby - 1);
@@ -1933,14 +1949,6 @@ __global__ __launch_bounds__(256, 2) void k_score_strip(const Level *__restrict_
                 acc[r] = shift_row_right(acc[r]);
             }
             if (done) *reinterpret_cast<float4_t *>(outb + (wy_done - wy_lo) * kStripW + 4 * q) = o;
-            if (more) {
-                store_row((Y + 2) & 3, pre2);
-                lds_order();
-                // Next block row's norms, one row ahead of their use.
-                const float sq2 = row_sq((Y + 2) & 3);
-                block_norms(Y + 1, sq1, sq2);
-                sq1 = sq2;
-            }
             pre2 = pre3;
             if (Y + 4 <= y_last + 1) pre3 = fetch(Y + 4);
         }
