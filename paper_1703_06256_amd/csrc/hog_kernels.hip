@@ -292,6 +292,28 @@ __device__ __forceinline__ void stage_bin_tile(uint8_t *tb, __amdgpu_buffer_rsrc
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
 }
 
+// Compiler-only ordering point for wave-private LDS traffic.
+__device__ __forceinline__ void lds_order()
+{
+    __builtin_amdgcn_wave_barrier();
+    asm volatile("" ::: "memory");
+}
+
+// Inclusive prefix sum over the 64 lanes of a full wave, by DPP: shifts of
+// 1, 2, 4 and 8 lanes inside each row of 16 (zero fill), then the last lane
+// of row 0 (row 2) added to row 1 (row 3), then the last lane of row 1 added
+// to rows 2 and 3. Every lane must be active.
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v)
+{
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xF, 0xF, true);   // row_shr:1
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xF, 0xF, true);   // row_shr:2
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xF, 0xF, true);   // row_shr:4
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xF, 0xF, true);   // row_shr:8
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xA, 0xF, false);  // row_bcast:15
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xC, 0xF, false);  // row_bcast:31
+    return v;
+}
+
 // ---------------------------------------------------------------------------
 // Integral images (Eq. 4 + Eq. 5) over pixel tiles of kTile x kTile: tile
 // (tx, ty) holds pixels [64 tx, 64 tx + 64) x [64 ty, 64 ty + 64), lane L on
@@ -334,7 +356,6 @@ __global__ __launch_bounds__(64) void k_int_reduce(const Level *__restrict__ lv,
     // Bins below nb: dword b / 4; no bin (255): the spare slot nw.
     auto slot = [nw](int b) { return min(b >> 2, nw) * 64; };
     auto one = [](int b) { return 1u << (8 * (b & 3)); };
-    auto count = [&](const uint32_t *h, int b, int ln) { return (h[slot(b) + ln] >> (8 * (b & 3))) & 255u; };
     {
         typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
         const __amdgpu_buffer_rsrc_t bsrc = buffer_rsrc(bins + v.bins_off, (uint32_t)(v.bins_pitch * v.h));
@@ -403,36 +424,35 @@ __global__ __launch_bounds__(64) void k_int_reduce(const Level *__restrict__ lv,
     else
         counts(std::false_type{});
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    // rowtot [tx][n][hp], lane = row; coltot [ty][n][wp], lane = column (0
-    // right of the level); tiletot [ty][tx][n].
-    const int hp = kTile * v.tiles_y, wp = kTile * v.tiles_x;
-    uint8_t *rowtot = ws + v.ws_rowtot + (int64_t)tx * nb * hp + y0 + lane;
-    uint8_t *coltot = ws + v.ws_coltot + (int64_t)ty * nb * wp + x;
-    uint32_t *tiletot = reinterpret_cast<uint32_t *>(ws + v.ws_tiletot) + ((int64_t)ty * v.tiles_x + tx) * nb;
-    for (int n = 0; n < nb; ++n) {
-        if (lane < nrows) rowtot[(int64_t)n * hp] = (uint8_t)count(rowh, n, lane);
-        coltot[(int64_t)n * wp] = (uint8_t)count(colh, n, lane);
-    }
-    // Lane n < nb sums bin n's 64 column counts.
-    if (lane < nb) {
-        typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
-        const u32x4 *cp = reinterpret_cast<const u32x4 *>(colh + slot(lane));
-        const uint32_t sh = 8u * (lane & 3);
-        uint32_t t = 0;
+    // rowtot [tx][n][hp], lane = row (rows below the level are not
+    // written); coltot [ty][n][wp], lane = column (0 right of the level);
+    // tiletot [ty][tx][n]. Each histogram dword (four bins) is read once,
+    // and the stores go through buffer descriptors with the bin's offset in
+    // the scalar operand; lanes with nothing to store take an offset past
+    // the range.
+    const uint32_t hp = kTile * v.tiles_y, wp = kTile * v.tiles_x;
+    const __amdgpu_buffer_rsrc_t rts = buffer_rsrc(ws + v.ws_rowtot + (int64_t)tx * nb * hp + y0, (uint32_t)nb * hp);
+    const __amdgpu_buffer_rsrc_t cts = buffer_rsrc(ws + v.ws_coltot + (int64_t)ty * nb * wp + tx * kTile, (uint32_t)nb * wp);
+    const __amdgpu_buffer_rsrc_t tts =
+        buffer_rsrc(ws + v.ws_tiletot + ((int64_t)ty * v.tiles_x + tx) * nb * 4, (uint32_t)nb * 4u);
+    const int rvo = lane < nrows ? lane : (int)0x80000000u;
+    for (int k = 0; k < nw; ++k) {
+        const uint32_t rs = rowh[k * 64 + lane], cs = colh[k * 64 + lane];
 #pragma unroll
-        for (int k = 0; k < 16; ++k) {
-            const u32x4 q4 = cp[k];
-            t += (((q4[0] >> sh) & 255u) + ((q4[1] >> sh) & 255u)) + (((q4[2] >> sh) & 255u) + ((q4[3] >> sh) & 255u));
-        }
-        tiletot[lane] = t;
+        for (int e = 0; e < 4; ++e)
+            if (4 * k + e < nb) {  // wave-uniform
+                __builtin_amdgcn_raw_buffer_store_b8((uint8_t)(rs >> (8 * e)), rts, rvo, (4 * k + e) * (int)hp, 0);
+                __builtin_amdgcn_raw_buffer_store_b8((uint8_t)(cs >> (8 * e)), cts, lane, (4 * k + e) * (int)wp, 0);
+            }
+        // The four bins' tile totals: sums over the 64 columns of bytes 0
+        // and 2, and of bytes 1 and 3, in 16-bit halves (at most 4096 each).
+        const uint32_t lo = wave_incl_scan(cs & 0x00FF00FFu), hi = wave_incl_scan((cs >> 8) & 0x00FF00FFu);
+        const uint32_t tl = (uint32_t)__builtin_amdgcn_readlane((int)lo, 63);
+        const uint32_t th = (uint32_t)__builtin_amdgcn_readlane((int)hi, 63);
+        const uint32_t tot = (((lane & 1) ? th : tl) >> (16 * (lane >> 1))) & 0xFFFFu;
+        __builtin_amdgcn_raw_buffer_store_b32(tot, tts, (lane < 4) & (4 * k + lane < nb) ? 4 * (4 * k + lane) : (int)0x80000000u,
+                                              0, 0);
     }
-}
-
-// Compiler-only ordering point for wave-private LDS traffic.
-__device__ __forceinline__ void lds_order()
-{
-    __builtin_amdgcn_wave_barrier();
-    asm volatile("" ::: "memory");
 }
 
 // ---------------------------------------------------------------------------
@@ -641,20 +661,6 @@ struct ScanRanges {
     int rows_blocks, cols_blocks;  // then blocks of the first two kinds; the rest are tiles
 };
 
-// Inclusive prefix sum over the 64 lanes of a full wave, by DPP: shifts of
-// 1, 2, 4 and 8 lanes inside each row of 16 (zero fill), then the last lane
-// of row 0 (row 2) added to row 1 (row 3), then the last lane of row 1 added
-// to rows 2 and 3. Every lane must be active.
-__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v)
-{
-    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xF, 0xF, true);   // row_shr:1
-    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xF, 0xF, true);   // row_shr:2
-    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xF, 0xF, true);   // row_shr:4
-    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xF, 0xF, true);   // row_shr:8
-    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xA, 0xF, false);  // row_bcast:15
-    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xC, 0xF, false);  // row_bcast:31
-    return v;
-}
 
 // NBP > 0: the launch also prepares the one-template strip scorer's weights
 // (strip_prep, four waves per template) in its first r.prep_blocks
