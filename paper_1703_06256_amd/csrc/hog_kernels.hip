@@ -1073,7 +1073,8 @@ __global__ __launch_bounds__(64) void k_soft_reduce(const Level *__restrict__ lv
         colh[k * 64 + lane] = 0u;
         rowh[k * 64 + lane] = 0u;
     }
-    auto slot = [nb, nw](uint32_t b) { return (b < (uint32_t)nb ? (int)(b >> 1) : nw) * 64; };
+    // Bins below nb: dword b / 2; no bin (255): the spare slot nw.
+    auto slot = [nw](uint32_t b) { return min((int)(b >> 1), nw) * 64; };
     auto shift = [](uint32_t b) { return 16u * (b & 1u); };
     // Adds the votes of entry e to the histogram slots of lane ln (an entry
     // with no bin, b0 = 255, sends both to the spare slot).
@@ -1105,19 +1106,21 @@ __global__ __launch_bounds__(64) void k_soft_reduce(const Level *__restrict__ lv
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     const int y0 = ty * kTile, nrows = min(kTile, v.h - y0);
     const int ncols = min(kTile, v.w - tx * kTile);
-    // Column totals: lane = column; 16 rows read before their adds.
-    if (lane < ncols) {
+    // FULL: the whole tile lies inside the level (most tiles), so no entry
+    // needs a test.
+    auto totals = [&](auto full_c) {
+        constexpr bool FULL = decltype(full_c)::value;
+        // Column totals: lane = column; 16 rows read before their adds.
         const uint16_t *cp = reinterpret_cast<const uint16_t *>(tb) + lane;
-        for (int r0 = 0; r0 < nrows; r0 += 16) {
+        for (int r0 = 0; r0 < (FULL ? kTile : nrows); r0 += 16) {
             uint32_t e[16];
 #pragma unroll
             for (int j = 0; j < 16; ++j) e[j] = cp[(r0 + j) * (kStride / 2)];
 #pragma unroll
-            for (int j = 0; j < 16; ++j) vote(colh, r0 + j < nrows ? e[j] : (uint32_t)kNoBin, lane);
+            for (int j = 0; j < 16; ++j)
+                vote(colh, FULL ? e[j] : ((lane < ncols) & (r0 + j < nrows) ? e[j] : (uint32_t)kNoBin), lane);
         }
-    }
-    // Row totals: lane = row; two entries per dword.
-    if (lane < nrows) {
+        // Row totals: lane = row; two entries per dword.
         const uint32_t *rp = reinterpret_cast<const uint32_t *>(tb + lane * kStride);
         for (int k0 = 0; k0 < kTile / 2; k0 += 8) {
             uint32_t d[8];
@@ -1126,21 +1129,33 @@ __global__ __launch_bounds__(64) void k_soft_reduce(const Level *__restrict__ lv
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
                 const int c = 2 * (k0 + j);
-                vote(rowh, c < ncols ? d[j] & 0xFFFFu : (uint32_t)kNoBin, lane);
-                vote(rowh, c + 1 < ncols ? d[j] >> 16 : (uint32_t)kNoBin, lane);
+                const bool rin = lane < nrows;
+                vote(rowh, FULL ? d[j] & 0xFFFFu : (rin & (c < ncols) ? d[j] & 0xFFFFu : (uint32_t)kNoBin), lane);
+                vote(rowh, FULL ? d[j] >> 16 : (rin & (c + 1 < ncols) ? d[j] >> 16 : (uint32_t)kNoBin), lane);
             }
         }
-    }
+    };
+    if (nrows == kTile && ncols == kTile)
+        totals(std::true_type{});
+    else
+        totals(std::false_type{});
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     // Row totals [n][tx][hp] (lane = row), column totals [n][ty][wp] (lane =
-    // column; 0 right of the level).
+    // column; 0 right of the level); each histogram dword (two bins) is read
+    // once.
     const int64_t hp = (int64_t)kTile * v.tiles_y, wp = (int64_t)kTile * v.tiles_x;
     uint32_t *rowtot = reinterpret_cast<uint32_t *>(ws + v.ws_stot) + (int64_t)tx * hp + y0 + lane;
     uint32_t *coltot = reinterpret_cast<uint32_t *>(ws + v.ws_scol) + (int64_t)ty * wp + tx * kTile + lane;
-    for (int n = 0; n < nb; ++n) {
-        const uint32_t b = (uint32_t)n;
-        if (lane < nrows) rowtot[(int64_t)n * v.tiles_x * hp] = (rowh[slot(b) + lane] >> shift(b)) & 0xFFFFu;
-        coltot[(int64_t)n * v.tiles_y * wp] = (colh[slot(b) + lane] >> shift(b)) & 0xFFFFu;
+    for (int k = 0; k < nw; ++k) {
+        const uint32_t rs = rowh[k * 64 + lane], cs = colh[k * 64 + lane];
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            const int n = 2 * k + e;
+            if (n < nb) {  // wave-uniform
+                if (lane < nrows) rowtot[(int64_t)n * v.tiles_x * hp] = (rs >> (16 * e)) & 0xFFFFu;
+                coltot[(int64_t)n * v.tiles_y * wp] = (cs >> (16 * e)) & 0xFFFFu;
+            }
+        }
     }
 }
 
