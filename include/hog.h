@@ -328,8 +328,9 @@ hog_status hog_plan_get_tiles(const hog_plan *plan, hog_tiles *out);
  * uses the plan is in flight. Results do not depend on the tile shapes. */
 hog_status hog_plan_set_tiles(hog_plan *plan, const hog_tiles *tiles);
 
-/* Autotuner: times the whole path (hog_run; the fastest of reps runs, each
- * timed alone, per candidate) on the caller's buffers for each candidate tile
+/* Autotuner: times the whole path (hog_run; per candidate, the per-run time
+ * of reps back-to-back runs, the best of three such rounds) on the caller's
+ * buffers for each candidate tile
  * shape -- bins per integral wave,
  * then window rows per strip, then the table in LDS or through L2, then
  * 1..HOG_MAX_LEVEL_GROUPS level groups --

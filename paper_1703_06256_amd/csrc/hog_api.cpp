@@ -1259,9 +1259,11 @@ extern "C" hog_status hog_plan_autotune(hog_plan *plan, const hog_lut *lut, cons
         if (e0) (void)hipEventDestroy(e0);
         return device_fail(e, "hipEventCreate");
     }
-    // The fastest of reps whole runs, each timed alone (after one untimed
-    // run), with these tiles: the minimum is steadier than the mean when
-    // candidates differ by less than a per cent of the step.
+    // Per-run time of reps whole runs back to back (the way a caller runs
+    // the path step after step), the best of three such rounds, after one
+    // untimed run, with these tiles: the best round is steadier than one
+    // long average, and back-to-back runs rank level groups, which overlap
+    // work across streams, as a stream of steps sees them.
     int best_lut = plan->dev.lut_global;
     auto time_with = [&](int chunk, int rows, int groups, float *ms) -> hog_status {
         hog_status r = apply_tiles(plan, chunk, rows, groups, best_lut);
@@ -1269,16 +1271,17 @@ extern "C" hog_status hog_plan_autotune(hog_plan *plan, const hog_lut *lut, cons
         r = run_plan(plan, lut, img, img_pitch, bins, ii, tmpl, bias, scores, workspace, stream);
         if (r != HOG_OK) return r;
         float best_ms = 1e30f;
-        for (int i = 0; i < reps; ++i) {
+        for (int round = 0; round < 3; ++round) {
             hipError_t he = hipEventRecord(e0, s);
-            r = run_plan(plan, lut, img, img_pitch, bins, ii, tmpl, bias, scores, workspace, stream);
+            for (int i = 0; i < reps && r == HOG_OK; ++i)
+                r = run_plan(plan, lut, img, img_pitch, bins, ii, tmpl, bias, scores, workspace, stream);
             if (r != HOG_OK) return r;
-            float one = 0.f;
+            float total = 0.f;
             if (he == hipSuccess) he = hipEventRecord(e1, s);
             if (he == hipSuccess) he = hipEventSynchronize(e1);
-            if (he == hipSuccess) he = hipEventElapsedTime(&one, e0, e1);
+            if (he == hipSuccess) he = hipEventElapsedTime(&total, e0, e1);
             if (he != hipSuccess) return device_fail(he, "autotune timing");
-            best_ms = std::min(best_ms, one);
+            best_ms = std::min(best_ms, total / (float)reps);
         }
         *ms = best_ms;
         return HOG_OK;
