@@ -535,32 +535,39 @@ __device__ __forceinline__ void strip_prep(const StripArgs &a, const float *__re
     float *wb = wbuf + w * kStripPrepRows * RS;
     if (threadIdx.x == 0) *need_exact = 0;
     float vals[BXW][Sh::S][8];
+    // The weights of block column bx are one run of 4 N_b consecutive
+    // template elements per block row offset n (its four cells' bins):
+    // loaded whole, 64 lanes at a time, every column of the wave at once,
+    // then written to this wave's LDS rows one column at a time and gathered
+    // into the fragment layout. (Gathered straight from the template, each
+    // load would touch 64 cache lines.)
+    const int run = 4 * a.nb;
+    float t[BXW][kStripPrepRows][NL];
 #pragma unroll
     for (int r = 0; r < BXW; ++r) {
         const int bx = w + W * r;
-        float mx = 0.f;
         if (bx < kStripMaxBX) {  // wave-uniform
-            // The weights of block column bx are one run of 4 N_b consecutive
-            // template elements per block row offset n (its four cells'
-            // bins): loaded whole, 64 lanes at a time, into this wave's LDS
-            // rows, then gathered into the fragment layout. (Gathered straight
-            // from the template, each load would touch 64 cache lines.)
-            const int run = 4 * a.nb;
-            float t[kStripPrepRows][NL];
 #pragma unroll
             for (int m = 0; m < kStripPrepRows; ++m)
 #pragma unroll
                 for (int h = 0; h < NL; ++h) {
                     const int e = 64 * h + lane;
                     const bool ok = (m < a.nby) & (e < run);
-                    t[m][h] = tk[ok ? (m * kStripMaxBX + bx) * run + e : 0];
+                    t[r][m][h] = tk[ok ? (m * kStripMaxBX + bx) * run + e : 0];
                 }
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < BXW; ++r) {
+        const int bx = w + W * r;
+        float mx = 0.f;
+        if (bx < kStripMaxBX) {  // wave-uniform
             lds_order();  // the previous column's gather reads come first
 #pragma unroll
             for (int m = 0; m < kStripPrepRows; ++m)
 #pragma unroll
                 for (int h = 0; h < NL; ++h)
-                    if (64 * h + lane < RS) wb[m * RS + 64 * h + lane] = t[m][h];
+                    if (64 * h + lane < RS) wb[m * RS + 64 * h + lane] = t[r][m][h];
             lds_order();
         }
 #pragma unroll
