@@ -669,12 +669,16 @@ struct ScanRanges {
 };
 
 
+// Workgroups of eight waves: the template prep below then gives each wave
+// one block column (kStripMaxBX = 7).
+constexpr int kScanWaves = 8, kScanThreads = 64 * kScanWaves;
+
 // NBP > 0: the launch also prepares the one-template strip scorer's weights
-// (strip_prep, four waves per template) in its first r.prep_blocks
+// (strip_prep, one wave per block column) in its first r.prep_blocks
 // workgroups, beside the carries rather than as a launch of its own on the
 // path (the two write disjoint parts of the workspace).
 template <int NBP>
-__global__ __launch_bounds__(256) void k_int_scan(const Level *__restrict__ lv,
+__global__ __launch_bounds__(kScanThreads) void k_int_scan(const Level *__restrict__ lv,
                                                   const int32_t *__restrict__ first_e,
                                                   const int32_t *__restrict__ first_c,
                                                   const int32_t *__restrict__ first_p, int n_levels,
@@ -686,8 +690,8 @@ __global__ __launch_bounds__(256) void k_int_scan(const Level *__restrict__ lv,
         if (blk < r.prep_blocks) {
             __shared__ float colmax[kStripMaxBX][64];
             __shared__ int need_exact;
-            __shared__ float wbuf[4 * kStripPrepRows * 4 * (NBP > 0 ? NBP : 1)];
-            strip_prep<NBP, 4>(pa, tmpl, ws, blk, colmax, &need_exact, wbuf);
+            __shared__ float wbuf[kScanWaves * kStripPrepRows * 4 * (NBP > 0 ? NBP : 1)];
+            strip_prep<NBP, kScanWaves>(pa, tmpl, ws, blk, colmax, &need_exact, wbuf);
             return;
         }
         blk -= r.prep_blocks;
@@ -724,7 +728,7 @@ __global__ __launch_bounds__(256) void k_int_scan(const Level *__restrict__ lv,
         for (; t < count; ++t) step(__builtin_amdgcn_raw_buffer_load_b32(src, vs, (int)((uint32_t)t * stride), 0), t);
     };
     if (blk < r.rows_blocks) {
-        const int g0 = __builtin_amdgcn_readfirstlane(blk * 256 + (int)(threadIdx.x & ~63u));
+        const int g0 = __builtin_amdgcn_readfirstlane(blk * kScanThreads + (int)(threadIdx.x & ~63u));
         if (g0 >= first_e[n_levels]) return;
         const int l = find_level(first_e, n_levels, g0);
         const Level &v = lv[l];
@@ -742,7 +746,7 @@ __global__ __launch_bounds__(256) void k_int_scan(const Level *__restrict__ lv,
         return;
     }
     if (blk < r.rows_blocks + r.cols_blocks) {
-        const int g0 = __builtin_amdgcn_readfirstlane((blk - r.rows_blocks) * 256 + (int)(threadIdx.x & ~63u));
+        const int g0 = __builtin_amdgcn_readfirstlane((blk - r.rows_blocks) * kScanThreads + (int)(threadIdx.x & ~63u));
         if (g0 >= first_c[n_levels]) return;
         const int l = find_level(first_c, n_levels, g0);
         const Level &v = lv[l];
@@ -759,7 +763,7 @@ __global__ __launch_bounds__(256) void k_int_scan(const Level *__restrict__ lv,
         return;
     }
     // Tiles: one wave per (level, n); lanes over tile columns in chunks of 64.
-    const int g = (blk - r.rows_blocks - r.cols_blocks) * 4 + wave_id_in_block();
+    const int g = (blk - r.rows_blocks - r.cols_blocks) * kScanWaves + wave_id_in_block();
     if (g >= first_p[n_levels]) return;
     const int l = find_level(first_p, n_levels, g);
     const Level &v = lv[l];
@@ -2549,12 +2553,12 @@ hipError_t launch_int_scan(const PlanDev &p, uint8_t *ws, hipStream_t stream, co
     const bool prep = tmpl && scan_runs_prep(p);
     const StripArgs pa = prep ? strip_args(p) : StripArgs{};
     r.prep_blocks = prep ? pa.k : 0;
-    r.rows_blocks = (int)blocks_for(p.total[KB_ESCAN], 256);
-    r.cols_blocks = (int)blocks_for(p.total[KB_CSCAN], 256);
-    const int tile_blocks = (int)blocks_for(p.total[KB_PSCAN], 4);
+    r.rows_blocks = (int)blocks_for(p.total[KB_ESCAN], kScanThreads);
+    r.cols_blocks = (int)blocks_for(p.total[KB_CSCAN], kScanThreads);
+    const int tile_blocks = (int)blocks_for(p.total[KB_PSCAN], kScanWaves);
     const int n = r.prep_blocks + r.rows_blocks + r.cols_blocks + tile_blocks;
     if (n == 0) return hipSuccess;
-    const dim3 grid((unsigned)n), block(256);
+    const dim3 grid((unsigned)n), block(kScanThreads);
     const int32_t *fe = first_of(p, KB_ESCAN), *fc = first_of(p, KB_CSCAN), *fp = first_of(p, KB_PSCAN);
     switch (prep ? p.mfma_ks : 0) {
     case 0: hipLaunchKernelGGL(k_int_scan<0>, grid, block, 0, stream, p.levels, fe, fc, fp, p.n_levels, p.n_bins, r, ws, pa, tmpl); break;
