@@ -512,8 +512,8 @@ __device__ __forceinline__ int strip_weight_index(int k, int nbp, int nb, int nb
 // block (the 16x16x4 FP32 products' layout), and scale 1.
 //
 // The prep of template kk by the W waves of a workgroup, wave w taking the
-// block columns bx = w, w + W, ... (k_score_prep: W = kStripMaxBX, one each;
-// the carry scan's prep workgroups: W = 4, up to two each). colmax,
+// block columns bx = w, w + W, ... (k_score_prep: W = kStripMaxBX; the carry
+// scan's prep workgroups: W = 8, the last wave idle; one column each). colmax,
 // need_exact and wbuf (W x kStripPrepRows x 4 NBP floats) are the
 // workgroup's LDS.
 constexpr int kStripPrepRows = 16;  // block row offsets n a template may have (lane & 15)
