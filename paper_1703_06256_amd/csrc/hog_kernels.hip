@@ -829,9 +829,14 @@ __global__ __launch_bounds__(kScanThreads) void k_int_scan(const Level *__restri
 // integral images, taken mod 2^(8 PB) so that four-corner sums of areas below
 // 2^(8 PB) pixels stay exact). The running values in registers are full
 // 32-bit counts either way, so the cell cache is the same for every PB.
+//
+// Occupancy: the uint16 writer with the cell cache waits mostly on
+// instruction dependencies, so it is held to 8 waves per SIMD (at most 64
+// VGPRs, no spills for any NBC), where the default allocation gives it 6.
+// The uint32 writer (HBM-bound) and the uint8 writer ran slower so held.
 // ---------------------------------------------------------------------------
 template <int NBC, bool CELLS, int PB>
-__global__ __launch_bounds__(256) void k_int_emit(const Level *__restrict__ lv,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PB == 2 && CELLS ? 8 : 1))) void k_int_emit(const Level *__restrict__ lv,
                                                   const int32_t *__restrict__ first, int n_levels,
                                                   int nb, int n_chunk,
                                                   const uint8_t *__restrict__ bins,
