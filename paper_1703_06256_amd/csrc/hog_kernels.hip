@@ -118,8 +118,11 @@ __device__ __forceinline__ uint32_t from_right_lane(uint32_t v)
 // the L1/L2 caches instead of the LDS half table (no staging and no LDS, so
 // smaller workgroups, several per CU); the plan picks one
 // (hog_tiles.lut_global).
+// Occupancy: the soft RGB form reads its table through L2 and waits on
+// loads; held to 6 waves per SIMD (at most 80 VGPRs, no spills) it runs
+// faster than at the 5 its default allocation gives.
 template <int C, bool SOFT, bool GLUT = false>
-__global__ __launch_bounds__(1024) void k_bin_map(const Level *__restrict__ lv,
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(SOFT && C == 3 ? 6 : 1))) void k_bin_map(const Level *__restrict__ lv,
                                                   const int32_t *__restrict__ first, int n_levels,
                                                   const int32_t *__restrict__ mapx,
                                                   const int32_t *__restrict__ mapy,
@@ -2464,6 +2467,25 @@ inline const int32_t *first_of(const PlanDev &p, int k)
     return p.first + (int64_t)k * (p.n_levels + 1);
 }
 
+// Workgroups of `block` threads (no dynamic LDS) of a persistent kernel that
+// one CU holds at once, from the runtime's occupancy calculator (at least 1).
+// A persistent grid larger than what is resident would leave its last
+// workgroups to run as a second, thinly occupied round.
+template <typename K>
+int resident_blocks(K kernel, int block)
+{
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kernel, block, 0) != hipSuccess || n < 1) n = 1;
+    return n;
+}
+
+// Persistent grid over `items` wave items: at most one item per wave, at
+// most per_cu workgroups of `waves` waves per CU.
+inline unsigned persistent_grid(const PlanDev &p, int64_t items, int64_t waves, int per_cu)
+{
+    return (unsigned)std::min<int64_t>((items + waves - 1) / waves, (int64_t)per_cu * p.n_cu);
+}
+
 }  // namespace
 
 hipError_t launch_bin_map(const PlanDev &p, const uint8_t *lut_half, const uint8_t *lut_full,
@@ -2472,16 +2494,18 @@ hipError_t launch_bin_map(const PlanDev &p, const uint8_t *lut_half, const uint8
     const int64_t items = p.total[KB_BINMAP];
     if (items == 0) return hipSuccess;
     const int64_t per_block = 16;  // waves of a 1024-thread workgroup
-    if (p.lut_global) {  // no LDS table: 4-wave workgroups, up to 7 per CU (the registers allow 7 waves per SIMD)
-        const unsigned grid = (unsigned)std::min<int64_t>((items + 3) / 4, 7 * (int64_t)p.n_cu);
-        if (p.channels == 1)
-            hipLaunchKernelGGL((k_bin_map<1, false, true>), dim3(grid), dim3(256), 0, stream, p.levels,
-                               first_of(p, KB_BINMAP), p.n_levels, p.mapx, p.mapy, img, img_pitch,
-                               p.n_bins, lut_full, nullptr, bins);
-        else
-            hipLaunchKernelGGL((k_bin_map<3, false, true>), dim3(grid), dim3(256), 0, stream, p.levels,
-                               first_of(p, KB_BINMAP), p.n_levels, p.mapx, p.mapy, img, img_pitch,
-                               p.n_bins, lut_full, nullptr, bins);
+    if (p.lut_global) {  // no LDS table: 4-wave workgroups, as many per CU as its registers allow
+        if (p.channels == 1) {
+            static const int per_cu = resident_blocks(k_bin_map<1, false, true>, 256);
+            hipLaunchKernelGGL((k_bin_map<1, false, true>), dim3(persistent_grid(p, items, 4, per_cu)), dim3(256), 0,
+                               stream, p.levels, first_of(p, KB_BINMAP), p.n_levels, p.mapx, p.mapy, img,
+                               img_pitch, p.n_bins, lut_full, nullptr, bins);
+        } else {
+            static const int per_cu = resident_blocks(k_bin_map<3, false, true>, 256);
+            hipLaunchKernelGGL((k_bin_map<3, false, true>), dim3(persistent_grid(p, items, 4, per_cu)), dim3(256), 0,
+                               stream, p.levels, first_of(p, KB_BINMAP), p.n_levels, p.mapx, p.mapy, img,
+                               img_pitch, p.n_bins, lut_full, nullptr, bins);
+        }
         return hipGetLastError();
     }
     const unsigned grid = (unsigned)std::min<int64_t>((items + per_block - 1) / per_block, p.n_cu);
@@ -2501,16 +2525,18 @@ hipError_t launch_bin_map_soft(const PlanDev &p, const uint16_t *soft_lut, const
 {
     const int64_t items = p.total[KB_BINMAP];
     if (items == 0) return hipSuccess;
-    const int64_t per_block = 16;  // waves of a 1024-thread workgroup; no LDS table: two per CU
-    const unsigned grid = (unsigned)std::min<int64_t>((items + per_block - 1) / per_block, 2 * (int64_t)p.n_cu);
-    if (p.channels == 1)
-        hipLaunchKernelGGL((k_bin_map<1, true>), dim3(grid), dim3(1024), 0, stream, p.levels,
-                           first_of(p, KB_BINMAP), p.n_levels, p.mapx, p.mapy, img, img_pitch,
+    // No LDS table: 4-wave workgroups, as many per CU as its registers allow.
+    if (p.channels == 1) {
+        static const int per_cu = resident_blocks(k_bin_map<1, true>, 256);
+        hipLaunchKernelGGL((k_bin_map<1, true>), dim3(persistent_grid(p, items, 4, per_cu)), dim3(256), 0, stream,
+                           p.levels, first_of(p, KB_BINMAP), p.n_levels, p.mapx, p.mapy, img, img_pitch,
                            p.n_bins, nullptr, soft_lut, bins);
-    else
-        hipLaunchKernelGGL((k_bin_map<3, true>), dim3(grid), dim3(1024), 0, stream, p.levels,
-                           first_of(p, KB_BINMAP), p.n_levels, p.mapx, p.mapy, img, img_pitch,
+    } else {
+        static const int per_cu = resident_blocks(k_bin_map<3, true>, 256);
+        hipLaunchKernelGGL((k_bin_map<3, true>), dim3(persistent_grid(p, items, 4, per_cu)), dim3(256), 0, stream,
+                           p.levels, first_of(p, KB_BINMAP), p.n_levels, p.mapx, p.mapy, img, img_pitch,
                            p.n_bins, nullptr, soft_lut, bins);
+    }
     return hipGetLastError();
 }
 
