@@ -464,9 +464,11 @@ static hog_status create_plan(const hog_plan_desc *descs, int n_img, bool batch,
     int raw_waves = 0;
     if (scorer == 0 && sp.norm == HOG_NORM_RAW) {
         // Raw features: 64 windows per workgroup (tw x th = 64, one per lane),
-        // min(wcy, 16) waves splitting each window's cell rows; the shape
-        // staging the fewest cells per tile that fits 64 KB of LDS.
-        const int R = std::min(sp.win_cells_y, 16);
+        // min(wcy, 8) waves splitting each window's cell rows; the shape
+        // staging the fewest cells per tile that fits 64 KB of LDS. Eight
+        // waves rather than one per cell row: one image's step is as fast,
+        // and a batch's many tiles overlap more workgroups per CU.
+        const int R = std::min(sp.win_cells_y, 8);
         int64_t best_cells = INT64_MAX;
         for (int tw = 64; tw >= 1; tw /= 2) {
             const int th = 64 / tw;
