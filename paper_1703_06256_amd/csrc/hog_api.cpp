@@ -1306,7 +1306,9 @@ extern "C" hog_status hog_plan_autotune(hog_plan *plan, const hog_lut *lut, cons
         }
     }
     if (st == HOG_OK && plan->dev.scorer == 1) {
-        const int cand[] = {8, 12, 16, 24, 32};
+        // Small heights suit small images (more, shorter waves); 20 puts the
+        // 1920 x 1080 pyramid's strips at one wave per SIMD (991 strips).
+        const int cand[] = {4, 6, 8, 12, 16, 20, 24, 32};
         for (int rows : cand) {
             float ms = 0.f;
             st = time_with(best_chunk, rows, 1, &ms);
