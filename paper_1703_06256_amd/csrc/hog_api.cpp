@@ -787,6 +787,11 @@ static hog_status create_plan(const hog_plan_desc *descs, int n_img, bool batch,
             ncu < 1)
             ncu = 256;
         pd.n_cu = ncu;
+        // The bin map's cache-read forms size their persistent grids from the
+        // runtime's occupancy figures: asked here, so that no launch asks
+        // first under stream capture.
+        (void)hogk::bin_map_blocks_per_cu(false, pd.channels);
+        (void)hogk::bin_map_blocks_per_cu(true, pd.channels);
         pd.tprep_off = tprep_off;
         pd.tprep_stride = tprep_stride;
     }

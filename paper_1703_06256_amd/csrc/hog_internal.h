@@ -127,6 +127,12 @@ struct PlanDev {
 // Sets the calling thread's hog_last_error() message (hog_api.cpp).
 void set_last_error(const char *msg);
 
+// Four-wave workgroups per CU that the bin map's cache-read forms keep
+// resident (the full table through L2, or the soft table), from the
+// runtime's occupancy calculator, asked once per form. The plan builder asks
+// first, so that no launch makes that call under stream capture.
+int bin_map_blocks_per_cu(bool soft, int channels);
+
 // Launchers (hog_kernels.hip). Each enqueues one kernel on `stream` and
 // returns the launch status.
 hipError_t launch_bin_map(const PlanDev &p, const uint8_t *lut_half, const uint8_t *lut_full,

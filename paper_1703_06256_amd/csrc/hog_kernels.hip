@@ -2488,6 +2488,16 @@ inline unsigned persistent_grid(const PlanDev &p, int64_t items, int64_t waves, 
 
 }  // namespace
 
+int bin_map_blocks_per_cu(bool soft, int channels)
+{
+    static const int l2_1 = resident_blocks(k_bin_map<1, false, true>, 256);
+    static const int l2_3 = resident_blocks(k_bin_map<3, false, true>, 256);
+    static const int soft_1 = resident_blocks(k_bin_map<1, true>, 256);
+    static const int soft_3 = resident_blocks(k_bin_map<3, true>, 256);
+    if (soft) return channels == 1 ? soft_1 : soft_3;
+    return channels == 1 ? l2_1 : l2_3;
+}
+
 hipError_t launch_bin_map(const PlanDev &p, const uint8_t *lut_half, const uint8_t *lut_full,
                           const uint8_t *img, int64_t img_pitch, uint8_t *bins, hipStream_t stream)
 {
@@ -2495,13 +2505,12 @@ hipError_t launch_bin_map(const PlanDev &p, const uint8_t *lut_half, const uint8
     if (items == 0) return hipSuccess;
     const int64_t per_block = 16;  // waves of a 1024-thread workgroup
     if (p.lut_global) {  // no LDS table: 4-wave workgroups, as many per CU as its registers allow
+        const int per_cu = bin_map_blocks_per_cu(false, p.channels);
         if (p.channels == 1) {
-            static const int per_cu = resident_blocks(k_bin_map<1, false, true>, 256);
             hipLaunchKernelGGL((k_bin_map<1, false, true>), dim3(persistent_grid(p, items, 4, per_cu)), dim3(256), 0,
                                stream, p.levels, first_of(p, KB_BINMAP), p.n_levels, p.mapx, p.mapy, img,
                                img_pitch, p.n_bins, lut_full, nullptr, bins);
         } else {
-            static const int per_cu = resident_blocks(k_bin_map<3, false, true>, 256);
             hipLaunchKernelGGL((k_bin_map<3, false, true>), dim3(persistent_grid(p, items, 4, per_cu)), dim3(256), 0,
                                stream, p.levels, first_of(p, KB_BINMAP), p.n_levels, p.mapx, p.mapy, img,
                                img_pitch, p.n_bins, lut_full, nullptr, bins);
@@ -2526,13 +2535,12 @@ hipError_t launch_bin_map_soft(const PlanDev &p, const uint16_t *soft_lut, const
     const int64_t items = p.total[KB_BINMAP];
     if (items == 0) return hipSuccess;
     // No LDS table: 4-wave workgroups, as many per CU as its registers allow.
+    const int per_cu = bin_map_blocks_per_cu(true, p.channels);
     if (p.channels == 1) {
-        static const int per_cu = resident_blocks(k_bin_map<1, true>, 256);
         hipLaunchKernelGGL((k_bin_map<1, true>), dim3(persistent_grid(p, items, 4, per_cu)), dim3(256), 0, stream,
                            p.levels, first_of(p, KB_BINMAP), p.n_levels, p.mapx, p.mapy, img, img_pitch,
                            p.n_bins, nullptr, soft_lut, bins);
     } else {
-        static const int per_cu = resident_blocks(k_bin_map<3, true>, 256);
         hipLaunchKernelGGL((k_bin_map<3, true>), dim3(persistent_grid(p, items, 4, per_cu)), dim3(256), 0, stream,
                            p.levels, first_of(p, KB_BINMAP), p.n_levels, p.mapx, p.mapy, img, img_pitch,
                            p.n_bins, nullptr, soft_lut, bins);
